@@ -1,0 +1,457 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+known-answer values, exact rational arithmetic, hand-derived fixtures, brute
+force on tiny inputs, closed forms and invariants of the Count Sketch (Sec. 2.2),
+chosen so that a dropped term, a wrong sign or index, or a transposed operand in
+the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+import struct
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+CONFIG_MESHES = [(100.0, 0.1), (1000.0, 0.25), (3000.0, 0.25), (3000.0, 0.5), (3000.0, 1.0)]
+
+
+def f32_below(x):
+    b = struct.unpack("I", struct.pack("f", x))[0]
+    return struct.unpack("f", struct.pack("I", b - 1))[0]
+
+
+def exact_index(p: float, G: int, L: float) -> int:
+    """floor(p*G/L) on exact rationals, wrapped — with Python's Fraction."""
+    q = Fraction(p) * G / Fraction(L)
+    return math.floor(q) % G
+
+
+# ------------------------------------------------------------------ SplitMix64
+
+def test_splitmix64_known_answers():
+    # Published reference outputs of SplitMix64 (Steele, Lea & Flood 2014).
+    assert [int(x) for x in oracle.splitmix64(0, 3)] == [
+        0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert [int(x) for x in oracle.splitmix64(1234567, 5)] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423,
+        4593380528125082431, 16408922859458223821]
+
+
+def test_hash_tables_layout_follows_generator_stream():
+    seed, d = 12345, 5
+    T = oracle.hash_tables(seed, d).ravel()
+    z = oracle.splitmix64(seed, T.size // 2)
+    assert np.array_equal(T[0::2], (z & np.uint64(0xFFFFFFFF)).astype(np.uint32))
+    assert np.array_equal(T[1::2], (z >> np.uint64(32)).astype(np.uint32))
+
+
+def test_hash_tables_prefix_rows_do_not_depend_on_d():
+    assert np.array_equal(oracle.hash_tables(7, 3), oracle.hash_tables(7, 5)[:3])
+
+
+# ------------------------------------------------------------------ mesh (O1)
+
+def test_grid_valid_and_invalid():
+    assert oracle.grid(0.1, 100.0) == 1000
+    assert oracle.grid(0.25, 1000.0) == 4000
+    assert oracle.grid(0.25, 3000.0) == 12000
+    assert oracle.grid(0.1, 500.0) == 5000          # the paper's Millennium mesh, Sec. 4.1
+    for bad in [(0.0, 100.0), (-0.1, 100.0), (0.3, 100.0), (0.001, 100.0), (float("nan"), 1.0),
+                (1.0, float("inf")), (1e-3, 1000.0)]:
+        with pytest.raises(ValueError):
+            oracle.grid(*bad)
+
+
+# ------------------------------------------------------------ cell index (O2)
+
+def test_cell_index_golden_fixture():
+    doc = json.load(open(os.path.join(GOLDEN, "cell_keys.json")))
+    for c in doc["cell_index"]:
+        p = float.fromhex(c["p_hex"]) if "0x" in c["p_hex"] else float(c["p_hex"])
+        G = oracle.grid(c["delta"], c["L"])
+        got = oracle.cell_index(p, G, c["L"])
+        want = -1 if c["expected"] is None else c["expected"]
+        assert got == want, c
+
+
+def test_cell_key_golden_fixture():
+    doc = json.load(open(os.path.join(GOLDEN, "cell_keys.json")))
+    for c in doc["cell_key"]:
+        xyz = np.array([[float.fromhex(h) for h in c["xyz_hex"]]], dtype=np.float32)
+        assert int(oracle.keys(xyz, c["delta"], c["L"])[0]) == c["expected_key"], c
+
+
+@pytest.mark.parametrize("L,delta", CONFIG_MESHES)
+def test_cell_index_matches_exact_rationals(L, delta):
+    G = oracle.grid(delta, L)
+    rng = np.random.default_rng(1)
+    ps = list(rng.uniform(-L, 2 * L, 3000).astype(np.float32))
+    # floats adjacent to cell boundaries j * L / G
+    for j in rng.integers(0, 2 * G, 600):
+        b = np.float32(j * L / G)
+        ps += [b, np.nextafter(b, np.float32(np.inf)), np.nextafter(b, np.float32(-np.inf))]
+    ps += [np.float32(0.0), np.float32(-0.0), np.float32(L), np.float32(1e-38), np.float32(-1e-45)]
+    got = oracle.cell_index_many(np.array(ps, dtype=np.float32), G, L)
+    for p, g in zip(ps, got):
+        want = exact_index(float(p), G, L) if abs(float(p)) < 2 * L else -1
+        assert g == want, (float(p), g, want)
+
+
+def test_cell_index_nests_across_resolutions():
+    # floor(floor(p G / L) / m) = floor(p (G/m) / L) for an integer m dividing G:
+    # the 0.25 -> 0.5 -> 1.0 Mpc/h meshes of one box nest exactly.
+    L = 3000.0
+    rng = np.random.default_rng(2)
+    p = rng.uniform(0, L, 20000).astype(np.float32)
+    fine = oracle.cell_index_many(p, 12000, L)
+    for m, G in [(2, 6000), (4, 3000)]:
+        assert np.array_equal(fine // m, oracle.cell_index_many(p, G, L))
+
+
+def test_keys_round_trip_and_order():
+    L, delta = 1000.0, 0.25
+    G = oracle.grid(delta, L)
+    rng = np.random.default_rng(3)
+    pos = rng.uniform(0, L, (5000, 3)).astype(np.float32)
+    k = oracle.keys(pos, delta, L).astype(np.int64)
+    ix, rest = np.divmod(k, G * G)
+    iy, iz = np.divmod(rest, G)
+    for axis, idx in enumerate([ix, iy, iz]):
+        assert np.array_equal(idx, oracle.cell_index_many(pos[:, axis], G, L))
+    assert k.max() < G ** 3
+
+
+def test_keys_skip_out_of_domain_particles():
+    pos = np.array([[1, 2, 3], [np.nan, 1, 1], [1, np.inf, 1], [1, 1, 250.0], [4, 5, 6]], dtype=np.float32)
+    k = oracle.keys(pos, 1.0, 100.0)
+    assert list(k) == [(1 * 100 + 2) * 100 + 3, (4 * 100 + 5) * 100 + 6]
+
+
+def test_periodic_wrap_gives_same_key():
+    rng = np.random.default_rng(4)
+    pos = rng.uniform(0, 100, (2000, 3)).astype(np.float32)
+    shifted = (pos.astype(np.float64) - 100.0).astype(np.float32)
+    exact_shift = (shifted.astype(np.float64) + 100.0) == pos.astype(np.float64)
+    rows = exact_shift.all(axis=1)
+    assert rows.sum() > 100
+    assert np.array_equal(oracle.keys(pos[rows], 0.1, 100.0), oracle.keys(shifted[rows], 0.1, 100.0))
+
+
+# ------------------------------------------------------------ row hash (O5)
+
+def test_tabulation_structure():
+    # Simple tabulation: two keys that differ only in byte c have hashes that differ
+    # by T[r][c][a] ^ T[r][c][b], whatever the other bytes are.
+    T = oracle.hash_tables(99, 4)
+    rng = np.random.default_rng(5)
+    base = rng.integers(0, 2 ** 48, 200, dtype=np.uint64)
+    for c in range(6):
+        a, b = 17, 201
+        mask = ~np.uint64(0xFF << (8 * c))
+        k1 = (base & mask) | np.uint64(a << (8 * c))
+        k2 = (base & mask) | np.uint64(b << (8 * c))
+        for r in range(4):
+            x = oracle.row_hash(T, r, k1) ^ oracle.row_hash(T, r, k2)
+            assert np.all(x == (T[r, c, a] ^ T[r, c, b]))
+    assert oracle.row_hash(T, 2, np.array([0], dtype=np.uint64))[0] == np.bitwise_xor.reduce(T[2, :, 0])
+
+
+def test_bucket_range_reduction():
+    rng = np.random.default_rng(6)
+    hs = [int(x) for x in rng.integers(0, 2 ** 32, 2000, dtype=np.uint64)] + [0, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFF]
+    for w in [1, 2, 3, 1000, 4154983, 1 << 16, 1 << 24, 1 << 30]:
+        for h in hs:
+            b = oracle.bucket(h, w)
+            assert 0 <= b < w
+            # floor(h31 * w / 2^31) with h31 the low 31 bits
+            assert b == ((h & 0x7FFFFFFF) * w) >> 31
+            if w & (w - 1) == 0:
+                lg = w.bit_length() - 1
+                assert b == (h & 0x7FFFFFFF) >> (31 - lg)
+
+
+def test_sign_from_top_bit():
+    assert oracle.sign(0) == 1 and oracle.sign(0x7FFFFFFF) == 1
+    assert oracle.sign(0x80000000) == -1 and oracle.sign(0xFFFFFFFF) == -1
+
+
+def test_hash_statistics():
+    # Buckets uniform (chi-square), signs balanced, rows independent (collision
+    # rate of two rows ~ 1/w^2 per pair of keys rather than 1/w).
+    T = oracle.hash_tables(2024, 3)
+    keys = np.arange(200_000, dtype=np.uint64) * np.uint64(7919)
+    w = 1024
+    H = [oracle.row_hash(T, r, keys) for r in range(3)]
+    B = [((h.astype(np.uint64) & np.uint64(0x7FFFFFFF)) * np.uint64(w)) >> np.uint64(31) for h in H]
+    for r in range(3):
+        counts = np.bincount(B[r].astype(np.int64), minlength=w)
+        e = keys.size / w
+        chi2 = ((counts - e) ** 2 / e).sum()
+        assert abs(chi2 - (w - 1)) < 6 * math.sqrt(2 * (w - 1))
+        s = (H[r] >> np.uint32(31)).astype(np.int64)
+        assert abs(s.mean() - 0.5) < 5 * 0.5 / math.sqrt(keys.size)
+    joint = B[0] * np.uint64(w) + B[1]
+    cj = np.bincount(joint.astype(np.int64), minlength=w * w)
+    e = keys.size / (w * w)
+    assert abs(cj.mean() - e) < 1e-9
+    assert cj.max() < 20
+
+
+# ------------------------------------------------------------ Add (O6)
+
+def small_stream(n=20000, L=100.0, seed=0):
+    """Clustered stream: a few dense clumps plus uniform background."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0, L, (12, 3))
+    which = rng.integers(0, 12, n)
+    clump = centres[which] + rng.normal(0, 0.15, (n, 3))
+    bg = rng.uniform(0, L, (n, 3))
+    pos = np.where((rng.random(n) < 0.6)[:, None], clump, bg)
+    return np.mod(pos, L).astype(np.float32)
+
+
+def brute_counters(T, d, w, keys_, variant=oracle.VARIANT_CS):
+    """Histogram-driven brute force: M[r][b] = sum over distinct keys j with
+    bucket_r(j) = b of f_j * sign_r(j)."""
+    uniq, f = oracle.histogram(keys_)
+    M = np.zeros((d, w), dtype=np.int64)
+    for r in range(d):
+        h = oracle.row_hash(T, r, uniq).astype(np.uint64)
+        b = ((h & np.uint64(0x7FFFFFFF)) * np.uint64(w)) >> np.uint64(31)
+        s = np.where(h >> np.uint64(31), -1, 1) if variant == oracle.VARIANT_CS else np.ones_like(f)
+        np.add.at(M[r], b.astype(np.int64), f * s)
+    return ((M + 2 ** 31) % 2 ** 32 - 2 ** 31).astype(np.int32)
+
+
+@pytest.mark.parametrize("d,w", [(5, 1 << 10), (3, 1000), (1, 1), (8, 4154983 // 4096)])
+def test_stream_counters_equal_histogram_brute_force(d, w):
+    pos = small_stream()
+    M, skipped = oracle.sketch(pos, d, w, 11, 0.1, 100.0)
+    assert skipped == 0
+    assert np.array_equal(M, brute_counters(oracle.hash_tables(11, d), d, w, oracle.keys(pos, 0.1, 100.0)))
+
+
+def test_count_min_rows_sum_to_n():
+    pos = small_stream(15000)
+    pos[::97] = np.nan
+    n_valid = len(oracle.keys(pos, 0.1, 100.0))
+    M, skipped = oracle.sketch(pos, 5, 777, 3, 0.1, 100.0, variant=oracle.VARIANT_CM)
+    assert skipped == len(pos) - n_valid > 0
+    assert np.all(M.astype(np.int64).sum(axis=1) == n_valid)
+
+
+def test_count_sketch_row_sums_are_signed_totals():
+    pos = small_stream(15000)
+    d, w, seed = 5, 512, 8
+    M, _ = oracle.sketch(pos, d, w, seed, 0.1, 100.0)
+    T = oracle.hash_tables(seed, d)
+    k = oracle.keys(pos, 0.1, 100.0)
+    for r in range(d):
+        s = np.where(oracle.row_hash(T, r, k) >> np.uint32(31), -1, 1)
+        assert M[r].astype(np.int64).sum() == s.sum()
+
+
+def test_single_counter_is_signed_sum():
+    # d = w = 1: one counter = sum_j f_j s(j) (the single +-1 counter of Fig. 2).
+    pos = small_stream(5000)
+    M, _ = oracle.sketch(pos, 1, 1, 5, 0.1, 100.0)
+    T = oracle.hash_tables(5, 1)
+    uniq, f = oracle.histogram(oracle.keys(pos, 0.1, 100.0))
+    s = np.where(oracle.row_hash(T, 0, uniq) >> np.uint32(31), -1, 1)
+    assert int(M[0, 0]) == int((f * s).sum())
+
+
+def test_permutation_chunking_and_merge_invariance():
+    pos = small_stream(12000)
+    d, w, seed = 5, 333, 21
+    M, _ = oracle.sketch(pos, d, w, seed, 0.1, 100.0)
+    perm = np.random.default_rng(9).permutation(len(pos))
+    Mp, _ = oracle.sketch(pos[perm], d, w, seed, 0.1, 100.0)
+    assert np.array_equal(M, Mp)
+    # sketches of disjoint parts sum to the sketch of the whole (mergeability, Sec. 5)
+    A, _ = oracle.sketch(pos[:5000], d, w, seed, 0.1, 100.0)
+    B, _ = oracle.sketch(pos[5000:], d, w, seed, 0.1, 100.0)
+    assert np.array_equal(M, (A.view(np.uint32) + B.view(np.uint32)).view(np.int32))
+    # incremental update equals one update over the concatenation
+    T = oracle.hash_tables(seed, d)
+    Mi = np.zeros((d, w), np.int32)
+    oracle.sketch_update(Mi, T, pos[:7000], 0.1, 100.0)
+    oracle.sketch_update(Mi, T, pos[7000:], 0.1, 100.0)
+    assert np.array_equal(M, Mi)
+    Mt, _ = oracle.sketch(pos, d, w, seed, 0.1, 100.0, threads=4)
+    assert np.array_equal(M, Mt)
+
+
+def test_counters_wrap_modulo_2_32():
+    d, w = 1, 1
+    T = oracle.hash_tables(0, 1)
+    M = np.full((d, w), 2 ** 31 - 1, dtype=np.int32)
+    pos = np.zeros((1, 3), np.float32)
+    key0 = oracle.keys(pos, 1.0, 10.0)
+    s = 1 if oracle.row_hash(T, 0, key0)[0] < 2 ** 31 else -1
+    if s < 0:
+        M[:] = -(2 ** 31)
+    oracle.sketch_update(M, T, pos, 1.0, 10.0)
+    assert int(M[0, 0]) == (-(2 ** 31) if s > 0 else 2 ** 31 - 1)
+
+
+# ------------------------------------------------------------ Estimate (O7)
+
+def per_row_estimates(M, T, keys_):
+    d, w = M.shape
+    out = []
+    for r in range(d):
+        h = oracle.row_hash(T, r, keys_).astype(np.uint64)
+        b = (((h & np.uint64(0x7FFFFFFF)) * np.uint64(w)) >> np.uint64(31)).astype(np.int64)
+        s = np.where(h >> np.uint64(31), -1, 1)
+        out.append(M[r, b].astype(np.int64) * s)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("d", [1, 2, 4, 5, 7])
+def test_estimate_is_lower_median_of_row_estimates(d):
+    pos = small_stream(8000)
+    w, seed = 64, 13
+    M, _ = oracle.sketch(pos, d, w, seed, 0.1, 100.0)
+    T = oracle.hash_tables(seed, d)
+    uniq, _ = oracle.histogram(oracle.keys(pos, 0.1, 100.0))
+    E = per_row_estimates(M, T, uniq)
+    want = np.sort(E, axis=0)[(d - 1) // 2]
+    assert np.array_equal(oracle.estimate(M, T, uniq), want)
+
+
+def test_estimate_exact_without_collisions():
+    # If key j shares its bucket with no other present key in at least floor(d/2)+1
+    # rows, every such row returns f_j exactly and the median of d (odd) is f_j.
+    rng = np.random.default_rng(10)
+    cells = rng.uniform(0, 100, (50, 3))
+    counts = rng.integers(1, 300, 50)
+    pos = np.repeat(cells, counts, axis=0).astype(np.float32)
+    pos = pos[rng.permutation(len(pos))]
+    d, w, seed = 5, 1 << 20, 17
+    M, _ = oracle.sketch(pos, d, w, seed, 0.1, 100.0)
+    T = oracle.hash_tables(seed, d)
+    uniq, f = oracle.histogram(oracle.keys(pos, 0.1, 100.0))
+    est = oracle.estimate(M, T, uniq)
+    clean = 0
+    for j in range(len(uniq)):
+        free_rows = 0
+        for r in range(d):
+            h = oracle.row_hash(T, r, uniq).astype(np.uint64)
+            b = ((h & np.uint64(0x7FFFFFFF)) * np.uint64(w)) >> np.uint64(31)
+            free_rows += int((b == b[j]).sum() == 1)
+        if free_rows >= d // 2 + 1:
+            assert est[j] == f[j]
+            clean += 1
+    assert clean >= 45
+    # with exact estimates the sketch top-k is the exact top-k
+    ks, es, st = oracle.topk_sketch(M, T, pos, 0.1, 100.0, oracle.INT32_MIN, 10)
+    kx, fx = oracle.topk_exact(uniq, f, 10)
+    assert np.array_equal(ks, kx) and np.array_equal(es, fx)
+
+
+def test_count_min_never_underestimates():
+    pos = small_stream(10000)
+    M, _ = oracle.sketch(pos, 4, 97, 1, 0.1, 100.0, variant=oracle.VARIANT_CM)
+    T = oracle.hash_tables(1, 4)
+    uniq, f = oracle.histogram(oracle.keys(pos, 0.1, 100.0))
+    est = oracle.estimate(M, T, uniq, variant=oracle.VARIANT_CM)
+    assert np.all(est >= f)
+    assert np.array_equal(est, per_row_estimates(M.astype(np.int64), T, uniq).__abs__().min(axis=0))
+
+
+def test_row_estimate_is_unbiased_over_seeds():
+    # E[M[r][h(j)] * s(j)] = f_j under pairwise-independent hashing (Sec. 2.2).
+    pos = small_stream(3000, seed=3)
+    uniq, f = oracle.histogram(oracle.keys(pos, 0.1, 100.0))
+    j = int(np.argmax(f))
+    d, w = 1, 16
+    vals = []
+    for seed in range(400):
+        M, _ = oracle.sketch(pos, d, w, 1000 + seed, 0.1, 100.0)
+        vals.append(int(oracle.estimate(M, oracle.hash_tables(1000 + seed, d), uniq[j:j + 1])[0]))
+    vals = np.array(vals, dtype=np.float64)
+    f2_rest = float((f.astype(np.float64) ** 2).sum() - f[j] ** 2)
+    sd = math.sqrt(f2_rest / w)
+    assert abs(vals.mean() - f[j]) < 5 * sd / math.sqrt(len(vals))
+
+
+def test_additive_error_scale():
+    # |est - f| ~ sqrt(F2_res / w) (Sec. 4.3: additive error set by the l2 norm).
+    pos = small_stream(60000, seed=5)
+    d, w, seed = 5, 2048, 2
+    M, _ = oracle.sketch(pos, d, w, seed, 0.1, 100.0)
+    uniq, f = oracle.histogram(oracle.keys(pos, 0.1, 100.0))
+    est = oracle.estimate(M, oracle.hash_tables(seed, d), uniq)
+    top = np.argsort(-f)[:200]
+    f2_res = float((np.sort(f.astype(np.float64))[:-200] ** 2).sum())
+    err = np.abs(est[top].astype(np.int64) - f[top])
+    assert np.median(err) < 3 * math.sqrt(f2_res / w)
+
+
+# ------------------------------------------------------------ histogram (O8)
+
+def test_histogram_matches_dense_counting():
+    rng = np.random.default_rng(12)
+    L, delta = 10.0, 0.5          # G = 20: a dense array of 8000 cells
+    pos = rng.uniform(-L, 2 * L, (30000, 3)).astype(np.float32)
+    k = oracle.keys(pos, delta, L)
+    uniq, f = oracle.histogram(k)
+    dense = np.bincount(k.astype(np.int64), minlength=20 ** 3)
+    nz = np.nonzero(dense)[0]
+    assert np.array_equal(uniq.astype(np.int64), nz)
+    assert np.array_equal(f, dense[nz])
+    assert f.sum() == len(pos)
+
+
+# ------------------------------------------------------------ top-k (O9, O10)
+
+def python_topk(keys_, vals, k, theta=None):
+    items = [(-int(v), int(kk)) for kk, v in zip(keys_, vals) if theta is None or v >= theta]
+    items.sort()
+    return [kk for _, kk in items[:k]], [-v for v, _ in items[:k]]
+
+
+def test_topk_tie_order_and_theta_invariance():
+    # Many equal counts: the order is (estimate desc, key asc).
+    rng = np.random.default_rng(13)
+    cells = rng.uniform(0, 100, (300, 3))
+    counts = rng.integers(1, 6, 300)
+    pos = np.repeat(cells, counts, axis=0).astype(np.float32)
+    d, w, seed = 5, 1 << 18, 4
+    M, _ = oracle.sketch(pos, d, w, seed, 0.1, 100.0)
+    T = oracle.hash_tables(seed, d)
+    uniq, f = oracle.histogram(oracle.keys(pos, 0.1, 100.0))
+    est = oracle.estimate(M, T, uniq)
+    for k in [1, 7, 50, 299, 1000]:
+        ks, es, st = oracle.topk_sketch(M, T, pos, 0.1, 100.0, oracle.INT32_MIN, k)
+        wk, we = python_topk(uniq, est, k)
+        assert list(ks) == wk and list(es) == we and st == oracle.OK
+        kth = we[-1]
+        for theta in [kth, kth - 1, -5]:
+            ks2, es2, st2 = oracle.topk_sketch(M, T, pos, 0.1, 100.0, theta, k)
+            assert np.array_equal(ks, ks2) and np.array_equal(es, es2)
+            assert st2 == (oracle.W_INCOMPLETE if len(wk) < k else oracle.OK)
+    # a theta above the k-th estimate returns fewer items and says so
+    n_max = int((est == est.max()).sum())
+    ks3, es3, st3 = oracle.topk_sketch(M, T, pos, 0.1, 100.0, int(est.max()), n_max + 1)
+    assert st3 == oracle.W_INCOMPLETE and len(ks3) == n_max and np.all(es3 == est.max())
+    kx, fx = oracle.topk_exact(uniq, f, 40)
+    wk, wf = python_topk(uniq, f, 40)
+    assert list(kx) == wk and list(fx) == wf
+
+
+def test_empty_stream():
+    pos = np.zeros((0, 3), np.float32)
+    M, sk = oracle.sketch(pos, 5, 64, 1, 0.1, 100.0)
+    assert sk == 0 and not M.any()
+    ks, es, st = oracle.topk_sketch(M, oracle.hash_tables(1, 5), pos, 0.1, 100.0, oracle.INT32_MIN, 10)
+    assert len(ks) == 0 and st == oracle.OK
+    uniq, f = oracle.histogram(np.zeros(0, np.uint64))
+    assert len(uniq) == 0

@@ -1,0 +1,116 @@
+"""Seeded synthetic particle streams (Plummer halos + uniform background).
+
+Stand-ins for the paper's Millennium (Sec. 4.1) and Millennium XXL (Sec. 4.5)
+snapshots, which are not available.  The generator lives in ``plummer.c``; this
+module marshals arguments and names the workload configurations.  It holds none
+of the sketch method's arithmetic, so both the GPU library and the CPU oracle can
+consume what it produces.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsk_workloads.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = C.CDLL(LIB_PATH)
+    P, u64, u32, f64, i64 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_double, C.c_int64
+    lib.wl_philox4x32_10.restype = None
+    lib.wl_philox4x32_10.argtypes = [P, P, P]
+    lib.wl_halo_catalogue.restype = None
+    lib.wl_halo_catalogue.argtypes = [u64, u32, f64, f64, f64, f64, P, P]
+    lib.wl_gen_exact.restype = i64
+    lib.wl_gen_exact.argtypes = [u64, f64, u32, f64, f64, f64, f64, u64, P]
+    lib.wl_gen_mixture.restype = i64
+    lib.wl_gen_mixture.argtypes = [u64, u64, f64, u32, f64, f64, f64, f64, f64, u64, P]
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, dtype=np.uint32)
+    _load().wl_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One synthetic stream and the sketch parameters it is measured with."""
+    name: str
+    n: int                 # particles
+    L: float               # box side (Mpc/h)
+    delta: float           # cell side (Mpc/h)
+    d: int                 # sketch rows (t in the paper)
+    w: int                 # counters per row (b in the paper)
+    k: int                 # heavy cells wanted
+    seed: int
+    n_halo: int
+    m_lo: float
+    m_hi: float
+    slope: float = 1.9
+    a: float = 0.2         # Plummer scale radius (Mpc/h)
+    f_bg: float = -1.0     # < 0: exact-count recipe (halo j gets floor(M_j) particles, rest uniform)
+    chunk: int = 0         # particles per generated chunk (0: one piece)
+    extra: dict = field(default_factory=dict)
+
+    def generate(self, start: int = 0, count: int | None = None, out: np.ndarray | None = None) -> np.ndarray:
+        """float32 [count][3] positions of particles [start, start + count)."""
+        if count is None:
+            count = self.n - start
+        if out is None:
+            out = np.empty((count, 3), dtype=np.float32)
+        assert out.shape == (count, 3) and out.dtype == np.float32
+        lib = _load()
+        if self.f_bg < 0:
+            assert start == 0 and count == self.n, "exact-count recipe is generated whole"
+            lib.wl_gen_exact(self.n, self.L, self.n_halo, self.m_lo, self.m_hi, self.slope, self.a,
+                             self.seed, _p(out))
+        else:
+            lib.wl_gen_mixture(start, count, self.L, self.n_halo, self.m_lo, self.m_hi, self.slope,
+                               self.a, self.f_bg, self.seed, _p(out))
+        return out
+
+    def with_(self, **kw) -> "Workload":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Workload(**d)
+
+
+# 2^20 particles, L = 100 Mpc/h, 256 Plummer halos (a = 0.2), masses ~ M^-1.9 on
+# [100, 1e4], remainder uniform; cell 0.1 Mpc/h (1000^3 cells), d = 5, w = 2^16, k = 100.
+SMALL = Workload(name="plummer-2^20-L100-d0.1-w2^16", n=1 << 20, L=100.0, delta=0.1, d=5,
+                 w=1 << 16, k=100, seed=1, n_halo=256, m_lo=100.0, m_hi=1.0e4)
+
+# 2^30 particles in 2^26-particle chunks, L = 1000 Mpc/h, 2^20 halos with masses
+# ~ M^-1.9 on [50, 1e6], 30 % uniform background; cell 0.25 Mpc/h (4000^3 cells),
+# d = 5, w = 2^24, k = 1e4.
+SCALE = Workload(name="plummer-2^30-L1000-d0.25-w2^24", n=1 << 30, L=1000.0, delta=0.25, d=5,
+                 w=1 << 24, k=10_000, seed=1, n_halo=1 << 20, m_lo=50.0, m_hi=1.0e6, f_bg=0.3,
+                 chunk=1 << 26)
+
+
+def halo_catalogue(wl: Workload):
+    mass = np.empty(wl.n_halo, dtype=np.float64)
+    cen = np.empty((wl.n_halo, 3), dtype=np.float64)
+    _load().wl_halo_catalogue(wl.seed, wl.n_halo, wl.L, wl.m_lo, wl.m_hi, wl.slope, _p(mass), _p(cen))
+    return mass, cen
