@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the streaming Count-Sketch halo-finder hot path on one MI355X.
+
+One step = one pass of the whole hot path over the resident synthetic stream:
+zero the sketch, Add every particle (update), collect the distinct cells whose
+estimate passes theta (second pass), select the top-k.  `value` is particles/s of
+whole steps.  The roofline object covers csk_sketch_update (bin + accumulate
+kernels), timed with HIP events on the stream the library launches on.
+
+Workload (default): 2^30 float32 particles, L = 1000 Mpc/h, 2^20 Plummer halos
+(power-law masses, slope -1.9, 50..1e6 particles), 30 % uniform background;
+cells of 0.25 Mpc/h (4000^3), d = 5 rows, w = 2^24 counters, k = 1e4.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["scale", "small"], default="scale")
+    ap.add_argument("--n", type=int, default=0, help="override the particle count (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24)
+    return ap.parse_args()
+
+
+def make_positions(wl, n, torch):
+    """Generate the stream on the host in chunks and copy it into one device tensor."""
+    import numpy as np
+    chunk = wl.chunk or n
+    dev = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    host = torch.empty((min(chunk, n), 3), dtype=torch.float32).pin_memory()
+    hv = host.numpy()
+    t0 = time.time()
+    if wl.f_bg < 0:
+        dev.copy_(torch.from_numpy(wl.generate()))
+    else:
+        for a in range(0, n, chunk):
+            m = min(chunk, n - a)
+            wl.generate(a, m, out=hv[:m])
+            dev[a:a + m].copy_(host[:m], non_blocking=False)
+            log(f"  generated {a + m}/{n} particles ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return dev
+
+
+def calibrate_theta(s, pos, wl, csk):
+    """Geometric search for a threshold that leaves at least k candidates (the paper
+    moves its threshold geometrically, Sec. 3.1 item 4).  With >= k candidates the
+    top-k does not depend on theta."""
+    theta = 1 << 22
+    while True:
+        s.clear_candidates()
+        s.collect(pos, wl.delta, wl.L, theta)
+        keys, est, rc = s.topk(wl.k)
+        if rc == csk.CSK_OK:
+            return theta, int(est[-1].item())
+        if theta <= 1:
+            return csk.INT32_MIN, None
+        theta //= 2
+
+
+def cpu_baseline(pos_dev, wl, sample, torch):
+    """The oracle as it stands, single thread, on the first `sample` particles."""
+    import numpy as np
+    import oracle
+    pos = pos_dev[:sample].cpu().numpy()
+    t0 = time.perf_counter()
+    M, _ = oracle.sketch(pos, wl.d, wl.w, wl.seed, wl.delta, wl.L)
+    t1 = time.perf_counter()
+    oracle.topk_sketch(M, oracle.hash_tables(wl.seed, wl.d), pos, wl.delta, wl.L, oracle.INT32_MIN, wl.k)
+    t2 = time.perf_counter()
+    return {"value": sample / (t2 - t0), "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample} particles of the same stream; keys + Add ({t1 - t0:.1f} s), "
+                      f"estimates of every distinct cell + top-{wl.k} ({t2 - t1:.1f} s), one thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        log("bench.py measures one GPU only: multi-GPU runs are not part of this build")
+        sys.exit(2)
+    import torch
+    import workloads
+    import paper_1711_00975_amd as csk
+
+    wl = workloads.SCALE if args.workload == "scale" else workloads.SMALL
+    n = args.n or wl.n
+    torch.cuda.set_device(0)
+    log(f"workload {wl.name}: n={n} d={wl.d} w={wl.w} k={wl.k}")
+    pos = make_positions(wl, n, torch)
+    s = csk.Sketch(wl.d, wl.w, wl.seed, max_candidates=1 << 22)
+    stream = torch.cuda.current_stream()
+
+    def step(theta, ev=None):
+        s.reset()
+        if ev is not None:
+            ev[0].record(stream)
+        s.update(pos, wl.delta, wl.L)
+        if ev is not None:
+            ev[1].record(stream)
+        s.collect(pos, wl.delta, wl.L, theta)
+        if ev is not None:
+            ev[2].record(stream)
+        keys, est, rc = s.topk(wl.k)
+        return rc
+
+    # warm-up: first update allocates scratch; then find theta
+    s.update(pos, wl.delta, wl.L)
+    theta, kth = calibrate_theta(s, pos, wl, csk)
+    log(f"theta = {theta} (k-th estimate {kth})")
+    for _ in range(args.warmup):
+        step(theta)
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    rcs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        rcs.append(step(theta, evs[i]))
+        log(f"  step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert all(rc == csk.CSK_OK for rc in rcs), "a timed step returned an incomplete top-k"
+    ms = (t1 - t0) * 1e3 / args.steps
+    upd_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    col_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    value = n / (ms / 1e3)
+    achieved = BYTES_PER_PARTICLE * n / (upd_ms / 1e3) / 1e9
+    out = {
+        "metric": "particles/s sketched (update + collect + top-k per step)",
+        "value": value,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded Plummer halos + uniform background, generated on the host)",
+        "config": {"workload": wl.name, "particles": n, "L": wl.L, "delta": wl.delta, "d": wl.d, "w": wl.w,
+                   "k": wl.k, "seed": wl.seed, "theta": theta, "parallelism": "single GPU"},
+        "update_ms": upd_ms,
+        "update_particles_per_s": n / (upd_ms / 1e3),
+        "collect_ms": col_ms,
+        "roofline": {"kernel": "csk_sketch_update (bin_kernel + accumulate_kernel)", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one thread) ...")
+        out["cpu_baseline"] = cpu_baseline(pos, wl, min(args.cpu_sample, n), torch)
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,149 @@
+/*
+ * csk.h — C ABI of the MI355X (gfx950) streaming Count-Sketch halo finder.
+ *
+ * The hot path of Ivkin et al., "Scalable Streaming Tools for Analyzing N-body
+ * Simulations" (arXiv:1711.00975): every particle position becomes the key of the
+ * mesh cell it lies in (Sec. 2.1), the keys are streamed into a Count Sketch of
+ * d rows ("t" in the paper) by w counters ("b") with a bucket hash and a +-1 sign
+ * hash per row (Sec. 2.2, Add), each distinct cell of the stream is queried for
+ * the median of its d signed counters (Sec. 2.2, Estimate) and the k cells with
+ * the largest estimates are returned (Sec. 2.2 UpdateHeap / Alg. 1; Sec. 3.1 item 4,
+ * the threshold-filtered array of heavy cells).
+ *
+ * Conventions shared by every call
+ *   - Data pointers marked (device) are caller-owned device memory that must stay
+ *     valid until the stream reaches the call.  (host) pointers are read or written
+ *     before the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).  Calls are
+ *     asynchronous and stream-ordered unless marked "synchronizes".  A handle is
+ *     not thread-safe; use one stream per handle.
+ *   - Positions are float32, array-of-structures [n][3] = (x, y, z), in a periodic
+ *     box of side L (Mpc/h); cells have side delta, G = round(L / delta) per side.
+ *     The mesh is valid when delta, L > 0, 1 <= G <= 65535 and |L/delta - G| <=
+ *     1e-6 G.  The first update or collect latches (delta, L); a different mesh on
+ *     the same handle returns CSK_E_STATE until csk_reset.
+ *   - Cell index along one axis: i = floor(p * G / L) on the exact values of p and L,
+ *     wrapped into [0, G); key = (ix * G + iy) * G + iz (< 2^48).  A coordinate that
+ *     is not finite or has |p| >= 2L puts the particle outside the domain: it is
+ *     skipped and CSK_E_DOMAIN is latched (see "errors").
+ *   - Row hash: simple tabulation over the six key bytes with tables drawn from
+ *     SplitMix64(seed); bucket = ((h & 0x7FFFFFFF) * w) >> 31, sign = -1 if bit 31
+ *     of h is set.  Counters are int32 and wrap modulo 2^32.
+ *   - Errors: argument errors are returned at once and leave the handle unchanged.
+ *     Conditions found by kernels (CSK_E_DOMAIN, CSK_E_CAPACITY) are latched on the
+ *     device and returned by the next call that synchronizes (csk_topk,
+ *     csk_get_counters, csk_check); CSK_E_CAPACITY takes precedence.  The latch is
+ *     cleared when it is returned.  csk_last_error() gives the text of the last
+ *     error raised on the calling thread.
+ */
+#ifndef CSK_H
+#define CSK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct csk_sketch csk_sketch; /* opaque; owned by the library */
+typedef int32_t csk_status;
+
+#define CSK_OK            0
+#define CSK_W_INCOMPLETE  1   /* fewer than k candidates passed theta            */
+#define CSK_E_INVALID    (-1) /* bad argument                                      */
+#define CSK_E_NOMEM      (-2) /* device allocation failed                          */
+#define CSK_E_HIP        (-3) /* HIP runtime error                                 */
+#define CSK_E_CAPACITY   (-4) /* candidate set overflowed: raise theta or capacity */
+#define CSK_E_DOMAIN     (-5) /* some particle had a non-finite or |p| >= 2L coordinate */
+#define CSK_E_STATE      (-6) /* mesh differs from the one latched on the handle   */
+
+#define CSK_VARIANT_COUNT_SKETCH 0 /* Sec. 2.2: signed Add, median Estimate          */
+#define CSK_VARIANT_COUNT_MIN    1 /* Sec. 2.2 Count-Min: Add +1, Estimate = minimum */
+
+#define CSK_MAX_ROWS 32u
+#define CSK_MAX_WIDTH (1u << 30)
+#define CSK_DEFAULT_CANDIDATES (1u << 21)
+
+/* Create a Count Sketch of d rows by w counters with hash tables drawn from `seed`
+ * (Sec. 2.2: b x t counters, t bucket hashes and t sign hashes; Alg. 1
+ * Initialization zeroes M).  1 <= d <= 32, 1 <= w <= 2^30.  Counters start at zero.
+ * Allocates device memory on the current device; synchronizes. */
+csk_status csk_sketch_init(csk_sketch **out, uint32_t d, uint32_t w, uint64_t seed);
+
+/* As csk_sketch_init, with the variant (CSK_VARIANT_*) and the maximum number of
+ * distinct candidate cells csk_collect may hold (0: CSK_DEFAULT_CANDIDATES). */
+csk_status csk_sketch_init_ex(csk_sketch **out, uint32_t d, uint32_t w, uint64_t seed,
+                              int32_t variant, uint64_t max_candidates);
+
+/* Free the handle and all device memory it owns.  Synchronizes the device. */
+csk_status csk_sketch_destroy(csk_sketch *s);
+
+/* Add n particles to the sketch: for every in-domain particle and every row r,
+ * M[r][bucket_r(key)] += sign_r(key) (Count-Min: += 1).  Sec. 2.2 Add; Alg. 1
+ * "Processing the stream"; Alg. 4 Update; Sec. 3.1 stages 1-3.
+ * pos (device): n x 3 float32.  n may be 0.  The result does not depend on the
+ * order of particles or on how the stream is cut into calls. */
+csk_status csk_sketch_update(csk_sketch *s, const float *pos, uint64_t n, double delta, double L,
+                             void *stream);
+
+/* Estimates of m cell keys: est[j] = the element at index floor((d-1)/2) of the
+ * ascending sort of { M[r][bucket_r(key_j)] * sign_r(key_j) } (Count-Min: the
+ * minimum of M[r][bucket_r(key_j)]).  Sec. 2.2 Estimate; Alg. 4 Estimate.
+ * keys (device): m uint64 (any value; only the low 48 bits are hashed).
+ * est (device): m int32. */
+csk_status csk_sketch_query(csk_sketch *s, const uint64_t *keys, uint64_t m, int32_t *est,
+                            void *stream);
+
+/* Cell keys of n particles (Sec. 2.1, Sec. 3.1 stage 1), for callers that want to
+ * query cells of their own: keys[j] = key of particle j, or UINT64_MAX if it is
+ * outside the domain (nothing is latched).  pos, keys (device). */
+csk_status csk_cell_keys(const float *pos, uint64_t n, double delta, double L, uint64_t *keys,
+                         void *stream);
+
+/* Candidate pass over the particles: every in-domain particle whose cell estimate
+ * is >= theta adds its cell key to the handle's set of distinct candidates (Sec. 3.1
+ * item 4: keep the items above a threshold).  Repeated calls accumulate; the set
+ * is emptied by csk_candidates_clear, csk_reset and csk_set_counters.  More than
+ * max_candidates distinct keys latches CSK_E_CAPACITY.  pos (device). */
+csk_status csk_collect(csk_sketch *s, const float *pos, uint64_t n, double delta, double L,
+                       int32_t theta, void *stream);
+
+/* Empty the candidate set. */
+csk_status csk_candidates_clear(csk_sketch *s, void *stream);
+
+/* Top-k of the candidate set: the min(k, |C|) candidates with the largest
+ * estimates from the current counters, ordered by (estimate desc, key asc)
+ * (Sec. 2.2 UpdateHeap; Alg. 1 query).  keys (device): k uint64; est (device):
+ * k int32; *k_out (host) = the number written.  Returns CSK_W_INCOMPLETE when
+ * *k_out < k and some csk_collect since the last clear used theta > INT32_MIN;
+ * with theta = INT32_MIN the set is every distinct in-domain cell of the stream.
+ * Synchronizes; returns a latched error if any (then *k_out is 0). */
+csk_status csk_topk(csk_sketch *s, uint32_t k, uint64_t *keys, int32_t *est, uint32_t *k_out,
+                    void *stream);
+
+/* Copy the counters out: out (device) d*w int32, row-major [d][w].  Synchronizes
+ * and returns a latched error if any (the copy is made either way). */
+csk_status csk_get_counters(const csk_sketch *s, int32_t *out, void *stream);
+
+/* Replace the counters (resume from a checkpoint, or load a sum of sketches built
+ * with the same d, w and seed: sketches are linear in the stream, Sec. 5).
+ * in (device) d*w int32.  Empties the candidate set. */
+csk_status csk_set_counters(csk_sketch *s, const int32_t *in, void *stream);
+
+/* Zero the counters, empty the candidate set, clear the latch and the mesh. */
+csk_status csk_reset(csk_sketch *s, void *stream);
+
+/* Synchronize the stream and return (and clear) the latched device error, if any. */
+csk_status csk_check(csk_sketch *s, void *stream);
+
+/* Bytes of device memory the handle holds right now. */
+uint64_t csk_device_bytes(const csk_sketch *s);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *csk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSK_H */

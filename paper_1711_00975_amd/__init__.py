@@ -1,0 +1,280 @@
+"""Streaming Count-Sketch halo finder for AMD MI355X (gfx950).
+
+Python binding of ``libcsk.so``, the HIP library behind ``include/csk.h``.  The
+functions below carry the C ABI's names and only marshal arguments: device
+pointers come from PyTorch tensors (PyTorch supplies device memory and streams),
+and every step of the hot path runs in the library's HIP kernels.  If the
+library is missing this module raises; there is no CPU fallback.
+
+Hot path (arXiv:1711.00975): particle -> mesh-cell key (Sec. 2.1) -> Count Sketch
+Add (Sec. 2.2) -> median Estimate of each distinct cell (Sec. 2.2) -> top-k
+(Sec. 2.2 UpdateHeap, Alg. 1; Sec. 3.1 item 4).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsk.so")
+
+CSK_OK = 0
+CSK_W_INCOMPLETE = 1
+CSK_E_INVALID = -1
+CSK_E_NOMEM = -2
+CSK_E_HIP = -3
+CSK_E_CAPACITY = -4
+CSK_E_DOMAIN = -5
+CSK_E_STATE = -6
+CSK_VARIANT_COUNT_SKETCH = 0
+CSK_VARIANT_COUNT_MIN = 1
+CSK_MAX_ROWS = 32
+CSK_MAX_WIDTH = 1 << 30
+CSK_DEFAULT_CANDIDATES = 1 << 21
+INT32_MIN = -(2 ** 31)
+
+EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_destroy", "csk_sketch_update",
+           "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_candidates_clear", "csk_topk",
+           "csk_get_counters", "csk_set_counters", "csk_reset", "csk_check", "csk_device_bytes",
+           "csk_last_error"]
+
+
+class CskError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"csk error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcsk.so and declare its signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() "
+                           "(or python -m paper_1711_00975_amd.build)")
+    lib = C.CDLL(path)
+    P, u64, u32, i32, f64 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int32, C.c_double
+    PP = C.POINTER(C.c_void_p)
+    sig = {
+        "csk_sketch_init": [PP, u32, u32, u64],
+        "csk_sketch_init_ex": [PP, u32, u32, u64, i32, u64],
+        "csk_sketch_destroy": [P],
+        "csk_sketch_update": [P, P, u64, f64, f64, P],
+        "csk_sketch_query": [P, P, u64, P, P],
+        "csk_cell_keys": [P, u64, f64, f64, P, P],
+        "csk_collect": [P, P, u64, f64, f64, i32, P],
+        "csk_candidates_clear": [P, P],
+        "csk_topk": [P, u32, P, P, C.POINTER(C.c_uint32), P],
+        "csk_get_counters": [P, P, P],
+        "csk_set_counters": [P, P, P],
+        "csk_reset": [P, P],
+        "csk_check": [P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = i32
+        fn.argtypes = args
+    lib.csk_device_bytes.restype = u64
+    lib.csk_device_bytes.argtypes = [P]
+    lib.csk_last_error.restype = C.c_char_p
+    lib.csk_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, allow_warning: bool = False) -> int:
+    if rc == CSK_OK or (allow_warning and rc > 0):
+        return rc
+    raise CskError(rc, load_library().csk_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, shape_last=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if shape_last is not None and (t.dim() != 2 or t.shape[1] != shape_last):
+        raise ValueError(f"expected shape [n, {shape_last}]")
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------- C ABI, by name
+
+def csk_sketch_init(d: int, w: int, seed: int):
+    h = C.c_void_p()
+    _check(load_library().csk_sketch_init(C.byref(h), d, w, seed))
+    return h
+
+
+def csk_sketch_init_ex(d: int, w: int, seed: int, variant: int = CSK_VARIANT_COUNT_SKETCH,
+                       max_candidates: int = 0):
+    h = C.c_void_p()
+    _check(load_library().csk_sketch_init_ex(C.byref(h), d, w, seed, variant, max_candidates))
+    return h
+
+
+def csk_sketch_destroy(h) -> None:
+    _check(load_library().csk_sketch_destroy(h))
+
+
+def csk_sketch_update(h, pos, delta: float, L: float, stream=None) -> None:
+    import torch
+    _check(load_library().csk_sketch_update(h, _dev(pos, torch.float32, 3), pos.shape[0], delta, L,
+                                            _stream(stream)))
+
+
+def csk_sketch_query(h, keys, est, stream=None) -> None:
+    import torch
+    if keys.numel() != est.numel():
+        raise ValueError("keys and est differ in length")
+    _check(load_library().csk_sketch_query(h, _dev(keys, torch.int64), keys.numel(), _dev(est, torch.int32),
+                                           _stream(stream)))
+
+
+def csk_cell_keys(pos, delta: float, L: float, keys, stream=None) -> None:
+    import torch
+    if keys.numel() != pos.shape[0]:
+        raise ValueError("keys must hold one entry per particle")
+    _check(load_library().csk_cell_keys(_dev(pos, torch.float32, 3), pos.shape[0], delta, L,
+                                        _dev(keys, torch.int64), _stream(stream)))
+
+
+def csk_collect(h, pos, delta: float, L: float, theta: int, stream=None) -> None:
+    import torch
+    _check(load_library().csk_collect(h, _dev(pos, torch.float32, 3), pos.shape[0], delta, L, theta,
+                                      _stream(stream)))
+
+
+def csk_candidates_clear(h, stream=None) -> None:
+    _check(load_library().csk_candidates_clear(h, _stream(stream)))
+
+
+def csk_topk(h, k: int, keys, est, stream=None) -> tuple[int, int]:
+    """Returns (k_out, status); status is CSK_OK or CSK_W_INCOMPLETE."""
+    import torch
+    if keys.numel() < k or est.numel() < k:
+        raise ValueError("output tensors hold fewer than k entries")
+    kout = C.c_uint32(0)
+    rc = _check(load_library().csk_topk(h, k, _dev(keys, torch.int64), _dev(est, torch.int32), C.byref(kout),
+                                        _stream(stream)), allow_warning=True)
+    return kout.value, rc
+
+
+def csk_get_counters(h, out, stream=None) -> None:
+    import torch
+    _check(load_library().csk_get_counters(h, _dev(out, torch.int32), _stream(stream)))
+
+
+def csk_set_counters(h, src, stream=None) -> None:
+    import torch
+    _check(load_library().csk_set_counters(h, _dev(src, torch.int32), _stream(stream)))
+
+
+def csk_reset(h, stream=None) -> None:
+    _check(load_library().csk_reset(h, _stream(stream)))
+
+
+def csk_check(h, stream=None) -> None:
+    _check(load_library().csk_check(h, _stream(stream)))
+
+
+def csk_device_bytes(h) -> int:
+    return int(load_library().csk_device_bytes(h))
+
+
+def csk_last_error() -> str:
+    return load_library().csk_last_error().decode()
+
+
+# ------------------------------------------------------------- convenience
+
+class Sketch:
+    """Owns one handle.  d rows ("t" in the paper) by w counters ("b")."""
+
+    def __init__(self, d: int, w: int, seed: int, variant: int = CSK_VARIANT_COUNT_SKETCH,
+                 max_candidates: int = 0):
+        self.d, self.w, self.seed, self.variant = d, w, seed, variant
+        self.h = csk_sketch_init_ex(d, w, seed, variant, max_candidates)
+
+    def close(self):
+        if self.h is not None:
+            csk_sketch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, pos, delta, L, stream=None):
+        csk_sketch_update(self.h, pos, delta, L, stream)
+
+    def query(self, keys, stream=None):
+        import torch
+        est = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+        csk_sketch_query(self.h, keys, est, stream)
+        return est
+
+    def collect(self, pos, delta, L, theta=INT32_MIN, stream=None):
+        csk_collect(self.h, pos, delta, L, theta, stream)
+
+    def clear_candidates(self, stream=None):
+        csk_candidates_clear(self.h, stream)
+
+    def topk(self, k, stream=None):
+        """(keys int64 [k_out], est int32 [k_out], status) on the device."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        keys = torch.empty(max(k, 1), dtype=torch.int64, device=dev)
+        est = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
+        kout, rc = csk_topk(self.h, k, keys, est, stream)
+        return keys[:kout], est[:kout], rc
+
+    def counters(self, stream=None):
+        import torch
+        out = torch.empty((self.d, self.w), dtype=torch.int32,
+                          device=torch.device("cuda", torch.cuda.current_device()))
+        csk_get_counters(self.h, out, stream)
+        return out
+
+    def set_counters(self, src, stream=None):
+        csk_set_counters(self.h, src, stream)
+
+    def reset(self, stream=None):
+        csk_reset(self.h, stream)
+
+    def check(self, stream=None):
+        csk_check(self.h, stream)
+
+    def device_bytes(self):
+        return csk_device_bytes(self.h)
+
+
+def cell_keys(pos, delta, L, stream=None):
+    import torch
+    keys = torch.empty(pos.shape[0], dtype=torch.int64, device=pos.device)
+    csk_cell_keys(pos, delta, L, keys, stream)
+    return keys

@@ -1,0 +1,403 @@
+// csk_api.hip — the C ABI declared in include/csk.h: argument checks, device memory of a
+// handle, hash-table seeding, and the kernel sequences of each call.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "csk.h"
+#include "csk_internal.h"
+
+using namespace csk;
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+csk_status fail(csk_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+csk_status hip_fail(hipError_t e, const char* where) {
+  if (e == hipErrorOutOfMemory) return fail(CSK_E_NOMEM, "%s: out of device memory", where);
+  return fail(CSK_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define CSK_HIP(expr, where)                       \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+// SplitMix64 (Steele, Lea & Flood 2014): Weyl increment, then the variant-13 mixer.
+uint64_t splitmix64(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Tabulation tables T[r][c][v], filled row by row, character by character, value by
+// value from one SplitMix64 stream: two 32-bit entries per draw, low half first.
+std::vector<uint32_t> make_tables(uint64_t seed, uint32_t d) {
+  std::vector<uint32_t> T((size_t)d * kTableWords);
+  uint64_t st = seed;
+  for (size_t i = 0; i < T.size(); i += 2) {
+    const uint64_t z = splitmix64(st);
+    T[i] = (uint32_t)z;
+    if (i + 1 < T.size()) T[i + 1] = (uint32_t)(z >> 32);
+  }
+  return T;
+}
+
+}  // namespace
+
+struct csk_sketch {
+  int device = 0;
+  uint32_t d = 0, w = 0;
+  uint64_t seed = 0;
+  int32_t variant = CSK_VARIANT_COUNT_SKETCH;
+  int32_t* M = nullptr;
+  uint32_t* tab = nullptr;
+  uint64_t* set = nullptr;
+  uint32_t slots = 0;
+  uint32_t max_cand = 0;
+  uint32_t* ctl = nullptr;   // [0] error latch, [1] set count
+  SelState* sel = nullptr;
+  uint64_t* cand_key = nullptr;
+  int32_t* cand_est = nullptr;
+  uint64_t* sel_key = nullptr;
+  int32_t* sel_est = nullptr;
+  uint32_t sel_cap = 0;
+  uint16_t* tok = nullptr;
+  uint64_t tok_bytes = 0;
+  uint32_t* cnt = nullptr;
+  uint64_t cnt_bytes = 0;
+  SelState* host_sel = nullptr;   // pinned
+  uint32_t* host_ctl = nullptr;   // pinned
+  bool mesh_set = false;
+  double delta = 0, L = 0;
+  Mesh mesh{};
+  bool partial_set = false;   // some collect since the last clear used theta > INT32_MIN
+  uint64_t bytes = 0;
+
+  uint32_t* err() const { return ctl; }
+  uint32_t* set_count() const { return ctl + 1; }
+  Tables tables() const {
+    Tables t;
+    t.tab = tab;
+    t.d = d;
+    t.w = w;
+    t.cm = (variant == CSK_VARIANT_COUNT_MIN) ? 1u : 0u;
+    return t;
+  }
+};
+
+namespace {
+
+template <typename T>
+hipError_t dmalloc(csk_sketch* s, T** p, uint64_t count) {
+  const uint64_t b = count * sizeof(T);
+  hipError_t e = hipMalloc((void**)p, b ? b : 1);
+  if (e == hipSuccess) s->bytes += b;
+  return e;
+}
+
+void free_all(csk_sketch* s) {
+  void* ptrs[] = {s->M, s->tab, s->set, s->ctl, s->sel, s->cand_key, s->cand_est, s->sel_key, s->sel_est,
+                  s->tok, s->cnt};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (s->host_sel) (void)hipHostFree(s->host_sel);
+  if (s->host_ctl) (void)hipHostFree(s->host_ctl);
+}
+
+csk_status check_mesh(csk_sketch* s, double delta, double L, Mesh* out) {
+  if (!(delta > 0.0) || !(L > 0.0) || !std::isfinite(delta) || !std::isfinite(L))
+    return fail(CSK_E_INVALID, "mesh: delta and L must be finite and positive (delta=%g, L=%g)", delta, L);
+  const double q = L / delta;
+  if (!(q >= 0.5) || !(q < 65535.5))
+    return fail(CSK_E_INVALID, "mesh: L/delta = %g outside [1, 65535]", q);
+  const long long G = std::llround(q);
+  if (G < 1 || G > 65535 || std::fabs(q - (double)G) > 1e-6 * (double)G)
+    return fail(CSK_E_INVALID, "mesh: L/delta = %.17g is not within 1e-6 of an integer in [1, 65535]", q);
+  if (s != nullptr && s->mesh_set && (s->delta != delta || s->L != L))
+    return fail(CSK_E_STATE, "mesh (delta=%g, L=%g) differs from the one latched on this handle (%g, %g)", delta,
+                L, s->delta, s->L);
+  out->L = L;
+  out->invL = 1.0 / L;
+  out->twoL = 2.0 * L;
+  out->Gd = (double)G;
+  out->G = (int32_t)G;
+  return CSK_OK;
+}
+
+void latch_mesh(csk_sketch* s, double delta, double L, const Mesh& m) {
+  s->mesh_set = true;
+  s->delta = delta;
+  s->L = L;
+  s->mesh = m;
+}
+
+csk_status clear_candidates(csk_sketch* s, hipStream_t st) {
+  CSK_HIP(launch_fill_u64(s->set, s->slots, kEmptyKey, st), "clear candidates");
+  CSK_HIP(launch_fill_u32(s->set_count(), 1, 0u, st), "clear candidates");
+  s->partial_set = false;
+  return CSK_OK;
+}
+
+// Read the latch (synchronizing) and clear it.
+csk_status take_latch(csk_sketch* s, hipStream_t st, uint32_t* bits) {
+  CSK_HIP(hipMemcpyAsync(s->host_ctl, s->ctl, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st), "read latch");
+  CSK_HIP(hipStreamSynchronize(st), "synchronize");
+  *bits = s->host_ctl[0];
+  if (*bits) CSK_HIP(launch_fill_u32(s->err(), 1, 0u, st), "clear latch");
+  return CSK_OK;
+}
+
+csk_status latch_status(uint32_t bits) {
+  if (bits & kErrCapacity)
+    return fail(CSK_E_CAPACITY, "candidate set overflowed its capacity: raise theta or max_candidates");
+  if (bits & kErrDomain)
+    return fail(CSK_E_DOMAIN, "some particle had a non-finite coordinate or |p| >= 2L and was skipped");
+  return CSK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+csk_status csk_sketch_init_ex(csk_sketch** out, uint32_t d, uint32_t w, uint64_t seed, int32_t variant,
+                              uint64_t max_candidates) {
+  if (out == nullptr) return fail(CSK_E_INVALID, "init: out is NULL");
+  *out = nullptr;
+  if (d < 1 || d > CSK_MAX_ROWS) return fail(CSK_E_INVALID, "init: d=%u outside [1, %u]", d, CSK_MAX_ROWS);
+  if (w < 1 || w > CSK_MAX_WIDTH) return fail(CSK_E_INVALID, "init: w=%u outside [1, 2^30]", w);
+  if (variant != CSK_VARIANT_COUNT_SKETCH && variant != CSK_VARIANT_COUNT_MIN)
+    return fail(CSK_E_INVALID, "init: unknown variant %d", variant);
+  if (max_candidates == 0) max_candidates = CSK_DEFAULT_CANDIDATES;
+  if (max_candidates > (1ull << 30)) return fail(CSK_E_INVALID, "init: max_candidates above 2^30");
+  csk_sketch* s = new (std::nothrow) csk_sketch();
+  if (!s) return fail(CSK_E_NOMEM, "init: host allocation failed");
+  s->d = d;
+  s->w = w;
+  s->seed = seed;
+  s->variant = variant;
+  s->max_cand = (uint32_t)max_candidates;
+  uint64_t slots = 1024;
+  while (slots < 2 * max_candidates) slots <<= 1;
+  s->slots = (uint32_t)slots;
+  hipError_t e = hipGetDevice(&s->device);
+  const auto T = make_tables(seed, d);
+  if (e == hipSuccess) e = dmalloc(s, &s->M, (uint64_t)d * w);
+  if (e == hipSuccess) e = dmalloc(s, &s->tab, T.size());
+  if (e == hipSuccess) e = dmalloc(s, &s->set, slots);
+  if (e == hipSuccess) e = dmalloc(s, &s->ctl, 4);
+  if (e == hipSuccess) e = dmalloc(s, &s->sel, 1);
+  if (e == hipSuccess) e = dmalloc(s, &s->cand_key, max_candidates);
+  if (e == hipSuccess) e = dmalloc(s, &s->cand_est, max_candidates);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->host_sel, sizeof(SelState), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->host_ctl, 4 * sizeof(uint32_t), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemcpy(s->tab, T.data(), T.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)s->M, (uint64_t)d * w, 0u, nullptr);
+  if (e == hipSuccess) e = launch_fill_u32(s->ctl, 4, 0u, nullptr);
+  if (e == hipSuccess) e = launch_fill_u64(s->set, slots, kEmptyKey, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_all(s);
+    delete s;
+    return hip_fail(e, "init");
+  }
+  *out = s;
+  return CSK_OK;
+}
+
+csk_status csk_sketch_init(csk_sketch** out, uint32_t d, uint32_t w, uint64_t seed) {
+  return csk_sketch_init_ex(out, d, w, seed, CSK_VARIANT_COUNT_SKETCH, 0);
+}
+
+csk_status csk_sketch_destroy(csk_sketch* s) {
+  if (s == nullptr) return CSK_OK;
+  (void)hipDeviceSynchronize();
+  free_all(s);
+  delete s;
+  return CSK_OK;
+}
+
+csk_status csk_sketch_update(csk_sketch* s, const float* pos, uint64_t n, double delta, double L, void* stream) {
+  if (s == nullptr) return fail(CSK_E_INVALID, "update: NULL handle");
+  Mesh mesh;
+  csk_status rc = check_mesh(s, delta, L, &mesh);
+  if (rc != CSK_OK) return rc;
+  if (n > 0 && pos == nullptr) return fail(CSK_E_INVALID, "update: NULL positions");
+  if (n > (1ull << 40)) return fail(CSK_E_INVALID, "update: n above 2^40");
+  latch_mesh(s, delta, L, mesh);
+  if (n == 0) return CSK_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const Tables t = s->tables();
+  const uint64_t piece_max = 1ull << 30;
+  for (uint64_t off = 0; off < n; off += piece_max) {
+    const uint64_t m = (n - off < piece_max) ? n - off : piece_max;
+    const float* p = pos + 3 * off;
+    BinPlan plan;
+    if (!plan_bin(m, s->d, s->w, plan)) {
+      CSK_HIP(launch_update_direct(p, m, mesh, t, s->M, s->err(), st), "update (direct)");
+      continue;
+    }
+    const uint64_t tok_need = (uint64_t)plan.P * plan.nwg * plan.cap * sizeof(uint16_t);
+    const uint64_t cnt_need = (uint64_t)plan.P * plan.nwg * sizeof(uint32_t);
+    if (tok_need > s->tok_bytes || cnt_need > s->cnt_bytes) {
+      CSK_HIP(hipStreamSynchronize(st), "update: grow scratch");
+      if (tok_need > s->tok_bytes) {
+        if (s->tok) (void)hipFree(s->tok);
+        s->bytes -= s->tok_bytes;
+        s->tok = nullptr;
+        s->tok_bytes = 0;
+        CSK_HIP(dmalloc(s, &s->tok, tok_need / sizeof(uint16_t)), "update: token scratch");
+        s->tok_bytes = tok_need;
+      }
+      if (cnt_need > s->cnt_bytes) {
+        if (s->cnt) (void)hipFree(s->cnt);
+        s->bytes -= s->cnt_bytes;
+        s->cnt = nullptr;
+        s->cnt_bytes = 0;
+        CSK_HIP(dmalloc(s, &s->cnt, cnt_need / sizeof(uint32_t)), "update: count scratch");
+        s->cnt_bytes = cnt_need;
+      }
+    }
+    CSK_HIP(launch_bin(p, m, mesh, t, plan, s->tok, s->cnt, s->M, s->err(), st), "update (bin)");
+    CSK_HIP(launch_accumulate(s->tok, s->cnt, plan, s->w, s->M, st), "update (accumulate)");
+  }
+  return CSK_OK;
+}
+
+csk_status csk_sketch_query(csk_sketch* s, const uint64_t* keys, uint64_t m, int32_t* est, void* stream) {
+  if (s == nullptr) return fail(CSK_E_INVALID, "query: NULL handle");
+  if (m > 0 && (keys == nullptr || est == nullptr)) return fail(CSK_E_INVALID, "query: NULL keys or est");
+  if (m == 0) return CSK_OK;
+  CSK_HIP(launch_query(keys, m, s->tables(), s->M, est, (hipStream_t)stream), "query");
+  return CSK_OK;
+}
+
+csk_status csk_cell_keys(const float* pos, uint64_t n, double delta, double L, uint64_t* keys, void* stream) {
+  Mesh mesh;
+  csk_status rc = check_mesh(nullptr, delta, L, &mesh);
+  if (rc != CSK_OK) return rc;
+  if (n > 0 && (pos == nullptr || keys == nullptr)) return fail(CSK_E_INVALID, "cell_keys: NULL pointer");
+  if (n == 0) return CSK_OK;
+  CSK_HIP(launch_keys(pos, n, mesh, keys, (hipStream_t)stream), "cell_keys");
+  return CSK_OK;
+}
+
+csk_status csk_collect(csk_sketch* s, const float* pos, uint64_t n, double delta, double L, int32_t theta,
+                       void* stream) {
+  if (s == nullptr) return fail(CSK_E_INVALID, "collect: NULL handle");
+  Mesh mesh;
+  csk_status rc = check_mesh(s, delta, L, &mesh);
+  if (rc != CSK_OK) return rc;
+  if (n > 0 && pos == nullptr) return fail(CSK_E_INVALID, "collect: NULL positions");
+  latch_mesh(s, delta, L, mesh);
+  if (theta != INT32_MIN) s->partial_set = true;
+  if (n == 0) return CSK_OK;
+  CSK_HIP(launch_collect(pos, n, mesh, s->tables(), s->M, theta, s->set, s->slots - 1, s->set_count(), s->max_cand,
+                         s->err(), (hipStream_t)stream),
+          "collect");
+  return CSK_OK;
+}
+
+csk_status csk_candidates_clear(csk_sketch* s, void* stream) {
+  if (s == nullptr) return fail(CSK_E_INVALID, "candidates_clear: NULL handle");
+  return clear_candidates(s, (hipStream_t)stream);
+}
+
+csk_status csk_topk(csk_sketch* s, uint32_t k, uint64_t* keys, int32_t* est, uint32_t* k_out, void* stream) {
+  if (s == nullptr || k_out == nullptr) return fail(CSK_E_INVALID, "topk: NULL handle or k_out");
+  *k_out = 0;
+  if (k > 0 && (keys == nullptr || est == nullptr)) return fail(CSK_E_INVALID, "topk: NULL output");
+  if (k > s->max_cand) return fail(CSK_E_INVALID, "topk: k=%u above max_candidates=%u", k, s->max_cand);
+  hipStream_t st = (hipStream_t)stream;
+  if (k > s->sel_cap) {
+    CSK_HIP(hipStreamSynchronize(st), "topk: grow scratch");
+    if (s->sel_key) (void)hipFree(s->sel_key);
+    if (s->sel_est) (void)hipFree(s->sel_est);
+    s->bytes -= (uint64_t)s->sel_cap * (sizeof(uint64_t) + sizeof(int32_t));
+    s->sel_key = nullptr;
+    s->sel_est = nullptr;
+    s->sel_cap = 0;
+    CSK_HIP(dmalloc(s, &s->sel_key, k), "topk: scratch");
+    CSK_HIP(dmalloc(s, &s->sel_est, k), "topk: scratch");
+    s->sel_cap = k;
+  }
+  if (k > 0) {
+    CSK_HIP(launch_topk(s->set, s->slots, s->tables(), s->M, s->max_cand, k, s->sel, s->cand_key, s->cand_est,
+                        s->sel_key, s->sel_est, keys, est, s->err(), st),
+            "topk");
+  } else {
+    CSK_HIP(launch_fill_u32((uint32_t*)s->sel, sizeof(SelState) / 4, 0u, st), "topk");
+  }
+  CSK_HIP(hipMemcpyAsync(s->host_sel, s->sel, sizeof(SelState), hipMemcpyDeviceToHost, st), "topk: read back");
+  uint32_t bits = 0;
+  csk_status rc = take_latch(s, st, &bits);
+  if (rc != CSK_OK) return rc;
+  rc = latch_status(bits);
+  if (rc != CSK_OK) return rc;
+  const uint32_t m = s->host_sel->m;
+  const uint32_t got = (k < m) ? k : m;
+  *k_out = got;
+  if (got < k && s->partial_set)
+    return fail(CSK_W_INCOMPLETE, "topk: only %u of %u candidates passed theta", got, k);
+  return CSK_OK;
+}
+
+csk_status csk_get_counters(const csk_sketch* cs, int32_t* out, void* stream) {
+  csk_sketch* s = const_cast<csk_sketch*>(cs);
+  if (s == nullptr || out == nullptr) return fail(CSK_E_INVALID, "get_counters: NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  CSK_HIP(hipMemcpyAsync(out, s->M, (uint64_t)s->d * s->w * sizeof(int32_t), hipMemcpyDeviceToDevice, st),
+          "get_counters");
+  uint32_t bits = 0;
+  csk_status rc = take_latch(s, st, &bits);
+  if (rc != CSK_OK) return rc;
+  return latch_status(bits);
+}
+
+csk_status csk_set_counters(csk_sketch* s, const int32_t* in, void* stream) {
+  if (s == nullptr || in == nullptr) return fail(CSK_E_INVALID, "set_counters: NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  CSK_HIP(hipMemcpyAsync(s->M, in, (uint64_t)s->d * s->w * sizeof(int32_t), hipMemcpyDeviceToDevice, st),
+          "set_counters");
+  return clear_candidates(s, st);
+}
+
+csk_status csk_reset(csk_sketch* s, void* stream) {
+  if (s == nullptr) return fail(CSK_E_INVALID, "reset: NULL handle");
+  hipStream_t st = (hipStream_t)stream;
+  CSK_HIP(launch_fill_u32((uint32_t*)s->M, (uint64_t)s->d * s->w, 0u, st), "reset");
+  CSK_HIP(launch_fill_u32(s->err(), 1, 0u, st), "reset");
+  s->mesh_set = false;
+  return clear_candidates(s, st);
+}
+
+csk_status csk_check(csk_sketch* s, void* stream) {
+  if (s == nullptr) return fail(CSK_E_INVALID, "check: NULL handle");
+  uint32_t bits = 0;
+  csk_status rc = take_latch(s, (hipStream_t)stream, &bits);
+  if (rc != CSK_OK) return rc;
+  return latch_status(bits);
+}
+
+uint64_t csk_device_bytes(const csk_sketch* s) { return s ? s->bytes : 0; }
+
+const char* csk_last_error(void) { return g_last_error; }
+
+}  // extern "C"

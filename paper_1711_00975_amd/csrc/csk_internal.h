@@ -1,0 +1,73 @@
+// csk_internal.h — kernel launch interface between the C ABI (csk_api.hip) and the
+// kernels (csk_kernels.hip).  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "csk_device.h"
+
+namespace csk {
+
+// Candidate selection state (one per handle, device memory).
+struct SelState {
+  uint32_t m;           // candidates compacted from the set
+  uint32_t k_rem;       // items still to take inside the current class
+  uint32_t est_prefix;  // chosen high bits of (est ^ 0x80000000)
+  uint32_t est_mask;
+  uint64_t key_prefix;  // chosen high bits of the key among est == T
+  uint64_t key_mask;
+  uint32_t n_sel;       // items gathered
+  uint32_t err;         // snapshot of the error latch, read back by the host
+  uint32_t hist[256];
+};
+
+struct Tables {
+  const uint32_t* tab;  // [d][6][256] uint32, device
+  uint32_t d;
+  uint32_t w;
+  uint32_t cm;          // 1: Count-Min (no sign, minimum), 0: Count Sketch
+};
+
+// Binned update: sizes chosen by the host.
+struct BinPlan {
+  uint32_t Pr;          // slices per row: ceil(w / 2^15)
+  uint32_t P;           // d * Pr
+  uint32_t nwg;         // workgroups of the bin kernel
+  uint64_t ntiles;      // ceil(n / tile)
+  uint32_t cap;         // tokens per (slice, workgroup) region, multiple of 8
+  uint32_t tile;        // particles per tile
+  uint32_t tab_rows_lds;
+  uint32_t lds_bytes;
+};
+
+constexpr int kBinThreads = 512;
+constexpr int kBinPPT = 16;                       // particles per thread per tile
+constexpr int kBinTile = kBinThreads * kBinPPT;   // 8192
+constexpr int kAccThreads = 1024;
+constexpr uint32_t kMaxSlicesPerRow = 4096;
+constexpr uint32_t kMaxLds = 160 * 1024;
+
+// Returns false if the binned path does not fit (then use the direct path).
+bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& plan);
+
+hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
+                      uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, hipStream_t s);
+hipError_t launch_accumulate(const uint16_t* tok, const uint32_t* cnt, const BinPlan& plan, uint32_t w,
+                             int32_t* M, hipStream_t s);
+hipError_t launch_update_direct(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, int32_t* M,
+                                uint32_t* err, hipStream_t s);
+hipError_t launch_keys(const float* pos, uint64_t n, const Mesh& mesh, uint64_t* keys, hipStream_t s);
+hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const int32_t* M, int32_t* est,
+                        hipStream_t s);
+hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,
+                          int32_t theta, uint64_t* set, uint32_t slot_mask, uint32_t* set_count,
+                          uint32_t max_cand, uint32_t* err, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,
+                       uint32_t max_cand, uint32_t k, SelState* st, uint64_t* cand_key, int32_t* cand_est,
+                       uint64_t* sel_key, int32_t* sel_est, uint64_t* out_key, int32_t* out_est,
+                       const uint32_t* err, hipStream_t s);
+
+}  // namespace csk

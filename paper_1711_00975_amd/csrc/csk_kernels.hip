@@ -1,0 +1,672 @@
+// csk_kernels.hip — gfx950 kernels of the streaming Count-Sketch hot path.
+//
+// update  (Sec. 2.2 Add; Alg. 4 Update; Sec. 3.1 stages 1-3), in two kernels:
+//   bin         one pass over the positions: exact cell key, d tabulated row words, and a
+//               16-bit token (15-bit counter offset + sign) per row, counting-sorted in LDS
+//               by counter slice (2^15 counters) and appended as coalesced runs to a
+//               per-(slice, workgroup) region.  No global atomics on the hot path.
+//   accumulate  one workgroup per slice: sums the slice's tokens into an LDS copy of the
+//               slice with LDS atomics, then adds it to the counters with a plain
+//               read-modify-write (the workgroup owns the slice).
+// query   (Sec. 2.2 Estimate; Alg. 4 Estimate): lower median of the d signed counters.
+// collect (Sec. 3.1 item 4): threshold test per particle, distinct keys into a hash set.
+// topk    (Sec. 2.2 UpdateHeap; Alg. 1 query): two-stage radix select on
+//         (estimate desc, key asc), then an exact rank placement of the k winners.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "csk_internal.h"
+
+namespace csk {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= (uint32_t)o) v += t;
+  }
+  return v;
+}
+
+// Wave-aggregated append: every lane of the wave must call it.  Returns the slot of a
+// lane with pred set.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return 0;
+  const uint32_t lane = lane_id();
+  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = __shfl(base, (int)leader, 64);
+  const uint64_t below = (lane == 0) ? 0ull : (mask & ((~0ull) >> (64 - lane)));
+  return base + (uint32_t)__popcll(below);
+}
+
+// Exclusive scan of in[0..n) into out[0..n) by a block of NT threads; total -> *total.
+// Contains barriers: every thread of the block must call it.
+template <int NT>
+__device__ __forceinline__ void block_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t n,
+                                                     uint32_t* wsum, uint32_t* total) {
+  constexpr int NW = NT / 64;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (n + NT - 1) / NT;
+  const uint32_t lo = min(n, tid * per), hi = min(n, lo + per);
+  uint32_t s = 0;
+  for (uint32_t i = lo; i < hi; ++i) s += in[i];
+  const uint32_t incl = wave_incl_scan(s);
+  const uint32_t wave = tid >> 6;
+  if (lane_id() == 63) wsum[wave] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t t = wsum[w];
+      wsum[w] = acc;
+      acc += t;
+    }
+    *total = acc;
+  }
+  __syncthreads();
+  uint32_t run = wsum[wave] + incl - s;
+  for (uint32_t i = lo; i < hi; ++i) {
+    out[i] = run;
+    run += in[i];
+  }
+  __syncthreads();
+}
+
+// Signed estimate of one row: M * sign (Count-Min: M), modulo 2^32.
+__device__ __forceinline__ int32_t row_estimate(const uint32_t* tab_r, const int32_t* __restrict__ Mr,
+                                                uint32_t w, uint32_t cm, uint64_t key) {
+  const uint32_t h = row_hash(tab_r, key);
+  const uint32_t c = (uint32_t)Mr[bucket_of(h, w)];
+  const uint32_t neg = (h >> 31) & (cm ^ 1u);
+  return (int32_t)(neg ? (0u - c) : c);
+}
+
+template <int MAXD>
+__device__ __forceinline__ int32_t estimate_key(const uint32_t* tabs, const int32_t* __restrict__ M,
+                                                uint32_t d, uint32_t w, uint32_t cm, uint64_t key) {
+  int32_t v[MAXD];
+#pragma unroll
+  for (int r = 0; r < MAXD; ++r) {
+    v[r] = ((uint32_t)r < d) ? row_estimate(tabs + r * kTableWords, M + (uint64_t)r * w, w, cm, key) : 0;
+  }
+  if (cm) {
+    int32_t mn = v[0];
+#pragma unroll
+    for (int r = 1; r < MAXD; ++r)
+      if ((uint32_t)r < d) mn = min(mn, v[r]);
+    return mn;
+  }
+  return lower_median<MAXD>(v, (int)d);
+}
+
+// Stage the tables of the first `rows` rows in LDS.
+__device__ __forceinline__ void load_tables(uint32_t* dst, const uint32_t* __restrict__ src, uint32_t rows) {
+  for (uint32_t i = threadIdx.x; i < rows * kTableWords; i += blockDim.x) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ bin
+
+struct BinArgs {
+  const float* __restrict__ pos;
+  uint64_t n;
+  Mesh mesh;
+  const uint32_t* __restrict__ tab;
+  uint32_t d, w, cm;
+  BinPlan plan;
+  uint16_t* __restrict__ tok;
+  uint32_t* __restrict__ cnt;
+  int32_t* __restrict__ M;
+  uint32_t* __restrict__ err;
+};
+
+// LDS layout (uint32 words): tables [tab_rows_lds * 1536] | cursor [P] | hist [Pr] |
+// base [Pr] | stage [tile] | wsum [NW + 1].
+template <bool TAB_LDS>
+__global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
+  extern __shared__ uint32_t lds[];
+  const BinPlan& pl = a.plan;
+  uint32_t* tabs = lds;
+  uint32_t* cursor = tabs + pl.tab_rows_lds * kTableWords;
+  uint32_t* hist = cursor + pl.P;
+  uint32_t* base = hist + pl.Pr;
+  uint32_t* stage = base + pl.Pr;
+  uint32_t* wsum = stage + kBinTile;
+  uint32_t* total = wsum + kBinThreads / 64;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t g = blockIdx.x;
+
+  if (TAB_LDS) load_tables(tabs, a.tab, pl.tab_rows_lds);
+  for (uint32_t i = tid; i < pl.P; i += kBinThreads) cursor[i] = 0;
+  __syncthreads();
+
+  for (uint64_t tile = g; tile < pl.ntiles; tile += pl.nwg) {
+    const uint64_t first = tile * (uint64_t)kBinTile;
+    uint64_t key[kBinPPT];
+    uint32_t valid = 0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < kBinPPT; ++j) {
+      const uint64_t i = first + (uint64_t)j * kBinThreads + tid;
+      key[j] = 0;
+      if (i < a.n) {
+        const float x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
+        if (cell_key(x, y, z, a.mesh, key[j])) valid |= 1u << j;
+        else bad = true;
+      }
+    }
+    if (bad) atomicOr(a.err, kErrDomain);
+
+    for (uint32_t r = 0; r < a.d; ++r) {
+      const uint32_t* tab_r = TAB_LDS ? tabs + r * kTableWords : a.tab + r * kTableWords;
+      for (uint32_t b = tid; b < pl.Pr; b += kBinThreads) hist[b] = 0;
+      __syncthreads();
+      uint32_t sv[kBinPPT], rk[kBinPPT];
+#pragma unroll
+      for (int j = 0; j < kBinPPT; ++j) {
+        sv[j] = 0;
+        rk[j] = 0;
+        if (valid & (1u << j)) {
+          const uint32_t h = row_hash(tab_r, key[j]);
+          const uint32_t b = bucket_of(h, a.w);
+          const uint32_t neg = (h >> 31) & (a.cm ^ 1u);
+          const uint32_t sl = b >> kSliceBits;
+          sv[j] = (sl << 16) | (b & (kSlice - 1)) | (neg << 15);
+          rk[j] = atomicAdd(&hist[sl], 1u);
+        }
+      }
+      __syncthreads();
+      block_exclusive_scan<kBinThreads>(hist, base, pl.Pr, wsum, total);
+#pragma unroll
+      for (int j = 0; j < kBinPPT; ++j) {
+        if (valid & (1u << j)) stage[base[sv[j] >> 16] + rk[j]] = sv[j];
+      }
+      __syncthreads();
+      const uint32_t ntok = *total;
+      const uint64_t region_row = (uint64_t)r * pl.Pr;
+      for (uint32_t q = tid; q < ntok; q += kBinThreads) {
+        const uint32_t v = stage[q];
+        const uint32_t sl = v >> 16;
+        const uint32_t c = cursor[region_row + sl] + (q - base[sl]);
+        if (c < pl.cap) {
+          a.tok[((region_row + sl) * pl.nwg + g) * (uint64_t)pl.cap + c] = (uint16_t)(v & 0xFFFFu);
+        } else {
+          // region full: add this one update straight to the counter (rare; same sum)
+          const uint32_t bkt = (sl << kSliceBits) | (v & (kSlice - 1));
+          atomicAdd(&a.M[(uint64_t)r * a.w + bkt], (v & 0x8000u) ? -1 : 1);
+        }
+      }
+      __syncthreads();
+      for (uint32_t b = tid; b < pl.Pr; b += kBinThreads) cursor[region_row + b] += hist[b];
+      __syncthreads();
+    }
+  }
+  for (uint32_t s = tid; s < pl.P; s += kBinThreads) a.cnt[(uint64_t)s * pl.nwg + g] = cursor[s];
+}
+
+bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& p) {
+  p.Pr = (w + kSlice - 1) / kSlice;
+  p.P = d * p.Pr;
+  p.tile = kBinTile;
+  p.ntiles = (n + kBinTile - 1) / kBinTile;
+  if (p.Pr > kMaxSlicesPerRow || p.ntiles == 0) return false;
+  p.tab_rows_lds = (d <= (uint32_t)kTabLdsRows) ? d : 0;
+  const uint64_t words = (uint64_t)p.tab_rows_lds * kTableWords + p.P + 2ull * p.Pr + kBinTile +
+                         kBinThreads / 64 + 1;
+  if (words * 4 > kMaxLds) return false;
+  p.lds_bytes = (uint32_t)(words * 4);
+  p.nwg = (uint32_t)(p.ntiles < 512 ? p.ntiles : 512);
+  const uint64_t tiles_per_wg = (p.ntiles + p.nwg - 1) / p.nwg;
+  const uint64_t per_wg = tiles_per_wg * kBinTile;   // most particles one workgroup sees
+  // a full slice holds 2^15 of the w buckets of its row: mean tokens = per_wg * 2^15 / w
+  const uint64_t span = (w < kSlice) ? w : kSlice;
+  uint64_t cap = (per_wg * span * 13 + (uint64_t)w * 10 - 1) / ((uint64_t)w * 10) + 64;  // 1.3x mean + 64
+  if (cap > per_wg) cap = per_wg;                    // a region never gets more than this
+  cap = (cap + 7) & ~7ull;
+  if (cap > 0xFFFFFFF0ull) return false;
+  p.cap = (uint32_t)cap;
+  return true;
+}
+
+hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
+                      uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, hipStream_t s) {
+  BinArgs a;
+  a.pos = pos;
+  a.n = n;
+  a.mesh = mesh;
+  a.tab = t.tab;
+  a.d = t.d;
+  a.w = t.w;
+  a.cm = t.cm;
+  a.plan = plan;
+  a.tok = tok;
+  a.cnt = cnt;
+  a.M = M;
+  a.err = err;
+  if (plan.tab_rows_lds > 0)
+    hipLaunchKernelGGL(bin_kernel<true>, dim3(plan.nwg), dim3(kBinThreads), plan.lds_bytes, s, a);
+  else
+    hipLaunchKernelGGL(bin_kernel<false>, dim3(plan.nwg), dim3(kBinThreads), plan.lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ accumulate
+
+struct AccArgs {
+  const uint16_t* __restrict__ tok;
+  const uint32_t* __restrict__ cnt;
+  BinPlan plan;
+  uint32_t w;
+  int32_t* __restrict__ M;
+};
+
+__global__ __launch_bounds__(kAccThreads) void accumulate_kernel(AccArgs a) {
+  extern __shared__ uint32_t lds[];
+  int32_t* acc = (int32_t*)lds;  // kSlice counters
+  const BinPlan& pl = a.plan;
+  const uint32_t s = blockIdx.x;
+  const uint32_t r = s / pl.Pr, sl = s % pl.Pr;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+  for (uint32_t i = tid; i < kSlice; i += kAccThreads) acc[i] = 0;
+  __syncthreads();
+  constexpr uint32_t U = 4;
+  for (uint32_t g = wave; g < pl.nwg; g += kAccThreads / 64) {
+    const uint32_t c = min(a.cnt[(uint64_t)s * pl.nwg + g], pl.cap);
+    const uint4* t4 = (const uint4*)(a.tok + ((uint64_t)s * pl.nwg + g) * (uint64_t)pl.cap);
+    const uint32_t nchunk = (c + 7) / 8;
+    for (uint32_t q0 = 0; q0 < nchunk; q0 += 64 * U) {
+      uint4 v[U];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t q = q0 + u * 64 + lane;
+        v[u] = (q < nchunk) ? t4[q] : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t q = q0 + u * 64 + lane;
+        const uint32_t wds[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+        for (uint32_t e = 0; e < 8; ++e) {
+          if (q * 8 + e < c) {
+            const uint32_t tk = (wds[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+            atomicAdd(&acc[tk & (kSlice - 1)], (tk & 0x8000u) ? -1 : 1);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t b0 = sl * kSlice;
+  const uint32_t len = min(kSlice, a.w - b0);
+  int32_t* Mrow = a.M + (uint64_t)r * a.w + b0;
+  for (uint32_t i = tid; i < len; i += kAccThreads) Mrow[i] = (int32_t)((uint32_t)Mrow[i] + (uint32_t)acc[i]);
+}
+
+hipError_t launch_accumulate(const uint16_t* tok, const uint32_t* cnt, const BinPlan& plan, uint32_t w,
+                             int32_t* M, hipStream_t s) {
+  AccArgs a;
+  a.tok = tok;
+  a.cnt = cnt;
+  a.plan = plan;
+  a.w = w;
+  a.M = M;
+  hipLaunchKernelGGL(accumulate_kernel, dim3(plan.P), dim3(kAccThreads), kSlice * sizeof(int32_t), s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ direct update
+
+// Fallback when the binned plan does not fit in LDS (very wide or very many rows):
+// one global atomic per row per particle.
+__global__ __launch_bounds__(256) void update_direct_kernel(const float* __restrict__ pos, uint64_t n, Mesh mesh,
+                                                            const uint32_t* __restrict__ tab, uint32_t d,
+                                                            uint32_t w, uint32_t cm, int32_t* __restrict__ M,
+                                                            uint32_t* __restrict__ err) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint64_t key;
+    if (!cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mesh, key)) {
+      atomicOr(err, kErrDomain);
+      continue;
+    }
+    for (uint32_t r = 0; r < d; ++r) {
+      const uint32_t h = row_hash(tab + r * kTableWords, key);
+      const uint32_t neg = (h >> 31) & (cm ^ 1u);
+      atomicAdd(&M[(uint64_t)r * w + bucket_of(h, w)], neg ? -1 : 1);
+    }
+  }
+}
+
+static uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t max_blocks) {
+  uint64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return (uint32_t)b;
+}
+
+hipError_t launch_update_direct(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, int32_t* M,
+                                uint32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(update_direct_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, pos, n, mesh, t.tab,
+                     t.d, t.w, t.cm, M, err);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ keys
+
+__global__ __launch_bounds__(256) void keys_kernel(const float* __restrict__ pos, uint64_t n, Mesh mesh,
+                                                   uint64_t* __restrict__ keys) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint64_t key;
+    keys[i] = cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mesh, key) ? key : kEmptyKey;
+  }
+}
+
+hipError_t launch_keys(const float* pos, uint64_t n, const Mesh& mesh, uint64_t* keys, hipStream_t s) {
+  hipLaunchKernelGGL(keys_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, pos, n, mesh, keys);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ query
+
+template <int MAXD, bool TAB_LDS>
+__global__ __launch_bounds__(256) void query_kernel(const uint64_t* __restrict__ keys, uint64_t m, Tables t,
+                                                    const int32_t* __restrict__ M, int32_t* __restrict__ est) {
+  __shared__ uint32_t tabs_lds[TAB_LDS ? kTabLdsRows * kTableWords : 1];
+  const uint32_t* tabs = t.tab;
+  if (TAB_LDS) {
+    load_tables(tabs_lds, t.tab, t.d);
+    __syncthreads();
+    tabs = tabs_lds;
+  }
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    est[i] = estimate_key<MAXD>(tabs, M, t.d, t.w, t.cm, keys[i] & 0xFFFFFFFFFFFFull);
+  }
+}
+
+hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const int32_t* M, int32_t* est,
+                        hipStream_t s) {
+  const dim3 grid(grid_for(m, 256, 8192));
+  if (t.d <= (uint32_t)kTabLdsRows)
+    hipLaunchKernelGGL((query_kernel<kTabLdsRows, true>), grid, dim3(256), 0, s, keys, m, t, M, est);
+  else
+    hipLaunchKernelGGL((query_kernel<32, false>), grid, dim3(256), 0, s, keys, m, t, M, est);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ collect
+
+__device__ __forceinline__ void set_insert(uint64_t* set, uint32_t mask, uint64_t key, uint32_t* count,
+                                           uint32_t max_cand, uint32_t* err) {
+  uint32_t i = (uint32_t)slot_mix(key) & mask;
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    // A slot only ever changes from empty to a key, so a stale read can only show
+    // "empty"; the compare-and-swap then tells the truth.
+    const uint64_t cur = set[i];
+    if (cur == key) return;
+    if (cur == kEmptyKey) {
+      const uint64_t old = atomicCAS((unsigned long long*)&set[i], (unsigned long long)kEmptyKey,
+                                     (unsigned long long)key);
+      if (old == kEmptyKey) {
+        if (atomicAdd(count, 1u) >= max_cand) atomicOr(err, kErrCapacity);
+        return;
+      }
+      if (old == key) return;
+    }
+    i = (i + 1) & mask;
+  }
+  atomicOr(err, kErrCapacity);
+}
+
+// est(key) >= theta  <=>  at least need = d - floor((d-1)/2) of the d signed row
+// estimates are >= theta (Count-Min: all d).  Rows are read until the answer is known.
+template <bool TAB_LDS>
+__global__ __launch_bounds__(256) void collect_kernel(const float* __restrict__ pos, uint64_t n, Mesh mesh, Tables t,
+                                                      const int32_t* __restrict__ M, int32_t theta,
+                                                      uint64_t* set, uint32_t slot_mask, uint32_t* set_count,
+                                                      uint32_t max_cand, uint32_t* err) {
+  __shared__ uint32_t tabs_lds[TAB_LDS ? kTabLdsRows * kTableWords : 1];
+  const uint32_t* tabs = t.tab;
+  if (TAB_LDS) {
+    load_tables(tabs_lds, t.tab, t.d);
+    __syncthreads();
+    tabs = tabs_lds;
+  }
+  const uint32_t need = t.cm ? t.d : t.d - ((t.d - 1) >> 1);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint64_t key;
+    if (!cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mesh, key)) {
+      atomicOr(err, kErrDomain);
+      continue;
+    }
+    uint32_t pass = 0;
+    for (uint32_t r = 0; r < t.d; ++r) {
+      if (pass >= need || pass + (t.d - r) < need) break;
+      if (row_estimate(tabs + r * kTableWords, M + (uint64_t)r * t.w, t.w, t.cm, key) >= theta) ++pass;
+    }
+    if (pass >= need) set_insert(set, slot_mask, key, set_count, max_cand, err);
+  }
+}
+
+hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,
+                          int32_t theta, uint64_t* set, uint32_t slot_mask, uint32_t* set_count,
+                          uint32_t max_cand, uint32_t* err, hipStream_t s) {
+  const dim3 grid(grid_for(n, 256, 8192));
+  if (t.d <= (uint32_t)kTabLdsRows)
+    hipLaunchKernelGGL(collect_kernel<true>, grid, dim3(256), 0, s, pos, n, mesh, t, M, theta, set, slot_mask,
+                       set_count, max_cand, err);
+  else
+    hipLaunchKernelGGL(collect_kernel<false>, grid, dim3(256), 0, s, pos, n, mesh, t, M, theta, set, slot_mask,
+                       set_count, max_cand, err);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fills
+
+__global__ void fill_u64_kernel(uint64_t* p, uint64_t n, uint64_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+__global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ top-k
+
+__global__ void sel_init_kernel(SelState* st) {
+  uint32_t* w = (uint32_t*)st;
+  for (uint32_t i = threadIdx.x; i < sizeof(SelState) / 4; i += blockDim.x) w[i] = 0;
+}
+
+// Distinct keys of the set -> (key, estimate from the current counters).
+template <int MAXD, bool TAB_LDS>
+__global__ __launch_bounds__(256) void compact_kernel(const uint64_t* __restrict__ set, uint32_t slots, Tables t,
+                                                      const int32_t* __restrict__ M, uint32_t max_cand,
+                                                      SelState* st, uint64_t* __restrict__ ck,
+                                                      int32_t* __restrict__ ce) {
+  __shared__ uint32_t tabs_lds[TAB_LDS ? kTabLdsRows * kTableWords : 1];
+  const uint32_t* tabs = t.tab;
+  if (TAB_LDS) {
+    load_tables(tabs_lds, t.tab, t.d);
+    __syncthreads();
+    tabs = tabs_lds;
+  }
+  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < slots; i0 += gridDim.x * blockDim.x) {
+    const uint32_t i = i0 + threadIdx.x;
+    const uint64_t key = (i < slots) ? set[i] : kEmptyKey;
+    const bool have = key != kEmptyKey;
+    const uint32_t slot = wave_append(&st->m, have);
+    if (have && slot < max_cand) {
+      ck[slot] = key;
+      ce[slot] = estimate_key<MAXD>(tabs, M, t.d, t.w, t.cm, key);
+    }
+  }
+}
+
+__global__ void clamp_m_kernel(SelState* st, uint32_t max_cand) {
+  if (threadIdx.x == 0 && st->m > max_cand) st->m = max_cand;
+}
+
+// Histogram of one 8-bit digit over the current class (stage 1: est; stage 2: key
+// among est == T).
+template <bool KEYS>
+__global__ __launch_bounds__(256) void sel_hist_kernel(const uint64_t* __restrict__ ck, const int32_t* __restrict__ ce,
+                                                       SelState* st, int shift) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t m = st->m;
+  const uint32_t epre = st->est_prefix, emask = st->est_mask;
+  const uint64_t kpre = st->key_prefix, kmask = st->key_mask;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    const uint32_t u = (uint32_t)ce[i] ^ 0x80000000u;
+    if (!KEYS) {
+      if ((u & emask) == epre) atomicAdd(&h[(u >> shift) & 255u], 1u);
+    } else {
+      const uint64_t k = ck[i];
+      if (u == epre && (k & kmask) == kpre) atomicAdd(&h[(uint32_t)(k >> shift) & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// Pick the digit holding the k_rem-th item: descending for estimates, ascending for keys.
+template <bool KEYS>
+__global__ void sel_pick_kernel(SelState* st, uint32_t k, int shift) {
+  if (threadIdx.x != 0) return;
+  if (!KEYS && shift == 24) st->k_rem = min(k, st->m);
+  const uint32_t need = st->k_rem;
+  if (need > 0) {
+    uint32_t cum = 0;
+    int dg;
+    if (!KEYS) {
+      for (dg = 255; dg > 0; --dg) {
+        if (cum + st->hist[dg] >= need) break;
+        cum += st->hist[dg];
+      }
+      st->est_prefix |= (uint32_t)dg << shift;
+      st->est_mask |= 255u << shift;
+    } else {
+      for (dg = 0; dg < 255; ++dg) {
+        if (cum + st->hist[dg] >= need) break;
+        cum += st->hist[dg];
+      }
+      st->key_prefix |= (uint64_t)dg << shift;
+      st->key_mask |= 255ull << shift;
+    }
+    st->k_rem = need - cum;
+  }
+  for (int i = 0; i < 256; ++i) st->hist[i] = 0;
+}
+
+// Winners: est > T, or est == T and key <= K (T, K from the two stages).
+__global__ __launch_bounds__(256) void sel_gather_kernel(const uint64_t* __restrict__ ck, const int32_t* __restrict__ ce,
+                                                         SelState* st, uint32_t k, uint64_t* __restrict__ sk,
+                                                         int32_t* __restrict__ se) {
+  const uint32_t m = st->m;
+  const uint32_t T = st->est_prefix;
+  const uint64_t K = st->key_prefix;
+  const bool any = min(k, m) > 0;
+  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < m; i0 += gridDim.x * blockDim.x) {
+    const uint32_t i = i0 + threadIdx.x;
+    bool take = false;
+    uint64_t key = 0;
+    int32_t e = 0;
+    if (i < m && any) {
+      key = ck[i];
+      e = ce[i];
+      const uint32_t u = (uint32_t)e ^ 0x80000000u;
+      take = (u > T) || (u == T && key <= K);
+    }
+    const uint32_t slot = wave_append(&st->n_sel, take);
+    if (take && slot < k) {
+      sk[slot] = key;
+      se[slot] = e;
+    }
+  }
+}
+
+// Place each winner at its rank in (est desc, key asc); keys are distinct.
+__global__ __launch_bounds__(256) void rank_place_kernel(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
+                                                         SelState* st, uint32_t k, uint64_t* __restrict__ ok,
+                                                         int32_t* __restrict__ oe) {
+  __shared__ uint64_t tk[256];
+  __shared__ int32_t te[256];
+  const uint32_t n = min(st->n_sel, k);
+  for (uint32_t i0 = blockIdx.x * 256; i0 < n; i0 += gridDim.x * 256) {
+    const uint32_t i = i0 + threadIdx.x;
+    const bool act = i < n;
+    const uint64_t ki = act ? sk[i] : 0;
+    const int32_t ei = act ? se[i] : 0;
+    uint32_t rank = 0;
+    for (uint32_t j0 = 0; j0 < n; j0 += 256) {
+      __syncthreads();
+      if (j0 + threadIdx.x < n) {
+        tk[threadIdx.x] = sk[j0 + threadIdx.x];
+        te[threadIdx.x] = se[j0 + threadIdx.x];
+      }
+      __syncthreads();
+      const uint32_t lim = min(256u, n - j0);
+      for (uint32_t t = 0; t < lim; ++t) rank += (te[t] > ei) || (te[t] == ei && tk[t] < ki);
+    }
+    if (act) {
+      ok[rank] = ki;
+      oe[rank] = ei;
+    }
+  }
+}
+
+__global__ void sel_finish_kernel(SelState* st, const uint32_t* err) {
+  if (threadIdx.x == 0) st->err = *err;
+}
+
+hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,
+                       uint32_t max_cand, uint32_t k, SelState* st, uint64_t* ck, int32_t* ce,
+                       uint64_t* sk, int32_t* se, uint64_t* ok, int32_t* oe, const uint32_t* err,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, s, st);
+  const dim3 cgrid(grid_for(slots, 256, 4096));
+  if (t.d <= (uint32_t)kTabLdsRows)
+    hipLaunchKernelGGL((compact_kernel<kTabLdsRows, true>), cgrid, dim3(256), 0, s, set, slots, t, M, max_cand, st,
+                       ck, ce);
+  else
+    hipLaunchKernelGGL((compact_kernel<32, false>), cgrid, dim3(256), 0, s, set, slots, t, M, max_cand, st, ck,
+                       ce);
+  hipLaunchKernelGGL(clamp_m_kernel, dim3(1), dim3(64), 0, s, st, max_cand);
+  const dim3 hgrid(grid_for(max_cand, 256, 1024));
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(sel_hist_kernel<false>, hgrid, dim3(256), 0, s, ck, ce, st, shift);
+    hipLaunchKernelGGL(sel_pick_kernel<false>, dim3(1), dim3(64), 0, s, st, k, shift);
+  }
+  for (int shift = 40; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(sel_hist_kernel<true>, hgrid, dim3(256), 0, s, ck, ce, st, shift);
+    hipLaunchKernelGGL(sel_pick_kernel<true>, dim3(1), dim3(64), 0, s, st, k, shift);
+  }
+  hipLaunchKernelGGL(sel_gather_kernel, hgrid, dim3(256), 0, s, ck, ce, st, k, sk, se);
+  hipLaunchKernelGGL(rank_place_kernel, dim3(grid_for(k, 256, 1024)), dim3(256), 0, s, sk, se, st, k, ok, oe);
+  hipLaunchKernelGGL(sel_finish_kernel, dim3(1), dim3(64), 0, s, st, err);
+  return hipGetLastError();
+}
+
+}  // namespace csk
