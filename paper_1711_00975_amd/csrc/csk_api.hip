@@ -60,6 +60,15 @@ std::vector<uint32_t> make_tables(uint64_t seed, uint32_t d) {
   return T;
 }
 
+// The same tables with the rows of each (character, value) entry side by side,
+// padded to dp = 4 or 8 words, for kernels that hash every row in one pass.
+std::vector<uint32_t> interleave_tables(const std::vector<uint32_t>& T, uint32_t d, uint32_t dp) {
+  std::vector<uint32_t> Ti((size_t)kTableWords * dp, 0u);
+  for (uint32_t r = 0; r < d; ++r)
+    for (uint32_t e = 0; e < (uint32_t)kTableWords; ++e) Ti[(size_t)e * dp + r] = T[(size_t)r * kTableWords + e];
+  return Ti;
+}
+
 }  // namespace
 
 struct csk_sketch {
@@ -69,6 +78,9 @@ struct csk_sketch {
   int32_t variant = CSK_VARIANT_COUNT_SKETCH;
   int32_t* M = nullptr;
   uint32_t* tab = nullptr;
+  uint32_t* tabi = nullptr;  // row-interleaved tables (d <= 8)
+  uint32_t dp = 0;
+  uint32_t* filter = nullptr; // Bloom filter of hot items + [kFilterWords] item count
   uint64_t* set = nullptr;
   uint32_t slots = 0;
   uint32_t max_cand = 0;
@@ -96,6 +108,8 @@ struct csk_sketch {
   Tables tables() const {
     Tables t;
     t.tab = tab;
+    t.tabi = tabi;
+    t.dp = dp;
     t.d = d;
     t.w = w;
     t.cm = (variant == CSK_VARIANT_COUNT_MIN) ? 1u : 0u;
@@ -114,7 +128,7 @@ hipError_t dmalloc(csk_sketch* s, T** p, uint64_t count) {
 }
 
 void free_all(csk_sketch* s) {
-  void* ptrs[] = {s->M, s->tab, s->set, s->ctl, s->sel, s->cand_key, s->cand_est, s->sel_key, s->sel_est,
+  void* ptrs[] = {s->M, s->tab, s->tabi, s->filter, s->set, s->ctl, s->sel, s->cand_key, s->cand_est, s->sel_key, s->sel_est,
                   s->tok, s->cnt};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -199,8 +213,13 @@ csk_status csk_sketch_init_ex(csk_sketch** out, uint32_t d, uint32_t w, uint64_t
   s->slots = (uint32_t)slots;
   hipError_t e = hipGetDevice(&s->device);
   const auto T = make_tables(seed, d);
+  s->dp = (d <= 4) ? 4u : (d <= (uint32_t)kTabLdsRows ? 8u : 0u);
+  std::vector<uint32_t> Ti;
+  if (s->dp) Ti = interleave_tables(T, d, s->dp);
   if (e == hipSuccess) e = dmalloc(s, &s->M, (uint64_t)d * w);
   if (e == hipSuccess) e = dmalloc(s, &s->tab, T.size());
+  if (e == hipSuccess && s->dp) e = dmalloc(s, &s->tabi, Ti.size());
+  if (e == hipSuccess && s->dp) e = dmalloc(s, &s->filter, (uint64_t)kFilterWords + 1);
   if (e == hipSuccess) e = dmalloc(s, &s->set, slots);
   if (e == hipSuccess) e = dmalloc(s, &s->ctl, 4);
   if (e == hipSuccess) e = dmalloc(s, &s->sel, 1);
@@ -209,6 +228,8 @@ csk_status csk_sketch_init_ex(csk_sketch** out, uint32_t d, uint32_t w, uint64_t
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->host_sel, sizeof(SelState), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->host_ctl, 4 * sizeof(uint32_t), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemcpy(s->tab, T.data(), T.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && s->dp)
+    e = hipMemcpy(s->tabi, Ti.data(), Ti.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)s->M, (uint64_t)d * w, 0u, nullptr);
   if (e == hipSuccess) e = launch_fill_u32(s->ctl, 4, 0u, nullptr);
   if (e == hipSuccess) e = launch_fill_u64(s->set, slots, kEmptyKey, nullptr);
@@ -309,8 +330,17 @@ csk_status csk_collect(csk_sketch* s, const float* pos, uint64_t n, double delta
   latch_mesh(s, delta, L, mesh);
   if (theta != INT32_MIN) s->partial_set = true;
   if (n == 0) return CSK_OK;
-  CSK_HIP(launch_collect(pos, n, mesh, s->tables(), s->M, theta, s->set, s->slots - 1, s->set_count(), s->max_cand,
-                         s->err(), (hipStream_t)stream),
+  hipStream_t st = (hipStream_t)stream;
+  const Tables t = s->tables();
+  const uint32_t* filter = nullptr;
+  const uint32_t* hot = nullptr;
+  if (s->filter != nullptr && theta > 0) {
+    CSK_HIP(launch_filter_build(t, s->M, theta, s->filter, s->filter + kFilterWords, st), "collect (filter)");
+    filter = s->filter;
+    hot = s->filter + kFilterWords;
+  }
+  CSK_HIP(launch_collect(pos, n, mesh, t, s->M, theta, filter, hot, s->set, s->slots - 1, s->set_count(),
+                         s->max_cand, s->err(), st),
           "collect");
   return CSK_OK;
 }

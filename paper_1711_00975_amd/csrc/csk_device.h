@@ -16,6 +16,8 @@ constexpr int kSliceBits = 15;         // counters per accumulation slice = 2^15
 constexpr uint32_t kSlice = 1u << kSliceBits;
 constexpr uint64_t kEmptyKey = ~0ull;  // empty slot of the candidate set / invalid key
 constexpr int kTabLdsRows = 8;         // rows whose tables are staged in LDS
+constexpr int kFilterWords = 24576;    // LDS Bloom filter of hot (row, bucket, sign): 96 KiB
+constexpr uint32_t kFilterMaxItems = kFilterWords * 32 / 6;  // denser filters are not used
 
 // error latch bits (device word)
 constexpr uint32_t kErrDomain = 1u;
@@ -75,6 +77,28 @@ __device__ __forceinline__ uint32_t row_hash(const uint32_t* __restrict__ tab_r,
   return h;
 }
 
+// Tabulated words of rows 0..DP-1 from row-interleaved tables Ti[c][v][DP] (DP = 4 or 8,
+// 16-byte aligned rows): two (or one) 16-byte reads per key byte give every row at once.
+template <int DP>
+__device__ __forceinline__ void row_hashes(const uint32_t* __restrict__ ti, uint64_t key, uint32_t (&h)[DP]) {
+  const uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
+  const uint32_t byte[kChars] = {lo & 255u, (lo >> 8) & 255u, (lo >> 16) & 255u, lo >> 24, hi & 255u, (hi >> 8) & 255u};
+#pragma unroll
+  for (int r = 0; r < DP; ++r) h[r] = 0;
+#pragma unroll
+  for (int c = 0; c < kChars; ++c) {
+    const uint4* e = (const uint4*)(ti + (c * 256 + byte[c]) * DP);
+#pragma unroll
+    for (int q = 0; q < DP / 4; ++q) {
+      const uint4 v = e[q];
+      h[4 * q + 0] ^= v.x;
+      h[4 * q + 1] ^= v.y;
+      h[4 * q + 2] ^= v.z;
+      h[4 * q + 3] ^= v.w;
+    }
+  }
+}
+
 // Bucket hash: low 31 bits scaled onto [0, w).
 __device__ __forceinline__ uint32_t bucket_of(uint32_t h, uint32_t w) {
   return (uint32_t)(((uint64_t)(h & 0x7FFFFFFFu) * (uint64_t)w) >> 31);
@@ -103,7 +127,14 @@ __device__ __forceinline__ int32_t lower_median(const int32_t (&v)[MAXD], int d)
   return res;
 }
 
-// 64-bit finaliser (MurmurHash3 fmix64) used only to place keys in the candidate set.
+// Blocked Bloom filter over (row, bucket, sign) items: one 32-bit word, three bits.
+struct FilterProbe {
+  uint32_t word;
+  uint32_t mask;
+};
+
+// 64-bit finaliser (MurmurHash3 fmix64) used only to place keys in the candidate set
+// and items in the Bloom filter.
 __device__ __forceinline__ uint64_t slot_mix(uint64_t k) {
   k ^= k >> 33;
   k *= 0xff51afd7ed558ccdull;
@@ -111,6 +142,22 @@ __device__ __forceinline__ uint64_t slot_mix(uint64_t k) {
   k *= 0xc4ceb9fe1a85ec53ull;
   k ^= k >> 33;
   return k;
+}
+
+// Probe of the filter for the item (row r, bucket b, sign bit neg): fmix32 of the item,
+// word index from its high bits, three bit positions from a second multiply.
+__device__ __forceinline__ FilterProbe filter_probe(uint32_t r, uint32_t b, uint32_t neg) {
+  uint32_t x = ((b << 1) | neg) ^ (r * 0x9E3779B9u);
+  x ^= x >> 16;
+  x *= 0x85EBCA6Bu;
+  x ^= x >> 13;
+  x *= 0xC2B2AE35u;
+  x ^= x >> 16;
+  const uint32_t y = x * 0xCC9E2D51u;
+  FilterProbe p;
+  p.word = (uint32_t)(((uint64_t)x * (uint64_t)kFilterWords) >> 32);
+  p.mask = (1u << (y >> 27)) | (1u << ((y >> 22) & 31u)) | (1u << ((y >> 17) & 31u));
+  return p;
 }
 
 }  // namespace csk

@@ -24,6 +24,8 @@ struct SelState {
 
 struct Tables {
   const uint32_t* tab;  // [d][6][256] uint32, device
+  const uint32_t* tabi; // row-interleaved [6][256][dp] uint32 (d <= 8), device
+  uint32_t dp;          // 4 (d <= 4) or 8 (d <= 8); 0 when d > 8
   uint32_t d;
   uint32_t w;
   uint32_t cm;          // 1: Count-Min (no sign, minimum), 0: Count Sketch
@@ -39,8 +41,13 @@ struct BinPlan {
   uint32_t tile;        // particles per tile
   uint32_t tab_rows_lds;
   uint32_t lds_bytes;
+  uint32_t fast;        // 1: row-interleaved kernel (d <= 8)
 };
 
+constexpr int kBin2Threads = 1024;                 // row-interleaved bin kernel
+// particles per thread per tile: all d tokens of each stay in registers
+constexpr int bin2_ppt(int d) { return d <= 5 ? 8 : 4; }
+constexpr int kCollectThreads = 1024;
 constexpr int kBinThreads = 512;
 constexpr int kBinPPT = 16;                       // particles per thread per tile
 constexpr int kBinTile = kBinThreads * kBinPPT;   // 8192
@@ -60,9 +67,14 @@ hipError_t launch_update_direct(const float* pos, uint64_t n, const Mesh& mesh, 
 hipError_t launch_keys(const float* pos, uint64_t n, const Mesh& mesh, uint64_t* keys, hipStream_t s);
 hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const int32_t* M, int32_t* est,
                         hipStream_t s);
+// Bloom filter of the (row, bucket, sign) items whose signed counter is >= theta
+// (theta > 0); filter: kFilterWords words, hot: item count (both zeroed here).
+hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta, uint32_t* filter, uint32_t* hot,
+                               hipStream_t s);
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,
-                          int32_t theta, uint64_t* set, uint32_t slot_mask, uint32_t* set_count,
-                          uint32_t max_cand, uint32_t* err, hipStream_t s);
+                          int32_t theta, const uint32_t* filter, const uint32_t* hot, uint64_t* set,
+                          uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
+                          hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,

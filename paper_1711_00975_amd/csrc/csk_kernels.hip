@@ -119,6 +119,7 @@ struct BinArgs {
   uint64_t n;
   Mesh mesh;
   const uint32_t* __restrict__ tab;
+  const uint32_t* __restrict__ tabi;
   uint32_t d, w, cm;
   BinPlan plan;
   uint16_t* __restrict__ tok;
@@ -211,20 +212,152 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
   for (uint32_t s = tid; s < pl.P; s += kBinThreads) a.cnt[(uint64_t)s * pl.nwg + g] = cursor[s];
 }
 
+
+// ------------------------------------------------------------------ bin (d <= 8)
+
+// Row-interleaved variant for d <= 8: every row word of a particle comes from one
+// pass over the six key bytes, all d tokens of a tile stay in registers, and each
+// row is counting-sorted in LDS while the previous row's runs are written out.
+// LDS layout (words): Ti [1536 * DP] | dst (u64) [Pr] | cursor [P] | hist [Pr] |
+// base [Pr] | lim [Pr] | stage [tile] | wsum [NW].
+template <int D>
+__global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
+  constexpr int DP = (D <= 4) ? 4 : 8;
+  constexpr int NT = kBin2Threads, PPT = bin2_ppt(D), TILE = NT * PPT, NW = NT / 64;
+  extern __shared__ __align__(16) uint32_t lds2[];
+  const BinPlan& pl = a.plan;
+  uint32_t* ti = lds2;
+  uint64_t* dst = (uint64_t*)(ti + kTableWords * DP);
+  uint32_t* cursor = (uint32_t*)(dst + pl.Pr);
+  uint32_t* hist = cursor + pl.P;
+  uint32_t* base = hist + pl.Pr;
+  uint32_t* lim = base + pl.Pr;
+  uint32_t* stage = lim + pl.Pr;
+  uint32_t* wsum = stage + TILE;
+  const uint32_t tid = threadIdx.x, g = blockIdx.x, wave = tid >> 6;
+
+  for (uint32_t i = tid; i < (uint32_t)(kTableWords * DP); i += NT) ti[i] = a.tabi[i];
+  for (uint32_t i = tid; i < pl.P; i += NT) cursor[i] = 0;
+  for (uint32_t i = tid; i < pl.Pr; i += NT) hist[i] = 0;
+  __syncthreads();
+
+  const uint32_t per = (pl.Pr + NT - 1) / NT;          // scan: bins per thread
+  const uint32_t blo = min(pl.Pr, tid * per), bhi = min(pl.Pr, blo + per);
+  bool pending = false;                                  // a sorted row waits in stage
+  uint32_t pend_row = 0, pend_total = 0;
+
+  auto write_out = [&]() {
+    for (uint32_t q = tid; q < pend_total; q += NT) {
+      const uint32_t v = stage[q];
+      const uint32_t sl = v >> 16;
+      if (q < lim[sl]) {
+        a.tok[dst[sl] + q] = (uint16_t)(v & 0xFFFFu);
+      } else {
+        // region full: add this one update straight to the counter (rare; same sum)
+        const uint32_t bkt = (sl << kSliceBits) | (v & (kSlice - 1));
+        atomicAdd(&a.M[(uint64_t)pend_row * a.w + bkt], (v & 0x8000u) ? -1 : 1);
+      }
+    }
+  };
+
+  for (uint64_t tile = g; tile < pl.ntiles; tile += pl.nwg) {
+    const uint64_t first = tile * (uint64_t)TILE;
+    uint32_t sv[D][PPT];
+    uint32_t valid = 0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const uint64_t i = first + (uint64_t)j * NT + tid;
+#pragma unroll
+      for (int r = 0; r < D; ++r) sv[r][j] = 0;
+      if (i < a.n) {
+        uint64_t key;
+        if (cell_key(a.pos[3 * i], a.pos[3 * i + 1], a.pos[3 * i + 2], a.mesh, key)) {
+          valid |= 1u << j;
+          uint32_t h[DP];
+          row_hashes<DP>(ti, key, h);
+#pragma unroll
+          for (int r = 0; r < D; ++r) {
+            const uint32_t b = bucket_of(h[r], a.w);
+            const uint32_t neg = (h[r] >> 31) & (a.cm ^ 1u);
+            sv[r][j] = ((b >> kSliceBits) << 16) | (b & (kSlice - 1)) | (neg << 15);
+          }
+        } else {
+          bad = true;
+        }
+      }
+    }
+    if (bad) atomicOr(a.err, kErrDomain);
+
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      if (pending) write_out();
+      uint32_t rk[PPT];
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) rk[j] = (valid & (1u << j)) ? atomicAdd(&hist[sv[r][j] >> 16], 1u) : 0u;
+      __syncthreads();  // counts complete; the previous row is written out
+      uint32_t cnt_local = 0;
+      for (uint32_t b = blo; b < bhi; ++b) cnt_local += hist[b];
+      const uint32_t incl = wave_incl_scan(cnt_local);
+      if ((tid & 63u) == 63u) wsum[wave] = incl;
+      __syncthreads();
+      uint32_t run = incl - cnt_local, total = 0;
+      for (int w2 = 0; w2 < NW; ++w2) {
+        const uint32_t x = wsum[w2];
+        if (w2 < (int)wave) run += x;
+        total += x;
+      }
+      const uint64_t slice0 = (uint64_t)r * pl.Pr;
+      for (uint32_t b = blo; b < bhi; ++b) {
+        const uint32_t hb = hist[b];
+        const uint32_t cur = cursor[slice0 + b];
+        base[b] = run;
+        dst[b] = ((slice0 + b) * pl.nwg + g) * (uint64_t)pl.cap + cur - run;
+        lim[b] = run + (cur < pl.cap ? pl.cap - cur : 0u);
+        cursor[slice0 + b] = cur + hb;
+        hist[b] = 0;
+        run += hb;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        if (valid & (1u << j)) {
+          const uint32_t v = sv[r][j];
+          stage[base[v >> 16] + rk[j]] = v;
+        }
+      }
+      __syncthreads();
+      pending = true;
+      pend_row = (uint32_t)r;
+      pend_total = total;
+    }
+  }
+  if (pending) write_out();
+  for (uint32_t s = tid; s < pl.P; s += NT) a.cnt[(uint64_t)s * pl.nwg + g] = cursor[s];
+}
+
 bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& p) {
   p.Pr = (w + kSlice - 1) / kSlice;
   p.P = d * p.Pr;
-  p.tile = kBinTile;
-  p.ntiles = (n + kBinTile - 1) / kBinTile;
+  p.fast = (d <= (uint32_t)kTabLdsRows) ? 1u : 0u;
+  p.tile = p.fast ? kBin2Threads * bin2_ppt((int)d) : kBinTile;
+  p.ntiles = (n + p.tile - 1) / p.tile;
   if (p.Pr > kMaxSlicesPerRow || p.ntiles == 0) return false;
-  p.tab_rows_lds = (d <= (uint32_t)kTabLdsRows) ? d : 0;
-  const uint64_t words = (uint64_t)p.tab_rows_lds * kTableWords + p.P + 2ull * p.Pr + kBinTile +
-                         kBinThreads / 64 + 1;
+  uint64_t words;
+  if (p.fast) {
+    const uint32_t dp = (d <= 4) ? 4u : 8u;
+    p.tab_rows_lds = 0;
+    words = (uint64_t)kTableWords * dp + 2ull * p.Pr + p.P + 3ull * p.Pr + p.tile + kBin2Threads / 64;
+  } else {
+    p.tab_rows_lds = 0;
+    words = (uint64_t)p.P + 2ull * p.Pr + kBinTile + kBinThreads / 64 + 1;
+  }
   if (words * 4 > kMaxLds) return false;
   p.lds_bytes = (uint32_t)(words * 4);
-  p.nwg = (uint32_t)(p.ntiles < 512 ? p.ntiles : 512);
+  const uint64_t max_wg = p.fast ? 256 : 512;
+  p.nwg = (uint32_t)(p.ntiles < max_wg ? p.ntiles : max_wg);
   const uint64_t tiles_per_wg = (p.ntiles + p.nwg - 1) / p.nwg;
-  const uint64_t per_wg = tiles_per_wg * kBinTile;   // most particles one workgroup sees
+  const uint64_t per_wg = tiles_per_wg * p.tile;     // most particles one workgroup sees
   // a full slice holds 2^15 of the w buckets of its row: mean tokens = per_wg * 2^15 / w
   const uint64_t span = (w < kSlice) ? w : kSlice;
   uint64_t cap = (per_wg * span * 13 + (uint64_t)w * 10 - 1) / ((uint64_t)w * 10) + 64;  // 1.3x mean + 64
@@ -250,10 +383,22 @@ hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
   a.cnt = cnt;
   a.M = M;
   a.err = err;
-  if (plan.tab_rows_lds > 0)
-    hipLaunchKernelGGL(bin_kernel<true>, dim3(plan.nwg), dim3(kBinThreads), plan.lds_bytes, s, a);
-  else
+  a.tabi = t.tabi;
+  if (plan.fast) {
+    const dim3 grid(plan.nwg), block(kBin2Threads);
+    switch (t.d) {
+      case 1: hipLaunchKernelGGL(bin2_kernel<1>, grid, block, plan.lds_bytes, s, a); break;
+      case 2: hipLaunchKernelGGL(bin2_kernel<2>, grid, block, plan.lds_bytes, s, a); break;
+      case 3: hipLaunchKernelGGL(bin2_kernel<3>, grid, block, plan.lds_bytes, s, a); break;
+      case 4: hipLaunchKernelGGL(bin2_kernel<4>, grid, block, plan.lds_bytes, s, a); break;
+      case 5: hipLaunchKernelGGL(bin2_kernel<5>, grid, block, plan.lds_bytes, s, a); break;
+      case 6: hipLaunchKernelGGL(bin2_kernel<6>, grid, block, plan.lds_bytes, s, a); break;
+      case 7: hipLaunchKernelGGL(bin2_kernel<7>, grid, block, plan.lds_bytes, s, a); break;
+      default: hipLaunchKernelGGL(bin2_kernel<8>, grid, block, plan.lds_bytes, s, a); break;
+    }
+  } else {
     hipLaunchKernelGGL(bin_kernel<false>, dim3(plan.nwg), dim3(kBinThreads), plan.lds_bytes, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -457,16 +602,130 @@ __global__ __launch_bounds__(256) void collect_kernel(const float* __restrict__ 
   }
 }
 
+// Row-interleaved collect for d <= 8.  When a Bloom filter of the hot (row, bucket,
+// sign) items is supplied, a particle whose rows pass the filter fewer than `need`
+// times cannot have est >= theta (the filter has no false negatives) and is dropped
+// without touching the counters; the rest take the exact test.
+template <int D>
+__global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* __restrict__ pos, uint64_t n, Mesh mesh,
+                                                                   Tables t, const int32_t* __restrict__ M,
+                                                                   int32_t theta, const uint32_t* __restrict__ filter,
+                                                                   const uint32_t* __restrict__ hot, uint32_t use_filter,
+                                                                   uint64_t* set, uint32_t slot_mask,
+                                                                   uint32_t* set_count, uint32_t max_cand,
+                                                                   uint32_t* err) {
+  constexpr int DP = (D <= 4) ? 4 : 8;
+  extern __shared__ __align__(16) uint32_t lds3[];
+  uint32_t* ti = lds3;
+  uint32_t* filt = ti + kTableWords * DP;
+  for (uint32_t i = threadIdx.x; i < (uint32_t)(kTableWords * DP); i += blockDim.x) ti[i] = t.tabi[i];
+  const bool uf = use_filter && (*hot <= kFilterMaxItems);
+  if (uf)
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kFilterWords; i += blockDim.x) filt[i] = filter[i];
+  __syncthreads();
+  constexpr uint32_t kNeedCS = D - ((D - 1) >> 1);
+  const uint32_t need = t.cm ? (uint32_t)D : kNeedCS;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint64_t key;
+    if (!cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mesh, key)) {
+      bad = true;
+      continue;
+    }
+    uint32_t h[DP];
+    row_hashes<DP>(ti, key, h);
+    uint32_t bk[D], ng[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      bk[r] = bucket_of(h[r], t.w);
+      ng[r] = (h[r] >> 31) & (t.cm ^ 1u);
+    }
+    if (uf) {
+      uint32_t fp = 0;
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        const FilterProbe pr = filter_probe((uint32_t)r, bk[r], ng[r]);
+        fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
+      }
+      if (fp < need) continue;
+    }
+    uint32_t pass = 0;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      if (pass >= need || pass + (uint32_t)(D - r) < need) break;
+      const uint32_t c = (uint32_t)M[(uint64_t)r * t.w + bk[r]];
+      if ((int32_t)(ng[r] ? 0u - c : c) >= theta) ++pass;
+    }
+    if (pass >= need) set_insert(set, slot_mask, key, set_count, max_cand, err);
+  }
+  if (bad) atomicOr(err, kErrDomain);
+}
+
+// Items (r, b, sign) with sign * M[r][b] >= theta (Count-Min: M[r][b] >= theta) go into
+// the filter; theta > 0, so empty buckets never do.
+__global__ __launch_bounds__(256) void filter_build_kernel(const int32_t* __restrict__ M, uint32_t d, uint32_t w,
+                                                           uint32_t cm, int32_t theta, uint32_t* __restrict__ filter,
+                                                           uint32_t* __restrict__ hot) {
+  for (uint32_t r = 0; r < d; ++r) {
+    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < w; b0 += gridDim.x * blockDim.x) {
+      const uint32_t b = b0 + threadIdx.x;
+      bool hp = false, hn = false;
+      if (b < w) {
+        const int64_t c = M[(uint64_t)r * w + b];
+        hp = c >= theta;
+        hn = !cm && (-c >= theta);
+      }
+      if (hp) {
+        const FilterProbe pr = filter_probe(r, b, 0u);
+        atomicOr(&filter[pr.word], pr.mask);
+      }
+      if (hn) {
+        const FilterProbe pr = filter_probe(r, b, 1u);
+        atomicOr(&filter[pr.word], pr.mask);
+      }
+      const uint32_t items = (uint32_t)__popcll(__ballot(hp)) + (uint32_t)__popcll(__ballot(hn));
+      if ((threadIdx.x & 63u) == 0 && items) atomicAdd(hot, items);
+    }
+  }
+}
+
+hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta, uint32_t* filter, uint32_t* hot,
+                               hipStream_t s) {
+  hipError_t e = launch_fill_u32(filter, kFilterWords, 0u, s);
+  if (e == hipSuccess) e = launch_fill_u32(hot, 1, 0u, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(filter_build_kernel, dim3(grid_for(t.w, 256, 2048)), dim3(256), 0, s, M, t.d, t.w, t.cm, theta,
+                     filter, hot);
+  return hipGetLastError();
+}
+
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,
-                          int32_t theta, uint64_t* set, uint32_t slot_mask, uint32_t* set_count,
-                          uint32_t max_cand, uint32_t* err, hipStream_t s) {
-  const dim3 grid(grid_for(n, 256, 8192));
-  if (t.d <= (uint32_t)kTabLdsRows)
-    hipLaunchKernelGGL(collect_kernel<true>, grid, dim3(256), 0, s, pos, n, mesh, t, M, theta, set, slot_mask,
-                       set_count, max_cand, err);
-  else
-    hipLaunchKernelGGL(collect_kernel<false>, grid, dim3(256), 0, s, pos, n, mesh, t, M, theta, set, slot_mask,
-                       set_count, max_cand, err);
+                          int32_t theta, const uint32_t* filter, const uint32_t* hot, uint64_t* set,
+                          uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
+                          hipStream_t s) {
+  if (t.d <= (uint32_t)kTabLdsRows) {
+    const uint32_t use_filter = (filter != nullptr && hot != nullptr) ? 1u : 0u;
+    const size_t lds = ((size_t)kTableWords * t.dp + (use_filter ? kFilterWords : 0)) * sizeof(uint32_t);
+    const dim3 grid(grid_for(n, kCollectThreads, 512)), block(kCollectThreads);
+#define CSK_COLLECT2(DD)                                                                                   \
+  hipLaunchKernelGGL(collect2_kernel<DD>, grid, block, lds, s, pos, n, mesh, t, M, theta, filter, hot, use_filter, \
+                     set, slot_mask, set_count, max_cand, err)
+    switch (t.d) {
+      case 1: CSK_COLLECT2(1); break;
+      case 2: CSK_COLLECT2(2); break;
+      case 3: CSK_COLLECT2(3); break;
+      case 4: CSK_COLLECT2(4); break;
+      case 5: CSK_COLLECT2(5); break;
+      case 6: CSK_COLLECT2(6); break;
+      case 7: CSK_COLLECT2(7); break;
+      default: CSK_COLLECT2(8); break;
+    }
+#undef CSK_COLLECT2
+  } else {
+    hipLaunchKernelGGL(collect_kernel<false>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, pos, n, mesh, t, M, theta,
+                       set, slot_mask, set_count, max_cand, err);
+  }
   return hipGetLastError();
 }
 

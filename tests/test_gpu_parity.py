@@ -131,6 +131,8 @@ CASES = [
     (100_000, 9, 12345, 3000.0, 1.0, 11, 0),
     (60_000, 16, 1 << 14, 100.0, 0.1, 12, 0),
     (40_000, 32, 777, 100.0, 0.1, 13, 0),
+    (70_000, 6, 50_000, 1000.0, 0.25, 16, 0),
+    (70_000, 3, 1 << 18, 1000.0, 0.25, 17, 0),
     (100_000, 5, 1 << 16, 100.0, 0.1, 14, 1),
     (100_000, 7, 999, 3000.0, 0.5, 15, 1),
 ]
@@ -294,6 +296,15 @@ def test_topk_ties_and_sizes(k):
     topk_case(pos, 5, 1 << 16, 8, 0.1, 100.0, k, oracle.INT32_MIN)
     topk_case(pos, 4, 1 << 12, 8, 0.1, 100.0, k, 2)
     topk_case(pos, 3, 97, 8, 0.1, 100.0, k, oracle.INT32_MIN, variant=1)
+
+
+@pytest.mark.parametrize("d,w,theta,variant", [(8, 4096, 3, 0), (9, 4096, 3, 0), (6, 2000, 4, 0),
+                                               (3, 1000, 20, 1), (5, 1 << 12, 1, 0)])
+def test_topk_filtered_collect(d, w, theta, variant):
+    # theta > 0 puts a Bloom filter of hot (row, bucket, sign) items in front of the
+    # exact test (d <= 8); theta = 1 makes the filter too dense, so it is skipped
+    pos = clustered(120_000, 100.0, 80 + d, frac=0.7, sigma=0.05)
+    topk_case(pos, d, w, 23, 0.1, 100.0, 500, theta, variant)
 
 
 def test_topk_empty_and_k_above_candidates():
