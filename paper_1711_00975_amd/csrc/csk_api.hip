@@ -61,7 +61,7 @@ std::vector<uint32_t> make_tables(uint64_t seed, uint32_t d) {
 }
 
 // The same tables with the rows of each (character, value) entry side by side,
-// padded to dp = 4 or 8 words, for kernels that hash every row in one pass.
+// padded to dp = 4, 6 or 8 words, for kernels that hash every row in one pass.
 std::vector<uint32_t> interleave_tables(const std::vector<uint32_t>& T, uint32_t d, uint32_t dp) {
   std::vector<uint32_t> Ti((size_t)kTableWords * dp, 0u);
   for (uint32_t r = 0; r < d; ++r)
@@ -112,6 +112,8 @@ struct csk_sketch {
     t.dp = dp;
     t.d = d;
     t.w = w;
+    t.wshift = 0;
+    if (w >= 2 && (w & (w - 1)) == 0) t.wshift = 32u - (uint32_t)__builtin_ctz(w);
     t.cm = (variant == CSK_VARIANT_COUNT_MIN) ? 1u : 0u;
     return t;
   }
@@ -153,6 +155,19 @@ csk_status check_mesh(csk_sketch* s, double delta, double L, Mesh* out) {
   out->twoL = 2.0 * L;
   out->Gd = (double)G;
   out->G = (int32_t)G;
+  out->nch = key_chars((int32_t)G);
+  // exact-ratio modes: R = G/L exactly representable with <= 29 significant bits
+  out->mode = kMeshGeneral;
+  out->R = (double)G / L;
+  out->Rf = (float)out->R;
+  out->twoLf = (float)(2.0 * L);
+  if (std::fma(out->R, L, -(double)G) == 0.0 && std::isfinite(out->R) && out->R > 0.0) {
+    int ex;
+    const double mant = std::frexp(out->R, &ex);       // R = mant * 2^ex, mant in [0.5, 1)
+    const double scaled = std::ldexp(mant, 29);         // integer iff <= 29 significant bits
+    if (scaled == std::floor(scaled)) out->mode = kMeshExactRatio;
+    if (mant == 0.5 && ex >= 1 && (double)out->twoLf == 2.0 * L) out->mode = kMeshPow2Ratio;
+  }
   return CSK_OK;
 }
 
@@ -213,7 +228,7 @@ csk_status csk_sketch_init_ex(csk_sketch** out, uint32_t d, uint32_t w, uint64_t
   s->slots = (uint32_t)slots;
   hipError_t e = hipGetDevice(&s->device);
   const auto T = make_tables(seed, d);
-  s->dp = (d <= 4) ? 4u : (d <= (uint32_t)kTabLdsRows ? 8u : 0u);
+  s->dp = (d <= 4) ? 4u : (d <= 6 ? 6u : (d <= (uint32_t)kTabLdsRows ? 8u : 0u));
   std::vector<uint32_t> Ti;
   if (s->dp) Ti = interleave_tables(T, d, s->dp);
   if (e == hipSuccess) e = dmalloc(s, &s->M, (uint64_t)d * w);

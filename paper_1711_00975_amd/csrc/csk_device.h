@@ -29,35 +29,60 @@ struct Mesh {
   double twoL;    // domain bound: |p| < 2L
   double Gd;      // cells per side, as a double
   int32_t G;      // cells per side
+  uint32_t nch;   // key bytes that can be non-zero (keys < G^3)
+  uint32_t mode;  // kMeshGeneral, kMeshExactRatio or kMeshPow2Ratio
+  double R;       // G / L when it is exact (modes 1, 2)
+  float Rf;       // G / L as a float (mode 2: a power of two >= 1)
+  float twoLf;    // 2L as a float (mode 2: exact)
 };
+
+// How a mesh's cell index is computed (every mode gives floor(p * G / L) exactly):
+//   general     floor estimate of p*G*(1/L) corrected by the signs of two fma residuals
+//   exact ratio R = G/L is a double with at most 29 significant bits, so p*R is exact in
+//               binary64 and floor(p*R) is the answer
+//   pow2 ratio  R = 2^k, k >= 0, and 2L is a float: p*R is exact in binary32
+constexpr uint32_t kMeshGeneral = 0;
+constexpr uint32_t kMeshExactRatio = 1;
+constexpr uint32_t kMeshPow2Ratio = 2;
 
 // Exact cell index along one axis: floor(p * G / L) on the exact values, wrapped into
 // [0, G).  p*G is exact in binary64 (24-bit significand times a 16-bit integer).  The
-// quotient estimate floor((p*G) * (1/L)) is within one of the exact floor, because its
-// relative error is a few ulp and |p*G/L| < 2^17; the sign of a single-rounded fma
-// t - q*L equals the sign of the exact remainder, which fixes the estimate.
-// Returns false for a non-finite p or |p| >= 2L.
+// quotient estimate q = floor((p*G) * (1/L)) is within one of the exact floor, because
+// its relative error is a few ulp and |p*G/L| < 2^17; the signs of the single-rounded
+// fma residuals t - q*L and t - (q+1)*L equal the signs of the exact ones and move q
+// to the floor.  Branch-free; the result is meaningful only when it returns true
+// (p finite and |p| < 2L).
 __device__ __forceinline__ bool cell_index(float p, const Mesh& m, int32_t& out) {
-  const double x = (double)p;
-  if (!(__builtin_fabs(x) < m.twoL)) return false;
-  const double t = x * m.Gd;
-  double q = __builtin_floor(t * m.invL);
-  if (__builtin_fma(-q, m.L, t) < 0.0) {
-    q -= 1.0;
-  } else if (__builtin_fma(-(q + 1.0), m.L, t) >= 0.0) {
-    q += 1.0;
+  int32_t i;
+  bool ok;
+  if (m.mode == kMeshPow2Ratio) {
+    ok = __builtin_fabsf(p) < m.twoLf;
+    i = ok ? (int32_t)__builtin_floorf(p * m.Rf) : 0;
+  } else if (m.mode == kMeshExactRatio) {
+    const double x = (double)p;
+    ok = __builtin_fabs(x) < m.twoL;
+    i = ok ? (int32_t)__builtin_floor(x * m.R) : 0;
+  } else {
+    const double x = (double)p;
+    ok = __builtin_fabs(x) < m.twoL;
+    const double t = x * m.Gd;
+    const double q = __builtin_floor(t * m.invL);
+    const double r0 = __builtin_fma(-q, m.L, t);
+    const double r1 = __builtin_fma(-(q + 1.0), m.L, t);
+    i = ok ? (int32_t)q : 0;  // in [-2G, 2G)
+    i += (r1 >= 0.0) ? 1 : 0;
+    i -= (r0 < 0.0) ? 1 : 0;
   }
-  int32_t i = (int32_t)q;          // in [-2G, 2G)
-  if (i < 0) i += m.G;
-  if (i < 0) i += m.G;
-  if (i >= m.G) i -= m.G;
+  i += (i < 0) ? m.G : 0;
+  i += (i < 0) ? m.G : 0;
+  i -= (i >= m.G) ? m.G : 0;
   out = i;
-  return true;
+  return ok;
 }
 
 // Cell key (ix * G + iy) * G + iz of one particle; false if it is outside the domain.
 __device__ __forceinline__ bool cell_key(float x, float y, float z, const Mesh& m, uint64_t& key) {
-  int32_t ix = 0, iy = 0, iz = 0;
+  int32_t ix, iy, iz;
   const bool ok = (int)cell_index(x, m, ix) & (int)cell_index(y, m, iy) & (int)cell_index(z, m, iz);
   const uint32_t xy = (uint32_t)ix * (uint32_t)m.G + (uint32_t)iy;  // < G^2 <= 2^32
   key = (uint64_t)xy * (uint64_t)(uint32_t)m.G + (uint64_t)(uint32_t)iz;
@@ -77,31 +102,78 @@ __device__ __forceinline__ uint32_t row_hash(const uint32_t* __restrict__ tab_r,
   return h;
 }
 
-// Tabulated words of rows 0..DP-1 from row-interleaved tables Ti[c][v][DP] (DP = 4 or 8,
-// 16-byte aligned rows): two (or one) 16-byte reads per key byte give every row at once.
+// Row words of rows 0..DP-1 from row-interleaved tables Ti[c][v][DP] (DP = 4, 6 or 8),
+// read with 16-byte (DP = 4, 8) or 8-byte (DP = 6) LDS loads.  Only key bytes below
+// `nch` are looked up; stage_tables() folds the constant contribution of the other
+// bytes (always 0 for keys < G^3 <= 2^(8 nch)) into the entries of byte nch - 1.
 template <int DP>
-__device__ __forceinline__ void row_hashes(const uint32_t* __restrict__ ti, uint64_t key, uint32_t (&h)[DP]) {
+__device__ __forceinline__ void row_hashes(const uint32_t* __restrict__ ti, uint64_t key, uint32_t nch,
+                                           uint32_t (&h)[DP]) {
   const uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
   const uint32_t byte[kChars] = {lo & 255u, (lo >> 8) & 255u, (lo >> 16) & 255u, lo >> 24, hi & 255u, (hi >> 8) & 255u};
 #pragma unroll
   for (int r = 0; r < DP; ++r) h[r] = 0;
 #pragma unroll
   for (int c = 0; c < kChars; ++c) {
-    const uint4* e = (const uint4*)(ti + (c * 256 + byte[c]) * DP);
+    if ((uint32_t)c < nch) {
+      const uint32_t* e = ti + (c * 256 + byte[c]) * DP;
+      if (DP % 4 == 0) {
 #pragma unroll
-    for (int q = 0; q < DP / 4; ++q) {
-      const uint4 v = e[q];
-      h[4 * q + 0] ^= v.x;
-      h[4 * q + 1] ^= v.y;
-      h[4 * q + 2] ^= v.z;
-      h[4 * q + 3] ^= v.w;
+        for (int q = 0; q < DP / 4; ++q) {
+          const uint4 v = ((const uint4*)e)[q];
+          h[4 * q + 0] ^= v.x;
+          h[4 * q + 1] ^= v.y;
+          h[4 * q + 2] ^= v.z;
+          h[4 * q + 3] ^= v.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < DP / 2; ++q) {
+          const uint2 v = ((const uint2*)e)[q];
+          h[2 * q + 0] ^= v.x;
+          h[2 * q + 1] ^= v.y;
+        }
+      }
     }
   }
 }
 
-// Bucket hash: low 31 bits scaled onto [0, w).
+// Number of key bytes that can be non-zero for a mesh of G cells per side.
+__host__ __device__ __forceinline__ uint32_t key_chars(int32_t G) {
+  const uint64_t top = (uint64_t)G * (uint64_t)G * (uint64_t)G;  // keys are < G^3
+  uint32_t n = 1;
+  while (n < (uint32_t)kChars && ((top - 1) >> (8 * n)) != 0) ++n;
+  return n;
+}
+
+// Copy the interleaved tables into LDS; entries of byte nch - 1 absorb the XOR of the
+// value-0 entries of bytes nch..5.  Ends with a barrier.
+template <int DP>
+__device__ __forceinline__ void stage_tables(uint32_t* ti, const uint32_t* __restrict__ src, uint32_t nch) {
+  for (uint32_t i = threadIdx.x; i < (uint32_t)(kTableWords * DP); i += blockDim.x) {
+    uint32_t v = src[i];
+    const uint32_t c = i / (256 * DP);
+    if (c == nch - 1) {
+      const uint32_t r = i % DP;
+      for (uint32_t c2 = nch; c2 < (uint32_t)kChars; ++c2) v ^= src[(c2 * 256) * DP + r];
+    }
+    ti[i] = v;
+  }
+  __syncthreads();
+}
+
+template <int D>
+struct RowPad {
+  static constexpr int value = (D <= 4) ? 4 : (D <= 6 ? 6 : 8);
+};
+
+// Bucket hash: low 31 bits scaled onto [0, w), i.e. floor(h31 * w / 2^31), taken as the
+// high word of (h31 << 1) * w.  For w = 2^lw (lw_shift = 32 - lw) it is a plain shift.
 __device__ __forceinline__ uint32_t bucket_of(uint32_t h, uint32_t w) {
-  return (uint32_t)(((uint64_t)(h & 0x7FFFFFFFu) * (uint64_t)w) >> 31);
+  return __umulhi(h << 1, w);
+}
+__device__ __forceinline__ uint32_t bucket_of(uint32_t h, uint32_t w, uint32_t lw_shift) {
+  return lw_shift ? (h << 1) >> lw_shift : __umulhi(h << 1, w);
 }
 
 // Lower median (index floor((d-1)/2) of the ascending order) of v[0..d), d <= MAXD,

@@ -25,9 +25,10 @@ struct SelState {
 struct Tables {
   const uint32_t* tab;  // [d][6][256] uint32, device
   const uint32_t* tabi; // row-interleaved [6][256][dp] uint32 (d <= 8), device
-  uint32_t dp;          // 4 (d <= 4) or 8 (d <= 8); 0 when d > 8
+  uint32_t dp;          // 4 (d <= 4), 6 (d <= 6) or 8 (d <= 8); 0 when d > 8
   uint32_t d;
   uint32_t w;
+  uint32_t wshift;      // 32 - log2(w) when w is a power of two >= 2, else 0
   uint32_t cm;          // 1: Count-Min (no sign, minimum), 0: Count Sketch
 };
 
@@ -46,8 +47,10 @@ struct BinPlan {
 
 constexpr int kBin2Threads = 1024;                 // row-interleaved bin kernel
 // particles per thread per tile: all d tokens of each stay in registers
-constexpr int bin2_ppt(int d) { return d <= 5 ? 8 : 4; }
+constexpr int bin2_ppt(int d) { return d == 1 ? 16 : (d == 2 ? 12 : (d <= 5 ? 8 : 4)); }
+constexpr int kBin2Rows = 2;                       // rows sorted per LDS pass
 constexpr int kCollectThreads = 1024;
+constexpr int kCollectCache = 1024;               // per-workgroup cache of inserted keys
 constexpr int kBinThreads = 512;
 constexpr int kBinPPT = 16;                       // particles per thread per tile
 constexpr int kBinTile = kBinThreads * kBinPPT;   // 8192

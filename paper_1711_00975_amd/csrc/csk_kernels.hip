@@ -120,7 +120,7 @@ struct BinArgs {
   Mesh mesh;
   const uint32_t* __restrict__ tab;
   const uint32_t* __restrict__ tabi;
-  uint32_t d, w, cm;
+  uint32_t d, w, wshift, cm;
   BinPlan plan;
   uint16_t* __restrict__ tok;
   uint32_t* __restrict__ cnt;
@@ -216,46 +216,52 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
 // ------------------------------------------------------------------ bin (d <= 8)
 
 // Row-interleaved variant for d <= 8: every row word of a particle comes from one
-// pass over the six key bytes, all d tokens of a tile stay in registers, and each
-// row is counting-sorted in LDS while the previous row's runs are written out.
-// LDS layout (words): Ti [1536 * DP] | dst (u64) [Pr] | cursor [P] | hist [Pr] |
-// base [Pr] | lim [Pr] | stage [tile] | wsum [NW].
+// pass over the key bytes, all d tokens of a tile stay in registers, and the rows
+// are counting-sorted in LDS two at a time (bin = row-in-pass * Pr + slice) while the
+// previous pass's runs are written out.  A run that would overflow its region goes
+// to the counters through atomics instead (same sum), flagged by the top bit of dst.
+// LDS layout (words): Ti [1536 * DP] | dst (u64) [RP * Pr] | cursor [P] |
+// hist [RP * Pr] | base [RP * Pr] | stage [RP * tile] | wsum [NW].
+constexpr uint64_t kDstOverflow = 1ull << 63;
+constexpr uint64_t kDstBias = 1ull << 62;   // keeps region + cursor - base positive
+
 template <int D>
 __global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
-  constexpr int DP = (D <= 4) ? 4 : 8;
-  constexpr int NT = kBin2Threads, PPT = bin2_ppt(D), TILE = NT * PPT, NW = NT / 64;
+  constexpr int DP = RowPad<D>::value;
+  constexpr int NT = kBin2Threads, PPT = bin2_ppt(D), TILE = NT * PPT, NW = NT / 64, RP = kBin2Rows;
   extern __shared__ __align__(16) uint32_t lds2[];
   const BinPlan& pl = a.plan;
+  const uint32_t nbins = RP * pl.Pr;
   uint32_t* ti = lds2;
   uint64_t* dst = (uint64_t*)(ti + kTableWords * DP);
-  uint32_t* cursor = (uint32_t*)(dst + pl.Pr);
+  uint32_t* cursor = (uint32_t*)(dst + nbins);
   uint32_t* hist = cursor + pl.P;
-  uint32_t* base = hist + pl.Pr;
-  uint32_t* lim = base + pl.Pr;
-  uint32_t* stage = lim + pl.Pr;
-  uint32_t* wsum = stage + TILE;
+  uint32_t* base = hist + nbins;
+  uint32_t* stage = base + nbins;
+  uint32_t* wsum = stage + RP * TILE;
   const uint32_t tid = threadIdx.x, g = blockIdx.x, wave = tid >> 6;
 
-  for (uint32_t i = tid; i < (uint32_t)(kTableWords * DP); i += NT) ti[i] = a.tabi[i];
   for (uint32_t i = tid; i < pl.P; i += NT) cursor[i] = 0;
-  for (uint32_t i = tid; i < pl.Pr; i += NT) hist[i] = 0;
-  __syncthreads();
+  for (uint32_t i = tid; i < nbins; i += NT) hist[i] = 0;
+  stage_tables<DP>(ti, a.tabi, a.mesh.nch);
 
-  const uint32_t per = (pl.Pr + NT - 1) / NT;          // scan: bins per thread
-  const uint32_t blo = min(pl.Pr, tid * per), bhi = min(pl.Pr, blo + per);
-  bool pending = false;                                  // a sorted row waits in stage
-  uint32_t pend_row = 0, pend_total = 0;
+  const uint32_t per = (nbins + NT - 1) / NT;           // scan: bins per thread
+  const uint32_t blo = min(nbins, tid * per), bhi = min(nbins, blo + per);
+  bool pending = false;                                  // a sorted pass waits in stage
+  uint32_t pend_row0 = 0, pend_total = 0;
 
   auto write_out = [&]() {
     for (uint32_t q = tid; q < pend_total; q += NT) {
       const uint32_t v = stage[q];
-      const uint32_t sl = v >> 16;
-      if (q < lim[sl]) {
-        a.tok[dst[sl] + q] = (uint16_t)(v & 0xFFFFu);
+      const uint64_t dq = dst[v >> 16];
+      if (!(dq & kDstOverflow)) {
+        a.tok[dq - kDstBias + q] = (uint16_t)(v & 0xFFFFu);
       } else {
         // region full: add this one update straight to the counter (rare; same sum)
+        const uint32_t bin = v >> 16;
+        const uint32_t r = pend_row0 + bin / pl.Pr, sl = bin % pl.Pr;
         const uint32_t bkt = (sl << kSliceBits) | (v & (kSlice - 1));
-        atomicAdd(&a.M[(uint64_t)pend_row * a.w + bkt], (v & 0x8000u) ? -1 : 1);
+        atomicAdd(&a.M[(uint64_t)r * a.w + bkt], (v & 0x8000u) ? -1 : 1);
       }
     }
   };
@@ -275,10 +281,10 @@ __global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
         if (cell_key(a.pos[3 * i], a.pos[3 * i + 1], a.pos[3 * i + 2], a.mesh, key)) {
           valid |= 1u << j;
           uint32_t h[DP];
-          row_hashes<DP>(ti, key, h);
+          row_hashes<DP>(ti, key, a.mesh.nch, h);
 #pragma unroll
           for (int r = 0; r < D; ++r) {
-            const uint32_t b = bucket_of(h[r], a.w);
+            const uint32_t b = bucket_of(h[r], a.w, a.wshift);
             const uint32_t neg = (h[r] >> 31) & (a.cm ^ 1u);
             sv[r][j] = ((b >> kSliceBits) << 16) | (b & (kSlice - 1)) | (neg << 15);
           }
@@ -290,12 +296,18 @@ __global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
     if (bad) atomicOr(a.err, kErrDomain);
 
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
+    for (int r0 = 0; r0 < D; r0 += RP) {
+      const int nr = (D - r0 < RP) ? D - r0 : RP;
       if (pending) write_out();
-      uint32_t rk[PPT];
+      uint32_t rk[RP][PPT];
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) rk[j] = (valid & (1u << j)) ? atomicAdd(&hist[sv[r][j] >> 16], 1u) : 0u;
-      __syncthreads();  // counts complete; the previous row is written out
+      for (int rr = 0; rr < RP; ++rr)
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+          rk[rr][j] = (rr < nr && (valid & (1u << j)))
+                          ? atomicAdd(&hist[rr * pl.Pr + (sv[r0 + rr < D ? r0 + rr : 0][j] >> 16)], 1u)
+                          : 0u;
+      __syncthreads();  // counts complete; the previous pass is written out
       uint32_t cnt_local = 0;
       for (uint32_t b = blo; b < bhi; ++b) cnt_local += hist[b];
       const uint32_t incl = wave_incl_scan(cnt_local);
@@ -307,28 +319,37 @@ __global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
         if (w2 < (int)wave) run += x;
         total += x;
       }
-      const uint64_t slice0 = (uint64_t)r * pl.Pr;
+      const uint64_t slice0 = (uint64_t)r0 * pl.Pr;
       for (uint32_t b = blo; b < bhi; ++b) {
         const uint32_t hb = hist[b];
-        const uint32_t cur = cursor[slice0 + b];
-        base[b] = run;
-        dst[b] = ((slice0 + b) * pl.nwg + g) * (uint64_t)pl.cap + cur - run;
-        lim[b] = run + (cur < pl.cap ? pl.cap - cur : 0u);
-        cursor[slice0 + b] = cur + hb;
         hist[b] = 0;
+        if (b < (uint32_t)nr * pl.Pr) {
+          const uint32_t cur = cursor[slice0 + b];
+          base[b] = run;
+          if ((uint64_t)cur + hb <= pl.cap) {
+            dst[b] = ((slice0 + b) * pl.nwg + g) * (uint64_t)pl.cap + cur + kDstBias - run;
+            cursor[slice0 + b] = cur + hb;
+          } else {
+            dst[b] = kDstOverflow;
+          }
+        }
         run += hb;
       }
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        if (valid & (1u << j)) {
-          const uint32_t v = sv[r][j];
-          stage[base[v >> 16] + rk[j]] = v;
+      for (int rr = 0; rr < RP; ++rr) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+          if (rr < nr && (valid & (1u << j))) {
+            const uint32_t v = sv[r0 + rr < D ? r0 + rr : 0][j];
+            const uint32_t bin = rr * pl.Pr + (v >> 16);
+            stage[base[bin] + rk[rr][j]] = (bin << 16) | (v & 0xFFFFu);
+          }
         }
       }
       __syncthreads();
       pending = true;
-      pend_row = (uint32_t)r;
+      pend_row0 = (uint32_t)r0;
       pend_total = total;
     }
   }
@@ -345,9 +366,10 @@ bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& p) {
   if (p.Pr > kMaxSlicesPerRow || p.ntiles == 0) return false;
   uint64_t words;
   if (p.fast) {
-    const uint32_t dp = (d <= 4) ? 4u : 8u;
+    const uint32_t dp = (d <= 4) ? 4u : (d <= 6 ? 6u : 8u);
     p.tab_rows_lds = 0;
-    words = (uint64_t)kTableWords * dp + 2ull * p.Pr + p.P + 3ull * p.Pr + p.tile + kBin2Threads / 64;
+    const uint64_t nb = (uint64_t)kBin2Rows * p.Pr;
+    words = (uint64_t)kTableWords * dp + 2 * nb + p.P + 2 * nb + (uint64_t)kBin2Rows * p.tile + kBin2Threads / 64;
   } else {
     p.tab_rows_lds = 0;
     words = (uint64_t)p.P + 2ull * p.Pr + kBinTile + kBinThreads / 64 + 1;
@@ -377,6 +399,7 @@ hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
   a.tab = t.tab;
   a.d = t.d;
   a.w = t.w;
+  a.wshift = t.wshift;
   a.cm = t.cm;
   a.plan = plan;
   a.tok = tok;
@@ -614,15 +637,16 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
                                                                    uint64_t* set, uint32_t slot_mask,
                                                                    uint32_t* set_count, uint32_t max_cand,
                                                                    uint32_t* err) {
-  constexpr int DP = (D <= 4) ? 4 : 8;
+  constexpr int DP = RowPad<D>::value;
   extern __shared__ __align__(16) uint32_t lds3[];
   uint32_t* ti = lds3;
-  uint32_t* filt = ti + kTableWords * DP;
-  for (uint32_t i = threadIdx.x; i < (uint32_t)(kTableWords * DP); i += blockDim.x) ti[i] = t.tabi[i];
+  uint64_t* cache = (uint64_t*)(ti + kTableWords * DP);   // kCollectCache keys
+  uint32_t* filt = (uint32_t*)(cache + kCollectCache);
   const bool uf = use_filter && (*hot <= kFilterMaxItems);
   if (uf)
     for (uint32_t i = threadIdx.x; i < (uint32_t)kFilterWords; i += blockDim.x) filt[i] = filter[i];
-  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kCollectCache; i += blockDim.x) cache[i] = kEmptyKey;
+  stage_tables<DP>(ti, t.tabi, mesh.nch);
   constexpr uint32_t kNeedCS = D - ((D - 1) >> 1);
   const uint32_t need = t.cm ? (uint32_t)D : kNeedCS;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -634,22 +658,27 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
       continue;
     }
     uint32_t h[DP];
-    row_hashes<DP>(ti, key, h);
+    row_hashes<DP>(ti, key, mesh.nch, h);
     uint32_t bk[D], ng[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-      bk[r] = bucket_of(h[r], t.w);
+      bk[r] = bucket_of(h[r], t.w, t.wshift);
       ng[r] = (h[r] >> 31) & (t.cm ^ 1u);
     }
     if (uf) {
+      // rows read until the verdict is certain: at most need + (D - need) probes
       uint32_t fp = 0;
 #pragma unroll
       for (int r = 0; r < D; ++r) {
+        if (fp >= need || fp + (uint32_t)(D - r) < need) break;
         const FilterProbe pr = filter_probe((uint32_t)r, bk[r], ng[r]);
         fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
       }
       if (fp < need) continue;
     }
+    // a key inserted recently by this workgroup needs neither the exact test nor the set
+    const uint32_t ci = (uint32_t)(key ^ (key >> 21)) & (kCollectCache - 1);
+    if (__hip_atomic_load(&cache[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == key) continue;
     uint32_t pass = 0;
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -657,7 +686,10 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
       const uint32_t c = (uint32_t)M[(uint64_t)r * t.w + bk[r]];
       if ((int32_t)(ng[r] ? 0u - c : c) >= theta) ++pass;
     }
-    if (pass >= need) set_insert(set, slot_mask, key, set_count, max_cand, err);
+    if (pass >= need) {
+      set_insert(set, slot_mask, key, set_count, max_cand, err);
+      __hip_atomic_store(&cache[ci], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
   }
   if (bad) atomicOr(err, kErrDomain);
 }
@@ -706,7 +738,8 @@ hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const 
                           hipStream_t s) {
   if (t.d <= (uint32_t)kTabLdsRows) {
     const uint32_t use_filter = (filter != nullptr && hot != nullptr) ? 1u : 0u;
-    const size_t lds = ((size_t)kTableWords * t.dp + (use_filter ? kFilterWords : 0)) * sizeof(uint32_t);
+    const size_t lds = ((size_t)kTableWords * t.dp + 2 * kCollectCache + (use_filter ? kFilterWords : 0)) *
+                       sizeof(uint32_t);
     const dim3 grid(grid_for(n, kCollectThreads, 512)), block(kCollectThreads);
 #define CSK_COLLECT2(DD)                                                                                   \
   hipLaunchKernelGGL(collect2_kernel<DD>, grid, block, lds, s, pos, n, mesh, t, M, theta, filter, hot, use_filter, \

@@ -14,7 +14,10 @@ import paper_1711_00975_amd as csk
 
 pytestmark = pytest.mark.gpu
 
-MESHES = [(100.0, 0.1), (1000.0, 0.25), (3000.0, 0.25), (3000.0, 0.5), (3000.0, 1.0)]
+# (L, delta): exact G/L = 10 (binary64 path), G/L = 4, 2, 1 (binary32 path), and two
+# meshes whose G/L is not exact (floor estimate + fma residual path)
+MESHES = [(100.0, 0.1), (1000.0, 0.25), (3000.0, 0.25), (3000.0, 0.5), (3000.0, 1.0), (7.0, 0.7),
+          (123.456, 0.123456)]
 
 
 def torch():
@@ -78,11 +81,11 @@ def test_cell_keys_match_oracle(L, delta):
     assert np.all(keys[~ok] == np.uint64(0xFFFFFFFFFFFFFFFF))
 
 
-def test_cell_keys_exhaustive_float_sweep():
-    # every float32 in [0, L] for the 100 Mpc/h box with 0.1 Mpc/h cells, as all three
-    # coordinates at once, against the oracle's exact-rational floor
+@pytest.mark.parametrize("L,delta", [(100.0, 0.1), (1000.0, 0.25), (7.0, 0.7)])
+def test_cell_keys_exhaustive_float_sweep(L, delta):
+    # every float32 in [0, L], as all three coordinates at once, against the oracle's
+    # exact-rational floor (one mesh per way the kernels compute the floor)
     from concurrent.futures import ThreadPoolExecutor
-    L, delta = 100.0, 0.1
     G = oracle.grid(delta, L)
     top = struct.unpack("I", struct.pack("f", L))[0]
     batch = 1 << 25
@@ -133,6 +136,8 @@ CASES = [
     (40_000, 32, 777, 100.0, 0.1, 13, 0),
     (70_000, 6, 50_000, 1000.0, 0.25, 16, 0),
     (70_000, 3, 1 << 18, 1000.0, 0.25, 17, 0),
+    (90_000, 5, 1 << 16, 7.0, 0.7, 18, 0),
+    (90_000, 5, 3333, 123.456, 0.123456, 19, 0),
     (100_000, 5, 1 << 16, 100.0, 0.1, 14, 1),
     (100_000, 7, 999, 3000.0, 0.5, 15, 1),
 ]
