@@ -81,6 +81,7 @@ struct csk_sketch {
   uint32_t* tabi = nullptr;  // row-interleaved tables (d <= 8)
   uint32_t dp = 0;
   uint32_t* filter = nullptr; // Bloom filter of hot items + [kFilterWords] item count
+  uint32_t* hot_table = nullptr; // exact set of hot items (kHotSlots words)
   uint64_t* set = nullptr;
   uint32_t slots = 0;
   uint32_t max_cand = 0;
@@ -130,7 +131,7 @@ hipError_t dmalloc(csk_sketch* s, T** p, uint64_t count) {
 }
 
 void free_all(csk_sketch* s) {
-  void* ptrs[] = {s->M, s->tab, s->tabi, s->filter, s->set, s->ctl, s->sel, s->cand_key, s->cand_est, s->sel_key, s->sel_est,
+  void* ptrs[] = {s->M, s->tab, s->tabi, s->filter, s->hot_table, s->set, s->ctl, s->sel, s->cand_key, s->cand_est, s->sel_key, s->sel_est,
                   s->tok, s->cnt};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -235,6 +236,8 @@ csk_status csk_sketch_init_ex(csk_sketch** out, uint32_t d, uint32_t w, uint64_t
   if (e == hipSuccess) e = dmalloc(s, &s->tab, T.size());
   if (e == hipSuccess && s->dp) e = dmalloc(s, &s->tabi, Ti.size());
   if (e == hipSuccess && s->dp) e = dmalloc(s, &s->filter, (uint64_t)kFilterWords + 1);
+  // items pack the bucket in 28 bits, so the exact hot set needs w < 2^28
+  if (e == hipSuccess && s->dp && w < (1u << 28)) e = dmalloc(s, &s->hot_table, (uint64_t)kHotSlots);
   if (e == hipSuccess) e = dmalloc(s, &s->set, slots);
   if (e == hipSuccess) e = dmalloc(s, &s->ctl, 4);
   if (e == hipSuccess) e = dmalloc(s, &s->sel, 1);
@@ -350,12 +353,13 @@ csk_status csk_collect(csk_sketch* s, const float* pos, uint64_t n, double delta
   const uint32_t* filter = nullptr;
   const uint32_t* hot = nullptr;
   if (s->filter != nullptr && theta > 0) {
-    CSK_HIP(launch_filter_build(t, s->M, theta, s->filter, s->filter + kFilterWords, st), "collect (filter)");
+    CSK_HIP(launch_filter_build(t, s->M, theta, s->filter, s->filter + kFilterWords, s->hot_table, st),
+            "collect (filter)");
     filter = s->filter;
     hot = s->filter + kFilterWords;
   }
-  CSK_HIP(launch_collect(pos, n, mesh, t, s->M, theta, filter, hot, s->set, s->slots - 1, s->set_count(),
-                         s->max_cand, s->err(), st),
+  CSK_HIP(launch_collect(pos, n, mesh, t, s->M, theta, filter, hot, filter ? s->hot_table : nullptr, s->set,
+                         s->slots - 1, s->set_count(), s->max_cand, s->err(), st),
           "collect");
   return CSK_OK;
 }

@@ -18,6 +18,9 @@ constexpr uint64_t kEmptyKey = ~0ull;  // empty slot of the candidate set / inva
 constexpr int kTabLdsRows = 8;         // rows whose tables are staged in LDS
 constexpr int kFilterWords = 24576;    // LDS Bloom filter of hot (row, bucket, sign): 96 KiB
 constexpr uint32_t kFilterMaxItems = kFilterWords * 32 / 6;  // denser filters are not used
+constexpr uint32_t kHotSlots = 1u << 19;   // exact set of hot items: 2 MiB, stays in L2
+constexpr uint32_t kHotMaxItems = kHotSlots / 2;
+constexpr uint32_t kHotEmpty = 0xFFFFFFFFu;
 
 // error latch bits (device word)
 constexpr uint32_t kErrDomain = 1u;
@@ -52,13 +55,14 @@ constexpr uint32_t kMeshPow2Ratio = 2;
 // fma residuals t - q*L and t - (q+1)*L equal the signs of the exact ones and move q
 // to the floor.  Branch-free; the result is meaningful only when it returns true
 // (p finite and |p| < 2L).
-__device__ __forceinline__ bool cell_index(float p, const Mesh& m, int32_t& out) {
+template <uint32_t MODE>
+__device__ __forceinline__ bool cell_index_m(float p, const Mesh& m, int32_t& out) {
   int32_t i;
   bool ok;
-  if (m.mode == kMeshPow2Ratio) {
+  if (MODE == kMeshPow2Ratio) {
     ok = __builtin_fabsf(p) < m.twoLf;
     i = ok ? (int32_t)__builtin_floorf(p * m.Rf) : 0;
-  } else if (m.mode == kMeshExactRatio) {
+  } else if (MODE == kMeshExactRatio) {
     const double x = (double)p;
     ok = __builtin_fabs(x) < m.twoL;
     i = ok ? (int32_t)__builtin_floor(x * m.R) : 0;
@@ -78,6 +82,22 @@ __device__ __forceinline__ bool cell_index(float p, const Mesh& m, int32_t& out)
   i -= (i >= m.G) ? m.G : 0;
   out = i;
   return ok;
+}
+
+template <uint32_t MODE>
+__device__ __forceinline__ bool cell_key_m(float x, float y, float z, const Mesh& m, uint64_t& key) {
+  int32_t ix, iy, iz;
+  const bool ok = (int)cell_index_m<MODE>(x, m, ix) & (int)cell_index_m<MODE>(y, m, iy) &
+                  (int)cell_index_m<MODE>(z, m, iz);
+  const uint32_t xy = (uint32_t)ix * (uint32_t)m.G + (uint32_t)iy;  // < G^2 <= 2^32
+  key = (uint64_t)xy * (uint64_t)(uint32_t)m.G + (uint64_t)(uint32_t)iz;
+  return ok;
+}
+
+__device__ __forceinline__ bool cell_index(float p, const Mesh& m, int32_t& out) {
+  if (m.mode == kMeshPow2Ratio) return cell_index_m<kMeshPow2Ratio>(p, m, out);
+  if (m.mode == kMeshExactRatio) return cell_index_m<kMeshExactRatio>(p, m, out);
+  return cell_index_m<kMeshGeneral>(p, m, out);
 }
 
 // Cell key (ix * G + iy) * G + iz of one particle; false if it is outside the domain.
@@ -218,6 +238,21 @@ __device__ __forceinline__ uint64_t slot_mix(uint64_t k) {
 
 // Probe of the filter for the item (row r, bucket b, sign bit neg): fmix32 of the item,
 // word index from its high bits, three bit positions from a second multiply.
+// Hot item (row r < 8, bucket b < 2^28 - 1, sign bit) packed in 32 bits (never kHotEmpty).
+__device__ __forceinline__ uint32_t hot_item(uint32_t r, uint32_t b, uint32_t neg) {
+  return (r << 29) | (b << 1) | neg;
+}
+
+__device__ __forceinline__ uint32_t hot_slot(uint32_t item) {
+  uint32_t x = item;
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  x *= 0x846CA68Bu;
+  x ^= x >> 16;
+  return x & (kHotSlots - 1);
+}
+
 __device__ __forceinline__ FilterProbe filter_probe(uint32_t r, uint32_t b, uint32_t neg) {
   uint32_t x = ((b << 1) | neg) ^ (r * 0x9E3779B9u);
   x ^= x >> 16;

@@ -72,11 +72,12 @@ hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const
                         hipStream_t s);
 // Bloom filter of the (row, bucket, sign) items whose signed counter is >= theta
 // (theta > 0); filter: kFilterWords words, hot: item count (both zeroed here).
+// hot_table (kHotSlots words, may be NULL) receives the items exactly while they fit.
 hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta, uint32_t* filter, uint32_t* hot,
-                               hipStream_t s);
+                               uint32_t* hot_table, hipStream_t s);
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,
-                          int32_t theta, const uint32_t* filter, const uint32_t* hot, uint64_t* set,
-                          uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
+                          int32_t theta, const uint32_t* filter, const uint32_t* hot, const uint32_t* hot_table,
+                          uint64_t* set, uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
                           hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);

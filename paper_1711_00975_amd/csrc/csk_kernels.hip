@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
         const uint32_t sl = v >> 16;
         const uint32_t c = cursor[region_row + sl] + (q - base[sl]);
         if (c < pl.cap) {
-          a.tok[((region_row + sl) * pl.nwg + g) * (uint64_t)pl.cap + c] = (uint16_t)(v & 0xFFFFu);
+          a.tok[((uint64_t)g * pl.P + region_row + sl) * (uint64_t)pl.cap + c] = (uint16_t)(v & 0xFFFFu);
         } else {
           // region full: add this one update straight to the counter (rare; same sum)
           const uint32_t bkt = (sl << kSliceBits) | (v & (kSlice - 1));
@@ -215,31 +215,36 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
 
 // ------------------------------------------------------------------ bin (d <= 8)
 
-// Row-interleaved variant for d <= 8: every row word of a particle comes from one
-// pass over the key bytes, all d tokens of a tile stay in registers, and the rows
-// are counting-sorted in LDS two at a time (bin = row-in-pass * Pr + slice) while the
-// previous pass's runs are written out.  A run that would overflow its region goes
-// to the counters through atomics instead (same sum), flagged by the top bit of dst.
-// LDS layout (words): Ti [1536 * DP] | dst (u64) [RP * Pr] | cursor [P] |
-// hist [RP * Pr] | base [RP * Pr] | stage [RP * tile] | wsum [NW].
-constexpr uint64_t kDstOverflow = 1ull << 63;
-constexpr uint64_t kDstBias = 1ull << 62;   // keeps region + cursor - base positive
+// Row-interleaved variant for d <= 8 (MODE: how the mesh computes its floor).  Every row
+// word of a particle comes from one pass over the key bytes; all d tokens of a tile stay
+// in registers; rows are counting-sorted in LDS two at a time (bin = row-in-pass * Pr +
+// slice) while the previous pass's runs are written out.  Tokens of particles outside
+// the stream or the domain go to a dummy bin that is never written.  A run that would
+// overflow its region goes to the counters through atomics instead (same sum).
+// Token scratch is workgroup-major: region (g, s) starts at (g * P + s) * cap.
+// LDS layout (words): Ti [1536 * DP] | dst [RP*Pr + 1] | cursor [P] | hist [RP*Pr + 1] |
+// base [RP*Pr + 1] | stage [RP * tile] | wsum [NW].
+constexpr uint32_t kDstDrop = 0xFFFFFFFFu;      // dummy bin: never written
+constexpr uint32_t kDstOverflow = 0xFFFFFFFEu;  // run added with atomics
+constexpr uint32_t kDstBias = 1u << 16;         // keeps offset + cursor - base positive
 
-template <int D>
-__global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
+template <int D, uint32_t MODE>
+__global__ __launch_bounds__(kBin2Threads) void bin3_kernel(BinArgs a) {
   constexpr int DP = RowPad<D>::value;
   constexpr int NT = kBin2Threads, PPT = bin2_ppt(D), TILE = NT * PPT, NW = NT / 64, RP = kBin2Rows;
   extern __shared__ __align__(16) uint32_t lds2[];
   const BinPlan& pl = a.plan;
-  const uint32_t nbins = RP * pl.Pr;
+  const uint32_t nbins = RP * pl.Pr + 1;                 // + the dummy bin
+  const uint32_t dummy = nbins - 1;
   uint32_t* ti = lds2;
-  uint64_t* dst = (uint64_t*)(ti + kTableWords * DP);
-  uint32_t* cursor = (uint32_t*)(dst + nbins);
+  uint32_t* dst = ti + kTableWords * DP;
+  uint32_t* cursor = dst + nbins;
   uint32_t* hist = cursor + pl.P;
   uint32_t* base = hist + nbins;
   uint32_t* stage = base + nbins;
   uint32_t* wsum = stage + RP * TILE;
   const uint32_t tid = threadIdx.x, g = blockIdx.x, wave = tid >> 6;
+  uint16_t* __restrict__ tokg = a.tok + (uint64_t)g * pl.P * pl.cap;   // this workgroup's regions
 
   for (uint32_t i = tid; i < pl.P; i += NT) cursor[i] = 0;
   for (uint32_t i = tid; i < nbins; i += NT) hist[i] = 0;
@@ -253,10 +258,10 @@ __global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
   auto write_out = [&]() {
     for (uint32_t q = tid; q < pend_total; q += NT) {
       const uint32_t v = stage[q];
-      const uint64_t dq = dst[v >> 16];
-      if (!(dq & kDstOverflow)) {
-        a.tok[dq - kDstBias + q] = (uint16_t)(v & 0xFFFFu);
-      } else {
+      const uint32_t dq = dst[v >> 16];
+      if (dq < kDstOverflow) {
+        tokg[dq - kDstBias + q] = (uint16_t)(v & 0xFFFFu);
+      } else if (dq == kDstOverflow) {
         // region full: add this one update straight to the counter (rare; same sum)
         const uint32_t bin = v >> 16;
         const uint32_t r = pend_row0 + bin / pl.Pr, sl = bin % pl.Pr;
@@ -268,17 +273,20 @@ __global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
 
   for (uint64_t tile = g; tile < pl.ntiles; tile += pl.nwg) {
     const uint64_t first = tile * (uint64_t)TILE;
+    const bool full = first + TILE <= a.n;
     uint32_t sv[D][PPT];
     uint32_t valid = 0;
-    bool bad = false;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const uint64_t i = first + (uint64_t)j * NT + tid;
 #pragma unroll
       for (int r = 0; r < D; ++r) sv[r][j] = 0;
-      if (i < a.n) {
+      if (full || i < a.n) {
+        const float x = __builtin_nontemporal_load(a.pos + 3 * i);
+        const float y = __builtin_nontemporal_load(a.pos + 3 * i + 1);
+        const float z = __builtin_nontemporal_load(a.pos + 3 * i + 2);
         uint64_t key;
-        if (cell_key(a.pos[3 * i], a.pos[3 * i + 1], a.pos[3 * i + 2], a.mesh, key)) {
+        if (cell_key_m<MODE>(x, y, z, a.mesh, key)) {
           valid |= 1u << j;
           uint32_t h[DP];
           row_hashes<DP>(ti, key, a.mesh.nch, h);
@@ -288,25 +296,37 @@ __global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
             const uint32_t neg = (h[r] >> 31) & (a.cm ^ 1u);
             sv[r][j] = ((b >> kSliceBits) << 16) | (b & (kSlice - 1)) | (neg << 15);
           }
-        } else {
-          bad = true;
         }
       }
     }
-    if (bad) atomicOr(a.err, kErrDomain);
+    const uint32_t inmask = full ? ((1u << PPT) - 1u) : 0u;
+    // particles of the stream that are outside the domain latch the error
+    {
+      uint32_t inside = inmask;
+      if (!full) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) inside |= ((first + (uint64_t)j * NT + tid) < a.n ? 1u : 0u) << j;
+      }
+      if (inside & ~valid) atomicOr(a.err, kErrDomain);
+    }
 
 #pragma unroll
     for (int r0 = 0; r0 < D; r0 += RP) {
       const int nr = (D - r0 < RP) ? D - r0 : RP;
       if (pending) write_out();
-      uint32_t rk[RP][PPT];
+      static_assert(RP == 2 && RP * TILE <= 65536, "ranks are packed two per word");
+      uint32_t rk[PPT];   // rank of row r0 in the low half, of row r0 + 1 in the high half
 #pragma unroll
-      for (int rr = 0; rr < RP; ++rr)
+      for (int j = 0; j < PPT; ++j) {
+        rk[j] = 0;
 #pragma unroll
-        for (int j = 0; j < PPT; ++j)
-          rk[rr][j] = (rr < nr && (valid & (1u << j)))
-                          ? atomicAdd(&hist[rr * pl.Pr + (sv[r0 + rr < D ? r0 + rr : 0][j] >> 16)], 1u)
-                          : 0u;
+        for (int rr = 0; rr < RP; ++rr) {
+          if (rr < nr) {
+            const uint32_t bin = (valid & (1u << j)) ? rr * pl.Pr + (sv[r0 + rr < D ? r0 + rr : 0][j] >> 16) : dummy;
+            rk[j] |= atomicAdd(&hist[bin], 1u) << (16 * rr);
+          }
+        }
+      }
       __syncthreads();  // counts complete; the previous pass is written out
       uint32_t cnt_local = 0;
       for (uint32_t b = blo; b < bhi; ++b) cnt_local += hist[b];
@@ -319,19 +339,21 @@ __global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
         if (w2 < (int)wave) run += x;
         total += x;
       }
-      const uint64_t slice0 = (uint64_t)r0 * pl.Pr;
+      const uint32_t slice0 = (uint32_t)r0 * pl.Pr;
       for (uint32_t b = blo; b < bhi; ++b) {
         const uint32_t hb = hist[b];
         hist[b] = 0;
+        base[b] = run;
         if (b < (uint32_t)nr * pl.Pr) {
           const uint32_t cur = cursor[slice0 + b];
-          base[b] = run;
-          if ((uint64_t)cur + hb <= pl.cap) {
-            dst[b] = ((slice0 + b) * pl.nwg + g) * (uint64_t)pl.cap + cur + kDstBias - run;
+          if (cur + hb <= pl.cap) {
+            dst[b] = (slice0 + b) * pl.cap + cur + kDstBias - run;
             cursor[slice0 + b] = cur + hb;
           } else {
             dst[b] = kDstOverflow;
           }
+        } else {
+          dst[b] = kDstDrop;   // the dummy bin (and unused row bins of the last pass)
         }
         run += hb;
       }
@@ -340,10 +362,10 @@ __global__ __launch_bounds__(kBin2Threads) void bin2_kernel(BinArgs a) {
       for (int rr = 0; rr < RP; ++rr) {
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-          if (rr < nr && (valid & (1u << j))) {
+          if (rr < nr) {
             const uint32_t v = sv[r0 + rr < D ? r0 + rr : 0][j];
-            const uint32_t bin = rr * pl.Pr + (v >> 16);
-            stage[base[bin] + rk[rr][j]] = (bin << 16) | (v & 0xFFFFu);
+            const uint32_t bin = (valid & (1u << j)) ? rr * pl.Pr + (v >> 16) : dummy;
+            stage[base[bin] + ((rk[j] >> (16 * rr)) & 0xFFFFu)] = (bin << 16) | (v & 0xFFFFu);
           }
         }
       }
@@ -368,8 +390,8 @@ bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& p) {
   if (p.fast) {
     const uint32_t dp = (d <= 4) ? 4u : (d <= 6 ? 6u : 8u);
     p.tab_rows_lds = 0;
-    const uint64_t nb = (uint64_t)kBin2Rows * p.Pr;
-    words = (uint64_t)kTableWords * dp + 2 * nb + p.P + 2 * nb + (uint64_t)kBin2Rows * p.tile + kBin2Threads / 64;
+    const uint64_t nb = (uint64_t)kBin2Rows * p.Pr + 1;
+    words = (uint64_t)kTableWords * dp + nb + p.P + 2 * nb + (uint64_t)kBin2Rows * p.tile + kBin2Threads / 64;
   } else {
     p.tab_rows_lds = 0;
     words = (uint64_t)p.P + 2ull * p.Pr + kBinTile + kBinThreads / 64 + 1;
@@ -385,7 +407,7 @@ bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& p) {
   uint64_t cap = (per_wg * span * 13 + (uint64_t)w * 10 - 1) / ((uint64_t)w * 10) + 64;  // 1.3x mean + 64
   if (cap > per_wg) cap = per_wg;                    // a region never gets more than this
   cap = (cap + 7) & ~7ull;
-  if (cap > 0xFFFFFFF0ull) return false;
+  if ((uint64_t)p.P * cap + kDstBias >= 0x7FFFFFFFull) return false;   // 32-bit region offsets
   p.cap = (uint32_t)cap;
   return true;
 }
@@ -409,16 +431,29 @@ hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
   a.tabi = t.tabi;
   if (plan.fast) {
     const dim3 grid(plan.nwg), block(kBin2Threads);
+#define CSK_BIN3(DD)                                                                               \
+  switch (mesh.mode) {                                                                            \
+    case kMeshPow2Ratio:                                                                          \
+      hipLaunchKernelGGL((bin3_kernel<DD, kMeshPow2Ratio>), grid, block, plan.lds_bytes, s, a);   \
+      break;                                                                                      \
+    case kMeshExactRatio:                                                                         \
+      hipLaunchKernelGGL((bin3_kernel<DD, kMeshExactRatio>), grid, block, plan.lds_bytes, s, a);  \
+      break;                                                                                      \
+    default:                                                                                      \
+      hipLaunchKernelGGL((bin3_kernel<DD, kMeshGeneral>), grid, block, plan.lds_bytes, s, a);     \
+      break;                                                                                      \
+  }
     switch (t.d) {
-      case 1: hipLaunchKernelGGL(bin2_kernel<1>, grid, block, plan.lds_bytes, s, a); break;
-      case 2: hipLaunchKernelGGL(bin2_kernel<2>, grid, block, plan.lds_bytes, s, a); break;
-      case 3: hipLaunchKernelGGL(bin2_kernel<3>, grid, block, plan.lds_bytes, s, a); break;
-      case 4: hipLaunchKernelGGL(bin2_kernel<4>, grid, block, plan.lds_bytes, s, a); break;
-      case 5: hipLaunchKernelGGL(bin2_kernel<5>, grid, block, plan.lds_bytes, s, a); break;
-      case 6: hipLaunchKernelGGL(bin2_kernel<6>, grid, block, plan.lds_bytes, s, a); break;
-      case 7: hipLaunchKernelGGL(bin2_kernel<7>, grid, block, plan.lds_bytes, s, a); break;
-      default: hipLaunchKernelGGL(bin2_kernel<8>, grid, block, plan.lds_bytes, s, a); break;
+      case 1: CSK_BIN3(1); break;
+      case 2: CSK_BIN3(2); break;
+      case 3: CSK_BIN3(3); break;
+      case 4: CSK_BIN3(4); break;
+      case 5: CSK_BIN3(5); break;
+      case 6: CSK_BIN3(6); break;
+      case 7: CSK_BIN3(7); break;
+      default: CSK_BIN3(8); break;
     }
+#undef CSK_BIN3
   } else {
     hipLaunchKernelGGL(bin_kernel<false>, dim3(plan.nwg), dim3(kBinThreads), plan.lds_bytes, s, a);
   }
@@ -447,27 +482,31 @@ __global__ __launch_bounds__(kAccThreads) void accumulate_kernel(AccArgs a) {
   constexpr uint32_t U = 4;
   for (uint32_t g = wave; g < pl.nwg; g += kAccThreads / 64) {
     const uint32_t c = min(a.cnt[(uint64_t)s * pl.nwg + g], pl.cap);
-    const uint4* t4 = (const uint4*)(a.tok + ((uint64_t)s * pl.nwg + g) * (uint64_t)pl.cap);
-    const uint32_t nchunk = (c + 7) / 8;
-    for (uint32_t q0 = 0; q0 < nchunk; q0 += 64 * U) {
+    const uint16_t* reg = a.tok + ((uint64_t)g * pl.P + s) * (uint64_t)pl.cap;
+    const uint4* t4 = (const uint4*)reg;
+    const uint32_t nfull = c / 8;  // whole 16-byte chunks
+    for (uint32_t q0 = 0; q0 < nfull; q0 += 64 * U) {
       uint4 v[U];
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u) {
         const uint32_t q = q0 + u * 64 + lane;
-        v[u] = (q < nchunk) ? t4[q] : make_uint4(0, 0, 0, 0);
+        v[u] = (q < nfull) ? t4[q] : make_uint4(0, 0, 0, 0);
       }
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u) {
-        const uint32_t q = q0 + u * 64 + lane;
-        const uint32_t wds[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+        if (q0 + u * 64 + lane < nfull) {
+          const uint32_t wds[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
-        for (uint32_t e = 0; e < 8; ++e) {
-          if (q * 8 + e < c) {
+          for (uint32_t e = 0; e < 8; ++e) {
             const uint32_t tk = (wds[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
             atomicAdd(&acc[tk & (kSlice - 1)], (tk & 0x8000u) ? -1 : 1);
           }
         }
       }
+    }
+    if (lane < c - nfull * 8) {
+      const uint32_t tk = reg[nfull * 8 + lane];
+      atomicAdd(&acc[tk & (kSlice - 1)], (tk & 0x8000u) ? -1 : 1);
     }
   }
   __syncthreads();
@@ -572,6 +611,18 @@ hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const
 
 // ------------------------------------------------------------------ collect
 
+// Is key already in the candidate set?  (A stale read can only miss a key.)
+__device__ __forceinline__ bool set_contains(const uint64_t* set, uint32_t mask, uint64_t key) {
+  uint32_t i = (uint32_t)slot_mix(key) & mask;
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const uint64_t cur = set[i];
+    if (cur == key) return true;
+    if (cur == kEmptyKey) return false;
+    i = (i + 1) & mask;
+  }
+  return false;
+}
+
 __device__ __forceinline__ void set_insert(uint64_t* set, uint32_t mask, uint64_t key, uint32_t* count,
                                            uint32_t max_cand, uint32_t* err) {
   uint32_t i = (uint32_t)slot_mix(key) & mask;
@@ -634,6 +685,7 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
                                                                    Tables t, const int32_t* __restrict__ M,
                                                                    int32_t theta, const uint32_t* __restrict__ filter,
                                                                    const uint32_t* __restrict__ hot, uint32_t use_filter,
+                                                                   const uint32_t* __restrict__ hot_table,
                                                                    uint64_t* set, uint32_t slot_mask,
                                                                    uint32_t* set_count, uint32_t max_cand,
                                                                    uint32_t* err) {
@@ -642,7 +694,10 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
   uint32_t* ti = lds3;
   uint64_t* cache = (uint64_t*)(ti + kTableWords * DP);   // kCollectCache keys
   uint32_t* filt = (uint32_t*)(cache + kCollectCache);
-  const bool uf = use_filter && (*hot <= kFilterMaxItems);
+  const uint32_t nhot = use_filter ? *hot : 0xFFFFFFFFu;
+  const bool uf = use_filter && nhot <= kFilterMaxItems;
+  // the exact hot-item set replaces the counter reads when it holds every hot item
+  const bool uh = use_filter && hot_table != nullptr && nhot <= kHotMaxItems;
   if (uf)
     for (uint32_t i = threadIdx.x; i < (uint32_t)kFilterWords; i += blockDim.x) filt[i] = filter[i];
   for (uint32_t i = threadIdx.x; i < (uint32_t)kCollectCache; i += blockDim.x) cache[i] = kEmptyKey;
@@ -676,15 +731,39 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
       }
       if (fp < need) continue;
     }
-    // a key inserted recently by this workgroup needs neither the exact test nor the set
+    // a key seen recently by this workgroup, or already in the set, needs no exact test:
+    // heavy cells repeat thousands of times, and the set only ever gains keys
     const uint32_t ci = (uint32_t)(key ^ (key >> 21)) & (kCollectCache - 1);
     if (__hip_atomic_load(&cache[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == key) continue;
+    if (set_contains(set, slot_mask, key)) {
+      __hip_atomic_store(&cache[ci], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      continue;
+    }
     uint32_t pass = 0;
+    if (uh) {
+      // row r passes (sign * M >= theta) exactly when its item is in the hot set
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
-      if (pass >= need || pass + (uint32_t)(D - r) < need) break;
-      const uint32_t c = (uint32_t)M[(uint64_t)r * t.w + bk[r]];
-      if ((int32_t)(ng[r] ? 0u - c : c) >= theta) ++pass;
+      for (int r = 0; r < D; ++r) {
+        if (pass >= need || pass + (uint32_t)(D - r) < need) break;
+        const uint32_t item = hot_item((uint32_t)r, bk[r], ng[r]);
+        uint32_t sl = hot_slot(item);
+        for (uint32_t probe = 0; probe < kHotSlots; ++probe) {
+          const uint32_t v = hot_table[sl];
+          if (v == item) {
+            ++pass;
+            break;
+          }
+          if (v == kHotEmpty) break;
+          sl = (sl + 1) & (kHotSlots - 1);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        if (pass >= need || pass + (uint32_t)(D - r) < need) break;
+        const uint32_t c = (uint32_t)M[(uint64_t)r * t.w + bk[r]];
+        if ((int32_t)(ng[r] ? 0u - c : c) >= theta) ++pass;
+      }
     }
     if (pass >= need) {
       set_insert(set, slot_mask, key, set_count, max_cand, err);
@@ -695,10 +774,20 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
 }
 
 // Items (r, b, sign) with sign * M[r][b] >= theta (Count-Min: M[r][b] >= theta) go into
-// the filter; theta > 0, so empty buckets never do.
+// the Bloom filter and, while it has room, into the exact hot-item set; theta > 0, so
+// empty buckets never do.  *hot counts the items.
+__device__ __forceinline__ void hot_insert(uint32_t* table, uint32_t item) {
+  uint32_t sl = hot_slot(item);
+  for (uint32_t probe = 0; probe < kHotSlots; ++probe) {
+    const uint32_t old = atomicCAS(&table[sl], kHotEmpty, item);
+    if (old == kHotEmpty || old == item) return;
+    sl = (sl + 1) & (kHotSlots - 1);
+  }
+}
+
 __global__ __launch_bounds__(256) void filter_build_kernel(const int32_t* __restrict__ M, uint32_t d, uint32_t w,
                                                            uint32_t cm, int32_t theta, uint32_t* __restrict__ filter,
-                                                           uint32_t* __restrict__ hot) {
+                                                           uint32_t* __restrict__ hot, uint32_t* __restrict__ hot_table) {
   for (uint32_t r = 0; r < d; ++r) {
     for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < w; b0 += gridDim.x * blockDim.x) {
       const uint32_t b = b0 + threadIdx.x;
@@ -716,25 +805,31 @@ __global__ __launch_bounds__(256) void filter_build_kernel(const int32_t* __rest
         const FilterProbe pr = filter_probe(r, b, 1u);
         atomicOr(&filter[pr.word], pr.mask);
       }
-      const uint32_t items = (uint32_t)__popcll(__ballot(hp)) + (uint32_t)__popcll(__ballot(hn));
-      if ((threadIdx.x & 63u) == 0 && items) atomicAdd(hot, items);
+      // number the items of this wave; the first kHotMaxItems of the whole pass go in
+      const uint32_t first = wave_append(hot, hp);
+      const uint32_t second = wave_append(hot, hn);
+      if (hot_table != nullptr) {
+        if (hp && first < kHotMaxItems) hot_insert(hot_table, hot_item(r, b, 0u));
+        if (hn && second < kHotMaxItems) hot_insert(hot_table, hot_item(r, b, 1u));
+      }
     }
   }
 }
 
 hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta, uint32_t* filter, uint32_t* hot,
-                               hipStream_t s) {
+                               uint32_t* hot_table, hipStream_t s) {
   hipError_t e = launch_fill_u32(filter, kFilterWords, 0u, s);
   if (e == hipSuccess) e = launch_fill_u32(hot, 1, 0u, s);
+  if (e == hipSuccess && hot_table != nullptr) e = launch_fill_u32(hot_table, kHotSlots, kHotEmpty, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(filter_build_kernel, dim3(grid_for(t.w, 256, 2048)), dim3(256), 0, s, M, t.d, t.w, t.cm, theta,
-                     filter, hot);
+                     filter, hot, hot_table);
   return hipGetLastError();
 }
 
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,
-                          int32_t theta, const uint32_t* filter, const uint32_t* hot, uint64_t* set,
-                          uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
+                          int32_t theta, const uint32_t* filter, const uint32_t* hot, const uint32_t* hot_table,
+                          uint64_t* set, uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
                           hipStream_t s) {
   if (t.d <= (uint32_t)kTabLdsRows) {
     const uint32_t use_filter = (filter != nullptr && hot != nullptr) ? 1u : 0u;
@@ -743,7 +838,7 @@ hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const 
     const dim3 grid(grid_for(n, kCollectThreads, 512)), block(kCollectThreads);
 #define CSK_COLLECT2(DD)                                                                                   \
   hipLaunchKernelGGL(collect2_kernel<DD>, grid, block, lds, s, pos, n, mesh, t, M, theta, filter, hot, use_filter, \
-                     set, slot_mask, set_count, max_cand, err)
+                     hot_table, set, slot_mask, set_count, max_cand, err)
     switch (t.d) {
       case 1: CSK_COLLECT2(1); break;
       case 2: CSK_COLLECT2(2); break;
