@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the particle count (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device three times (calibrates the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -100,6 +102,15 @@ def main():
     import torch
     import workloads
     import paper_1711_00975_amd as csk
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read_per_copy": src.numel() * 4}), flush=True)
+        return
 
     wl = workloads.SCALE if args.workload == "scale" else workloads.SMALL
     n = args.n or wl.n

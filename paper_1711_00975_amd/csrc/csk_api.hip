@@ -115,6 +115,7 @@ struct csk_sketch {
     t.w = w;
     t.wshift = 0;
     if (w >= 2 && (w & (w - 1)) == 0) t.wshift = 32u - (uint32_t)__builtin_ctz(w);
+    t.bnorm = (w >= 2) ? (uint32_t)__builtin_clz(w - 1) : 31u;
     t.cm = (variant == CSK_VARIANT_COUNT_MIN) ? 1u : 0u;
     return t;
   }

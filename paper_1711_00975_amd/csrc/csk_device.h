@@ -236,8 +236,6 @@ __device__ __forceinline__ uint64_t slot_mix(uint64_t k) {
   return k;
 }
 
-// Probe of the filter for the item (row r, bucket b, sign bit neg): fmix32 of the item,
-// word index from its high bits, three bit positions from a second multiply.
 // Hot item (row r < 8, bucket b < 2^28 - 1, sign bit) packed in 32 bits (never kHotEmpty).
 __device__ __forceinline__ uint32_t hot_item(uint32_t r, uint32_t b, uint32_t neg) {
   return (r << 29) | (b << 1) | neg;
@@ -253,17 +251,16 @@ __device__ __forceinline__ uint32_t hot_slot(uint32_t item) {
   return x & (kHotSlots - 1);
 }
 
-__device__ __forceinline__ FilterProbe filter_probe(uint32_t r, uint32_t b, uint32_t neg) {
-  uint32_t x = ((b << 1) | neg) ^ (r * 0x9E3779B9u);
-  x ^= x >> 16;
-  x *= 0x85EBCA6Bu;
-  x ^= x >> 13;
-  x *= 0xC2B2AE35u;
-  x ^= x >> 16;
-  const uint32_t y = x * 0xCC9E2D51u;
+// Probe of the filter for the item (row r, bucket b, sign bit neg).  Buckets are already
+// uniform hash outputs, so the probe only spreads them: u = (b << bnorm) ^ row salt puts
+// the bucket bits at the top of a word (bnorm = 32 - bits(w - 1)); the word comes from
+// the top of u, the three bit positions from its low bits mixed with the sign.
+__device__ __forceinline__ FilterProbe filter_probe(uint32_t r, uint32_t b, uint32_t neg, uint32_t bnorm) {
+  const uint32_t u = (b << bnorm) ^ (r * 0x9E3779B9u);
+  const uint32_t v = (b ^ (neg ? 0x5A5A5A5Au : 0u)) ^ (r * 0x7F4A7C15u) ^ (u >> 17);
   FilterProbe p;
-  p.word = (uint32_t)(((uint64_t)x * (uint64_t)kFilterWords) >> 32);
-  p.mask = (1u << (y >> 27)) | (1u << ((y >> 22) & 31u)) | (1u << ((y >> 17) & 31u));
+  p.word = (uint32_t)(((uint64_t)u * (uint64_t)kFilterWords) >> 32);
+  p.mask = (1u << (v & 31u)) | (1u << ((v >> 5) & 31u)) | (1u << ((v >> 10) & 31u));
   return p;
 }
 

@@ -29,6 +29,7 @@ struct Tables {
   uint32_t d;
   uint32_t w;
   uint32_t wshift;      // 32 - log2(w) when w is a power of two >= 2, else 0
+  uint32_t bnorm;       // 32 - bits(w - 1): shifts a bucket to the top of a word
   uint32_t cm;          // 1: Count-Min (no sign, minimum), 0: Count Sketch
 };
 

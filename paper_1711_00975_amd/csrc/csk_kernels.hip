@@ -228,10 +228,10 @@ constexpr uint32_t kDstDrop = 0xFFFFFFFFu;      // dummy bin: never written
 constexpr uint32_t kDstOverflow = 0xFFFFFFFEu;  // run added with atomics
 constexpr uint32_t kDstBias = 1u << 16;         // keeps offset + cursor - base positive
 
-template <int D, uint32_t MODE>
-__global__ __launch_bounds__(kBin2Threads) void bin3_kernel(BinArgs a) {
+template <int D, uint32_t MODE, int NT, int RP>
+__global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
   constexpr int DP = RowPad<D>::value;
-  constexpr int NT = kBin2Threads, PPT = bin2_ppt(D), TILE = NT * PPT, NW = NT / 64, RP = kBin2Rows;
+  constexpr int PPT = bin2_ppt(D), TILE = NT * PPT, NW = NT / 64;
   extern __shared__ __align__(16) uint32_t lds2[];
   const BinPlan& pl = a.plan;
   const uint32_t nbins = RP * pl.Pr + 1;                 // + the dummy bin
@@ -274,13 +274,15 @@ __global__ __launch_bounds__(kBin2Threads) void bin3_kernel(BinArgs a) {
   for (uint64_t tile = g; tile < pl.ntiles; tile += pl.nwg) {
     const uint64_t first = tile * (uint64_t)TILE;
     const bool full = first + TILE <= a.n;
+    // sv = (bin in its sort pass) << 16 | token; bin = (row % RP) * Pr + slice, or the dummy
+    // bin for a particle outside the stream or the domain
     uint32_t sv[D][PPT];
     uint32_t valid = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const uint64_t i = first + (uint64_t)j * NT + tid;
 #pragma unroll
-      for (int r = 0; r < D; ++r) sv[r][j] = 0;
+      for (int r = 0; r < D; ++r) sv[r][j] = dummy << 16;
       if (full || i < a.n) {
         const float x = __builtin_nontemporal_load(a.pos + 3 * i);
         const float y = __builtin_nontemporal_load(a.pos + 3 * i + 1);
@@ -294,15 +296,15 @@ __global__ __launch_bounds__(kBin2Threads) void bin3_kernel(BinArgs a) {
           for (int r = 0; r < D; ++r) {
             const uint32_t b = bucket_of(h[r], a.w, a.wshift);
             const uint32_t neg = (h[r] >> 31) & (a.cm ^ 1u);
-            sv[r][j] = ((b >> kSliceBits) << 16) | (b & (kSlice - 1)) | (neg << 15);
+            const uint32_t bin = (uint32_t)(r % RP) * pl.Pr + (b >> kSliceBits);
+            sv[r][j] = (bin << 16) | (b & (kSlice - 1)) | (neg << 15);
           }
         }
       }
     }
-    const uint32_t inmask = full ? ((1u << PPT) - 1u) : 0u;
     // particles of the stream that are outside the domain latch the error
     {
-      uint32_t inside = inmask;
+      uint32_t inside = full ? ((1u << PPT) - 1u) : 0u;
       if (!full) {
 #pragma unroll
         for (int j = 0; j < PPT; ++j) inside |= ((first + (uint64_t)j * NT + tid) < a.n ? 1u : 0u) << j;
@@ -314,18 +316,12 @@ __global__ __launch_bounds__(kBin2Threads) void bin3_kernel(BinArgs a) {
     for (int r0 = 0; r0 < D; r0 += RP) {
       const int nr = (D - r0 < RP) ? D - r0 : RP;
       if (pending) write_out();
-      static_assert(RP == 2 && RP * TILE <= 65536, "ranks are packed two per word");
+      static_assert((RP == 1 || RP == 2) && RP * TILE <= 65536, "ranks are packed two per word");
       uint32_t rk[PPT];   // rank of row r0 in the low half, of row r0 + 1 in the high half
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        rk[j] = 0;
-#pragma unroll
-        for (int rr = 0; rr < RP; ++rr) {
-          if (rr < nr) {
-            const uint32_t bin = (valid & (1u << j)) ? rr * pl.Pr + (sv[r0 + rr < D ? r0 + rr : 0][j] >> 16) : dummy;
-            rk[j] |= atomicAdd(&hist[bin], 1u) << (16 * rr);
-          }
-        }
+        rk[j] = atomicAdd(&hist[sv[r0][j] >> 16], 1u);
+        if (RP > 1 && nr > 1) rk[j] |= atomicAdd(&hist[sv[r0 + 1 < D ? r0 + 1 : r0][j] >> 16], 1u) << 16;
       }
       __syncthreads();  // counts complete; the previous pass is written out
       uint32_t cnt_local = 0;
@@ -359,14 +355,12 @@ __global__ __launch_bounds__(kBin2Threads) void bin3_kernel(BinArgs a) {
       }
       __syncthreads();
 #pragma unroll
-      for (int rr = 0; rr < RP; ++rr) {
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-          if (rr < nr) {
-            const uint32_t v = sv[r0 + rr < D ? r0 + rr : 0][j];
-            const uint32_t bin = (valid & (1u << j)) ? rr * pl.Pr + (v >> 16) : dummy;
-            stage[base[bin] + ((rk[j] >> (16 * rr)) & 0xFFFFu)] = (bin << 16) | (v & 0xFFFFu);
-          }
+      for (int j = 0; j < PPT; ++j) {
+        const uint32_t v0 = sv[r0][j];
+        stage[base[v0 >> 16] + (rk[j] & 0xFFFFu)] = v0;
+        if (RP > 1 && nr > 1) {
+          const uint32_t v1 = sv[r0 + 1 < D ? r0 + 1 : r0][j];
+          stage[base[v1 >> 16] + (rk[j] >> 16)] = v1;
         }
       }
       __syncthreads();
@@ -431,17 +425,17 @@ hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
   a.tabi = t.tabi;
   if (plan.fast) {
     const dim3 grid(plan.nwg), block(kBin2Threads);
-#define CSK_BIN3(DD)                                                                               \
-  switch (mesh.mode) {                                                                            \
-    case kMeshPow2Ratio:                                                                          \
-      hipLaunchKernelGGL((bin3_kernel<DD, kMeshPow2Ratio>), grid, block, plan.lds_bytes, s, a);   \
-      break;                                                                                      \
-    case kMeshExactRatio:                                                                         \
-      hipLaunchKernelGGL((bin3_kernel<DD, kMeshExactRatio>), grid, block, plan.lds_bytes, s, a);  \
-      break;                                                                                      \
-    default:                                                                                      \
-      hipLaunchKernelGGL((bin3_kernel<DD, kMeshGeneral>), grid, block, plan.lds_bytes, s, a);     \
-      break;                                                                                      \
+#define CSK_BIN3(DD)                                                                                          \
+  switch (mesh.mode) {                                                                                       \
+    case kMeshPow2Ratio:                                                                                     \
+      hipLaunchKernelGGL((bin3_kernel<DD, kMeshPow2Ratio, kBin2Threads, kBin2Rows>), grid, block, plan.lds_bytes, s, a); \
+      break;                                                                                                 \
+    case kMeshExactRatio:                                                                                    \
+      hipLaunchKernelGGL((bin3_kernel<DD, kMeshExactRatio, kBin2Threads, kBin2Rows>), grid, block, plan.lds_bytes, s, a); \
+      break;                                                                                                 \
+    default:                                                                                                 \
+      hipLaunchKernelGGL((bin3_kernel<DD, kMeshGeneral, kBin2Threads, kBin2Rows>), grid, block, plan.lds_bytes, s, a); \
+      break;                                                                                                 \
   }
     switch (t.d) {
       case 1: CSK_BIN3(1); break;
@@ -726,7 +720,7 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
 #pragma unroll
       for (int r = 0; r < D; ++r) {
         if (fp >= need || fp + (uint32_t)(D - r) < need) break;
-        const FilterProbe pr = filter_probe((uint32_t)r, bk[r], ng[r]);
+        const FilterProbe pr = filter_probe((uint32_t)r, bk[r], ng[r], t.bnorm);
         fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
       }
       if (fp < need) continue;
@@ -786,7 +780,8 @@ __device__ __forceinline__ void hot_insert(uint32_t* table, uint32_t item) {
 }
 
 __global__ __launch_bounds__(256) void filter_build_kernel(const int32_t* __restrict__ M, uint32_t d, uint32_t w,
-                                                           uint32_t cm, int32_t theta, uint32_t* __restrict__ filter,
+                                                           uint32_t cm, uint32_t bnorm, int32_t theta,
+                                                           uint32_t* __restrict__ filter,
                                                            uint32_t* __restrict__ hot, uint32_t* __restrict__ hot_table) {
   for (uint32_t r = 0; r < d; ++r) {
     for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < w; b0 += gridDim.x * blockDim.x) {
@@ -798,11 +793,11 @@ __global__ __launch_bounds__(256) void filter_build_kernel(const int32_t* __rest
         hn = !cm && (-c >= theta);
       }
       if (hp) {
-        const FilterProbe pr = filter_probe(r, b, 0u);
+        const FilterProbe pr = filter_probe(r, b, 0u, bnorm);
         atomicOr(&filter[pr.word], pr.mask);
       }
       if (hn) {
-        const FilterProbe pr = filter_probe(r, b, 1u);
+        const FilterProbe pr = filter_probe(r, b, 1u, bnorm);
         atomicOr(&filter[pr.word], pr.mask);
       }
       // number the items of this wave; the first kHotMaxItems of the whole pass go in
@@ -822,8 +817,8 @@ hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta,
   if (e == hipSuccess) e = launch_fill_u32(hot, 1, 0u, s);
   if (e == hipSuccess && hot_table != nullptr) e = launch_fill_u32(hot_table, kHotSlots, kHotEmpty, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(filter_build_kernel, dim3(grid_for(t.w, 256, 2048)), dim3(256), 0, s, M, t.d, t.w, t.cm, theta,
-                     filter, hot, hot_table);
+  hipLaunchKernelGGL(filter_build_kernel, dim3(grid_for(t.w, 256, 2048)), dim3(256), 0, s, M, t.d, t.w, t.cm, t.bnorm,
+                     theta, filter, hot, hot_table);
   return hipGetLastError();
 }
 
