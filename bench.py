@@ -23,6 +23,28 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
 
+# HBM bytes moved by one update (bin + accumulate) of the 2^30-particle workload, from
+# rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) scaled by a 1 GiB device copy
+# (profiles/update_kernels_plummer_2e30.md).  Reported only while the kernel sources hash
+# to what was profiled; any change to them makes `traffic` null until measured again.
+TRAFFIC = {"bytes": None, "sources_sha256": None, "particles": 1 << 30}
+TRAFFIC_SOURCES = ["csk_kernels.hip", "csk_device.h", "csk_internal.h", "csk_api.hip"]
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1711_00975_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n):
+    if TRAFFIC["bytes"] is None or n != TRAFFIC["particles"]:
+        return None
+    return TRAFFIC["bytes"] if sources_sha256() == TRAFFIC["sources_sha256"] else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -174,9 +196,9 @@ def main():
         "update_ms": upd_ms,
         "update_particles_per_s": n / (upd_ms / 1e3),
         "collect_ms": col_ms,
-        "roofline": {"kernel": "csk_sketch_update (bin_kernel + accumulate_kernel)", "bound": "hbm",
+        "roofline": {"kernel": "csk_sketch_update (bin3_kernel + accumulate_kernel)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n)},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one thread) ...")

@@ -52,6 +52,7 @@ constexpr int bin2_ppt(int d) { return d == 1 ? 16 : (d == 2 ? 12 : (d <= 5 ? 8 
 constexpr int kBin2Rows = 2;                       // rows sorted per LDS pass
 constexpr int kCollectThreads = 1024;
 constexpr int kCollectCache = 1024;               // per-workgroup cache of inserted keys
+constexpr int kCollectPPT = 8;                    // particles per thread per round (loads in flight)
 constexpr int kBinThreads = 512;
 constexpr int kBinPPT = 16;                       // particles per thread per tile
 constexpr int kBinTile = kBinThreads * kBinPPT;   // 8192
@@ -73,7 +74,8 @@ hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const
                         hipStream_t s);
 // Bloom filter of the (row, bucket, sign) items whose signed counter is >= theta
 // (theta > 0); filter: kFilterWords words, hot: item count (both zeroed here).
-// hot_table (kHotSlots words, may be NULL) receives the items exactly while they fit.
+// hot_table (kHotSlots words, may be NULL) receives every item when the count is at most
+// kHotMaxItems, and stays empty otherwise.
 hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta, uint32_t* filter, uint32_t* hot,
                                uint32_t* hot_table, hipStream_t s);
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,

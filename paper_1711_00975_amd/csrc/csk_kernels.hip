@@ -274,43 +274,41 @@ __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
   for (uint64_t tile = g; tile < pl.ntiles; tile += pl.nwg) {
     const uint64_t first = tile * (uint64_t)TILE;
     const bool full = first + TILE <= a.n;
+    // all PPT position loads are issued before any is used (a clamped index keeps the
+    // loads unconditional; particles beyond the stream are masked below)
+    float px[PPT], py[PPT], pz[PPT];
+    const uint64_t last = a.n - 1;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      uint64_t i = first + (uint64_t)j * NT + tid;
+      i = i < last ? i : last;
+      px[j] = __builtin_nontemporal_load(a.pos + 3 * i);
+      py[j] = __builtin_nontemporal_load(a.pos + 3 * i + 1);
+      pz[j] = __builtin_nontemporal_load(a.pos + 3 * i + 2);
+    }
     // sv = (bin in its sort pass) << 16 | token; bin = (row % RP) * Pr + slice, or the dummy
     // bin for a particle outside the stream or the domain
     uint32_t sv[D][PPT];
-    uint32_t valid = 0;
+    uint32_t valid = 0, inside = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      const uint64_t i = first + (uint64_t)j * NT + tid;
+      const bool in = full || (first + (uint64_t)j * NT + tid) < a.n;
+      uint64_t key;   // always a key of the mesh, so the table lookups stay in range
+      const bool ok = cell_key_m<MODE>(px[j], py[j], pz[j], a.mesh, key) && in;
+      inside |= (uint32_t)in << j;
+      valid |= (uint32_t)ok << j;
+      uint32_t h[DP];
+      row_hashes<DP>(ti, key, a.mesh.nch, h);
 #pragma unroll
-      for (int r = 0; r < D; ++r) sv[r][j] = dummy << 16;
-      if (full || i < a.n) {
-        const float x = __builtin_nontemporal_load(a.pos + 3 * i);
-        const float y = __builtin_nontemporal_load(a.pos + 3 * i + 1);
-        const float z = __builtin_nontemporal_load(a.pos + 3 * i + 2);
-        uint64_t key;
-        if (cell_key_m<MODE>(x, y, z, a.mesh, key)) {
-          valid |= 1u << j;
-          uint32_t h[DP];
-          row_hashes<DP>(ti, key, a.mesh.nch, h);
-#pragma unroll
-          for (int r = 0; r < D; ++r) {
-            const uint32_t b = bucket_of(h[r], a.w, a.wshift);
-            const uint32_t neg = (h[r] >> 31) & (a.cm ^ 1u);
-            const uint32_t bin = (uint32_t)(r % RP) * pl.Pr + (b >> kSliceBits);
-            sv[r][j] = (bin << 16) | (b & (kSlice - 1)) | (neg << 15);
-          }
-        }
+      for (int r = 0; r < D; ++r) {
+        const uint32_t b = bucket_of(h[r], a.w, a.wshift);
+        const uint32_t neg = (h[r] >> 31) & (a.cm ^ 1u);
+        const uint32_t bin = (uint32_t)(r % RP) * pl.Pr + (b >> kSliceBits);
+        sv[r][j] = ok ? ((bin << 16) | (b & (kSlice - 1)) | (neg << 15)) : (dummy << 16);
       }
     }
     // particles of the stream that are outside the domain latch the error
-    {
-      uint32_t inside = full ? ((1u << PPT) - 1u) : 0u;
-      if (!full) {
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) inside |= ((first + (uint64_t)j * NT + tid) < a.n ? 1u : 0u) << j;
-      }
-      if (inside & ~valid) atomicOr(a.err, kErrDomain);
-    }
+    if (inside & ~valid) atomicOr(a.err, kErrDomain);
 
 #pragma unroll
     for (int r0 = 0; r0 < D; r0 += RP) {
@@ -673,8 +671,10 @@ __global__ __launch_bounds__(256) void collect_kernel(const float* __restrict__ 
 // Row-interleaved collect for d <= 8.  When a Bloom filter of the hot (row, bucket,
 // sign) items is supplied, a particle whose rows pass the filter fewer than `need`
 // times cannot have est >= theta (the filter has no false negatives) and is dropped
-// without touching the counters; the rest take the exact test.
-template <int D>
+// without touching the counters; the rest take the exact test.  Each thread loads
+// kCollectPPT particles before working on any of them, so that enough position loads
+// are in flight to cover HBM latency at one workgroup per CU.
+template <int D, uint32_t MODE>
 __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* __restrict__ pos, uint64_t n, Mesh mesh,
                                                                    Tables t, const int32_t* __restrict__ M,
                                                                    int32_t theta, const uint32_t* __restrict__ filter,
@@ -684,6 +684,7 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
                                                                    uint32_t* set_count, uint32_t max_cand,
                                                                    uint32_t* err) {
   constexpr int DP = RowPad<D>::value;
+  constexpr int PPT = kCollectPPT;
   extern __shared__ __align__(16) uint32_t lds3[];
   uint32_t* ti = lds3;
   uint64_t* cache = (uint64_t*)(ti + kTableWords * DP);   // kCollectCache keys
@@ -698,78 +699,175 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
   stage_tables<DP>(ti, t.tabi, mesh.nch);
   constexpr uint32_t kNeedCS = D - ((D - 1) >> 1);
   const uint32_t need = t.cm ? (uint32_t)D : kNeedCS;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  constexpr uint32_t NT = kCollectThreads;
+  const uint64_t chunk = (uint64_t)NT * PPT;
   bool bad = false;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    uint64_t key;
-    if (!cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mesh, key)) {
-      bad = true;
-      continue;
-    }
-    uint32_t h[DP];
-    row_hashes<DP>(ti, key, mesh.nch, h);
-    uint32_t bk[D], ng[D];
+  for (uint64_t first = (uint64_t)blockIdx.x * chunk; first < n; first += (uint64_t)gridDim.x * chunk) {
+    const bool full = first + chunk <= n;
+    // all PPT position loads are issued before any is used (a clamped index keeps the
+    // loads unconditional; particles beyond the stream are masked below)
+    float px[PPT], py[PPT], pz[PPT];
+    const uint64_t last = n - 1;
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
-      bk[r] = bucket_of(h[r], t.w, t.wshift);
-      ng[r] = (h[r] >> 31) & (t.cm ^ 1u);
+    for (int j = 0; j < PPT; ++j) {
+      uint64_t i = first + (uint64_t)j * NT + threadIdx.x;
+      i = i < last ? i : last;
+      px[j] = __builtin_nontemporal_load(pos + 3 * i);
+      py[j] = __builtin_nontemporal_load(pos + 3 * i + 1);
+      pz[j] = __builtin_nontemporal_load(pos + 3 * i + 2);
     }
-    if (uf) {
-      // rows read until the verdict is certain: at most need + (D - need) probes
-      uint32_t fp = 0;
+    // keys and the filter verdict of all PPT particles, without branches
+    uint64_t keys[PPT];
+    uint32_t cand = 0;
 #pragma unroll
-      for (int r = 0; r < D; ++r) {
-        if (fp >= need || fp + (uint32_t)(D - r) < need) break;
-        const FilterProbe pr = filter_probe((uint32_t)r, bk[r], ng[r], t.bnorm);
-        fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
+    for (int j = 0; j < PPT; ++j) {
+      const bool in = full || (first + (uint64_t)j * NT + threadIdx.x) < n;
+      const bool ok = cell_key_m<MODE>(px[j], py[j], pz[j], mesh, keys[j]);
+      bad |= in && !ok;
+      bool go = in && ok;
+      if (uf) {
+        uint32_t h[DP];
+        row_hashes<DP>(ti, keys[j], mesh.nch, h);
+        uint32_t fp = 0;
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          const uint32_t bk = bucket_of(h[r], t.w, t.wshift);
+          const uint32_t ng = (h[r] >> 31) & (t.cm ^ 1u);
+          const FilterProbe pr = filter_probe((uint32_t)r, bk, ng, t.bnorm);
+          fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
+        }
+        go = go && fp >= need;
       }
-      if (fp < need) continue;
+      cand |= (uint32_t)go << j;
     }
-    // a key seen recently by this workgroup, or already in the set, needs no exact test:
-    // heavy cells repeat thousands of times, and the set only ever gains keys
-    const uint32_t ci = (uint32_t)(key ^ (key >> 21)) & (kCollectCache - 1);
-    if (__hip_atomic_load(&cache[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == key) continue;
-    if (set_contains(set, slot_mask, key)) {
-      __hip_atomic_store(&cache[ci], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      continue;
-    }
-    uint32_t pass = 0;
-    if (uh) {
-      // row r passes (sign * M >= theta) exactly when its item is in the hot set
+    // the particles that may pass: exact test, unless the key is known to be in the set
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (!(cand & (1u << j))) continue;
+      const uint64_t key = keys[j];
+      // a key seen recently by this workgroup, or already in the set, needs no exact test:
+      // heavy cells repeat thousands of times, and the set only ever gains keys
+      const uint32_t ci = (uint32_t)(key ^ (key >> 21)) & (kCollectCache - 1);
+      if (__hip_atomic_load(&cache[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == key) continue;
+      if (set_contains(set, slot_mask, key)) {
+        __hip_atomic_store(&cache[ci], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        continue;
+      }
+      uint32_t h[DP];
+      row_hashes<DP>(ti, key, mesh.nch, h);
+      uint32_t bk[D], ng[D];
 #pragma unroll
       for (int r = 0; r < D; ++r) {
-        if (pass >= need || pass + (uint32_t)(D - r) < need) break;
-        const uint32_t item = hot_item((uint32_t)r, bk[r], ng[r]);
-        uint32_t sl = hot_slot(item);
-        for (uint32_t probe = 0; probe < kHotSlots; ++probe) {
-          const uint32_t v = hot_table[sl];
-          if (v == item) {
-            ++pass;
-            break;
+        bk[r] = bucket_of(h[r], t.w, t.wshift);
+        ng[r] = (h[r] >> 31) & (t.cm ^ 1u);
+      }
+      uint32_t pass = 0;
+      if (uh) {
+        // row r passes (sign * M >= theta) exactly when its item is in the hot set
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          if (pass >= need || pass + (uint32_t)(D - r) < need) break;
+          const uint32_t item = hot_item((uint32_t)r, bk[r], ng[r]);
+          uint32_t sl = hot_slot(item);
+          for (uint32_t probe = 0; probe < kHotSlots; ++probe) {
+            const uint32_t v = hot_table[sl];
+            if (v == item) {
+              ++pass;
+              break;
+            }
+            if (v == kHotEmpty) break;
+            sl = (sl + 1) & (kHotSlots - 1);
           }
-          if (v == kHotEmpty) break;
-          sl = (sl + 1) & (kHotSlots - 1);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          if (pass >= need || pass + (uint32_t)(D - r) < need) break;
+          const uint32_t c = (uint32_t)M[(uint64_t)r * t.w + bk[r]];
+          if ((int32_t)(ng[r] ? 0u - c : c) >= theta) ++pass;
         }
       }
-    } else {
-#pragma unroll
-      for (int r = 0; r < D; ++r) {
-        if (pass >= need || pass + (uint32_t)(D - r) < need) break;
-        const uint32_t c = (uint32_t)M[(uint64_t)r * t.w + bk[r]];
-        if ((int32_t)(ng[r] ? 0u - c : c) >= theta) ++pass;
+      if (pass >= need) {
+        set_insert(set, slot_mask, key, set_count, max_cand, err);
+        __hip_atomic_store(&cache[ci], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
-    }
-    if (pass >= need) {
-      set_insert(set, slot_mask, key, set_count, max_cand, err);
-      __hip_atomic_store(&cache[ci], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
   if (bad) atomicOr(err, kErrDomain);
 }
 
 // Items (r, b, sign) with sign * M[r][b] >= theta (Count-Min: M[r][b] >= theta) go into
-// the Bloom filter and, while it has room, into the exact hot-item set; theta > 0, so
+// the Bloom filter and, when all of them fit, into the exact hot-item set; theta > 0, so
 // empty buckets never do.  *hot counts the items.
+// Is the signed counter of (r, b, sign) >= theta?  The signed estimate is -M modulo 2^32
+// for a negative sign (Count-Min: M itself), exactly as the collect test reads it.
+__device__ __forceinline__ void hot_pair(int32_t c, uint32_t cm, int32_t theta, bool valid, bool& hp, bool& hn) {
+  hp = valid && c >= theta;
+  hn = valid && !cm && ((int32_t)(0u - (uint32_t)c) >= theta);
+}
+
+// Loads kFilterVec groups of 4 counters of row r for this thread (16-byte loads when rows
+// are 16-byte aligned) before any is tested.
+constexpr int kFilterVec = 2;
+__device__ __forceinline__ void load_counters(const int32_t* __restrict__ Mr, uint32_t w, uint64_t b0,
+                                              int32_t (&c)[kFilterVec][4]) {
+  const bool vec = (w & 3u) == 0;
+#pragma unroll
+  for (int v = 0; v < kFilterVec; ++v) {
+    const uint64_t b = b0 + ((uint64_t)v * blockDim.x + threadIdx.x) * 4;
+    if (vec && b < w) {
+      const int4 q = *(const int4*)(Mr + b);
+      c[v][0] = q.x;
+      c[v][1] = q.y;
+      c[v][2] = q.z;
+      c[v][3] = q.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) c[v][e] = (b + e < w) ? Mr[b + e] : 0;
+    }
+  }
+}
+
+// Pass 1: sets the Bloom filter bits of every hot item and counts the items into *hot
+// (per-workgroup count in LDS, one global add per workgroup).
+__global__ __launch_bounds__(256) void filter_build_kernel(const int32_t* __restrict__ M, uint32_t d, uint32_t w,
+                                                           uint32_t cm, uint32_t bnorm, int32_t theta,
+                                                           uint32_t* __restrict__ filter, uint32_t* __restrict__ hot) {
+  __shared__ uint32_t count;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  uint32_t mine = 0;
+  const uint64_t span = (uint64_t)gridDim.x * blockDim.x * 4 * kFilterVec;
+  for (uint32_t r = 0; r < d; ++r) {
+    const int32_t* __restrict__ Mr = M + (uint64_t)r * w;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4 * kFilterVec; b0 < w; b0 += span) {
+      int32_t c[kFilterVec][4];
+      load_counters(Mr, w, b0, c);
+#pragma unroll
+      for (int v = 0; v < kFilterVec; ++v) {
+        const uint64_t b = b0 + ((uint64_t)v * blockDim.x + threadIdx.x) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          bool hp, hn;
+          hot_pair(c[v][e], cm, theta, b + e < w, hp, hn);
+          if (hp) {
+            const FilterProbe pr = filter_probe(r, (uint32_t)(b + e), 0u, bnorm);
+            atomicOr(&filter[pr.word], pr.mask);
+          }
+          if (hn) {
+            const FilterProbe pr = filter_probe(r, (uint32_t)(b + e), 1u, bnorm);
+            atomicOr(&filter[pr.word], pr.mask);
+          }
+          mine += (uint32_t)hp + (uint32_t)hn;
+        }
+      }
+    }
+  }
+  if (mine) atomicAdd(&count, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && count) atomicAdd(hot, count);
+}
+
 __device__ __forceinline__ void hot_insert(uint32_t* table, uint32_t item) {
   uint32_t sl = hot_slot(item);
   for (uint32_t probe = 0; probe < kHotSlots; ++probe) {
@@ -779,33 +877,28 @@ __device__ __forceinline__ void hot_insert(uint32_t* table, uint32_t item) {
   }
 }
 
-__global__ __launch_bounds__(256) void filter_build_kernel(const int32_t* __restrict__ M, uint32_t d, uint32_t w,
-                                                           uint32_t cm, uint32_t bnorm, int32_t theta,
-                                                           uint32_t* __restrict__ filter,
-                                                           uint32_t* __restrict__ hot, uint32_t* __restrict__ hot_table) {
+// Pass 2: when every hot item fits (*hot <= kHotMaxItems, so the table stays at most half
+// full), inserts them all into the exact hot-item set; otherwise does nothing.
+__global__ __launch_bounds__(256) void hot_build_kernel(const int32_t* __restrict__ M, uint32_t d, uint32_t w,
+                                                        uint32_t cm, int32_t theta, const uint32_t* __restrict__ hot,
+                                                        uint32_t* __restrict__ hot_table) {
+  if (*hot > kHotMaxItems) return;
+  const uint64_t span = (uint64_t)gridDim.x * blockDim.x * 4 * kFilterVec;
   for (uint32_t r = 0; r < d; ++r) {
-    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < w; b0 += gridDim.x * blockDim.x) {
-      const uint32_t b = b0 + threadIdx.x;
-      bool hp = false, hn = false;
-      if (b < w) {
-        const int64_t c = M[(uint64_t)r * w + b];
-        hp = c >= theta;
-        hn = !cm && (-c >= theta);
-      }
-      if (hp) {
-        const FilterProbe pr = filter_probe(r, b, 0u, bnorm);
-        atomicOr(&filter[pr.word], pr.mask);
-      }
-      if (hn) {
-        const FilterProbe pr = filter_probe(r, b, 1u, bnorm);
-        atomicOr(&filter[pr.word], pr.mask);
-      }
-      // number the items of this wave; the first kHotMaxItems of the whole pass go in
-      const uint32_t first = wave_append(hot, hp);
-      const uint32_t second = wave_append(hot, hn);
-      if (hot_table != nullptr) {
-        if (hp && first < kHotMaxItems) hot_insert(hot_table, hot_item(r, b, 0u));
-        if (hn && second < kHotMaxItems) hot_insert(hot_table, hot_item(r, b, 1u));
+    const int32_t* __restrict__ Mr = M + (uint64_t)r * w;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4 * kFilterVec; b0 < w; b0 += span) {
+      int32_t c[kFilterVec][4];
+      load_counters(Mr, w, b0, c);
+#pragma unroll
+      for (int v = 0; v < kFilterVec; ++v) {
+        const uint64_t b = b0 + ((uint64_t)v * blockDim.x + threadIdx.x) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          bool hp, hn;
+          hot_pair(c[v][e], cm, theta, b + e < w, hp, hn);
+          if (hp) hot_insert(hot_table, hot_item(r, (uint32_t)(b + e), 0u));
+          if (hn) hot_insert(hot_table, hot_item(r, (uint32_t)(b + e), 1u));
+        }
       }
     }
   }
@@ -817,8 +910,10 @@ hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta,
   if (e == hipSuccess) e = launch_fill_u32(hot, 1, 0u, s);
   if (e == hipSuccess && hot_table != nullptr) e = launch_fill_u32(hot_table, kHotSlots, kHotEmpty, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(filter_build_kernel, dim3(grid_for(t.w, 256, 2048)), dim3(256), 0, s, M, t.d, t.w, t.cm, t.bnorm,
-                     theta, filter, hot, hot_table);
+  const dim3 grid(grid_for((t.w + 4 * kFilterVec - 1) / (4 * kFilterVec), 256, 8192));
+  hipLaunchKernelGGL(filter_build_kernel, grid, dim3(256), 0, s, M, t.d, t.w, t.cm, t.bnorm, theta, filter, hot);
+  if (hot_table != nullptr)
+    hipLaunchKernelGGL(hot_build_kernel, grid, dim3(256), 0, s, M, t.d, t.w, t.cm, theta, hot, hot_table);
   return hipGetLastError();
 }
 
@@ -830,10 +925,16 @@ hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const 
     const uint32_t use_filter = (filter != nullptr && hot != nullptr) ? 1u : 0u;
     const size_t lds = ((size_t)kTableWords * t.dp + 2 * kCollectCache + (use_filter ? kFilterWords : 0)) *
                        sizeof(uint32_t);
-    const dim3 grid(grid_for(n, kCollectThreads, 512)), block(kCollectThreads);
+    const dim3 grid(grid_for((n + kCollectPPT - 1) / kCollectPPT, kCollectThreads, 256)), block(kCollectThreads);
+#define CSK_COLLECT2_M(DD, MM)                                                                             \
+  hipLaunchKernelGGL((collect2_kernel<DD, MM>), grid, block, lds, s, pos, n, mesh, t, M, theta, filter, hot,      \
+                     use_filter, hot_table, set, slot_mask, set_count, max_cand, err)
 #define CSK_COLLECT2(DD)                                                                                   \
-  hipLaunchKernelGGL(collect2_kernel<DD>, grid, block, lds, s, pos, n, mesh, t, M, theta, filter, hot, use_filter, \
-                     hot_table, set, slot_mask, set_count, max_cand, err)
+  switch (mesh.mode) {                                                                                     \
+    case kMeshPow2Ratio: CSK_COLLECT2_M(DD, kMeshPow2Ratio); break;                                        \
+    case kMeshExactRatio: CSK_COLLECT2_M(DD, kMeshExactRatio); break;                                      \
+    default: CSK_COLLECT2_M(DD, kMeshGeneral); break;                                                      \
+  }
     switch (t.d) {
       case 1: CSK_COLLECT2(1); break;
       case 2: CSK_COLLECT2(2); break;
@@ -845,6 +946,7 @@ hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const 
       default: CSK_COLLECT2(8); break;
     }
 #undef CSK_COLLECT2
+#undef CSK_COLLECT2_M
   } else {
     hipLaunchKernelGGL(collect_kernel<false>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, pos, n, mesh, t, M, theta,
                        set, slot_mask, set_count, max_cand, err);
@@ -990,32 +1092,50 @@ __global__ __launch_bounds__(256) void sel_gather_kernel(const uint64_t* __restr
 }
 
 // Place each winner at its rank in (est desc, key asc); keys are distinct.
-__global__ __launch_bounds__(256) void rank_place_kernel(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
-                                                         SelState* st, uint32_t k, uint64_t* __restrict__ ok,
-                                                         int32_t* __restrict__ oe) {
+// Rank of winner i = number of winners ahead of it in (estimate desc, key asc) order.
+// Block (x, y) counts, for the 256 winners of tile x, those ahead of them among the
+// `chunk` winners of chunk y, and adds the partial counts to rank[].  Keys are distinct,
+// so the ranks are a permutation of [0, n).
+constexpr uint32_t kRankChunk = 1024;      // smallest chunk
+constexpr uint32_t kMaxGridY = 65535;
+__global__ __launch_bounds__(256) void rank_count_kernel(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
+                                                         const SelState* st, uint32_t k, uint32_t chunk,
+                                                         uint32_t* __restrict__ rank) {
   __shared__ uint64_t tk[256];
   __shared__ int32_t te[256];
   const uint32_t n = min(st->n_sel, k);
-  for (uint32_t i0 = blockIdx.x * 256; i0 < n; i0 += gridDim.x * 256) {
-    const uint32_t i = i0 + threadIdx.x;
-    const bool act = i < n;
-    const uint64_t ki = act ? sk[i] : 0;
-    const int32_t ei = act ? se[i] : 0;
-    uint32_t rank = 0;
-    for (uint32_t j0 = 0; j0 < n; j0 += 256) {
-      __syncthreads();
-      if (j0 + threadIdx.x < n) {
-        tk[threadIdx.x] = sk[j0 + threadIdx.x];
-        te[threadIdx.x] = se[j0 + threadIdx.x];
-      }
-      __syncthreads();
-      const uint32_t lim = min(256u, n - j0);
-      for (uint32_t t = 0; t < lim; ++t) rank += (te[t] > ei) || (te[t] == ei && tk[t] < ki);
+  const uint32_t i0 = blockIdx.x * 256;
+  const uint64_t j_lo64 = (uint64_t)blockIdx.y * chunk;
+  if (i0 >= n || j_lo64 >= n) return;   // uniform over the block
+  const uint32_t j_lo = (uint32_t)j_lo64;
+  const uint32_t j_hi = (uint32_t)min((uint64_t)n, j_lo64 + chunk);
+  const uint32_t i = i0 + threadIdx.x;
+  const bool act = i < n;
+  const uint64_t ki = act ? sk[i] : 0;
+  const int32_t ei = act ? se[i] : 0;
+  uint32_t cnt = 0;
+  for (uint32_t j0 = j_lo; j0 < j_hi; j0 += 256) {
+    __syncthreads();
+    if (j0 + threadIdx.x < j_hi) {
+      tk[threadIdx.x] = sk[j0 + threadIdx.x];
+      te[threadIdx.x] = se[j0 + threadIdx.x];
     }
-    if (act) {
-      ok[rank] = ki;
-      oe[rank] = ei;
-    }
+    __syncthreads();
+    const uint32_t lim = min(256u, j_hi - j0);
+    for (uint32_t t = 0; t < lim; ++t) cnt += (te[t] > ei) || (te[t] == ei && tk[t] < ki);
+  }
+  if (act && cnt) atomicAdd(&rank[i], cnt);
+}
+
+__global__ __launch_bounds__(256) void rank_place_kernel(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
+                                                         const SelState* st, uint32_t k,
+                                                         const uint32_t* __restrict__ rank, uint64_t* __restrict__ ok,
+                                                         int32_t* __restrict__ oe) {
+  const uint32_t n = min(st->n_sel, k);
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const uint32_t r = rank[i];
+    ok[r] = sk[i];
+    oe[r] = se[i];
   }
 }
 
@@ -1046,7 +1166,15 @@ hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, con
     hipLaunchKernelGGL(sel_pick_kernel<true>, dim3(1), dim3(64), 0, s, st, k, shift);
   }
   hipLaunchKernelGGL(sel_gather_kernel, hgrid, dim3(256), 0, s, ck, ce, st, k, sk, se);
-  hipLaunchKernelGGL(rank_place_kernel, dim3(grid_for(k, 256, 1024)), dim3(256), 0, s, sk, se, st, k, ok, oe);
+  // the candidate estimates are no longer needed: their first k words hold the ranks
+  uint32_t* rank = (uint32_t*)ce;
+  hipError_t e = launch_fill_u32(rank, k, 0u, s);
+  if (e != hipSuccess) return e;
+  uint64_t chunk = kRankChunk;
+  while ((k + chunk - 1) / chunk > kMaxGridY) chunk *= 2;
+  hipLaunchKernelGGL(rank_count_kernel, dim3((k + 255) / 256, (uint32_t)((k + chunk - 1) / chunk)), dim3(256), 0, s,
+                     sk, se, st, k, (uint32_t)chunk, rank);
+  hipLaunchKernelGGL(rank_place_kernel, dim3(grid_for(k, 256, 1024)), dim3(256), 0, s, sk, se, st, k, rank, ok, oe);
   hipLaunchKernelGGL(sel_finish_kernel, dim3(1), dim3(64), 0, s, st, err);
   return hipGetLastError();
 }
