@@ -27,7 +27,8 @@ BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
 # rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) scaled by a 1 GiB device copy
 # (profiles/update_kernels_plummer_2e30.md).  Reported only while the kernel sources hash
 # to what was profiled; any change to them makes `traffic` null until measured again.
-TRAFFIC = {"bytes": None, "sources_sha256": None, "particles": 1 << 30}
+TRAFFIC = {"bytes": 46_057_567_232, "particles": 1 << 30,
+           "sources_sha256": "9e6ecf43441c78f95aea3c972dd02dcfd62409d36eaaea173da154ca75d51d86"}
 TRAFFIC_SOURCES = ["csk_kernels.hip", "csk_device.h", "csk_internal.h", "csk_api.hip"]
 
 
@@ -58,6 +59,7 @@ def parse():
     ap.add_argument("--workload", choices=["scale", "small"], default="scale")
     ap.add_argument("--n", type=int, default=0, help="override the particle count (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device three times (calibrates the HBM byte counters)")
@@ -100,19 +102,57 @@ def calibrate_theta(s, pos, wl, csk):
         theta //= 2
 
 
-def cpu_baseline(pos_dev, wl, sample, torch):
-    """The oracle as it stands, single thread, on the first `sample` particles."""
-    import numpy as np
+def cpu_baseline(pos_dev, wl, sample, threads):
+    """The oracle as it stands on the first `sample` particles.  With threads > 1 the Add
+    phase runs on that many threads (one sketch per thread, summed); the estimates of
+    every distinct cell and the top-k run on one thread either way."""
     import oracle
     pos = pos_dev[:sample].cpu().numpy()
     t0 = time.perf_counter()
-    M, _ = oracle.sketch(pos, wl.d, wl.w, wl.seed, wl.delta, wl.L)
+    M, _ = oracle.sketch(pos, wl.d, wl.w, wl.seed, wl.delta, wl.L, threads=threads)
     t1 = time.perf_counter()
     oracle.topk_sketch(M, oracle.hash_tables(wl.seed, wl.d), pos, wl.delta, wl.L, oracle.INT32_MIN, wl.k)
     t2 = time.perf_counter()
-    return {"value": sample / (t2 - t0), "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample} particles of the same stream; keys + Add ({t1 - t0:.1f} s), "
-                      f"estimates of every distinct cell + top-{wl.k} ({t2 - t1:.1f} s), one thread"}
+    return {"value": sample / (t2 - t0), "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} particles of the same stream; keys + Add ({t1 - t0:.1f} s on {threads} "
+                      f"thread{'s' if threads > 1 else ''}), estimates of every distinct cell + top-{wl.k} "
+                      f"({t2 - t1:.1f} s, one thread)"}
+
+
+def host_threads():
+    """Host threads this process may use, capped at the 16 that one GPU's share allows."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def recall(pos, wl, keys_top, est_top, csk, torch):
+    """Top-k recall of the sketch against the exact histogram of the whole stream.  The
+    exact counts come from torch.unique over the cell keys (csk_cell_keys, whose keys are
+    checked bit-exactly against the oracle in the tests).  strict: shared keys with the
+    exact top-k (ties at the k-th count broken by smaller key); tie_tolerant: returned keys
+    whose exact count is at least the exact k-th count.  Also the median and largest
+    relative error of the returned estimates against the exact counts."""
+    k = wl.k
+    keys = csk.cell_keys(pos, wl.delta, wl.L)
+    uniq, counts = torch.unique(keys, sorted=True, return_counts=True)
+    del keys
+    ck = torch.topk(counts, k).values[-1]
+    above = uniq[counts > ck]
+    ties = uniq[counts == ck]
+    exact = torch.cat([above, ties[: k - above.numel()]])
+    f = counts[torch.searchsorted(uniq, keys_top)]
+    rel = (est_top.to(torch.float64) - f.to(torch.float64)).abs() / f.to(torch.float64)
+    out = {"k": k, "strict": torch.isin(keys_top, exact).sum().item() / k,
+           "tie_tolerant": (f >= ck).sum().item() / k,
+           "rel_err_median": rel.median().item(), "rel_err_max": rel.max().item(),
+           "exact_kth_count": int(ck.item()), "distinct_cells": int(uniq.numel()),
+           "exact": "torch.unique over csk_cell_keys of the whole stream"}
+    del uniq, counts
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -153,7 +193,7 @@ def main():
         if ev is not None:
             ev[2].record(stream)
         keys, est, rc = s.topk(wl.k)
-        return rc
+        return rc, keys, est
 
     # warm-up: first update allocates scratch; then find theta
     s.update(pos, wl.delta, wl.L)
@@ -168,7 +208,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        rcs.append(step(theta, evs[i]))
+        rc, keys_top, est_top = step(theta, evs[i])
+        rcs.append(rc)
         log(f"  step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -200,9 +241,20 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n)},
     }
+    if not args.no_recall:
+        log("recall against the exact histogram ...")
+        try:
+            out["recall"] = recall(pos, wl, keys_top, est_top, csk, torch)
+        except RuntimeError as e:   # e.g. not enough device memory for the exact histogram
+            out["recall"] = {"error": str(e)[:200]}
     if not args.no_cpu_baseline:
+        sample = min(args.cpu_sample, n)
         log("cpu baseline (oracle, one thread) ...")
-        out["cpu_baseline"] = cpu_baseline(pos, wl, min(args.cpu_sample, n), torch)
+        out["cpu_baseline"] = cpu_baseline(pos, wl, sample, 1)
+        nt = host_threads()
+        if nt > 1:
+            log(f"cpu baseline (oracle, {nt} threads for Add) ...")
+            out["cpu_baseline_all_cores"] = cpu_baseline(pos, wl, sample, nt)
     s.close()
     print(json.dumps(out), flush=True)
 

@@ -455,3 +455,28 @@ def test_empty_stream():
     assert len(ks) == 0 and st == oracle.OK
     uniq, f = oracle.histogram(np.zeros(0, np.uint64))
     assert len(uniq) == 0
+
+
+def test_small_workload_recall():
+    # Heavy-hitter recovery (Sec. 2.2: the median of t unbiased row estimates tracks the
+    # frequencies of the heavy items) and the relative error |c - c_hat| / c of Sec. 4.3: on
+    # the 2^20-particle Plummer workload (d = 5, w = 2^16, k = 100) the sketch's top-k is
+    # checked against the exact top-k of the oracle's histogram.  The single-row noise
+    # sqrt(F2 / w) is about 6.5 while the 100th count is about 60, so nearly all of the top
+    # 100 must come back with small relative error; a wrong sign, bucket or median would
+    # destroy this.
+    import workloads
+    wl = workloads.SMALL
+    pos = wl.generate()
+    M, _ = oracle.sketch(pos, wl.d, wl.w, wl.seed, wl.delta, wl.L)
+    T = oracle.hash_tables(wl.seed, wl.d)
+    ks, es, st = oracle.topk_sketch(M, T, pos, wl.delta, wl.L, oracle.INT32_MIN, wl.k)
+    assert st == oracle.OK and len(ks) == wl.k
+    uniq, f = oracle.histogram(oracle.keys(pos, wl.delta, wl.L))
+    kx, fx = oracle.topk_exact(uniq, f, wl.k)
+    fmap = dict(zip(uniq.tolist(), f.tolist()))
+    strict = len(set(ks.tolist()) & set(kx.tolist())) / wl.k
+    tie_tolerant = sum(fmap[k] >= fx[-1] for k in ks.tolist()) / wl.k
+    rel = np.array([abs(int(e) - fmap[k]) / fmap[k] for k, e in zip(ks.tolist(), es.tolist())])
+    assert strict >= 0.95 and tie_tolerant >= 0.95
+    assert np.median(rel) < 0.05 and rel.max() < 0.25
