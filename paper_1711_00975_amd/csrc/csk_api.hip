@@ -69,6 +69,23 @@ std::vector<uint32_t> interleave_tables(const std::vector<uint32_t>& T, uint32_t
   return Ti;
 }
 
+// The top F = floor(128 / d) bits of every row's entry, packed into four words per
+// (character, value) entry with row r at bit r * F (d = 5..8).  Hashing is XOR, so the
+// packed XOR over a key's characters holds the top F bits of every row's word.
+std::vector<uint32_t> pack_tables(const std::vector<uint32_t>& T, uint32_t d) {
+  const uint32_t F = (uint32_t)packed_bits((int)d);
+  std::vector<uint32_t> P((size_t)kTableWords * 4, 0u);
+  for (uint32_t e = 0; e < (uint32_t)kTableWords; ++e) {
+    for (uint32_t r = 0; r < d; ++r) {
+      const uint32_t f = T[(size_t)r * kTableWords + e] >> (32u - F);
+      const uint32_t o = r * F, wi = o / 32u, sh = o % 32u;
+      P[(size_t)e * 4 + wi] |= f << sh;
+      if (sh + F > 32u) P[(size_t)e * 4 + wi + 1] |= f >> (32u - sh);
+    }
+  }
+  return P;
+}
+
 }  // namespace
 
 struct csk_sketch {
@@ -79,6 +96,7 @@ struct csk_sketch {
   int32_t* M = nullptr;
   uint32_t* tab = nullptr;
   uint32_t* tabi = nullptr;  // row-interleaved tables (d <= 8)
+  uint32_t* tabp = nullptr;  // packed top-bit tables (d = 5..8)
   uint32_t dp = 0;
   uint32_t* filter = nullptr; // Bloom filter of hot items + [kFilterWords] item count
   uint32_t* hot_table = nullptr; // exact set of hot items (kHotSlots words)
@@ -110,6 +128,7 @@ struct csk_sketch {
     Tables t;
     t.tab = tab;
     t.tabi = tabi;
+    t.tabp = tabp;
     t.dp = dp;
     t.d = d;
     t.w = w;
@@ -132,7 +151,7 @@ hipError_t dmalloc(csk_sketch* s, T** p, uint64_t count) {
 }
 
 void free_all(csk_sketch* s) {
-  void* ptrs[] = {s->M, s->tab, s->tabi, s->filter, s->hot_table, s->set, s->ctl, s->sel, s->cand_key, s->cand_est, s->sel_key, s->sel_est,
+  void* ptrs[] = {s->M, s->tab, s->tabi, s->tabp, s->filter, s->hot_table, s->set, s->ctl, s->sel, s->cand_key, s->cand_est, s->sel_key, s->sel_est,
                   s->tok, s->cnt};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -233,9 +252,12 @@ csk_status csk_sketch_init_ex(csk_sketch** out, uint32_t d, uint32_t w, uint64_t
   s->dp = (d <= 4) ? 4u : (d <= 6 ? 6u : (d <= (uint32_t)kTabLdsRows ? 8u : 0u));
   std::vector<uint32_t> Ti;
   if (s->dp) Ti = interleave_tables(T, d, s->dp);
+  std::vector<uint32_t> Tp;
+  if (d >= 5 && d <= (uint32_t)kTabLdsRows) Tp = pack_tables(T, d);
   if (e == hipSuccess) e = dmalloc(s, &s->M, (uint64_t)d * w);
   if (e == hipSuccess) e = dmalloc(s, &s->tab, T.size());
   if (e == hipSuccess && s->dp) e = dmalloc(s, &s->tabi, Ti.size());
+  if (e == hipSuccess && !Tp.empty()) e = dmalloc(s, &s->tabp, Tp.size());
   if (e == hipSuccess && s->dp) e = dmalloc(s, &s->filter, (uint64_t)kFilterWords + 1);
   // items pack the bucket in 28 bits, so the exact hot set needs w < 2^28
   if (e == hipSuccess && s->dp && w < (1u << 28)) e = dmalloc(s, &s->hot_table, (uint64_t)kHotSlots);
@@ -249,6 +271,8 @@ csk_status csk_sketch_init_ex(csk_sketch** out, uint32_t d, uint32_t w, uint64_t
   if (e == hipSuccess) e = hipMemcpy(s->tab, T.data(), T.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess && s->dp)
     e = hipMemcpy(s->tabi, Ti.data(), Ti.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !Tp.empty())
+    e = hipMemcpy(s->tabp, Tp.data(), Tp.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)s->M, (uint64_t)d * w, 0u, nullptr);
   if (e == hipSuccess) e = launch_fill_u32(s->ctl, 4, 0u, nullptr);
   if (e == hipSuccess) e = launch_fill_u64(s->set, slots, kEmptyKey, nullptr);

@@ -195,6 +195,66 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t h, uint32_t w) {
 __device__ __forceinline__ uint32_t bucket_of(uint32_t h, uint32_t w, uint32_t lw_shift) {
   return lw_shift ? (h << 1) >> lw_shift : __umulhi(h << 1, w);
 }
+// The same with the choice made at compile time (POW2: w = 2^lw, lw_shift = 32 - lw).
+template <bool POW2>
+__device__ __forceinline__ uint32_t bucket_of_t(uint32_t h, uint32_t w, uint32_t lw_shift) {
+  return POW2 ? (h << 1) >> lw_shift : __umulhi(h << 1, w);
+}
+
+// How the kernels that hash all rows at once get bucket and sign:
+//   kHashMulHi   any w: bucket = high word of (h31 << 1) * w (row-interleaved tables)
+//   kHashShift   w = 2^lw: bucket = (h << 1) >> (32 - lw) (row-interleaved tables)
+//   kHashPacked  w = 2^lw with lw + 1 <= F = floor(128 / d), d = 5..8: each table entry
+//                keeps only the top F bits of every row's word, packed into 128 bits
+//                (row r at bit r * F), so one 16-byte LDS load per key byte serves all
+//                rows.  XOR acts bit by bit, so the packed fields of the XOR are the top
+//                F bits of each row's XOR: the bucket bits (30 .. 31 - lw) and the sign
+//                bit 31 are exactly those of the full word.
+constexpr int kHashMulHi = 0;
+constexpr int kHashShift = 1;
+constexpr int kHashPacked = 2;
+constexpr int packed_bits(int d) { return 128 / d; }
+
+// Field r (F bits at bit r * F) of a 128-bit value held in four words.
+template <int F>
+__device__ __forceinline__ uint32_t packed_field(const uint32_t (&q)[4], int r) {
+  const int o = r * F, wi = o >> 5, sh = o & 31;
+  const uint32_t v = (sh + F <= 32) ? (q[wi] >> sh) : __builtin_amdgcn_alignbit(q[wi + 1], q[wi], (uint32_t)sh);
+  return (F >= 32) ? v : (v & ((1u << F) - 1u));
+}
+
+// Table entry width (words) that a kernel hashing all D rows at once stages in LDS.
+template <int D, int HM>
+struct HashWords {
+  static constexpr int value = (HM == kHashPacked) ? 4 : RowPad<D>::value;
+};
+
+// Bucket and sign bit (1 = negative) of every row of `key` from LDS tables staged for
+// mode HM (see kHashMulHi / kHashShift / kHashPacked).
+template <int D, int HM>
+__device__ __forceinline__ void rows_bucket_sign(const uint32_t* __restrict__ ti, uint64_t key, uint32_t nch,
+                                                 uint32_t w, uint32_t wshift, uint32_t (&b)[D], uint32_t (&neg)[D]) {
+  constexpr int DP = HashWords<D, HM>::value;
+  uint32_t h[DP];
+  row_hashes<DP>(ti, key, nch, h);
+  if constexpr (HM == kHashPacked) {
+    constexpr int F = packed_bits(D);
+    static_assert(D >= 5 && D <= 8 && F <= 25, "packed fields need d = 5..8");
+    const uint32_t q[4] = {h[0], h[1], h[2], h[3]};
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      const uint32_t f = packed_field<F>(q, r);
+      neg[r] = f >> (F - 1);
+      b[r] = (f << (33 - F)) >> wshift;   // (h << 1) >> wshift with bits below the field cleared
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      b[r] = bucket_of_t<HM == kHashShift>(h[r], w, wshift);
+      neg[r] = h[r] >> 31;
+    }
+  }
+}
 
 // Lower median (index floor((d-1)/2) of the ascending order) of v[0..d), d <= MAXD,
 // by counting: v[i] is the answer when #{v < v[i]} <= m < #{v <= v[i]}.

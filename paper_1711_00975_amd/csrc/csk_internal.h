@@ -25,12 +25,19 @@ struct SelState {
 struct Tables {
   const uint32_t* tab;  // [d][6][256] uint32, device
   const uint32_t* tabi; // row-interleaved [6][256][dp] uint32 (d <= 8), device
+  const uint32_t* tabp; // packed top-F-bit fields [6][256][4] uint32 (d = 5..8), device, or NULL
   uint32_t dp;          // 4 (d <= 4), 6 (d <= 6) or 8 (d <= 8); 0 when d > 8
   uint32_t d;
   uint32_t w;
   uint32_t wshift;      // 32 - log2(w) when w is a power of two >= 2, else 0
   uint32_t bnorm;       // 32 - bits(w - 1): shifts a bucket to the top of a word
   uint32_t cm;          // 1: Count-Min (no sign, minimum), 0: Count Sketch
+  // kHashPacked when the packed tables serve this w, else kHashShift (w = 2^lw) or kHashMulHi
+  int hash_mode() const {
+    if (tabp != nullptr && wshift != 0 && d >= 5 && d <= 8 && (32u - wshift) + 1u <= (uint32_t)packed_bits((int)d))
+      return kHashPacked;
+    return wshift ? kHashShift : kHashMulHi;
+  }
 };
 
 // Binned update: sizes chosen by the host.

@@ -120,6 +120,7 @@ struct BinArgs {
   Mesh mesh;
   const uint32_t* __restrict__ tab;
   const uint32_t* __restrict__ tabi;
+  const uint32_t* __restrict__ tabp;
   uint32_t d, w, wshift, cm;
   BinPlan plan;
   uint16_t* __restrict__ tok;
@@ -228,9 +229,9 @@ constexpr uint32_t kDstDrop = 0xFFFFFFFFu;      // dummy bin: never written
 constexpr uint32_t kDstOverflow = 0xFFFFFFFEu;  // run added with atomics
 constexpr uint32_t kDstBias = 1u << 16;         // keeps offset + cursor - base positive
 
-template <int D, uint32_t MODE, int NT, int RP>
+template <int D, uint32_t MODE, int NT, int RP, int HM>
 __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
-  constexpr int DP = RowPad<D>::value;
+  constexpr int DP = HashWords<D, HM>::value;
   constexpr int PPT = bin2_ppt(D), TILE = NT * PPT, NW = NT / 64;
   extern __shared__ __align__(16) uint32_t lds2[];
   const BinPlan& pl = a.plan;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
 
   for (uint32_t i = tid; i < pl.P; i += NT) cursor[i] = 0;
   for (uint32_t i = tid; i < nbins; i += NT) hist[i] = 0;
-  stage_tables<DP>(ti, a.tabi, a.mesh.nch);
+  stage_tables<DP>(ti, HM == kHashPacked ? a.tabp : a.tabi, a.mesh.nch);
 
   const uint32_t per = (nbins + NT - 1) / NT;           // scan: bins per thread
   const uint32_t blo = min(nbins, tid * per), bhi = min(nbins, blo + per);
@@ -297,12 +298,12 @@ __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
       const bool ok = cell_key_m<MODE>(px[j], py[j], pz[j], a.mesh, key) && in;
       inside |= (uint32_t)in << j;
       valid |= (uint32_t)ok << j;
-      uint32_t h[DP];
-      row_hashes<DP>(ti, key, a.mesh.nch, h);
+      uint32_t bk[D], sg[D];
+      rows_bucket_sign<D, HM>(ti, key, a.mesh.nch, a.w, a.wshift, bk, sg);
 #pragma unroll
       for (int r = 0; r < D; ++r) {
-        const uint32_t b = bucket_of(h[r], a.w, a.wshift);
-        const uint32_t neg = (h[r] >> 31) & (a.cm ^ 1u);
+        const uint32_t b = bk[r];
+        const uint32_t neg = sg[r] & (a.cm ^ 1u);
         const uint32_t bin = (uint32_t)(r % RP) * pl.Pr + (b >> kSliceBits);
         sv[r][j] = ok ? ((bin << 16) | (b & (kSlice - 1)) | (neg << 15)) : (dummy << 16);
       }
@@ -404,6 +405,42 @@ bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& p) {
   return true;
 }
 
+template <int D, uint32_t MM>
+static void launch_bin3_m(int hm, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, const BinArgs& a) {
+  if constexpr (D >= 5) {
+    if (hm == kHashPacked) {
+      hipLaunchKernelGGL((bin3_kernel<D, MM, kBin2Threads, kBin2Rows, kHashPacked>), grid, block, lds, s, a);
+      return;
+    }
+  }
+  if (hm == kHashMulHi)
+    hipLaunchKernelGGL((bin3_kernel<D, MM, kBin2Threads, kBin2Rows, kHashMulHi>), grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL((bin3_kernel<D, MM, kBin2Threads, kBin2Rows, kHashShift>), grid, block, lds, s, a);
+}
+
+template <int D>
+static void launch_bin3_dm(uint32_t mode, int hm, dim3 grid, dim3 block, uint32_t lds, hipStream_t s,
+                           const BinArgs& a) {
+  if (mode == kMeshPow2Ratio) launch_bin3_m<D, kMeshPow2Ratio>(hm, grid, block, lds, s, a);
+  else if (mode == kMeshExactRatio) launch_bin3_m<D, kMeshExactRatio>(hm, grid, block, lds, s, a);
+  else launch_bin3_m<D, kMeshGeneral>(hm, grid, block, lds, s, a);
+}
+
+static void launch_bin3_d(uint32_t d, uint32_t mode, int hm, dim3 grid, dim3 block, uint32_t lds, hipStream_t s,
+                          const BinArgs& a) {
+  switch (d) {
+    case 1: launch_bin3_dm<1>(mode, hm, grid, block, lds, s, a); break;
+    case 2: launch_bin3_dm<2>(mode, hm, grid, block, lds, s, a); break;
+    case 3: launch_bin3_dm<3>(mode, hm, grid, block, lds, s, a); break;
+    case 4: launch_bin3_dm<4>(mode, hm, grid, block, lds, s, a); break;
+    case 5: launch_bin3_dm<5>(mode, hm, grid, block, lds, s, a); break;
+    case 6: launch_bin3_dm<6>(mode, hm, grid, block, lds, s, a); break;
+    case 7: launch_bin3_dm<7>(mode, hm, grid, block, lds, s, a); break;
+    default: launch_bin3_dm<8>(mode, hm, grid, block, lds, s, a); break;
+  }
+}
+
 hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
                       uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, hipStream_t s) {
   BinArgs a;
@@ -421,31 +458,10 @@ hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
   a.M = M;
   a.err = err;
   a.tabi = t.tabi;
+  a.tabp = t.tabp;
   if (plan.fast) {
     const dim3 grid(plan.nwg), block(kBin2Threads);
-#define CSK_BIN3(DD)                                                                                          \
-  switch (mesh.mode) {                                                                                       \
-    case kMeshPow2Ratio:                                                                                     \
-      hipLaunchKernelGGL((bin3_kernel<DD, kMeshPow2Ratio, kBin2Threads, kBin2Rows>), grid, block, plan.lds_bytes, s, a); \
-      break;                                                                                                 \
-    case kMeshExactRatio:                                                                                    \
-      hipLaunchKernelGGL((bin3_kernel<DD, kMeshExactRatio, kBin2Threads, kBin2Rows>), grid, block, plan.lds_bytes, s, a); \
-      break;                                                                                                 \
-    default:                                                                                                 \
-      hipLaunchKernelGGL((bin3_kernel<DD, kMeshGeneral, kBin2Threads, kBin2Rows>), grid, block, plan.lds_bytes, s, a); \
-      break;                                                                                                 \
-  }
-    switch (t.d) {
-      case 1: CSK_BIN3(1); break;
-      case 2: CSK_BIN3(2); break;
-      case 3: CSK_BIN3(3); break;
-      case 4: CSK_BIN3(4); break;
-      case 5: CSK_BIN3(5); break;
-      case 6: CSK_BIN3(6); break;
-      case 7: CSK_BIN3(7); break;
-      default: CSK_BIN3(8); break;
-    }
-#undef CSK_BIN3
+    launch_bin3_d(t.d, mesh.mode, t.hash_mode(), grid, block, plan.lds_bytes, s, a);
   } else {
     hipLaunchKernelGGL(bin_kernel<false>, dim3(plan.nwg), dim3(kBinThreads), plan.lds_bytes, s, a);
   }
@@ -674,7 +690,7 @@ __global__ __launch_bounds__(256) void collect_kernel(const float* __restrict__ 
 // without touching the counters; the rest take the exact test.  Each thread loads
 // kCollectPPT particles before working on any of them, so that enough position loads
 // are in flight to cover HBM latency at one workgroup per CU.
-template <int D, uint32_t MODE>
+template <int D, uint32_t MODE, int HM>
 __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* __restrict__ pos, uint64_t n, Mesh mesh,
                                                                    Tables t, const int32_t* __restrict__ M,
                                                                    int32_t theta, const uint32_t* __restrict__ filter,
@@ -683,7 +699,7 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
                                                                    uint64_t* set, uint32_t slot_mask,
                                                                    uint32_t* set_count, uint32_t max_cand,
                                                                    uint32_t* err) {
-  constexpr int DP = RowPad<D>::value;
+  constexpr int DP = HashWords<D, HM>::value;
   constexpr int PPT = kCollectPPT;
   extern __shared__ __align__(16) uint32_t lds3[];
   uint32_t* ti = lds3;
@@ -696,7 +712,7 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
   if (uf)
     for (uint32_t i = threadIdx.x; i < (uint32_t)kFilterWords; i += blockDim.x) filt[i] = filter[i];
   for (uint32_t i = threadIdx.x; i < (uint32_t)kCollectCache; i += blockDim.x) cache[i] = kEmptyKey;
-  stage_tables<DP>(ti, t.tabi, mesh.nch);
+  stage_tables<DP>(ti, HM == kHashPacked ? t.tabp : t.tabi, mesh.nch);
   constexpr uint32_t kNeedCS = D - ((D - 1) >> 1);
   const uint32_t need = t.cm ? (uint32_t)D : kNeedCS;
   constexpr uint32_t NT = kCollectThreads;
@@ -726,14 +742,13 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
       bad |= in && !ok;
       bool go = in && ok;
       if (uf) {
-        uint32_t h[DP];
-        row_hashes<DP>(ti, keys[j], mesh.nch, h);
+        uint32_t bk[D], sg[D];
+        rows_bucket_sign<D, HM>(ti, keys[j], mesh.nch, t.w, t.wshift, bk, sg);
         uint32_t fp = 0;
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-          const uint32_t bk = bucket_of(h[r], t.w, t.wshift);
-          const uint32_t ng = (h[r] >> 31) & (t.cm ^ 1u);
-          const FilterProbe pr = filter_probe((uint32_t)r, bk, ng, t.bnorm);
+          const uint32_t ng = sg[r] & (t.cm ^ 1u);
+          const FilterProbe pr = filter_probe((uint32_t)r, bk[r], ng, t.bnorm);
           fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
         }
         go = go && fp >= need;
@@ -753,14 +768,10 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
         __hip_atomic_store(&cache[ci], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         continue;
       }
-      uint32_t h[DP];
-      row_hashes<DP>(ti, key, mesh.nch, h);
       uint32_t bk[D], ng[D];
+      rows_bucket_sign<D, HM>(ti, key, mesh.nch, t.w, t.wshift, bk, ng);
 #pragma unroll
-      for (int r = 0; r < D; ++r) {
-        bk[r] = bucket_of(h[r], t.w, t.wshift);
-        ng[r] = (h[r] >> 31) & (t.cm ^ 1u);
-      }
+      for (int r = 0; r < D; ++r) ng[r] &= t.cm ^ 1u;
       uint32_t pass = 0;
       if (uh) {
         // row r passes (sign * M >= theta) exactly when its item is in the hot set
@@ -917,6 +928,64 @@ hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta,
   return hipGetLastError();
 }
 
+struct CollectArgs {
+  const float* pos;
+  uint64_t n;
+  Mesh mesh;
+  Tables t;
+  const int32_t* M;
+  int32_t theta;
+  const uint32_t* filter;
+  const uint32_t* hot;
+  uint32_t use_filter;
+  const uint32_t* hot_table;
+  uint64_t* set;
+  uint32_t slot_mask;
+  uint32_t* set_count;
+  uint32_t max_cand;
+  uint32_t* err;
+};
+
+template <int D, uint32_t MM, int HM>
+static void launch_collect2_one(dim3 grid, dim3 block, size_t lds, hipStream_t s, const CollectArgs& c) {
+  hipLaunchKernelGGL((collect2_kernel<D, MM, HM>), grid, block, lds, s, c.pos, c.n, c.mesh, c.t, c.M, c.theta,
+                     c.filter, c.hot, c.use_filter, c.hot_table, c.set, c.slot_mask, c.set_count, c.max_cand, c.err);
+}
+
+template <int D, uint32_t MM>
+static void launch_collect2_m(int hm, dim3 grid, dim3 block, size_t lds, hipStream_t s, const CollectArgs& c) {
+  if constexpr (D >= 5) {
+    if (hm == kHashPacked) {
+      launch_collect2_one<D, MM, kHashPacked>(grid, block, lds, s, c);
+      return;
+    }
+  }
+  if (hm == kHashMulHi) launch_collect2_one<D, MM, kHashMulHi>(grid, block, lds, s, c);
+  else launch_collect2_one<D, MM, kHashShift>(grid, block, lds, s, c);
+}
+
+template <int D>
+static void launch_collect2_dm(uint32_t mode, int hm, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                               const CollectArgs& c) {
+  if (mode == kMeshPow2Ratio) launch_collect2_m<D, kMeshPow2Ratio>(hm, grid, block, lds, s, c);
+  else if (mode == kMeshExactRatio) launch_collect2_m<D, kMeshExactRatio>(hm, grid, block, lds, s, c);
+  else launch_collect2_m<D, kMeshGeneral>(hm, grid, block, lds, s, c);
+}
+
+static void launch_collect2_d(uint32_t d, uint32_t mode, int hm, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                              const CollectArgs& c) {
+  switch (d) {
+    case 1: launch_collect2_dm<1>(mode, hm, grid, block, lds, s, c); break;
+    case 2: launch_collect2_dm<2>(mode, hm, grid, block, lds, s, c); break;
+    case 3: launch_collect2_dm<3>(mode, hm, grid, block, lds, s, c); break;
+    case 4: launch_collect2_dm<4>(mode, hm, grid, block, lds, s, c); break;
+    case 5: launch_collect2_dm<5>(mode, hm, grid, block, lds, s, c); break;
+    case 6: launch_collect2_dm<6>(mode, hm, grid, block, lds, s, c); break;
+    case 7: launch_collect2_dm<7>(mode, hm, grid, block, lds, s, c); break;
+    default: launch_collect2_dm<8>(mode, hm, grid, block, lds, s, c); break;
+  }
+}
+
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,
                           int32_t theta, const uint32_t* filter, const uint32_t* hot, const uint32_t* hot_table,
                           uint64_t* set, uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
@@ -926,27 +995,9 @@ hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const 
     const size_t lds = ((size_t)kTableWords * t.dp + 2 * kCollectCache + (use_filter ? kFilterWords : 0)) *
                        sizeof(uint32_t);
     const dim3 grid(grid_for((n + kCollectPPT - 1) / kCollectPPT, kCollectThreads, 256)), block(kCollectThreads);
-#define CSK_COLLECT2_M(DD, MM)                                                                             \
-  hipLaunchKernelGGL((collect2_kernel<DD, MM>), grid, block, lds, s, pos, n, mesh, t, M, theta, filter, hot,      \
-                     use_filter, hot_table, set, slot_mask, set_count, max_cand, err)
-#define CSK_COLLECT2(DD)                                                                                   \
-  switch (mesh.mode) {                                                                                     \
-    case kMeshPow2Ratio: CSK_COLLECT2_M(DD, kMeshPow2Ratio); break;                                        \
-    case kMeshExactRatio: CSK_COLLECT2_M(DD, kMeshExactRatio); break;                                      \
-    default: CSK_COLLECT2_M(DD, kMeshGeneral); break;                                                      \
-  }
-    switch (t.d) {
-      case 1: CSK_COLLECT2(1); break;
-      case 2: CSK_COLLECT2(2); break;
-      case 3: CSK_COLLECT2(3); break;
-      case 4: CSK_COLLECT2(4); break;
-      case 5: CSK_COLLECT2(5); break;
-      case 6: CSK_COLLECT2(6); break;
-      case 7: CSK_COLLECT2(7); break;
-      default: CSK_COLLECT2(8); break;
-    }
-#undef CSK_COLLECT2
-#undef CSK_COLLECT2_M
+    const CollectArgs ca{pos, n, mesh, t, M, theta, filter, hot, use_filter, hot_table, set, slot_mask, set_count,
+                         max_cand, err};
+    launch_collect2_d(t.d, mesh.mode, t.hash_mode(), grid, block, lds, s, ca);
   } else {
     hipLaunchKernelGGL(collect_kernel<false>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, pos, n, mesh, t, M, theta,
                        set, slot_mask, set_count, max_cand, err);

@@ -140,6 +140,14 @@ CASES = [
     (90_000, 5, 3333, 123.456, 0.123456, 19, 0),
     (100_000, 5, 1 << 16, 100.0, 0.1, 14, 1),
     (100_000, 7, 999, 3000.0, 0.5, 15, 1),
+    # packed hash fields (w = 2^lw, lw + 1 <= floor(128 / d)) at each d's largest lw, and the
+    # shift path one step beyond it
+    (120_000, 5, 1 << 24, 1000.0, 0.25, 25, 0),
+    (80_000, 6, 1 << 20, 1000.0, 0.25, 20, 0),
+    (80_000, 6, 1 << 21, 1000.0, 0.25, 21, 0),
+    (80_000, 7, 1 << 17, 100.0, 0.1, 22, 0),
+    (80_000, 8, 1 << 15, 100.0, 0.1, 23, 1),
+    (80_000, 8, 1 << 16, 100.0, 0.1, 24, 0),
 ]
 
 
@@ -304,7 +312,8 @@ def test_topk_ties_and_sizes(k):
 
 
 @pytest.mark.parametrize("d,w,theta,variant", [(8, 4096, 3, 0), (9, 4096, 3, 0), (6, 2000, 4, 0),
-                                               (3, 1000, 20, 1), (5, 1 << 12, 1, 0)])
+                                               (3, 1000, 20, 1), (5, 1 << 12, 1, 0), (5, 1 << 16, 3, 0),
+                                               (6, 1 << 14, 3, 0), (7, 1 << 10, 3, 1)])
 def test_topk_filtered_collect(d, w, theta, variant):
     # theta > 0 puts a Bloom filter of hot (row, bucket, sign) items in front of the
     # exact test (d <= 8); theta = 1 makes the filter too dense, so it is skipped
