@@ -315,12 +315,19 @@ __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
     for (int r0 = 0; r0 < D; r0 += RP) {
       const int nr = (D - r0 < RP) ? D - r0 : RP;
       if (pending) write_out();
-      static_assert((RP == 1 || RP == 2) && RP * TILE <= 65536, "ranks are packed two per word");
-      uint32_t rk[PPT];   // rank of row r0 in the low half, of row r0 + 1 in the high half
+      static_assert(RP >= 1 && RP <= 4 && RP * TILE <= 65536, "ranks are packed two per word");
+      // rank of row r0 + q: low half of rk[q / 2] for even q, high half for odd q
+      uint32_t rk[(RP + 1) / 2][PPT];
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        rk[j] = atomicAdd(&hist[sv[r0][j] >> 16], 1u);
-        if (RP > 1 && nr > 1) rk[j] |= atomicAdd(&hist[sv[r0 + 1 < D ? r0 + 1 : r0][j] >> 16], 1u) << 16;
+#pragma unroll
+        for (int q = 0; q < RP; ++q) {
+          if (q < nr) {
+            const uint32_t x = atomicAdd(&hist[sv[(r0 + q < D) ? r0 + q : r0][j] >> 16], 1u);
+            if (q & 1) rk[q >> 1][j] |= x << 16;
+            else rk[q >> 1][j] = x;
+          }
+        }
       }
       __syncthreads();  // counts complete; the previous pass is written out
       uint32_t cnt_local = 0;
@@ -355,11 +362,13 @@ __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        const uint32_t v0 = sv[r0][j];
-        stage[base[v0 >> 16] + (rk[j] & 0xFFFFu)] = v0;
-        if (RP > 1 && nr > 1) {
-          const uint32_t v1 = sv[r0 + 1 < D ? r0 + 1 : r0][j];
-          stage[base[v1 >> 16] + (rk[j] >> 16)] = v1;
+#pragma unroll
+        for (int q = 0; q < RP; ++q) {
+          if (q < nr) {
+            const uint32_t v = sv[(r0 + q < D) ? r0 + q : r0][j];
+            const uint32_t r = (q & 1) ? (rk[q >> 1][j] >> 16) : (rk[q >> 1][j] & 0xFFFFu);
+            stage[base[v >> 16] + r] = v;
+          }
         }
       }
       __syncthreads();
