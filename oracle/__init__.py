@@ -57,6 +57,7 @@ def _load():
         "orc_histogram": (i64, [P, u64, P, P]),
         "orc_topk_sketch": (i64, [P, P, u32, u32, C.c_int, P, u64, f64, f64, i32, u64, P, P, P]),
         "orc_topk_exact": (i64, [P, P, u64, u64, P, P]),
+        "orc_topk_dictionary": (i64, [P, P, u32, u32, C.c_int, i64, i32, u64, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -208,6 +209,18 @@ def topk_sketch(M, T, pos, delta, L, theta, k, variant=VARIANT_CS):
     m = _load().orc_topk_sketch(_p(np.ascontiguousarray(M)), _p(np.ascontiguousarray(T)), d, w,
                                 variant, _p(a), a.shape[0], delta, L, theta, k,
                                 _p(ko), _p(eo), C.byref(st))
+    return ko[:m].copy(), eo[:m].copy(), st.value
+
+
+def topk_dictionary(M, T, G, theta, k, variant=VARIANT_CS):
+    """Top-k over every key of the G^3 mesh (CSFS).  Returns (keys, est, status)."""
+    d, w = M.shape
+    Mc = np.ascontiguousarray(M, dtype=np.int32)
+    Tc = np.ascontiguousarray(T, dtype=np.uint32)
+    ko = np.empty(max(k, 1), dtype=np.uint64)
+    eo = np.empty(max(k, 1), dtype=np.int32)
+    st = C.c_int32(0)
+    m = _load().orc_topk_dictionary(_p(Mc), _p(Tc), d, w, variant, G, theta, k, _p(ko), _p(eo), C.byref(st))
     return ko[:m].copy(), eo[:m].copy(), st.value
 
 

@@ -20,6 +20,7 @@
  *   exact      histogram by sort + run-length                        (Sec. 4.2, exact algorithm)
  *   top-k      distinct stream cells with estimate >= theta ordered by (estimate desc, key asc)
  *              (Sec. 2.2 UpdateHeap / Alg. 1 query loop; Sec. 3.1 item 4 threshold array)
+ *   full search the same over every key of the G^3 dictionary      (Sec. 2.2 item 1, CSFS; Alg. 1)
  *
  * Readings of points the paper leaves open (hash family, cell-ID formula, even-row
  * median, tie order, counter width) are the ones listed in the design notes; each
@@ -369,6 +370,49 @@ int64_t orc_topk_sketch(const int32_t *M, const uint32_t *T, uint32_t d, uint32_
     free(uniq);
     free(keys);
     return out;
+}
+
+/* Top-k over the whole dictionary (Count Sketch with Full Search): every cell key of
+ * the G^3 mesh, whether or not a particle fell in it, is estimated; the keys with
+ * estimate >= theta are ordered by (estimate desc, key asc) and the first min(k, |C|)
+ * are written.  Sec. 2.2 item 1 (CSFS: estimate each possible item of the dictionary
+ * and find the top k) and Alg. 1 (query loop over the dictionary).  `*status` is
+ * ORC_W_INCOMPLETE when fewer than k keys passed a theta above INT32_MIN, else ORC_OK;
+ * ORC_E_INVALID for G < 1 or G^3 above 2^32 keys (the oracle keeps every passing key in
+ * memory).  Returns the number written. */
+int64_t orc_topk_dictionary(const int32_t *M, const uint32_t *T, uint32_t d, uint32_t w, int variant,
+                            int64_t G, int32_t theta, uint64_t k,
+                            uint64_t *keys_out, int32_t *est_out, int32_t *status)
+{
+    if (G < 1 || G > 1625) {   /* 1625^3 < 2^32 */
+        *status = ORC_E_INVALID;
+        return 0;
+    }
+    const uint64_t nkeys = (uint64_t)G * (uint64_t)G * (uint64_t)G;
+    uint64_t cap = 1024, c = 0;
+    orc_item *items = (orc_item *)malloc(sizeof(orc_item) * cap);
+    for (uint64_t key = 0; key < nkeys; ++key) {
+        int32_t est;
+        orc_estimate(M, T, d, w, variant, &key, 1, &est);
+        if (est >= theta) {
+            if (c == cap) {
+                cap *= 2;
+                items = (orc_item *)realloc(items, sizeof(orc_item) * cap);
+            }
+            items[c].key = key;
+            items[c].value = est;
+            ++c;
+        }
+    }
+    qsort(items, (size_t)c, sizeof(orc_item), cmp_item);
+    uint64_t out = (c < k) ? c : k;
+    for (uint64_t j = 0; j < out; ++j) {
+        keys_out[j] = items[j].key;
+        est_out[j] = (int32_t)items[j].value;
+    }
+    *status = (out < k && theta != INT32_MIN) ? ORC_W_INCOMPLETE : ORC_OK;
+    free(items);
+    return (int64_t)out;
 }
 
 /* Exact top-k: the distinct keys ordered by (exact count desc, key asc), first k.

@@ -480,3 +480,50 @@ def test_small_workload_recall():
     rel = np.array([abs(int(e) - fmap[k]) / fmap[k] for k, e in zip(ks.tolist(), es.tolist())])
     assert strict >= 0.95 and tie_tolerant >= 0.95
     assert np.median(rel) < 0.05 and rel.max() < 0.25
+
+
+def test_dictionary_topk_brute_force_and_semantics():
+    # Count Sketch with Full Search (Sec. 2.2 item 1; Alg. 1): every key of the G^3 mesh is
+    # estimated, occupied or not.  Checked against a Python selection over all keys, with the
+    # estimates recomputed row by row from the counters (Sec. 2.2 Estimate).
+    G, d, w, seed, L = 12, 5, 256, 4, 12.0
+    rng = np.random.default_rng(7)
+    pos = (rng.random((3000, 3)) ** 2 * L).astype(np.float32)   # skewed occupancy
+    M, _ = oracle.sketch(pos, d, w, seed, 1.0, L)
+    T = oracle.hash_tables(seed, d)
+    keys = np.arange(G ** 3, dtype=np.uint64)
+    rows = per_row_estimates(M.astype(np.int64), T, keys)         # [d][G^3] signed row estimates
+    est = np.sort(rows, axis=0)[(d - 1) // 2].astype(np.int64)   # lower median
+    for theta, k in [(oracle.INT32_MIN, 40), (3, 40), (3, 10 ** 5), (int(est.max()) + 1, 5)]:
+        order = sorted((int(-e), int(kk)) for kk, e in zip(keys, est) if e >= theta)[:k]
+        ks, es, st = oracle.topk_dictionary(M, T, G, theta, k)
+        assert [int(x) for x in ks] == [kk for _, kk in order]
+        assert [int(x) for x in es] == [-e for e, _ in order]
+        short = len(order) < k and theta != oracle.INT32_MIN
+        assert st == (oracle.W_INCOMPLETE if short else oracle.OK)
+    # an invalid mesh is refused
+    _, _, st = oracle.topk_dictionary(M, T, 0, 0, 5)
+    assert st == oracle.E_INVALID
+
+
+def test_dictionary_topk_without_collisions_is_exact():
+    # With w far above the number of occupied cells every estimate is exact (no collision in
+    # a majority of rows), so the dictionary top-k is the exact top-k of the stream followed,
+    # for theta = INT32_MIN, by empty cells (estimate 0) in key order (Sec. 2.2).
+    G, d, w, seed, L = 10, 5, 1 << 16, 9, 10.0
+    rng = np.random.default_rng(3)
+    centres = rng.random((6, 3)) * L
+    pos = np.concatenate([c + rng.normal(0, 0.3, (400, 3)) for c in centres]) % L
+    pos = pos.astype(np.float32)
+    M, _ = oracle.sketch(pos, d, w, seed, 1.0, L)
+    T = oracle.hash_tables(seed, d)
+    uniq, f = oracle.histogram(oracle.keys(pos, 1.0, L))
+    est = oracle.estimate(M, T, uniq)
+    assert np.array_equal(est, f)   # no collisions at this width
+    k = len(uniq) + 20
+    ks, es, st = oracle.topk_dictionary(M, T, G, oracle.INT32_MIN, k)
+    kx, fx = oracle.topk_exact(uniq, f, len(uniq))
+    assert st == oracle.OK
+    assert np.array_equal(ks[:len(uniq)], kx) and np.array_equal(es[:len(uniq)], fx)
+    empty = [x for x in range(G ** 3) if x not in set(uniq.tolist())][:20]
+    assert ks[len(uniq):].tolist() == empty and not es[len(uniq):].any()
