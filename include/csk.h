@@ -108,6 +108,13 @@ csk_status csk_cell_keys(const float *pos, uint64_t n, double delta, double L, u
 csk_status csk_collect(csk_sketch *s, const float *pos, uint64_t n, double delta, double L,
                        int32_t theta, void *stream);
 
+/* Candidate pass over the whole dictionary (Count Sketch with Full Search: Sec. 2.2
+ * item 1, Alg. 1): every cell key of the G^3 mesh, G = round(L / delta), occupied or
+ * not, whose estimate is >= theta is added to the candidate set; no positions are
+ * read.  (delta, L) are validated and latched as in csk_collect, and the set, its
+ * capacity and csk_topk behave as after csk_collect.  Asynchronous on `stream`. */
+csk_status csk_collect_dictionary(csk_sketch *s, double delta, double L, int32_t theta, void *stream);
+
 /* Empty the candidate set. */
 csk_status csk_candidates_clear(csk_sketch *s, void *stream);
 

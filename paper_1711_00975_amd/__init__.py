@@ -34,7 +34,8 @@ CSK_DEFAULT_CANDIDATES = 1 << 21
 INT32_MIN = -(2 ** 31)
 
 EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_destroy", "csk_sketch_update",
-           "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_candidates_clear", "csk_topk",
+           "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_collect_dictionary", "csk_candidates_clear",
+           "csk_topk",
            "csk_get_counters", "csk_set_counters", "csk_reset", "csk_check", "csk_device_bytes",
            "csk_last_error"]
 
@@ -67,6 +68,7 @@ def load_library(path: str = LIB_PATH):
         "csk_sketch_query": [P, P, u64, P, P],
         "csk_cell_keys": [P, u64, f64, f64, P, P],
         "csk_collect": [P, P, u64, f64, f64, i32, P],
+        "csk_collect_dictionary": [P, f64, f64, i32, P],
         "csk_candidates_clear": [P, P],
         "csk_topk": [P, u32, P, P, C.POINTER(C.c_uint32), P],
         "csk_get_counters": [P, P, P],
@@ -161,6 +163,10 @@ def csk_collect(h, pos, delta: float, L: float, theta: int, stream=None) -> None
                                       _stream(stream)))
 
 
+def csk_collect_dictionary(h, delta: float, L: float, theta: int, stream=None) -> None:
+    _check(load_library().csk_collect_dictionary(h, delta, L, theta, _stream(stream)))
+
+
 def csk_candidates_clear(h, stream=None) -> None:
     _check(load_library().csk_candidates_clear(h, _stream(stream)))
 
@@ -240,6 +246,9 @@ class Sketch:
 
     def collect(self, pos, delta, L, theta=INT32_MIN, stream=None):
         csk_collect(self.h, pos, delta, L, theta, stream)
+
+    def collect_dictionary(self, delta, L, theta=INT32_MIN, stream=None):
+        csk_collect_dictionary(self.h, delta, L, theta, stream)
 
     def clear_candidates(self, stream=None):
         csk_candidates_clear(self.h, stream)

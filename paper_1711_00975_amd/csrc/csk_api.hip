@@ -389,6 +389,30 @@ csk_status csk_collect(csk_sketch* s, const float* pos, uint64_t n, double delta
   return CSK_OK;
 }
 
+csk_status csk_collect_dictionary(csk_sketch* s, double delta, double L, int32_t theta, void* stream) {
+  if (s == nullptr) return fail(CSK_E_INVALID, "collect_dictionary: NULL handle");
+  Mesh mesh;
+  csk_status rc = check_mesh(s, delta, L, &mesh);
+  if (rc != CSK_OK) return rc;
+  latch_mesh(s, delta, L, mesh);
+  if (theta != INT32_MIN) s->partial_set = true;
+  hipStream_t st = (hipStream_t)stream;
+  const Tables t = s->tables();
+  const uint32_t* filter = nullptr;
+  const uint32_t* hot = nullptr;
+  if (s->filter != nullptr && theta > 0) {
+    CSK_HIP(launch_filter_build(t, s->M, theta, s->filter, s->filter + kFilterWords, s->hot_table, st),
+            "collect_dictionary (filter)");
+    filter = s->filter;
+    hot = s->filter + kFilterWords;
+  }
+  const uint64_t nkeys = (uint64_t)mesh.G * mesh.G * mesh.G;
+  CSK_HIP(launch_collect_dictionary(nkeys, mesh, t, s->M, theta, filter, hot, filter ? s->hot_table : nullptr, s->set,
+                                    s->slots - 1, s->set_count(), s->max_cand, s->err(), st),
+          "collect_dictionary");
+  return CSK_OK;
+}
+
 csk_status csk_candidates_clear(csk_sketch* s, void* stream) {
   if (s == nullptr) return fail(CSK_E_INVALID, "candidates_clear: NULL handle");
   return clear_candidates(s, (hipStream_t)stream);

@@ -89,6 +89,12 @@ hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const 
                           int32_t theta, const uint32_t* filter, const uint32_t* hot, const uint32_t* hot_table,
                           uint64_t* set, uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
                           hipStream_t s);
+// Candidate pass over every key in [0, nkeys) (the whole G^3 dictionary); arguments as
+// launch_collect without the positions.
+hipError_t launch_collect_dictionary(uint64_t nkeys, const Mesh& mesh, const Tables& t, const int32_t* M,
+                                     int32_t theta, const uint32_t* filter, const uint32_t* hot,
+                                     const uint32_t* hot_table, uint64_t* set, uint32_t slot_mask,
+                                     uint32_t* set_count, uint32_t max_cand, uint32_t* err, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,

@@ -816,6 +816,95 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
   if (bad) atomicOr(err, kErrDomain);
 }
 
+// Candidate pass over the whole dictionary (Count Sketch with Full Search, Sec. 2.2
+// item 1; Alg. 1): every key in [0, nkeys) is estimated once, so no key cache or set
+// lookup is needed.  Keys whose rows pass the Bloom filter fewer than `need` times are
+// dropped; the rest take the exact test (hot-item set or counter reads) and, if they
+// pass, go into the set.  d <= 8, tables in LDS.
+template <int D, int HM>
+__global__ __launch_bounds__(kCollectThreads) void dict_collect_kernel(uint64_t nkeys, Mesh mesh, Tables t,
+                                                                       const int32_t* __restrict__ M, int32_t theta,
+                                                                       const uint32_t* __restrict__ filter,
+                                                                       const uint32_t* __restrict__ hot,
+                                                                       uint32_t use_filter,
+                                                                       const uint32_t* __restrict__ hot_table,
+                                                                       uint64_t* set, uint32_t slot_mask,
+                                                                       uint32_t* set_count, uint32_t max_cand,
+                                                                       uint32_t* err) {
+  constexpr int DP = HashWords<D, HM>::value;
+  extern __shared__ __align__(16) uint32_t lds4[];
+  uint32_t* ti = lds4;
+  uint32_t* filt = ti + kTableWords * DP;
+  const uint32_t nhot = use_filter ? *hot : 0xFFFFFFFFu;
+  const bool uf = use_filter && nhot <= kFilterMaxItems;
+  const bool uh = use_filter && hot_table != nullptr && nhot <= kHotMaxItems;
+  if (uf)
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kFilterWords; i += blockDim.x) filt[i] = filter[i];
+  stage_tables<DP>(ti, HM == kHashPacked ? t.tabp : t.tabi, mesh.nch);
+  constexpr uint32_t kNeedCS = D - ((D - 1) >> 1);
+  const uint32_t need = t.cm ? (uint32_t)D : kNeedCS;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t key = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; key < nkeys; key += stride) {
+    uint32_t bk[D], ng[D];
+    rows_bucket_sign<D, HM>(ti, key, mesh.nch, t.w, t.wshift, bk, ng);
+#pragma unroll
+    for (int r = 0; r < D; ++r) ng[r] &= t.cm ^ 1u;
+    if (uf) {
+      uint32_t fp = 0;
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        const FilterProbe pr = filter_probe((uint32_t)r, bk[r], ng[r], t.bnorm);
+        fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
+      }
+      if (fp < need) continue;
+    }
+    uint32_t pass = 0;
+    if (uh) {
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        if (pass >= need || pass + (uint32_t)(D - r) < need) break;
+        const uint32_t item = hot_item((uint32_t)r, bk[r], ng[r]);
+        uint32_t sl = hot_slot(item);
+        for (uint32_t probe = 0; probe < kHotSlots; ++probe) {
+          const uint32_t v = hot_table[sl];
+          if (v == item) {
+            ++pass;
+            break;
+          }
+          if (v == kHotEmpty) break;
+          sl = (sl + 1) & (kHotSlots - 1);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        if (pass >= need || pass + (uint32_t)(D - r) < need) break;
+        const uint32_t c = (uint32_t)M[(uint64_t)r * t.w + bk[r]];
+        if ((int32_t)(ng[r] ? 0u - c : c) >= theta) ++pass;
+      }
+    }
+    if (pass >= need) set_insert(set, slot_mask, key, set_count, max_cand, err);
+  }
+}
+
+// The same for any d, with row-major tables read from global memory (d > 8).
+__global__ __launch_bounds__(256) void dict_collect_generic_kernel(uint64_t nkeys, Tables t,
+                                                                   const int32_t* __restrict__ M, int32_t theta,
+                                                                   uint64_t* set, uint32_t slot_mask,
+                                                                   uint32_t* set_count, uint32_t max_cand,
+                                                                   uint32_t* err) {
+  const uint32_t need = t.cm ? t.d : t.d - ((t.d - 1) >> 1);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t key = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; key < nkeys; key += stride) {
+    uint32_t pass = 0;
+    for (uint32_t r = 0; r < t.d; ++r) {
+      if (pass >= need || pass + (t.d - r) < need) break;
+      if (row_estimate(t.tab + r * kTableWords, M + (uint64_t)r * t.w, t.w, t.cm, key) >= theta) ++pass;
+    }
+    if (pass >= need) set_insert(set, slot_mask, key, set_count, max_cand, err);
+  }
+}
+
 // Items (r, b, sign) with sign * M[r][b] >= theta (Count-Min: M[r][b] >= theta) go into
 // the Bloom filter and, when all of them fit, into the exact hot-item set; theta > 0, so
 // empty buckets never do.  *hot counts the items.
@@ -993,6 +1082,65 @@ static void launch_collect2_d(uint32_t d, uint32_t mode, int hm, dim3 grid, dim3
     case 7: launch_collect2_dm<7>(mode, hm, grid, block, lds, s, c); break;
     default: launch_collect2_dm<8>(mode, hm, grid, block, lds, s, c); break;
   }
+}
+
+template <int D, int HM>
+static void launch_dict_one(dim3 grid, dim3 block, size_t lds, hipStream_t s, uint64_t nkeys, const Mesh& mesh,
+                            const Tables& t, const int32_t* M, int32_t theta, const uint32_t* filter,
+                            const uint32_t* hot, uint32_t use_filter, const uint32_t* hot_table, uint64_t* set,
+                            uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err) {
+  hipLaunchKernelGGL((dict_collect_kernel<D, HM>), grid, block, lds, s, nkeys, mesh, t, M, theta, filter, hot,
+                     use_filter, hot_table, set, slot_mask, set_count, max_cand, err);
+}
+
+template <int D>
+static void launch_dict_d(int hm, dim3 grid, dim3 block, size_t lds, hipStream_t s, uint64_t nkeys, const Mesh& mesh,
+                          const Tables& t, const int32_t* M, int32_t theta, const uint32_t* filter,
+                          const uint32_t* hot, uint32_t use_filter, const uint32_t* hot_table, uint64_t* set,
+                          uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err) {
+  if constexpr (D >= 5) {
+    if (hm == kHashPacked) {
+      launch_dict_one<D, kHashPacked>(grid, block, lds, s, nkeys, mesh, t, M, theta, filter, hot, use_filter,
+                                      hot_table, set, slot_mask, set_count, max_cand, err);
+      return;
+    }
+  }
+  if (hm == kHashMulHi)
+    launch_dict_one<D, kHashMulHi>(grid, block, lds, s, nkeys, mesh, t, M, theta, filter, hot, use_filter, hot_table,
+                                   set, slot_mask, set_count, max_cand, err);
+  else
+    launch_dict_one<D, kHashShift>(grid, block, lds, s, nkeys, mesh, t, M, theta, filter, hot, use_filter, hot_table,
+                                   set, slot_mask, set_count, max_cand, err);
+}
+
+hipError_t launch_collect_dictionary(uint64_t nkeys, const Mesh& mesh, const Tables& t, const int32_t* M,
+                                     int32_t theta, const uint32_t* filter, const uint32_t* hot,
+                                     const uint32_t* hot_table, uint64_t* set, uint32_t slot_mask,
+                                     uint32_t* set_count, uint32_t max_cand, uint32_t* err, hipStream_t s) {
+  if (t.d <= (uint32_t)kTabLdsRows) {
+    const uint32_t use_filter = (filter != nullptr && hot != nullptr) ? 1u : 0u;
+    const size_t lds = ((size_t)kTableWords * t.dp + (use_filter ? kFilterWords : 0)) * sizeof(uint32_t);
+    const dim3 grid(grid_for(nkeys, kCollectThreads, 1024)), block(kCollectThreads);
+    const int hm = t.hash_mode();
+#define CSK_DICT(DD)                                                                                    \
+  launch_dict_d<DD>(hm, grid, block, lds, s, nkeys, mesh, t, M, theta, filter, hot, use_filter, hot_table, set, \
+                    slot_mask, set_count, max_cand, err)
+    switch (t.d) {
+      case 1: CSK_DICT(1); break;
+      case 2: CSK_DICT(2); break;
+      case 3: CSK_DICT(3); break;
+      case 4: CSK_DICT(4); break;
+      case 5: CSK_DICT(5); break;
+      case 6: CSK_DICT(6); break;
+      case 7: CSK_DICT(7); break;
+      default: CSK_DICT(8); break;
+    }
+#undef CSK_DICT
+  } else {
+    hipLaunchKernelGGL(dict_collect_generic_kernel, dim3(grid_for(nkeys, 256, 8192)), dim3(256), 0, s, nkeys, t, M,
+                       theta, set, slot_mask, set_count, max_cand, err);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,

@@ -272,7 +272,9 @@ def topk_case(pos, d, w, seed, delta, L, k, theta, variant=0):
     s.collect(dev(pos), delta, L, theta)
     keys, est, rc = s.topk(k)
     T = oracle.hash_tables(seed, d)
-    ko, eo, st = oracle.topk_sketch(M, T, pos, delta, L, theta, k, variant)
+    Mo, _ = oracle.sketch(pos, d, w, seed, delta, L, variant=variant, threads=8)   # the oracle's own counters
+    assert np.array_equal(M, Mo)
+    ko, eo, st = oracle.topk_sketch(Mo, T, pos, delta, L, theta, k, variant)
     assert np.array_equal(keys.cpu().numpy().view(np.uint64), ko)
     assert np.array_equal(est.cpu().numpy(), eo)
     assert rc == (csk.CSK_W_INCOMPLETE if st == oracle.W_INCOMPLETE else csk.CSK_OK)
@@ -343,4 +345,48 @@ def test_candidate_capacity_error():
     s.collect(dev(pos[:500]), 0.1, 100.0, oracle.INT32_MIN)
     keys, est, rc = s.topk(10)
     assert len(keys) == 10
+    s.close()
+
+
+@pytest.mark.parametrize("d,w,G,theta,variant", [
+    (5, 1 << 12, 20, oracle.INT32_MIN, 0),   # every key of the dictionary is a candidate
+    (5, 1 << 16, 40, 3, 0),                  # Bloom filter + exact hot set, packed hash fields
+    (3, 1000, 30, 2, 1),                     # Count-Min, multiply-high buckets
+    (8, 1 << 12, 25, 2, 0),                  # packed fields at d = 8
+    (6, 50000, 30, 4, 0),                    # multiply-high buckets with the filter
+    (9, 4096, 16, 1, 0),                     # d > 8: tables read from global memory
+    (5, 1 << 12, 24, 1 << 20, 0),            # nothing passes: empty result, incomplete
+])
+def test_dictionary_topk_matches_oracle(d, w, G, theta, variant):
+    # Count Sketch with Full Search (Sec. 2.2 item 1; Alg. 1): every key of the G^3 mesh
+    delta = 0.5
+    L = G * delta
+    say("dictionary", d, w, G, theta, variant)
+    pos = clustered(60_000, L, 100 + d, frac=0.7, sigma=0.3)
+    seed = 31 + d
+    s, M = gpu_counters(pos, d, w, seed, delta, L, variant)
+    Mo, _ = oracle.sketch(pos, d, w, seed, delta, L, variant=variant, threads=8)
+    assert np.array_equal(M, Mo)
+    k = 300
+    s.clear_candidates()
+    s.collect_dictionary(delta, L, theta)
+    keys, est, rc = s.topk(k)
+    ko, eo, st = oracle.topk_dictionary(Mo, oracle.hash_tables(seed, d), G, theta, k, variant)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), ko)
+    assert np.array_equal(est.cpu().numpy(), eo)
+    assert rc == (csk.CSK_W_INCOMPLETE if st == oracle.W_INCOMPLETE else csk.CSK_OK)
+    s.close()
+
+
+def test_dictionary_capacity_and_mesh_latch():
+    # More dictionary keys than max_candidates with theta = INT32_MIN latches the capacity
+    # error; a mesh other than the latched one is refused.
+    s = csk.Sketch(5, 1 << 12, 3, max_candidates=1000)
+    s.collect_dictionary(0.5, 10.0, oracle.INT32_MIN)    # 20^3 = 8000 keys
+    with pytest.raises(csk.CskError) as e:
+        s.topk(10)
+    assert e.value.code == csk.CSK_E_CAPACITY
+    with pytest.raises(csk.CskError) as e:
+        s.collect_dictionary(0.25, 10.0, 0)
+    assert e.value.code == csk.CSK_E_STATE
     s.close()
