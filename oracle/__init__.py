@@ -58,6 +58,9 @@ def _load():
         "orc_topk_sketch": (i64, [P, P, u32, u32, C.c_int, P, u64, f64, f64, i32, u64, P, P, P]),
         "orc_topk_exact": (i64, [P, P, u64, u64, P, P]),
         "orc_topk_dictionary": (i64, [P, P, u32, u32, C.c_int, i64, i32, u64, P, P, P]),
+        "orc_sketch_update_keys": (None, [P, P, u32, u32, C.c_int, P, u64]),
+        "orc_topk_hierarchical": (i64, [P, P, u32, u32, P, P, u32, u32, C.c_int, i64, u64, i32, i32, u64,
+                                        P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -221,6 +224,35 @@ def topk_dictionary(M, T, G, theta, k, variant=VARIANT_CS):
     eo = np.empty(max(k, 1), dtype=np.int32)
     st = C.c_int32(0)
     m = _load().orc_topk_dictionary(_p(Mc), _p(Tc), d, w, variant, G, theta, k, _p(ko), _p(eo), C.byref(st))
+    return ko[:m].copy(), eo[:m].copy(), st.value
+
+
+def sketch_keys(keys_, d, w, seed, variant=VARIANT_CS):
+    """Counters of a stream of item keys (uint64), each added once (Sec. 2.2 Add)."""
+    T = hash_tables(seed, d)
+    k = np.ascontiguousarray(keys_, dtype=np.uint64).ravel()
+    M = np.zeros((d, w), dtype=np.int32)
+    _load().orc_sketch_update_keys(_p(M), _p(T), d, w, variant, _p(k), k.size)
+    return M
+
+
+def super_sketch(pos, d, w, seed, delta, L, group, variant=VARIANT_CS):
+    """Counters of the super-item stream key // group (the coarse layer of the hierarchy).
+    Particles outside the domain are skipped, as in sketch()."""
+    return sketch_keys(keys(pos, delta, L) // np.uint64(group), d, w, seed, variant)
+
+
+def topk_hierarchical(M1, T1, M2, T2, G, group, theta1, theta2, k, variant=VARIANT_CS):
+    """Count Sketch Hierarchical query (Alg. 3).  Returns (keys, est, status)."""
+    d1, w1 = M1.shape
+    d2, w2 = M2.shape
+    a1, b1 = np.ascontiguousarray(M1, dtype=np.int32), np.ascontiguousarray(T1, dtype=np.uint32)
+    a2, b2 = np.ascontiguousarray(M2, dtype=np.int32), np.ascontiguousarray(T2, dtype=np.uint32)
+    ko = np.empty(max(k, 1), dtype=np.uint64)
+    eo = np.empty(max(k, 1), dtype=np.int32)
+    st = C.c_int32(0)
+    m = _load().orc_topk_hierarchical(_p(a1), _p(b1), d1, w1, _p(a2), _p(b2), d2, w2, variant, G, group, theta1,
+                                      theta2, k, _p(ko), _p(eo), C.byref(st))
     return ko[:m].copy(), eo[:m].copy(), st.value
 
 

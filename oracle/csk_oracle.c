@@ -21,6 +21,8 @@
  *   top-k      distinct stream cells with estimate >= theta ordered by (estimate desc, key asc)
  *              (Sec. 2.2 UpdateHeap / Alg. 1 query loop; Sec. 3.1 item 4 threshold array)
  *   full search the same over every key of the G^3 dictionary      (Sec. 2.2 item 1, CSFS; Alg. 1)
+ *   hierarchy  super-items key / R in a second sketch; children of heavy super-items only
+ *              (Sec. 2.2 item 3, CSHi; Alg. 3)
  *
  * Readings of points the paper leaves open (hash family, cell-ID formula, even-row
  * median, tie order, counter width) are the ones listed in the design notes; each
@@ -243,6 +245,23 @@ int64_t orc_sketch_update(int32_t *M, const uint32_t *T, uint32_t d, uint32_t w,
     return skipped;
 }
 
+/* Add every given item key to the counters, as orc_sketch_update does for the cell
+ * key of each particle (Sec. 2.2 Add).  Used for the super-item sketch of the
+ * hierarchical variant, whose items are cell keys divided by the group size. */
+void orc_sketch_update_keys(int32_t *M, const uint32_t *T, uint32_t d, uint32_t w, int variant,
+                            const uint64_t *keys, uint64_t m)
+{
+    for (uint64_t j = 0; j < m; ++j) {
+        for (uint32_t r = 0; r < d; ++r) {
+            uint32_t h = orc_row_hash(T, r, keys[j]);
+            uint32_t b = orc_bucket(h, w);
+            int32_t s = (variant == ORC_VARIANT_CM) ? 1 : orc_sign(h);
+            uint32_t *cell = (uint32_t *)&M[(uint64_t)r * w + b];
+            *cell = *cell + (uint32_t)s;
+        }
+    }
+}
+
 /* ------------------------------------------------------- Estimate (O7) */
 
 static int cmp_i32(const void *a, const void *b)
@@ -411,6 +430,59 @@ int64_t orc_topk_dictionary(const int32_t *M, const uint32_t *T, uint32_t d, uin
         est_out[j] = (int32_t)items[j].value;
     }
     *status = (out < k && theta != INT32_MIN) ? ORC_W_INCOMPLETE : ORC_OK;
+    free(items);
+    return (int64_t)out;
+}
+
+/* Top-k of the hierarchical variant (Count Sketch Hierarchical): M1 counts super-items
+ * key / R, M2 counts the cell keys.  Every super-item j of [0, ceil(G^3 / R)) is
+ * estimated from M1; for those with estimate >= theta1, every child key of
+ * [j R, min((j + 1) R, G^3)) is estimated from M2, and the children with estimate >=
+ * theta2 are the candidates, ordered by (estimate desc, key asc); the first min(k, |C|)
+ * are written.  Sec. 2.2 item 3 and Alg. 3 (query: heavy super-items first, then their
+ * items); the paper's strict ">" thresholds are written here as ">=" on the next integer.
+ * `*status` as orc_topk_dictionary (W_INCOMPLETE when fewer than k passed a theta2 above
+ * INT32_MIN); ORC_E_INVALID for G < 1, G^3 above 2^32 or R < 1. */
+int64_t orc_topk_hierarchical(const int32_t *M1, const uint32_t *T1, uint32_t d1, uint32_t w1,
+                              const int32_t *M2, const uint32_t *T2, uint32_t d2, uint32_t w2, int variant,
+                              int64_t G, uint64_t R, int32_t theta1, int32_t theta2, uint64_t k,
+                              uint64_t *keys_out, int32_t *est_out, int32_t *status)
+{
+    if (G < 1 || G > 1625 || R < 1) {
+        *status = ORC_E_INVALID;
+        return 0;
+    }
+    const uint64_t nkeys = (uint64_t)G * (uint64_t)G * (uint64_t)G;
+    const uint64_t nsuper = (nkeys + R - 1) / R;
+    uint64_t cap = 1024, c = 0;
+    orc_item *items = (orc_item *)malloc(sizeof(orc_item) * cap);
+    for (uint64_t j = 0; j < nsuper; ++j) {
+        int32_t e1;
+        orc_estimate(M1, T1, d1, w1, variant, &j, 1, &e1);
+        if (e1 < theta1)
+            continue;
+        const uint64_t hi = (j + 1) * R < nkeys ? (j + 1) * R : nkeys;
+        for (uint64_t key = j * R; key < hi; ++key) {
+            int32_t e2;
+            orc_estimate(M2, T2, d2, w2, variant, &key, 1, &e2);
+            if (e2 < theta2)
+                continue;
+            if (c == cap) {
+                cap *= 2;
+                items = (orc_item *)realloc(items, sizeof(orc_item) * cap);
+            }
+            items[c].key = key;
+            items[c].value = e2;
+            ++c;
+        }
+    }
+    qsort(items, (size_t)c, sizeof(orc_item), cmp_item);
+    uint64_t out = (c < k) ? c : k;
+    for (uint64_t j = 0; j < out; ++j) {
+        keys_out[j] = items[j].key;
+        est_out[j] = (int32_t)items[j].value;
+    }
+    *status = (out < k && theta2 != INT32_MIN) ? ORC_W_INCOMPLETE : ORC_OK;
     free(items);
     return (int64_t)out;
 }

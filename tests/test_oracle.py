@@ -527,3 +527,52 @@ def test_dictionary_topk_without_collisions_is_exact():
     assert np.array_equal(ks[:len(uniq)], kx) and np.array_equal(es[:len(uniq)], fx)
     empty = [x for x in range(G ** 3) if x not in set(uniq.tolist())][:20]
     assert ks[len(uniq):].tolist() == empty and not es[len(uniq):].any()
+
+
+def hier_case():
+    G, L, seed1, seed2, R = 12, 12.0, 41, 42, 7
+    rng = np.random.default_rng(11)
+    pos = (rng.random((4000, 3)) ** 2 * L).astype(np.float32)
+    M1 = oracle.super_sketch(pos, 5, 64, seed1, 1.0, L, R)
+    M2, _ = oracle.sketch(pos, 5, 512, seed2, 1.0, L)
+    return G, L, R, pos, M1, oracle.hash_tables(seed1, 5), M2, oracle.hash_tables(seed2, 5)
+
+
+def test_super_sketch_counts_key_div_group():
+    # The coarse layer adds key // R (Sec. 2.2 item 3: super-items s_j / 1000); with R = 1
+    # it is the plain sketch, and its counters equal a sketch of the divided keys.
+    G, L, R, pos, M1, T1, M2, T2 = hier_case()
+    assert np.array_equal(oracle.super_sketch(pos, 5, 512, 42, 1.0, L, 1), M2)
+    k = oracle.keys(pos, 1.0, L)
+    manual = np.zeros((5, 64), np.int64)
+    for r in range(5):
+        h = oracle.row_hash(T1, r, k // np.uint64(R)).astype(np.uint64)
+        b = (((h & np.uint64(0x7FFFFFFF)) * np.uint64(64)) >> np.uint64(31)).astype(np.int64)
+        np.add.at(manual[r], b, np.where(h >> np.uint64(31), -1, 1))
+    assert np.array_equal(M1, manual.astype(np.int32))
+
+
+def test_hierarchical_topk_brute_force():
+    # Alg. 3 query: heavy super-items by M1, then their children by M2; checked against a
+    # Python walk over all super-items with row-by-row estimates, and against the full
+    # dictionary search when every super-item passes (theta1 = INT32_MIN).
+    G, L, R, pos, M1, T1, M2, T2 = hier_case()
+    nkeys = G ** 3
+    sup = np.arange((nkeys + R - 1) // R, dtype=np.uint64)
+    e1 = np.sort(per_row_estimates(M1.astype(np.int64), T1, sup), axis=0)[2]
+    allk = np.arange(nkeys, dtype=np.uint64)
+    e2 = np.sort(per_row_estimates(M2.astype(np.int64), T2, allk), axis=0)[2]
+    for theta1, theta2, k in [(5, 2, 50), (20, oracle.INT32_MIN, 30), (10 ** 6, 0, 10), (3, 4, 10 ** 5)]:
+        cand = [(int(-e2[c]), c) for j in range(len(sup)) if e1[j] >= theta1
+                for c in range(j * R, min((j + 1) * R, nkeys)) if e2[c] >= theta2]
+        want = sorted(cand)[:k]
+        ks, es, st = oracle.topk_hierarchical(M1, T1, M2, T2, G, R, theta1, theta2, k)
+        assert [int(x) for x in ks] == [c for _, c in want]
+        assert [int(x) for x in es] == [-e for e, _ in want]
+        short = len(want) < k and theta2 != oracle.INT32_MIN
+        assert st == (oracle.W_INCOMPLETE if short else oracle.OK)
+    for theta2 in [oracle.INT32_MIN, 3]:
+        a = oracle.topk_hierarchical(M1, T1, M2, T2, G, R, oracle.INT32_MIN, theta2, 200)
+        b = oracle.topk_dictionary(M2, T2, G, theta2, 200)
+        assert all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[2] == b[2]
+    assert oracle.topk_hierarchical(M1, T1, M2, T2, G, 0, 0, 0, 5)[2] == oracle.E_INVALID
