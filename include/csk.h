@@ -75,6 +75,14 @@ csk_status csk_sketch_init(csk_sketch **out, uint32_t d, uint32_t w, uint64_t se
 csk_status csk_sketch_init_ex(csk_sketch **out, uint32_t d, uint32_t w, uint64_t seed,
                               int32_t variant, uint64_t max_candidates);
 
+/* As csk_sketch_init_ex, for a sketch whose items are cell keys divided by `group`
+ * (1 <= group <= 2^30): the super-items of the hierarchical variant (Sec. 2.2 item 3:
+ * items s_j / 1000; Alg. 3 Add(M1, s_i / 1000)).  Update and collect add and test
+ * key / group; csk_collect_dictionary walks the ceil(G^3 / group) super-items; query
+ * keys are super-items.  group 1 is csk_sketch_init_ex. */
+csk_status csk_sketch_init_group(csk_sketch **out, uint32_t d, uint32_t w, uint64_t seed, int32_t variant,
+                                 uint64_t max_candidates, uint32_t group);
+
 /* Free the handle and all device memory it owns.  Synchronizes the device. */
 csk_status csk_sketch_destroy(csk_sketch *s);
 
@@ -114,6 +122,16 @@ csk_status csk_collect(csk_sketch *s, const float *pos, uint64_t n, double delta
  * read.  (delta, L) are validated and latched as in csk_collect, and the set, its
  * capacity and csk_topk behave as after csk_collect.  Asynchronous on `stream`. */
 csk_status csk_collect_dictionary(csk_sketch *s, double delta, double L, int32_t theta, void *stream);
+
+/* Hierarchical query, second layer (Count Sketch Hierarchical: Sec. 2.2 item 3, Alg. 3).
+ * `coarse` is a handle made by csk_sketch_init_group with group R, whose candidate set
+ * holds super-items (typically from csk_collect_dictionary with threshold theta1);
+ * `fine` is an ordinary handle (group 1) updated with the same stream and mesh.  Every
+ * child cell key of [j R, min((j + 1) R, G^3)) of every super-item j in coarse's set is
+ * estimated from fine's counters; those with estimate >= theta join fine's candidate
+ * set, from which csk_topk selects.  CSK_E_STATE unless both handles latched the same
+ * mesh.  Uses coarse's candidate scratch; asynchronous on `stream`. */
+csk_status csk_collect_children(csk_sketch *fine, csk_sketch *coarse, int32_t theta, void *stream);
 
 /* Empty the candidate set. */
 csk_status csk_candidates_clear(csk_sketch *s, void *stream);

@@ -441,8 +441,9 @@ int64_t orc_topk_dictionary(const int32_t *M, const uint32_t *T, uint32_t d, uin
  * theta2 are the candidates, ordered by (estimate desc, key asc); the first min(k, |C|)
  * are written.  Sec. 2.2 item 3 and Alg. 3 (query: heavy super-items first, then their
  * items); the paper's strict ">" thresholds are written here as ">=" on the next integer.
- * `*status` as orc_topk_dictionary (W_INCOMPLETE when fewer than k passed a theta2 above
- * INT32_MIN); ORC_E_INVALID for G < 1, G^3 above 2^32 or R < 1. */
+ * `*status` is ORC_W_INCOMPLETE when fewer than k were found while either threshold is
+ * above INT32_MIN (then the candidates may not include every key), else ORC_OK;
+ * ORC_E_INVALID for G < 1, G^3 above 2^32 or R < 1. */
 int64_t orc_topk_hierarchical(const int32_t *M1, const uint32_t *T1, uint32_t d1, uint32_t w1,
                               const int32_t *M2, const uint32_t *T2, uint32_t d2, uint32_t w2, int variant,
                               int64_t G, uint64_t R, int32_t theta1, int32_t theta2, uint64_t k,
@@ -482,7 +483,7 @@ int64_t orc_topk_hierarchical(const int32_t *M1, const uint32_t *T1, uint32_t d1
         keys_out[j] = items[j].key;
         est_out[j] = (int32_t)items[j].value;
     }
-    *status = (out < k && theta2 != INT32_MIN) ? ORC_W_INCOMPLETE : ORC_OK;
+    *status = (out < k && (theta1 != INT32_MIN || theta2 != INT32_MIN)) ? ORC_W_INCOMPLETE : ORC_OK;
     free(items);
     return (int64_t)out;
 }

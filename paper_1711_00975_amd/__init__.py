@@ -33,8 +33,8 @@ CSK_MAX_WIDTH = 1 << 30
 CSK_DEFAULT_CANDIDATES = 1 << 21
 INT32_MIN = -(2 ** 31)
 
-EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_destroy", "csk_sketch_update",
-           "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_collect_dictionary", "csk_candidates_clear",
+EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "csk_sketch_destroy", "csk_sketch_update",
+           "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
            "csk_topk",
            "csk_get_counters", "csk_set_counters", "csk_reset", "csk_check", "csk_device_bytes",
            "csk_last_error"]
@@ -63,12 +63,14 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "csk_sketch_init": [PP, u32, u32, u64],
         "csk_sketch_init_ex": [PP, u32, u32, u64, i32, u64],
+        "csk_sketch_init_group": [PP, u32, u32, u64, i32, u64, u32],
         "csk_sketch_destroy": [P],
         "csk_sketch_update": [P, P, u64, f64, f64, P],
         "csk_sketch_query": [P, P, u64, P, P],
         "csk_cell_keys": [P, u64, f64, f64, P, P],
         "csk_collect": [P, P, u64, f64, f64, i32, P],
         "csk_collect_dictionary": [P, f64, f64, i32, P],
+        "csk_collect_children": [P, P, i32, P],
         "csk_candidates_clear": [P, P],
         "csk_topk": [P, u32, P, P, C.POINTER(C.c_uint32), P],
         "csk_get_counters": [P, P, P],
@@ -131,6 +133,13 @@ def csk_sketch_init_ex(d: int, w: int, seed: int, variant: int = CSK_VARIANT_COU
     return h
 
 
+def csk_sketch_init_group(d: int, w: int, seed: int, variant: int = CSK_VARIANT_COUNT_SKETCH,
+                          max_candidates: int = 0, group: int = 1):
+    h = C.c_void_p()
+    _check(load_library().csk_sketch_init_group(C.byref(h), d, w, seed, variant, max_candidates, group))
+    return h
+
+
 def csk_sketch_destroy(h) -> None:
     _check(load_library().csk_sketch_destroy(h))
 
@@ -165,6 +174,10 @@ def csk_collect(h, pos, delta: float, L: float, theta: int, stream=None) -> None
 
 def csk_collect_dictionary(h, delta: float, L: float, theta: int, stream=None) -> None:
     _check(load_library().csk_collect_dictionary(h, delta, L, theta, _stream(stream)))
+
+
+def csk_collect_children(fine, coarse, theta: int, stream=None) -> None:
+    _check(load_library().csk_collect_children(fine, coarse, theta, _stream(stream)))
 
 
 def csk_candidates_clear(h, stream=None) -> None:
@@ -214,9 +227,11 @@ class Sketch:
     """Owns one handle.  d rows ("t" in the paper) by w counters ("b")."""
 
     def __init__(self, d: int, w: int, seed: int, variant: int = CSK_VARIANT_COUNT_SKETCH,
-                 max_candidates: int = 0):
-        self.d, self.w, self.seed, self.variant = d, w, seed, variant
-        self.h = csk_sketch_init_ex(d, w, seed, variant, max_candidates)
+                 max_candidates: int = 0, group: int = 1):
+        """group > 1: the sketch counts super-items (cell key // group), the coarse layer
+        of the hierarchical variant."""
+        self.d, self.w, self.seed, self.variant, self.group = d, w, seed, variant, group
+        self.h = csk_sketch_init_group(d, w, seed, variant, max_candidates, group)
 
     def close(self):
         if self.h is not None:
@@ -249,6 +264,10 @@ class Sketch:
 
     def collect_dictionary(self, delta, L, theta=INT32_MIN, stream=None):
         csk_collect_dictionary(self.h, delta, L, theta, stream)
+
+    def collect_children(self, coarse, theta=INT32_MIN, stream=None):
+        """Children of coarse's candidate super-items with estimate >= theta join this set."""
+        csk_collect_children(self.h, coarse.h, theta, stream)
 
     def clear_candidates(self, stream=None):
         csk_candidates_clear(self.h, stream)

@@ -91,6 +91,7 @@ std::vector<uint32_t> pack_tables(const std::vector<uint32_t>& T, uint32_t d) {
 struct csk_sketch {
   int device = 0;
   uint32_t d = 0, w = 0;
+  uint32_t group = 1;        // items are cell keys / group (hierarchical coarse layer)
   uint64_t seed = 0;
   int32_t variant = CSK_VARIANT_COUNT_SKETCH;
   int32_t* M = nullptr;
@@ -177,6 +178,8 @@ csk_status check_mesh(csk_sketch* s, double delta, double L, Mesh* out) {
   out->Gd = (double)G;
   out->G = (int32_t)G;
   out->nch = key_chars((int32_t)G);
+  out->group = (s != nullptr) ? s->group : 1u;
+  out->ginv = 1.0 / (double)out->group;
   // exact-ratio modes: R = G/L exactly representable with <= 29 significant bits
   out->mode = kMeshGeneral;
   out->R = (double)G / L;
@@ -229,8 +232,14 @@ extern "C" {
 
 csk_status csk_sketch_init_ex(csk_sketch** out, uint32_t d, uint32_t w, uint64_t seed, int32_t variant,
                               uint64_t max_candidates) {
+  return csk_sketch_init_group(out, d, w, seed, variant, max_candidates, 1);
+}
+
+csk_status csk_sketch_init_group(csk_sketch** out, uint32_t d, uint32_t w, uint64_t seed, int32_t variant,
+                                 uint64_t max_candidates, uint32_t group) {
   if (out == nullptr) return fail(CSK_E_INVALID, "init: out is NULL");
   *out = nullptr;
+  if (group < 1 || group > (1u << 30)) return fail(CSK_E_INVALID, "init: group=%u outside [1, 2^30]", group);
   if (d < 1 || d > CSK_MAX_ROWS) return fail(CSK_E_INVALID, "init: d=%u outside [1, %u]", d, CSK_MAX_ROWS);
   if (w < 1 || w > CSK_MAX_WIDTH) return fail(CSK_E_INVALID, "init: w=%u outside [1, 2^30]", w);
   if (variant != CSK_VARIANT_COUNT_SKETCH && variant != CSK_VARIANT_COUNT_MIN)
@@ -241,6 +250,7 @@ csk_status csk_sketch_init_ex(csk_sketch** out, uint32_t d, uint32_t w, uint64_t
   if (!s) return fail(CSK_E_NOMEM, "init: host allocation failed");
   s->d = d;
   s->w = w;
+  s->group = group;
   s->seed = seed;
   s->variant = variant;
   s->max_cand = (uint32_t)max_candidates;
@@ -406,10 +416,31 @@ csk_status csk_collect_dictionary(csk_sketch* s, double delta, double L, int32_t
     filter = s->filter;
     hot = s->filter + kFilterWords;
   }
-  const uint64_t nkeys = (uint64_t)mesh.G * mesh.G * mesh.G;
+  const uint64_t ncells = (uint64_t)mesh.G * mesh.G * mesh.G;
+  const uint64_t nkeys = (ncells + s->group - 1) / s->group;   // the items: cell keys / group
   CSK_HIP(launch_collect_dictionary(nkeys, mesh, t, s->M, theta, filter, hot, filter ? s->hot_table : nullptr, s->set,
                                     s->slots - 1, s->set_count(), s->max_cand, s->err(), st),
           "collect_dictionary");
+  return CSK_OK;
+}
+
+csk_status csk_collect_children(csk_sketch* fine, csk_sketch* coarse, int32_t theta, void* stream) {
+  if (fine == nullptr || coarse == nullptr) return fail(CSK_E_INVALID, "collect_children: NULL handle");
+  if (fine == coarse) return fail(CSK_E_INVALID, "collect_children: fine and coarse are the same handle");
+  if (fine->group != 1) return fail(CSK_E_INVALID, "collect_children: the fine handle has group %u", fine->group);
+  if (!fine->mesh_set || !coarse->mesh_set)
+    return fail(CSK_E_STATE, "collect_children: both handles need a latched mesh (update or collect first)");
+  if (fine->delta != coarse->delta || fine->L != coarse->L)
+    return fail(CSK_E_STATE, "collect_children: the handles latched different meshes");
+  if (fine->device != coarse->device) return fail(CSK_E_INVALID, "collect_children: handles on different devices");
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t ncells = (uint64_t)fine->mesh.G * fine->mesh.G * fine->mesh.G;
+  // the coarse handle's candidate list array and a spare control word serve as scratch
+  CSK_HIP(launch_collect_children(coarse->set, coarse->slots, coarse->cand_key, coarse->ctl + 2, coarse->max_cand,
+                                  coarse->group, ncells, fine->tables(), fine->M, theta, fine->set, fine->slots - 1,
+                                  fine->set_count(), fine->max_cand, fine->err(), st),
+          "collect_children");
+  if (theta != INT32_MIN || coarse->partial_set) fine->partial_set = true;
   return CSK_OK;
 }
 

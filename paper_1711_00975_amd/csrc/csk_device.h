@@ -37,7 +37,21 @@ struct Mesh {
   double R;       // G / L when it is exact (modes 1, 2)
   float Rf;       // G / L as a float (mode 2: a power of two >= 1)
   float twoLf;    // 2L as a float (mode 2: exact)
+  uint32_t group; // items are cell keys divided by `group` (1: the cell keys themselves)
+  double ginv;    // binary64(1 / group)
 };
+
+// Item of a cell key: key / group exactly (the super-items of the hierarchical variant,
+// Sec. 2.2 item 3; group 1 leaves the key alone).  key < 2^48, so key * (1/group) in
+// binary64 is within 1/16 of the quotient and one correction step gives the floor.
+__device__ __forceinline__ uint64_t group_key(uint64_t key, const Mesh& m) {
+  if (m.group == 1u) return key;
+  uint64_t q = (uint64_t)((double)key * m.ginv);
+  const int64_t r = (int64_t)(key - q * (uint64_t)m.group);
+  if (r < 0) --q;
+  else if (r >= (int64_t)m.group) ++q;
+  return q;
+}
 
 // How a mesh's cell index is computed (every mode gives floor(p * G / L) exactly):
 //   general     floor estimate of p*G*(1/L) corrected by the signs of two fma residuals
@@ -90,7 +104,7 @@ __device__ __forceinline__ bool cell_key_m(float x, float y, float z, const Mesh
   const bool ok = (int)cell_index_m<MODE>(x, m, ix) & (int)cell_index_m<MODE>(y, m, iy) &
                   (int)cell_index_m<MODE>(z, m, iz);
   const uint32_t xy = (uint32_t)ix * (uint32_t)m.G + (uint32_t)iy;  // < G^2 <= 2^32
-  key = (uint64_t)xy * (uint64_t)(uint32_t)m.G + (uint64_t)(uint32_t)iz;
+  key = group_key((uint64_t)xy * (uint64_t)(uint32_t)m.G + (uint64_t)(uint32_t)iz, m);
   return ok;
 }
 
@@ -100,12 +114,13 @@ __device__ __forceinline__ bool cell_index(float p, const Mesh& m, int32_t& out)
   return cell_index_m<kMeshGeneral>(p, m, out);
 }
 
-// Cell key (ix * G + iy) * G + iz of one particle; false if it is outside the domain.
+// Cell key (ix * G + iy) * G + iz of one particle (divided by the mesh's group); false
+// if it is outside the domain.
 __device__ __forceinline__ bool cell_key(float x, float y, float z, const Mesh& m, uint64_t& key) {
   int32_t ix, iy, iz;
   const bool ok = (int)cell_index(x, m, ix) & (int)cell_index(y, m, iy) & (int)cell_index(z, m, iz);
   const uint32_t xy = (uint32_t)ix * (uint32_t)m.G + (uint32_t)iy;  // < G^2 <= 2^32
-  key = (uint64_t)xy * (uint64_t)(uint32_t)m.G + (uint64_t)(uint32_t)iz;
+  key = group_key((uint64_t)xy * (uint64_t)(uint32_t)m.G + (uint64_t)(uint32_t)iz, m);
   return ok;
 }
 

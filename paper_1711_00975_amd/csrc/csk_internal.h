@@ -95,6 +95,14 @@ hipError_t launch_collect_dictionary(uint64_t nkeys, const Mesh& mesh, const Tab
                                      int32_t theta, const uint32_t* filter, const uint32_t* hot,
                                      const uint32_t* hot_table, uint64_t* set, uint32_t slot_mask,
                                      uint32_t* set_count, uint32_t max_cand, uint32_t* err, hipStream_t s);
+// Hierarchical query, second layer: list the coarse set's super-items (list_count is
+// zeroed here; more than list_cap latches the capacity error in err), then insert every
+// child key of theirs whose fine estimate is >= theta into the fine set.
+hipError_t launch_collect_children(const uint64_t* coarse_set, uint32_t coarse_slots, uint64_t* list,
+                                   uint32_t* list_count, uint32_t list_cap, uint32_t group, uint64_t ncells,
+                                   const Tables& t, const int32_t* M, int32_t theta, uint64_t* set,
+                                   uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
+                                   hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,

@@ -905,6 +905,69 @@ __global__ __launch_bounds__(256) void dict_collect_generic_kernel(uint64_t nkey
   }
 }
 
+// The keys of a candidate set as a list (order unspecified): out[0 .. *count).  At most
+// `cap` are written; more keys than that latches the capacity error in *err.
+__global__ __launch_bounds__(256) void set_list_kernel(const uint64_t* __restrict__ set, uint32_t slots,
+                                                       uint64_t* __restrict__ out, uint32_t* count, uint32_t cap,
+                                                       uint32_t* err) {
+  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < slots; i0 += gridDim.x * blockDim.x) {
+    const uint32_t i = i0 + threadIdx.x;
+    const uint64_t key = (i < slots) ? set[i] : kEmptyKey;
+    const bool have = key != kEmptyKey;
+    const uint32_t slot = wave_append(count, have);
+    if (have) {
+      if (slot < cap) out[slot] = key;
+      else atomicOr(err, kErrCapacity);
+    }
+  }
+}
+
+// Second layer of the hierarchical query (Alg. 3): for each super-item j of the list,
+// every child key of [j R, min((j + 1) R, ncells)) is estimated from the fine counters
+// and goes into the fine set if its estimate is >= theta.  One workgroup per super-item
+// at a time, children spread over the threads.
+template <int MAXD, bool TAB_LDS>
+__global__ __launch_bounds__(256) void children_kernel(const uint64_t* __restrict__ list,
+                                                       const uint32_t* __restrict__ count, uint32_t cap,
+                                                       uint32_t group, uint64_t ncells, Tables t,
+                                                       const int32_t* __restrict__ M, int32_t theta, uint64_t* set,
+                                                       uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand,
+                                                       uint32_t* err) {
+  __shared__ uint32_t tabs_lds[TAB_LDS ? kTabLdsRows * kTableWords : 1];
+  const uint32_t* tabs = t.tab;
+  if (TAB_LDS) {
+    load_tables(tabs_lds, t.tab, t.d);
+    __syncthreads();
+    tabs = tabs_lds;
+  }
+  const uint32_t m = min(*count, cap);
+  for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
+    const uint64_t lo = list[i] * group;
+    const uint64_t hi = (lo + group < ncells) ? lo + group : ncells;
+    for (uint64_t c = lo + threadIdx.x; c < hi; c += blockDim.x)
+      if (estimate_key<MAXD>(tabs, M, t.d, t.w, t.cm, c) >= theta) set_insert(set, slot_mask, c, set_count, max_cand, err);
+  }
+}
+
+hipError_t launch_collect_children(const uint64_t* coarse_set, uint32_t coarse_slots, uint64_t* list,
+                                   uint32_t* list_count, uint32_t list_cap, uint32_t group, uint64_t ncells,
+                                   const Tables& t, const int32_t* M, int32_t theta, uint64_t* set,
+                                   uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
+                                   hipStream_t s) {
+  hipError_t e = launch_fill_u32(list_count, 1, 0u, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(set_list_kernel, dim3(grid_for(coarse_slots, 256, 4096)), dim3(256), 0, s, coarse_set,
+                     coarse_slots, list, list_count, list_cap, err);
+  const dim3 grid(2048), block(256);
+  if (t.d <= (uint32_t)kTabLdsRows)
+    hipLaunchKernelGGL((children_kernel<kTabLdsRows, true>), grid, block, 0, s, list, list_count, list_cap, group,
+                       ncells, t, M, theta, set, slot_mask, set_count, max_cand, err);
+  else
+    hipLaunchKernelGGL((children_kernel<32, false>), grid, block, 0, s, list, list_count, list_cap, group, ncells, t,
+                       M, theta, set, slot_mask, set_count, max_cand, err);
+  return hipGetLastError();
+}
+
 // Items (r, b, sign) with sign * M[r][b] >= theta (Count-Min: M[r][b] >= theta) go into
 // the Bloom filter and, when all of them fit, into the exact hot-item set; theta > 0, so
 // empty buckets never do.  *hot counts the items.

@@ -390,3 +390,82 @@ def test_dictionary_capacity_and_mesh_latch():
         s.collect_dictionary(0.25, 10.0, 0)
     assert e.value.code == csk.CSK_E_STATE
     s.close()
+
+
+@pytest.mark.parametrize("d,w,R,L,delta", [
+    (5, 1 << 12, 7, 100.0, 0.1),          # exact-ratio mesh, packed hash fields
+    (5, 1 << 12, 1000, 1000.0, 0.25),     # power-of-two ratio mesh; the paper's group of 1000
+    (3, 999, 1 << 20, 123.456, 0.123456), # general mesh, multiply-high buckets
+    (9, 4096, 64, 100.0, 0.1),            # d > 8: global-table bin kernel
+    (5, 1 << 12, 1, 100.0, 0.1),          # group 1 is the plain sketch
+])
+def test_grouped_counters_match_oracle(d, w, R, L, delta):
+    # The coarse layer of the hierarchy adds key // R (Sec. 2.2 item 3; Alg. 3 Add(M1, s / 1000))
+    say("grouped counters", d, w, R, L, delta)
+    pos = clustered(150_000, L, 60 + d)
+    s = csk.Sketch(d, w, 5, group=R)
+    s.update(dev(pos), delta, L)
+    Mo = oracle.super_sketch(pos, d, w, 5, delta, L, R)
+    assert np.array_equal(s.counters().cpu().numpy(), Mo)
+    # the stream candidate pass on super-items: distinct key // R with estimate >= theta
+    theta = 40
+    s.collect(dev(pos), delta, L, theta)
+    keys, est, rc = s.topk(200)
+    T = oracle.hash_tables(5, d)
+    sup = np.unique(oracle.keys(pos, delta, L) // np.uint64(R))
+    e = oracle.estimate(Mo, T, sup)
+    want = sorted((-int(x), int(k)) for k, x in zip(sup, e) if x >= theta)[:200]
+    assert keys.cpu().numpy().view(np.uint64).tolist() == [k for _, k in want]
+    assert est.cpu().numpy().tolist() == [-x for x, _ in want]
+    s.close()
+
+
+@pytest.mark.parametrize("R,theta1,theta2,k", [
+    (1000, 30, 5, 300),                   # the paper's group size
+    (64, 10, oracle.INT32_MIN, 200),      # every child of the heavy super-items
+    (7, oracle.INT32_MIN, 3, 150),        # every super-item: the full dictionary search
+    (500, 1 << 20, 0, 50),                # no heavy super-item: empty, incomplete
+])
+def test_hierarchical_topk_matches_oracle(R, theta1, theta2, k):
+    # Count Sketch Hierarchical (Sec. 2.2 item 3; Alg. 3): heavy super-items from the coarse
+    # sketch, then their children from the fine sketch
+    delta, L, G = 0.5, 15.0, 30
+    say("hierarchical", R, theta1, theta2, k)
+    pos = clustered(80_000, L, 77, frac=0.7, sigma=0.3)
+    coarse = csk.Sketch(5, 1 << 12, 21, group=R)
+    fine = csk.Sketch(5, 1 << 14, 22)
+    for s in (coarse, fine):
+        s.update(dev(pos), delta, L)
+    coarse.collect_dictionary(delta, L, theta1)
+    fine.collect_children(coarse, theta2)
+    keys, est, rc = fine.topk(k)
+    M1 = oracle.super_sketch(pos, 5, 1 << 12, 21, delta, L, R)
+    M2, _ = oracle.sketch(pos, 5, 1 << 14, 22, delta, L, threads=8)
+    assert np.array_equal(coarse.counters().cpu().numpy(), M1)
+    assert np.array_equal(fine.counters().cpu().numpy(), M2)
+    ko, eo, st = oracle.topk_hierarchical(M1, oracle.hash_tables(21, 5), M2, oracle.hash_tables(22, 5), G, R,
+                                          theta1, theta2, k)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), ko)
+    assert np.array_equal(est.cpu().numpy(), eo)
+    assert rc == (csk.CSK_W_INCOMPLETE if st == oracle.W_INCOMPLETE else csk.CSK_OK)
+    coarse.close()
+    fine.close()
+
+
+def test_hierarchical_argument_and_state_errors():
+    coarse = csk.Sketch(5, 1 << 10, 1, group=10)
+    fine = csk.Sketch(5, 1 << 10, 2)
+    with pytest.raises(csk.CskError) as e:      # no mesh latched yet
+        fine.collect_children(coarse, 0)
+    assert e.value.code == csk.CSK_E_STATE
+    pos = dev(clustered(1000, 10.0, 3))
+    coarse.update(pos, 0.5, 10.0)
+    fine.update(pos, 0.25, 10.0)
+    with pytest.raises(csk.CskError) as e:      # different meshes
+        fine.collect_children(coarse, 0)
+    assert e.value.code == csk.CSK_E_STATE
+    with pytest.raises(csk.CskError) as e:      # the fine layer must count cells (group 1)
+        coarse.collect_children(fine, 0)
+    assert e.value.code == csk.CSK_E_INVALID
+    coarse.close()
+    fine.close()

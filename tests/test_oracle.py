@@ -569,7 +569,7 @@ def test_hierarchical_topk_brute_force():
         ks, es, st = oracle.topk_hierarchical(M1, T1, M2, T2, G, R, theta1, theta2, k)
         assert [int(x) for x in ks] == [c for _, c in want]
         assert [int(x) for x in es] == [-e for e, _ in want]
-        short = len(want) < k and theta2 != oracle.INT32_MIN
+        short = len(want) < k and (theta1 != oracle.INT32_MIN or theta2 != oracle.INT32_MIN)
         assert st == (oracle.W_INCOMPLETE if short else oracle.OK)
     for theta2 in [oracle.INT32_MIN, 3]:
         a = oracle.topk_hierarchical(M1, T1, M2, T2, G, R, oracle.INT32_MIN, theta2, 200)
