@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the particle count (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-hierarchy", action="store_true",
+                    help="skip the two-layer (super-cell) search")
     ap.add_argument("--no-dictionary", action="store_true",
                     help="skip the full-dictionary search (every cell of the mesh estimated once)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
@@ -141,6 +143,45 @@ def dictionary_search(s, wl, theta, keys_top, torch):
             "topk_ms": e1.elapsed_time(e2), "status": rc,
             "shared_with_stream_topk": same / max(1, keys_top.numel()),
             "note": "every cell of the mesh, occupied or not (Sec. 2.2 item 1, Alg. 1)"}
+
+
+def hierarchical_search(s, pos, wl, theta, keys_top, csk, torch, group=1000, c=3):
+    """Count Sketch Hierarchical (Alg. 3) on the step's counters: a second sketch of the
+    same shape counts super-cells key // group over the same stream; its c*k heaviest
+    super-cells (threshold found by halving, as for theta) are searched cell by cell in
+    the step's sketch.  Times each stage with HIP events; compares the top-k with the
+    stream top-k of the step."""
+    stream = torch.cuda.current_stream()
+    coarse = csk.Sketch(wl.d, wl.w, wl.seed + 1, max_candidates=1 << 22, group=group)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    ev[0].record(stream)
+    coarse.update(pos, wl.delta, wl.L)
+    ev[1].record(stream)
+    theta1 = 1 << 22
+    while True:   # threshold that leaves at least c*k heavy super-cells
+        coarse.clear_candidates()
+        coarse.collect_dictionary(wl.delta, wl.L, theta1)
+        _, est1, rc1 = coarse.topk(c * wl.k)
+        if rc1 == csk.CSK_OK or theta1 <= 1:
+            break
+        theta1 //= 2
+    coarse.clear_candidates()
+    ev[2].record(stream)
+    coarse.collect_dictionary(wl.delta, wl.L, theta1)
+    ev[3].record(stream)
+    s.clear_candidates()
+    s.collect_children(coarse, theta)
+    ev[4].record(stream)
+    keys, est, rc = s.topk(wl.k)
+    torch.cuda.synchronize()
+    G = round(wl.L / wl.delta)
+    out = {"group": group, "super_cells": -(-G ** 3 // group), "theta1": theta1, "theta2": theta,
+           "coarse_update_ms": ev[0].elapsed_time(ev[1]), "super_dictionary_ms": ev[2].elapsed_time(ev[3]),
+           "children_ms": ev[3].elapsed_time(ev[4]), "status": rc,
+           "shared_with_stream_topk": torch.isin(keys, keys_top).sum().item() / max(1, keys_top.numel()),
+           "note": "heavy super-cells key // group first, then their cells (Sec. 2.2 item 3, Alg. 3)"}
+    coarse.close()
+    return out
 
 
 def host_threads():
@@ -268,6 +309,9 @@ def main():
     if not args.no_dictionary:
         log("full-dictionary search ...")
         out["dictionary_search"] = dictionary_search(s, wl, theta, keys_top, torch)
+    if not args.no_hierarchy:
+        log("hierarchical search ...")
+        out["hierarchical_search"] = hierarchical_search(s, pos, wl, theta, keys_top, csk, torch)
     if not args.no_recall:
         log("recall against the exact histogram ...")
         try:
