@@ -27,8 +27,8 @@ BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
 # rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) scaled by a 1 GiB device copy
 # (profiles/update_kernels_plummer_2e30.md).  Reported only while the kernel sources hash
 # to what was profiled; any change to them makes `traffic` null until measured again.
-TRAFFIC = {"bytes": 46_057_567_232, "particles": 1 << 30,
-           "sources_sha256": "9e6ecf43441c78f95aea3c972dd02dcfd62409d36eaaea173da154ca75d51d86"}
+TRAFFIC = {"bytes": 46_066_504_752, "particles": 1 << 30,
+           "sources_sha256": "9bd6d711d860ab752b618df64201337f39072ed6bae98cf8892fec51aa59b167"}
 TRAFFIC_SOURCES = ["csk_kernels.hip", "csk_device.h", "csk_internal.h", "csk_api.hip"]
 
 
