@@ -146,6 +146,15 @@ csk_status csk_candidates_clear(csk_sketch *s, void *stream);
 csk_status csk_topk(csk_sketch *s, uint32_t k, uint64_t *keys, int32_t *est, uint32_t *k_out,
                     void *stream);
 
+/* As csk_topk, without any host synchronization, so that it can be captured in a HIP
+ * graph: out (device, 2 uint32) receives out[0] = the number written and out[1] = 1
+ * when that is below k and the set is partial (CSK_W_INCOMPLETE of csk_topk), else 0.
+ * Device-side errors stay latched for the next synchronizing call (csk_check, csk_topk,
+ * csk_get_counters).  The first call with a k above every earlier one allocates
+ * scratch and synchronizes: make it once before capturing. */
+csk_status csk_topk_async(csk_sketch *s, uint32_t k, uint64_t *keys, int32_t *est, uint32_t *out,
+                          void *stream);
+
 /* Copy the counters out: out (device) d*w int32, row-major [d][w].  Synchronizes
  * and returns a latched error if any (the copy is made either way). */
 csk_status csk_get_counters(const csk_sketch *s, int32_t *out, void *stream);
@@ -166,6 +175,32 @@ uint64_t csk_device_bytes(const csk_sketch *s);
 
 /* Text of the last error raised on the calling thread ("" if none). */
 const char *csk_last_error(void);
+
+/* ---- Batched update of many sketches ----------------------------------------------
+ * Sketches of uneven size updated one after another leave most of the GPU idle when
+ * they are small.  A batch shares one bin launch and one accumulate launch among up to
+ * 64 sketches: each gets a fixed share of the workgroups in proportion to its largest
+ * stream.  The per-sketch arithmetic is exactly that of csk_sketch_update (Sec. 2.2
+ * Add; Alg. 4 Update), so each sketch ends with the counters it would have alone. */
+typedef struct csk_batch csk_batch;
+
+/* Build a batch of `count` (1..64) distinct handles with the same d (<= 8) whose
+ * widths take the same hashing form (for example all powers of two up to
+ * 2^(floor(128/d) - 1)).  The mesh (delta, L) is validated and latched on every
+ * handle.  max_n[i] (host) bounds the particles sketch i takes per call; wg_budget is
+ * the number of bin workgroups to share out (0: 512).  The handles must outlive the
+ * batch.  Allocates device memory and synchronizes. */
+csk_status csk_batch_create(csk_batch **out, csk_sketch *const *sketches, const uint64_t *max_n, uint32_t count,
+                            double delta, double L, uint32_t wg_budget);
+
+/* Add n[i] particles at pos[i] (device pointers; host arrays of the batch's count) to
+ * sketch i for every i, n[i] <= max_n[i].  Allocates nothing and does not synchronize,
+ * so it can be captured in a HIP graph; domain errors latch on each handle.
+ * Asynchronous on `stream`. */
+csk_status csk_batch_update(csk_batch *b, const float *const *pos, const uint64_t *n, void *stream);
+
+/* Free the batch (the handles stay). */
+csk_status csk_batch_destroy(csk_batch *b);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,7 @@ INT32_MIN = -(2 ** 31)
 
 EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "csk_sketch_destroy", "csk_sketch_update",
            "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
-           "csk_topk",
+           "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_update", "csk_batch_destroy",
            "csk_get_counters", "csk_set_counters", "csk_reset", "csk_check", "csk_device_bytes",
            "csk_last_error"]
 
@@ -73,6 +73,10 @@ def load_library(path: str = LIB_PATH):
         "csk_collect_children": [P, P, i32, P],
         "csk_candidates_clear": [P, P],
         "csk_topk": [P, u32, P, P, C.POINTER(C.c_uint32), P],
+        "csk_topk_async": [P, u32, P, P, P, P],
+        "csk_batch_create": [PP, P, P, u32, f64, f64, u32],
+        "csk_batch_update": [P, P, P, P],
+        "csk_batch_destroy": [P],
         "csk_get_counters": [P, P, P],
         "csk_set_counters": [P, P, P],
         "csk_reset": [P, P],
@@ -195,6 +199,14 @@ def csk_topk(h, k: int, keys, est, stream=None) -> tuple[int, int]:
     return kout.value, rc
 
 
+def csk_topk_async(h, k: int, keys, est, out, stream=None) -> None:
+    """No host synchronization: out (device uint32 [2]) gets (number written, incomplete flag)."""
+    import torch
+    _check(load_library().csk_topk_async(h, k, _dev(keys, torch.int64) if k else None,
+                                         _dev(est, torch.int32) if k else None, _dev(out, torch.int32),
+                                         _stream(stream)))
+
+
 def csk_get_counters(h, out, stream=None) -> None:
     import torch
     _check(load_library().csk_get_counters(h, _dev(out, torch.int32), _stream(stream)))
@@ -222,6 +234,39 @@ def csk_last_error() -> str:
 
 
 # ------------------------------------------------------------- convenience
+
+class Batch:
+    """Up to 64 sketches updated by one bin and one accumulate launch (csk_batch_*)."""
+
+    def __init__(self, sketches, max_n, delta, L, wg_budget: int = 0):
+        lib = load_library()
+        m = len(sketches)
+        arr = (C.c_void_p * m)(*[s.h.value if isinstance(s.h, C.c_void_p) else s.h for s in sketches])
+        mx = (C.c_uint64 * m)(*[int(x) for x in max_n])
+        h = C.c_void_p()
+        _check(lib.csk_batch_create(C.byref(h), arr, mx, m, delta, L, wg_budget))
+        self.h, self.sketches, self.count = h, list(sketches), m
+
+    def update(self, positions, stream=None):
+        """positions: one float32 [n_i][3] device tensor per sketch (n_i may be 0)."""
+        import torch
+        if len(positions) != self.count:
+            raise ValueError("one position tensor per sketch")
+        ptrs = (C.c_void_p * self.count)(*[_dev(t, torch.float32, 3) if t.shape[0] else None for t in positions])
+        ns = (C.c_uint64 * self.count)(*[int(t.shape[0]) for t in positions])
+        _check(load_library().csk_batch_update(self.h, ptrs, ns, _stream(stream)))
+
+    def close(self):
+        if self.h is not None:
+            _check(load_library().csk_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 class Sketch:
     """Owns one handle.  d rows ("t" in the paper) by w counters ("b")."""
@@ -280,6 +325,10 @@ class Sketch:
         est = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
         kout, rc = csk_topk(self.h, k, keys, est, stream)
         return keys[:kout], est[:kout], rc
+
+    def topk_async(self, k, keys, est, out, stream=None):
+        """Top-k into preallocated device tensors without synchronizing (graph-capturable)."""
+        csk_topk_async(self.h, k, keys, est, out, stream)
 
     def counters(self, stream=None):
         import torch

@@ -488,6 +488,34 @@ csk_status csk_topk(csk_sketch* s, uint32_t k, uint64_t* keys, int32_t* est, uin
   return CSK_OK;
 }
 
+csk_status csk_topk_async(csk_sketch* s, uint32_t k, uint64_t* keys, int32_t* est, uint32_t* out, void* stream) {
+  if (s == nullptr || out == nullptr) return fail(CSK_E_INVALID, "topk_async: NULL handle or out");
+  if (k > 0 && (keys == nullptr || est == nullptr)) return fail(CSK_E_INVALID, "topk_async: NULL output");
+  if (k > s->max_cand) return fail(CSK_E_INVALID, "topk_async: k=%u above max_candidates=%u", k, s->max_cand);
+  hipStream_t st = (hipStream_t)stream;
+  if (k > s->sel_cap) {   // first call with a larger k: grow the scratch (synchronizes)
+    CSK_HIP(hipStreamSynchronize(st), "topk_async: grow scratch");
+    if (s->sel_key) (void)hipFree(s->sel_key);
+    if (s->sel_est) (void)hipFree(s->sel_est);
+    s->bytes -= (uint64_t)s->sel_cap * (sizeof(uint64_t) + sizeof(int32_t));
+    s->sel_key = nullptr;
+    s->sel_est = nullptr;
+    s->sel_cap = 0;
+    CSK_HIP(dmalloc(s, &s->sel_key, k), "topk_async: scratch");
+    CSK_HIP(dmalloc(s, &s->sel_est, k), "topk_async: scratch");
+    s->sel_cap = k;
+  }
+  if (k > 0) {
+    CSK_HIP(launch_topk(s->set, s->slots, s->tables(), s->M, s->max_cand, k, s->sel, s->cand_key, s->cand_est,
+                        s->sel_key, s->sel_est, keys, est, s->err(), st),
+            "topk_async");
+  } else {
+    CSK_HIP(launch_fill_u32((uint32_t*)s->sel, sizeof(SelState) / 4, 0u, st), "topk_async");
+  }
+  CSK_HIP(launch_topk_out(s->sel, k, s->partial_set ? 1u : 0u, out, st), "topk_async");
+  return CSK_OK;
+}
+
 csk_status csk_get_counters(const csk_sketch* cs, int32_t* out, void* stream) {
   csk_sketch* s = const_cast<csk_sketch*>(cs);
   if (s == nullptr || out == nullptr) return fail(CSK_E_INVALID, "get_counters: NULL argument");
@@ -530,3 +558,178 @@ uint64_t csk_device_bytes(const csk_sketch* s) { return s ? s->bytes : 0; }
 const char* csk_last_error(void) { return g_last_error; }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batched update
+
+struct csk_batch {
+  int device = 0;
+  uint32_t count = 0, d = 0, mode = 0, nwg_total = 0, nacc_total = 0, lds_bytes = 0;
+  int hm = 0;
+  std::vector<csk_sketch*> sk;
+  std::vector<uint64_t> max_n;
+  BinArgs* bin = nullptr;        // per-sketch bin arguments (device)
+  AccArgs* acc = nullptr;        // per-sketch accumulate arguments (device)
+  uint16_t* wg_sketch = nullptr; // bin workgroup -> sketch (device)
+  uint32_t* wg_first = nullptr;  // sketch -> its first bin workgroup (device)
+  uint16_t* acc_sketch = nullptr;
+  uint32_t* acc_first = nullptr;
+  uint16_t* tok = nullptr;       // every sketch's token regions
+  uint32_t* cnt = nullptr;
+};
+
+namespace {
+
+void batch_free(csk_batch* b) {
+  void* ptrs[] = {b->bin, b->acc, b->wg_sketch, b->wg_first, b->acc_sketch, b->acc_first, b->tok, b->cnt};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+template <typename T>
+hipError_t bmalloc(T** p, uint64_t count) {
+  return hipMalloc((void**)p, (count ? count : 1) * sizeof(T));
+}
+
+}  // namespace
+
+csk_status csk_batch_create(csk_batch** out, csk_sketch* const* sketches, const uint64_t* max_n, uint32_t count,
+                            double delta, double L, uint32_t wg_budget) {
+  if (out == nullptr) return fail(CSK_E_INVALID, "batch_create: out is NULL");
+  *out = nullptr;
+  if (sketches == nullptr || max_n == nullptr) return fail(CSK_E_INVALID, "batch_create: NULL array");
+  if (count < 1 || count > kMaxBatch) return fail(CSK_E_INVALID, "batch_create: count=%u outside [1, %u]", count, kMaxBatch);
+  for (uint32_t i = 0; i < count; ++i) {
+    if (sketches[i] == nullptr) return fail(CSK_E_INVALID, "batch_create: sketch %u is NULL", i);
+    for (uint32_t j = 0; j < i; ++j)
+      if (sketches[j] == sketches[i]) return fail(CSK_E_INVALID, "batch_create: sketch %u appears twice", i);
+  }
+  const csk_sketch* s0 = sketches[0];
+  if (s0->d > (uint32_t)kTabLdsRows) return fail(CSK_E_INVALID, "batch_create: d=%u above %d", s0->d, kTabLdsRows);
+  const int hm = s0->tables().hash_mode();
+  Mesh mesh0;
+  for (uint32_t i = 0; i < count; ++i) {
+    const csk_sketch* s = sketches[i];
+    if (s->d != s0->d) return fail(CSK_E_INVALID, "batch_create: sketches of different d (%u, %u)", s0->d, s->d);
+    if (s->device != s0->device) return fail(CSK_E_INVALID, "batch_create: sketches on different devices");
+    if (s->tables().hash_mode() != hm)
+      return fail(CSK_E_INVALID, "batch_create: widths need different hash forms (sketch %u, w=%u)", i, s->w);
+    Mesh m;
+    csk_status rc = check_mesh(sketches[i], delta, L, &m);
+    if (rc != CSK_OK) return rc;
+    if (i == 0) mesh0 = m;
+  }
+  for (uint32_t i = 0; i < count; ++i) {
+    Mesh m;
+    (void)check_mesh(sketches[i], delta, L, &m);
+    latch_mesh(sketches[i], delta, L, m);
+  }
+  const uint32_t d = s0->d;
+  const uint64_t tile = (uint64_t)kBin2Threads * bin2_ppt((int)d);
+  uint64_t total_tiles = 0;
+  std::vector<uint64_t> tiles(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    tiles[i] = (max_n[i] + tile - 1) / tile;
+    total_tiles += tiles[i];
+  }
+  const uint64_t budget = wg_budget ? wg_budget : 512;
+  std::vector<BinArgs> hb(count);
+  std::vector<AccArgs> ha(count);
+  std::vector<uint16_t> wg_map, acc_map;
+  std::vector<uint32_t> wg_first(count), acc_first(count);
+  uint64_t tok_words = 0, cnt_words = 0, lds = 0;
+  std::vector<uint64_t> tok_off(count), cnt_off(count);
+  std::vector<BinPlan> plans(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    uint64_t want = total_tiles ? (budget * tiles[i] + total_tiles / 2) / total_tiles : 1;
+    if (want < 1) want = 1;
+    BinPlan& p = plans[i];
+    if (!plan_bin_wg(max_n[i] ? max_n[i] : 1, d, sketches[i]->w, want, p) || !p.fast)
+      return fail(CSK_E_INVALID, "batch_create: sketch %u (w=%u) does not fit the binned path", i, sketches[i]->w);
+    tok_off[i] = tok_words;
+    cnt_off[i] = cnt_words;
+    tok_words += (uint64_t)p.P * p.nwg * p.cap;
+    cnt_words += (uint64_t)p.P * p.nwg;
+    if (p.lds_bytes > lds) lds = p.lds_bytes;
+    wg_first[i] = (uint32_t)wg_map.size();
+    for (uint32_t g = 0; g < p.nwg; ++g) wg_map.push_back((uint16_t)i);
+    acc_first[i] = (uint32_t)acc_map.size();
+    for (uint32_t q = 0; q < p.P; ++q) acc_map.push_back((uint16_t)i);
+  }
+  if (wg_map.size() > 65535 || acc_map.size() > (1u << 30))
+    return fail(CSK_E_INVALID, "batch_create: %zu workgroups exceed the launch limit", wg_map.size());
+  csk_batch* b = new (std::nothrow) csk_batch();
+  if (!b) return fail(CSK_E_NOMEM, "batch_create: host allocation failed");
+  b->device = s0->device;
+  b->count = count;
+  b->d = d;
+  b->mode = mesh0.mode;
+  b->hm = hm;
+  b->sk.assign(sketches, sketches + count);
+  b->max_n.assign(max_n, max_n + count);
+  b->nwg_total = (uint32_t)wg_map.size();
+  b->nacc_total = (uint32_t)acc_map.size();
+  b->lds_bytes = (uint32_t)lds;
+  hipError_t e = bmalloc(&b->bin, count);
+  if (e == hipSuccess) e = bmalloc(&b->acc, count);
+  if (e == hipSuccess) e = bmalloc(&b->wg_sketch, wg_map.size());
+  if (e == hipSuccess) e = bmalloc(&b->wg_first, count);
+  if (e == hipSuccess) e = bmalloc(&b->acc_sketch, acc_map.size());
+  if (e == hipSuccess) e = bmalloc(&b->acc_first, count);
+  if (e == hipSuccess) e = bmalloc(&b->tok, tok_words);
+  if (e == hipSuccess) e = bmalloc(&b->cnt, cnt_words);
+  if (e == hipSuccess) {
+    for (uint32_t i = 0; i < count; ++i) {
+      csk_sketch* s = sketches[i];
+      Mesh m;
+      (void)check_mesh(s, delta, L, &m);
+      hb[i] = make_bin_args(nullptr, 0, m, s->tables(), plans[i], b->tok + tok_off[i], b->cnt + cnt_off[i], s->M,
+                            s->err());
+      ha[i].tok = b->tok + tok_off[i];
+      ha[i].cnt = b->cnt + cnt_off[i];
+      ha[i].plan = plans[i];
+      ha[i].w = s->w;
+      ha[i].M = s->M;
+    }
+    e = hipMemcpy(b->bin, hb.data(), count * sizeof(BinArgs), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemcpy(b->acc, ha.data(), count * sizeof(AccArgs), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->wg_sketch, wg_map.data(), wg_map.size() * 2, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->wg_first, wg_first.data(), count * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->acc_sketch, acc_map.data(), acc_map.size() * 2, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->acc_first, acc_first.data(), count * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    batch_free(b);
+    delete b;
+    return hip_fail(e, "batch_create");
+  }
+  *out = b;
+  return CSK_OK;
+}
+
+csk_status csk_batch_update(csk_batch* b, const float* const* pos, const uint64_t* n, void* stream) {
+  if (b == nullptr || pos == nullptr || n == nullptr) return fail(CSK_E_INVALID, "batch_update: NULL argument");
+  BatchCall call{};
+  for (uint32_t i = 0; i < b->count; ++i) {
+    if (n[i] > b->max_n[i])
+      return fail(CSK_E_INVALID, "batch_update: n[%u]=%llu above its max_n %llu", i, (unsigned long long)n[i],
+                  (unsigned long long)b->max_n[i]);
+    if (n[i] > 0 && pos[i] == nullptr) return fail(CSK_E_INVALID, "batch_update: pos[%u] is NULL", i);
+    call.pos[i] = pos[i];
+    call.n[i] = n[i];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  CSK_HIP(launch_bin_batch(b->bin, b->wg_sketch, b->wg_first, b->nwg_total, b->lds_bytes, b->d, b->mode, b->hm, call,
+                           st),
+          "batch_update (bin)");
+  CSK_HIP(launch_accumulate_batch(b->acc, b->acc_sketch, b->acc_first, b->nacc_total, st), "batch_update (accumulate)");
+  return CSK_OK;
+}
+
+csk_status csk_batch_destroy(csk_batch* b) {
+  if (b == nullptr) return CSK_OK;
+  (void)hipDeviceSynchronize();
+  batch_free(b);
+  delete b;
+  return CSK_OK;
+}

@@ -69,6 +69,52 @@ constexpr uint32_t kMaxLds = 160 * 1024;
 
 // Returns false if the binned path does not fit (then use the direct path).
 bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& plan);
+// The same with at most max_wg workgroups (>= 1) for the bin kernel.
+bool plan_bin_wg(uint64_t n, uint32_t d, uint32_t w, uint64_t max_wg, BinPlan& plan);
+
+// Everything the bin kernel needs for one sketch and one stream.
+struct BinArgs {
+  const float* __restrict__ pos;
+  uint64_t n;
+  Mesh mesh;
+  const uint32_t* __restrict__ tab;
+  const uint32_t* __restrict__ tabi;
+  const uint32_t* __restrict__ tabp;
+  uint32_t d, w, wshift, cm;
+  BinPlan plan;
+  uint16_t* __restrict__ tok;
+  uint32_t* __restrict__ cnt;
+  int32_t* __restrict__ M;
+  uint32_t* __restrict__ err;
+};
+
+// Everything the accumulate kernel needs for one sketch.
+struct AccArgs {
+  const uint16_t* __restrict__ tok;
+  const uint32_t* __restrict__ cnt;
+  BinPlan plan;
+  uint32_t w;
+  int32_t* __restrict__ M;
+};
+
+// Per-call streams of a batched update: sketch i reads n[i] particles at pos[i].
+constexpr uint32_t kMaxBatch = 64;
+struct BatchCall {
+  const float* pos[kMaxBatch];
+  uint64_t n[kMaxBatch];
+};
+
+BinArgs make_bin_args(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
+                      uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err);
+// One bin launch for many sketches of the same d, mesh mode and hash mode (fast path,
+// d <= 8): workgroup g serves sketch wg_sketch[g] as its workgroup g - wg_first[sketch].
+hipError_t launch_bin_batch(const BinArgs* descs, const uint16_t* wg_sketch, const uint32_t* wg_first,
+                            uint32_t nwg_total, uint32_t lds_bytes, uint32_t d, uint32_t mode, int hm,
+                            const BatchCall& call, hipStream_t s);
+// One accumulate launch for many sketches: block b sums slice b - acc_first[sketch] of
+// sketch acc_sketch[b].
+hipError_t launch_accumulate_batch(const AccArgs* descs, const uint16_t* acc_sketch, const uint32_t* acc_first,
+                                   uint32_t nblocks, hipStream_t s);
 
 hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
                       uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, hipStream_t s);
@@ -103,6 +149,8 @@ hipError_t launch_collect_children(const uint64_t* coarse_set, uint32_t coarse_s
                                    const Tables& t, const int32_t* M, int32_t theta, uint64_t* set,
                                    uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
                                    hipStream_t s);
+// out[0] = min(k, candidates), out[1] = 1 if that is below k and `partial`, else 0.
+hipError_t launch_topk_out(const SelState* st, uint32_t k, uint32_t partial, uint32_t* out, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,

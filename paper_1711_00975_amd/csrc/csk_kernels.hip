@@ -114,20 +114,6 @@ __device__ __forceinline__ void load_tables(uint32_t* dst, const uint32_t* __res
 
 // ------------------------------------------------------------------ bin
 
-struct BinArgs {
-  const float* __restrict__ pos;
-  uint64_t n;
-  Mesh mesh;
-  const uint32_t* __restrict__ tab;
-  const uint32_t* __restrict__ tabi;
-  const uint32_t* __restrict__ tabp;
-  uint32_t d, w, wshift, cm;
-  BinPlan plan;
-  uint16_t* __restrict__ tok;
-  uint32_t* __restrict__ cnt;
-  int32_t* __restrict__ M;
-  uint32_t* __restrict__ err;
-};
 
 // LDS layout (uint32 words): tables [tab_rows_lds * 1536] | cursor [P] | hist [Pr] |
 // base [Pr] | stage [tile] | wsum [NW + 1].
@@ -230,7 +216,9 @@ constexpr uint32_t kDstOverflow = 0xFFFFFFFEu;  // run added with atomics
 constexpr uint32_t kDstBias = 1u << 16;         // keeps offset + cursor - base positive
 
 template <int D, uint32_t MODE, int NT, int RP, int HM>
-__global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
+__device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const float* __restrict__ pos, uint64_t n,
+                                          uint32_t g) {
+  const BinArgs& a = *ap;   // read in place (argument segment or descriptor), not copied
   constexpr int DP = HashWords<D, HM>::value;
   constexpr int PPT = bin2_ppt(D), TILE = NT * PPT, NW = NT / 64;
   extern __shared__ __align__(16) uint32_t lds2[];
@@ -244,7 +232,7 @@ __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
   uint32_t* base = hist + nbins;
   uint32_t* stage = base + nbins;
   uint32_t* wsum = stage + RP * TILE;
-  const uint32_t tid = threadIdx.x, g = blockIdx.x, wave = tid >> 6;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6;
   uint16_t* __restrict__ tokg = a.tok + (uint64_t)g * pl.P * pl.cap;   // this workgroup's regions
 
   for (uint32_t i = tid; i < pl.P; i += NT) cursor[i] = 0;
@@ -272,20 +260,21 @@ __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
     }
   };
 
-  for (uint64_t tile = g; tile < pl.ntiles; tile += pl.nwg) {
+  const uint64_t ntiles = (n + TILE - 1) / TILE;
+  for (uint64_t tile = g; tile < ntiles; tile += pl.nwg) {
     const uint64_t first = tile * (uint64_t)TILE;
-    const bool full = first + TILE <= a.n;
+    const bool full = first + TILE <= n;
     // all PPT position loads are issued before any is used (a clamped index keeps the
     // loads unconditional; particles beyond the stream are masked below)
     float px[PPT], py[PPT], pz[PPT];
-    const uint64_t last = a.n - 1;
+    const uint64_t last = n - 1;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       uint64_t i = first + (uint64_t)j * NT + tid;
       i = i < last ? i : last;
-      px[j] = __builtin_nontemporal_load(a.pos + 3 * i);
-      py[j] = __builtin_nontemporal_load(a.pos + 3 * i + 1);
-      pz[j] = __builtin_nontemporal_load(a.pos + 3 * i + 2);
+      px[j] = __builtin_nontemporal_load(pos + 3 * i);
+      py[j] = __builtin_nontemporal_load(pos + 3 * i + 1);
+      pz[j] = __builtin_nontemporal_load(pos + 3 * i + 2);
     }
     // sv = (bin in its sort pass) << 16 | token; bin = (row % RP) * Pr + slice, or the dummy
     // bin for a particle outside the stream or the domain
@@ -293,7 +282,7 @@ __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
     uint32_t valid = 0, inside = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      const bool in = full || (first + (uint64_t)j * NT + tid) < a.n;
+      const bool in = full || (first + (uint64_t)j * NT + tid) < n;
       uint64_t key;   // always a key of the mesh, so the table lookups stay in range
       const bool ok = cell_key_m<MODE>(px[j], py[j], pz[j], a.mesh, key) && in;
       inside |= (uint32_t)in << j;
@@ -381,7 +370,27 @@ __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
   for (uint32_t s = tid; s < pl.P; s += NT) a.cnt[(uint64_t)s * pl.nwg + g] = cursor[s];
 }
 
+template <int D, uint32_t MODE, int NT, int RP, int HM>
+__global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
+  bin3_body<D, MODE, NT, RP, HM>(&a, a.pos, a.n, blockIdx.x);
+}
+
+// Many sketches in one launch: workgroup blockIdx.x serves sketch wg_sketch[blockIdx.x] as
+// its workgroup blockIdx.x - wg_first[sketch]; the per-call stream of each sketch comes in
+// `call`, the rest of its arguments from descs.
+template <int D, uint32_t MODE, int NT, int RP, int HM>
+__global__ __launch_bounds__(NT) void bin3_batch_kernel(const BinArgs* __restrict__ descs,
+                                                        const uint16_t* __restrict__ wg_sketch,
+                                                        const uint32_t* __restrict__ wg_first, BatchCall call) {
+  const uint32_t i = wg_sketch[blockIdx.x];
+  bin3_body<D, MODE, NT, RP, HM>(descs + i, call.pos[i], call.n[i], blockIdx.x - wg_first[i]);
+}
+
 bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& p) {
+  return plan_bin_wg(n, d, w, (d <= (uint32_t)kTabLdsRows) ? 256u : 512u, p);
+}
+
+bool plan_bin_wg(uint64_t n, uint32_t d, uint32_t w, uint64_t max_wg, BinPlan& p) {
   p.Pr = (w + kSlice - 1) / kSlice;
   p.P = d * p.Pr;
   p.fast = (d <= (uint32_t)kTabLdsRows) ? 1u : 0u;
@@ -400,7 +409,7 @@ bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& p) {
   }
   if (words * 4 > kMaxLds) return false;
   p.lds_bytes = (uint32_t)(words * 4);
-  const uint64_t max_wg = p.fast ? 256 : 512;
+  if (max_wg < 1) max_wg = 1;
   p.nwg = (uint32_t)(p.ntiles < max_wg ? p.ntiles : max_wg);
   const uint64_t tiles_per_wg = (p.ntiles + p.nwg - 1) / p.nwg;
   const uint64_t per_wg = tiles_per_wg * p.tile;     // most particles one workgroup sees
@@ -450,13 +459,15 @@ static void launch_bin3_d(uint32_t d, uint32_t mode, int hm, dim3 grid, dim3 blo
   }
 }
 
-hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
-                      uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, hipStream_t s) {
+BinArgs make_bin_args(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
+                      uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err) {
   BinArgs a;
   a.pos = pos;
   a.n = n;
   a.mesh = mesh;
   a.tab = t.tab;
+  a.tabi = t.tabi;
+  a.tabp = t.tabp;
   a.d = t.d;
   a.w = t.w;
   a.wshift = t.wshift;
@@ -466,8 +477,58 @@ hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
   a.cnt = cnt;
   a.M = M;
   a.err = err;
-  a.tabi = t.tabi;
-  a.tabp = t.tabp;
+  return a;
+}
+
+template <int D, uint32_t MM, int HM>
+static void launch_bin3_batch_one(dim3 grid, uint32_t lds, hipStream_t s, const BinArgs* descs,
+                                  const uint16_t* wg_sketch, const uint32_t* wg_first, const BatchCall& call) {
+  hipLaunchKernelGGL((bin3_batch_kernel<D, MM, kBin2Threads, kBin2Rows, HM>), grid, dim3(kBin2Threads), lds, s, descs,
+                     wg_sketch, wg_first, call);
+}
+
+template <int D, uint32_t MM>
+static void launch_bin3_batch_m(int hm, dim3 grid, uint32_t lds, hipStream_t s, const BinArgs* descs,
+                                const uint16_t* wg_sketch, const uint32_t* wg_first, const BatchCall& call) {
+  if constexpr (D >= 5) {
+    if (hm == kHashPacked) {
+      launch_bin3_batch_one<D, MM, kHashPacked>(grid, lds, s, descs, wg_sketch, wg_first, call);
+      return;
+    }
+  }
+  if (hm == kHashMulHi) launch_bin3_batch_one<D, MM, kHashMulHi>(grid, lds, s, descs, wg_sketch, wg_first, call);
+  else launch_bin3_batch_one<D, MM, kHashShift>(grid, lds, s, descs, wg_sketch, wg_first, call);
+}
+
+template <int D>
+static void launch_bin3_batch_d(uint32_t mode, int hm, dim3 grid, uint32_t lds, hipStream_t s, const BinArgs* descs,
+                                const uint16_t* wg_sketch, const uint32_t* wg_first, const BatchCall& call) {
+  if (mode == kMeshPow2Ratio) launch_bin3_batch_m<D, kMeshPow2Ratio>(hm, grid, lds, s, descs, wg_sketch, wg_first, call);
+  else if (mode == kMeshExactRatio)
+    launch_bin3_batch_m<D, kMeshExactRatio>(hm, grid, lds, s, descs, wg_sketch, wg_first, call);
+  else launch_bin3_batch_m<D, kMeshGeneral>(hm, grid, lds, s, descs, wg_sketch, wg_first, call);
+}
+
+hipError_t launch_bin_batch(const BinArgs* descs, const uint16_t* wg_sketch, const uint32_t* wg_first,
+                            uint32_t nwg_total, uint32_t lds_bytes, uint32_t d, uint32_t mode, int hm,
+                            const BatchCall& call, hipStream_t s) {
+  const dim3 grid(nwg_total);
+  switch (d) {
+    case 1: launch_bin3_batch_d<1>(mode, hm, grid, lds_bytes, s, descs, wg_sketch, wg_first, call); break;
+    case 2: launch_bin3_batch_d<2>(mode, hm, grid, lds_bytes, s, descs, wg_sketch, wg_first, call); break;
+    case 3: launch_bin3_batch_d<3>(mode, hm, grid, lds_bytes, s, descs, wg_sketch, wg_first, call); break;
+    case 4: launch_bin3_batch_d<4>(mode, hm, grid, lds_bytes, s, descs, wg_sketch, wg_first, call); break;
+    case 5: launch_bin3_batch_d<5>(mode, hm, grid, lds_bytes, s, descs, wg_sketch, wg_first, call); break;
+    case 6: launch_bin3_batch_d<6>(mode, hm, grid, lds_bytes, s, descs, wg_sketch, wg_first, call); break;
+    case 7: launch_bin3_batch_d<7>(mode, hm, grid, lds_bytes, s, descs, wg_sketch, wg_first, call); break;
+    default: launch_bin3_batch_d<8>(mode, hm, grid, lds_bytes, s, descs, wg_sketch, wg_first, call); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
+                      uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, hipStream_t s) {
+  const BinArgs a = make_bin_args(pos, n, mesh, t, plan, tok, cnt, M, err);
   if (plan.fast) {
     const dim3 grid(plan.nwg), block(kBin2Threads);
     launch_bin3_d(t.d, mesh.mode, t.hash_mode(), grid, block, plan.lds_bytes, s, a);
@@ -479,19 +540,11 @@ hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
 
 // ------------------------------------------------------------------ accumulate
 
-struct AccArgs {
-  const uint16_t* __restrict__ tok;
-  const uint32_t* __restrict__ cnt;
-  BinPlan plan;
-  uint32_t w;
-  int32_t* __restrict__ M;
-};
 
-__global__ __launch_bounds__(kAccThreads) void accumulate_kernel(AccArgs a) {
+__device__ __forceinline__ void accumulate_body(const AccArgs& a, uint32_t s) {
   extern __shared__ uint32_t lds[];
   int32_t* acc = (int32_t*)lds;  // kSlice counters
   const BinPlan& pl = a.plan;
-  const uint32_t s = blockIdx.x;
   const uint32_t r = s / pl.Pr, sl = s % pl.Pr;
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
   for (uint32_t i = tid; i < kSlice; i += kAccThreads) acc[i] = 0;
@@ -533,6 +586,17 @@ __global__ __launch_bounds__(kAccThreads) void accumulate_kernel(AccArgs a) {
   for (uint32_t i = tid; i < len; i += kAccThreads) Mrow[i] = (int32_t)((uint32_t)Mrow[i] + (uint32_t)acc[i]);
 }
 
+__global__ __launch_bounds__(kAccThreads) void accumulate_kernel(AccArgs a) { accumulate_body(a, blockIdx.x); }
+
+// Many sketches in one launch: block blockIdx.x sums slice blockIdx.x - acc_first[sketch]
+// of sketch acc_sketch[blockIdx.x].
+__global__ __launch_bounds__(kAccThreads) void accumulate_batch_kernel(const AccArgs* __restrict__ descs,
+                                                                       const uint16_t* __restrict__ acc_sketch,
+                                                                       const uint32_t* __restrict__ acc_first) {
+  const uint32_t i = acc_sketch[blockIdx.x];
+  accumulate_body(descs[i], blockIdx.x - acc_first[i]);
+}
+
 hipError_t launch_accumulate(const uint16_t* tok, const uint32_t* cnt, const BinPlan& plan, uint32_t w,
                              int32_t* M, hipStream_t s) {
   AccArgs a;
@@ -542,6 +606,13 @@ hipError_t launch_accumulate(const uint16_t* tok, const uint32_t* cnt, const Bin
   a.w = w;
   a.M = M;
   hipLaunchKernelGGL(accumulate_kernel, dim3(plan.P), dim3(kAccThreads), kSlice * sizeof(int32_t), s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate_batch(const AccArgs* descs, const uint16_t* acc_sketch, const uint32_t* acc_first,
+                                   uint32_t nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(accumulate_batch_kernel, dim3(nblocks), dim3(kAccThreads), kSlice * sizeof(int32_t), s, descs,
+                     acc_sketch, acc_first);
   return hipGetLastError();
 }
 
@@ -1408,6 +1479,21 @@ __global__ __launch_bounds__(256) void rank_place_kernel(const uint64_t* __restr
     ok[r] = sk[i];
     oe[r] = se[i];
   }
+}
+
+// Number written and status of a top-k, for callers that do not synchronize: out[0] =
+// min(k, m); out[1] = 1 (incomplete) when fewer than k were found from a partial set.
+__global__ void topk_out_kernel(const SelState* st, uint32_t k, uint32_t partial, uint32_t* out) {
+  if (threadIdx.x == 0) {
+    const uint32_t got = min(k, st->m);
+    out[0] = got;
+    out[1] = (got < k && partial) ? 1u : 0u;
+  }
+}
+
+hipError_t launch_topk_out(const SelState* st, uint32_t k, uint32_t partial, uint32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(topk_out_kernel, dim3(1), dim3(64), 0, s, st, k, partial, out);
+  return hipGetLastError();
 }
 
 __global__ void sel_finish_kernel(SelState* st, const uint32_t* err) {

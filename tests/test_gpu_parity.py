@@ -469,3 +469,108 @@ def test_hierarchical_argument_and_state_errors():
     assert e.value.code == csk.CSK_E_INVALID
     coarse.close()
     fine.close()
+
+
+BATCH_SHAPES = [   # (n first call, n second call, w, seed): empty, tiny, ragged, uneven widths
+    (0, 10, 1 << 14, 41), (1, 0, 1 << 14, 42), (8193, 100, 1 << 16, 43), (70_000, 5000, 1 << 15, 44),
+    (300_000, 20_000, 1 << 18, 45), (120_000, 120_000, 1 << 20, 46), (9_000, 1, 1 << 16, 47),
+]
+
+
+def batch_case(shapes, L=100.0, delta=0.1):
+    sk, pos1, pos2 = [], [], []
+    for j, (n1, n2, w, seed) in enumerate(shapes):
+        sk.append(csk.Sketch(5, w, seed))
+        pos1.append(clustered(n1, L, 200 + j))
+        pos2.append(clustered(n2, L, 300 + j))
+    return sk, pos1, pos2
+
+
+def test_batch_update_matches_oracle_per_sketch():
+    # one bin and one accumulate launch for uneven sketches give each sketch exactly the
+    # counters of its own stream (Sec. 2.2 Add); a second, smaller call adds on top
+    say("batch update", len(BATCH_SHAPES))
+    sk, pos1, pos2 = batch_case(BATCH_SHAPES)
+    max_n = [max(a, b) for a, b, _, _ in BATCH_SHAPES]
+    b = csk.Batch(sk, max_n, 0.1, 100.0, wg_budget=64)
+    b.update([dev(p) for p in pos1])
+    b.update([dev(p) for p in pos2])
+    for j, (n1, n2, w, seed) in enumerate(BATCH_SHAPES):
+        Mo, _ = oracle.sketch(np.concatenate([pos1[j], pos2[j]]), 5, w, seed, 0.1, 100.0, threads=8)
+        assert np.array_equal(sk[j].counters().cpu().numpy(), Mo), j
+    with pytest.raises(csk.CskError):                      # above max_n
+        b.update([dev(clustered(n + 1, 100.0, 9)) for n in max_n])
+    b.close()
+    for s in sk:
+        s.close()
+
+
+def test_batch_create_rejects_mixed_sketches():
+    a, c = csk.Sketch(5, 1 << 14, 1), csk.Sketch(4, 1 << 14, 2)
+    with pytest.raises(csk.CskError) as e:
+        csk.Batch([a, c], [10, 10], 0.1, 100.0)
+    assert e.value.code == csk.CSK_E_INVALID
+    with pytest.raises(csk.CskError) as e:
+        csk.Batch([a, a], [10, 10], 0.1, 100.0)
+    assert e.value.code == csk.CSK_E_INVALID
+    a.close()
+    c.close()
+
+
+def test_batch_pipeline_in_a_hip_graph():
+    # batched update -> per-sketch collect -> asynchronous top-k, captured once and
+    # replayed: every replay equals the eager pipeline and the oracle (zero-filled work
+    # between replays, eager launches and synchronizations in between)
+    import torch
+    shapes = BATCH_SHAPES[2:6]
+    sk, pos1, _ = batch_case(shapes)
+    pos = [dev(p) for p in pos1]
+    b = csk.Batch(sk, [p.shape[0] for p in pos1], 0.1, 100.0)
+    k, theta = 64, 3
+    keys = [torch.empty(k, dtype=torch.int64, device="cuda") for _ in sk]
+    est = [torch.empty(k, dtype=torch.int32, device="cuda") for _ in sk]
+    outs = [torch.zeros(2, dtype=torch.int32, device="cuda") for _ in sk]
+
+    def pipeline():
+        b.update(pos)
+        for j, s in enumerate(sk):
+            s.clear_candidates()
+            s.collect(pos[j], 0.1, 100.0, theta)
+            s.topk_async(k, keys[j], est[j], outs[j])
+
+    def reset_all():
+        for s in sk:
+            s.reset()
+
+    reset_all()
+    pipeline()                                    # eager run (also sizes the top-k scratch)
+    torch.cuda.synchronize()
+    want = [(o.cpu().numpy().copy(), kk.cpu().numpy().copy(), e.cpu().numpy().copy())
+            for o, kk, e in zip(outs, keys, est)]
+    for j, (n1, _, w, seed) in enumerate(shapes):
+        Mo, _ = oracle.sketch(pos1[j], 5, w, seed, 0.1, 100.0, threads=8)
+        ko, eo, st = oracle.topk_sketch(Mo, oracle.hash_tables(seed, 5), pos1[j], 0.1, 100.0, theta, k)
+        got = int(want[j][0][0])
+        assert got == len(ko) and want[j][0][1] == (1 if st == oracle.W_INCOMPLETE else 0)
+        assert np.array_equal(want[j][1][:got].view(np.uint64), ko) and np.array_equal(want[j][2][:got], eo)
+    reset_all()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pipeline()
+    for rep in range(3):
+        reset_all()                               # eager work between replays
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for j, (o, kk, e) in enumerate(zip(outs, keys, est)):
+            got = int(want[j][0][0])
+            assert np.array_equal(o.cpu().numpy(), want[j][0]), (rep, j)
+            assert np.array_equal(kk.cpu().numpy()[:got], want[j][1][:got]), (rep, j)
+            assert np.array_equal(e.cpu().numpy()[:got], want[j][2][:got]), (rep, j)
+    del g
+    b.close()
+    for s in sk:
+        s.close()

@@ -114,3 +114,22 @@ def halo_catalogue(wl: Workload):
     cen = np.empty((wl.n_halo, 3), dtype=np.float64)
     _load().wl_halo_catalogue(wl.seed, wl.n_halo, wl.L, wl.m_lo, wl.m_hi, wl.slope, _p(mass), _p(cen))
     return mass, cen
+
+
+def batch_subvolumes(count: int = 64, seed: int = 1) -> list:
+    """The batched-update workload: `count` independent sub-volumes of uneven size.
+
+    Sub-volume s: u_s = (first Philox4x32-10 word of counter (s, 0, 3, 0) under `seed`) / 2^32,
+    n_s = floor(2^(16 + 8 u_s)) particles (2^16 .. 2^24), L = 100, delta = 0.1,
+    w_s = 2^(14 + round(6 (log2 n_s - 16) / 8)) (2^14 .. 2^20), d = 5, k_s = floor(0.01 w_s),
+    max(1, round(256 n_s / 2^20)) Plummer halos with masses on [100, 1e4], the rest uniform
+    (the exact-count recipe of SMALL), seed 1 + s.
+    """
+    out = []
+    for s in range(count):
+        u = int(philox4x32_10([s, 0, 3, 0], [seed & 0xFFFFFFFF, seed >> 32])[0]) / 2.0 ** 32
+        n = int(np.floor(2.0 ** (16.0 + 8.0 * u)))
+        w = 1 << (14 + int(round(6.0 * (np.log2(n) - 16.0) / 8.0)))
+        out.append(Workload(name=f"subvolume-{s}", n=n, L=100.0, delta=0.1, d=5, w=w, k=max(1, w // 100),
+                            seed=1 + s, n_halo=max(1, int(round(256 * n / 2 ** 20))), m_lo=100.0, m_hi=1.0e4))
+    return out
