@@ -94,6 +94,16 @@ csk_status csk_sketch_destroy(csk_sketch *s);
 csk_status csk_sketch_update(csk_sketch *s, const float *pos, uint64_t n, double delta, double L,
                              void *stream);
 
+#define CSK_UPDATE_AUTO   0 /* LDS-binned when the rows fit it, else global atomics  */
+#define CSK_UPDATE_BINNED 1 /* LDS-binned tokens, summed per counter slice          */
+#define CSK_UPDATE_DIRECT 2 /* one global atomic add per row and particle           */
+
+/* How csk_sketch_update adds to the counters; the counters come out the same either
+ * way, only the speed differs (an autotuner picks per width and stream size).
+ * max_wg caps the bin workgroups (0: the default).  CSK_UPDATE_BINNED on rows too wide
+ * for the binned path behaves as CSK_UPDATE_AUTO. */
+csk_status csk_set_update_plan(csk_sketch *s, int32_t mode, uint32_t max_wg);
+
 /* Estimates of m cell keys: est[j] = the element at index floor((d-1)/2) of the
  * ascending sort of { M[r][bucket_r(key_j)] * sign_r(key_j) } (Count-Min: the
  * minimum of M[r][bucket_r(key_j)]).  Sec. 2.2 Estimate; Alg. 4 Estimate.

@@ -34,6 +34,7 @@ CSK_DEFAULT_CANDIDATES = 1 << 21
 INT32_MIN = -(2 ** 31)
 
 EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "csk_sketch_destroy", "csk_sketch_update",
+           "csk_set_update_plan",
            "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
            "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_update", "csk_batch_destroy",
            "csk_get_counters", "csk_set_counters", "csk_reset", "csk_check", "csk_device_bytes",
@@ -66,6 +67,7 @@ def load_library(path: str = LIB_PATH):
         "csk_sketch_init_group": [PP, u32, u32, u64, i32, u64, u32],
         "csk_sketch_destroy": [P],
         "csk_sketch_update": [P, P, u64, f64, f64, P],
+        "csk_set_update_plan": [P, i32, u32],
         "csk_sketch_query": [P, P, u64, P, P],
         "csk_cell_keys": [P, u64, f64, f64, P, P],
         "csk_collect": [P, P, u64, f64, f64, i32, P],
@@ -142,6 +144,13 @@ def csk_sketch_init_group(d: int, w: int, seed: int, variant: int = CSK_VARIANT_
     h = C.c_void_p()
     _check(load_library().csk_sketch_init_group(C.byref(h), d, w, seed, variant, max_candidates, group))
     return h
+
+
+CSK_UPDATE_AUTO, CSK_UPDATE_BINNED, CSK_UPDATE_DIRECT = 0, 1, 2
+
+
+def csk_set_update_plan(h, mode: int, max_wg: int = 0) -> None:
+    _check(load_library().csk_set_update_plan(h, mode, max_wg))
 
 
 def csk_sketch_destroy(h) -> None:
@@ -325,6 +334,9 @@ class Sketch:
         est = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
         kout, rc = csk_topk(self.h, k, keys, est, stream)
         return keys[:kout], est[:kout], rc
+
+    def set_update_plan(self, mode, max_wg=0):
+        csk_set_update_plan(self.h, mode, max_wg)
 
     def topk_async(self, k, keys, est, out, stream=None):
         """Top-k into preallocated device tensors without synchronizing (graph-capturable)."""

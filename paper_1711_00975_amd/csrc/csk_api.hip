@@ -92,6 +92,8 @@ struct csk_sketch {
   int device = 0;
   uint32_t d = 0, w = 0;
   uint32_t group = 1;        // items are cell keys / group (hierarchical coarse layer)
+  int32_t upd_mode = CSK_UPDATE_AUTO;  // how csk_sketch_update adds (csk_set_update_plan)
+  uint32_t upd_max_wg = 0;             // most bin workgroups (0: the default)
   uint64_t seed = 0;
   int32_t variant = CSK_VARIANT_COUNT_SKETCH;
   int32_t* M = nullptr;
@@ -308,6 +310,16 @@ csk_status csk_sketch_destroy(csk_sketch* s) {
   return CSK_OK;
 }
 
+csk_status csk_set_update_plan(csk_sketch* s, int32_t mode, uint32_t max_wg) {
+  if (s == nullptr) return fail(CSK_E_INVALID, "set_update_plan: NULL handle");
+  if (mode != CSK_UPDATE_AUTO && mode != CSK_UPDATE_BINNED && mode != CSK_UPDATE_DIRECT)
+    return fail(CSK_E_INVALID, "set_update_plan: unknown mode %d", mode);
+  if (max_wg > 65535) return fail(CSK_E_INVALID, "set_update_plan: max_wg=%u above 65535", max_wg);
+  s->upd_mode = mode;
+  s->upd_max_wg = max_wg;
+  return CSK_OK;
+}
+
 csk_status csk_sketch_update(csk_sketch* s, const float* pos, uint64_t n, double delta, double L, void* stream) {
   if (s == nullptr) return fail(CSK_E_INVALID, "update: NULL handle");
   Mesh mesh;
@@ -324,7 +336,8 @@ csk_status csk_sketch_update(csk_sketch* s, const float* pos, uint64_t n, double
     const uint64_t m = (n - off < piece_max) ? n - off : piece_max;
     const float* p = pos + 3 * off;
     BinPlan plan;
-    if (!plan_bin(m, s->d, s->w, plan)) {
+    const uint64_t max_wg = s->upd_max_wg ? s->upd_max_wg : ((s->d <= (uint32_t)kTabLdsRows) ? 256u : 512u);
+    if (s->upd_mode == CSK_UPDATE_DIRECT || !plan_bin_wg(m, s->d, s->w, max_wg, plan)) {
       CSK_HIP(launch_update_direct(p, m, mesh, t, s->M, s->err(), st), "update (direct)");
       continue;
     }

@@ -699,10 +699,15 @@ hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const
 
 // ------------------------------------------------------------------ collect
 
+// Longest probe sequence of the candidate set.  Inserts stop at max_candidates, so the
+// table (2^ceil(log2(2 max_candidates)) slots) stays at most about half full and real
+// probe runs are far shorter; the cap only bounds the work when the set is over capacity.
+constexpr uint32_t kMaxProbe = 4096;
+
 // Is key already in the candidate set?  (A stale read can only miss a key.)
 __device__ __forceinline__ bool set_contains(const uint64_t* set, uint32_t mask, uint64_t key) {
   uint32_t i = (uint32_t)slot_mix(key) & mask;
-  for (uint32_t probe = 0; probe <= mask; ++probe) {
+  for (uint32_t probe = 0; probe <= mask && probe < kMaxProbe; ++probe) {
     const uint64_t cur = set[i];
     if (cur == key) return true;
     if (cur == kEmptyKey) return false;
@@ -714,12 +719,17 @@ __device__ __forceinline__ bool set_contains(const uint64_t* set, uint32_t mask,
 __device__ __forceinline__ void set_insert(uint64_t* set, uint32_t mask, uint64_t key, uint32_t* count,
                                            uint32_t max_cand, uint32_t* err) {
   uint32_t i = (uint32_t)slot_mix(key) & mask;
-  for (uint32_t probe = 0; probe <= mask; ++probe) {
+  for (uint32_t probe = 0; probe <= mask && probe < kMaxProbe; ++probe) {
     // A slot only ever changes from empty to a key, so a stale read can only show
     // "empty"; the compare-and-swap then tells the truth.
     const uint64_t cur = set[i];
     if (cur == key) return;
     if (cur == kEmptyKey) {
+      // a new key: once the set holds max_candidates keys no more go in (capacity error)
+      if (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= max_cand) {
+        atomicOr(err, kErrCapacity);
+        return;
+      }
       const uint64_t old = atomicCAS((unsigned long long*)&set[i], (unsigned long long)kEmptyKey,
                                      (unsigned long long)key);
       if (old == kEmptyKey) {

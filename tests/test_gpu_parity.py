@@ -348,6 +348,29 @@ def test_candidate_capacity_error():
     s.close()
 
 
+def test_candidate_set_far_over_capacity_stays_fast():
+    # Regression: a set asked to take ~2000x its capacity (4 million distinct cells into
+    # 2048 slots) stops inserting at max_candidates and bounds every probe run, so the pass
+    # ends in well under a second and reports CSK_E_CAPACITY; the full dictionary of 10^9
+    # cells into a small set does the same.
+    import time
+    pos = clustered(1 << 22, 100.0, 72, frac=0.0)
+    s = csk.Sketch(5, 1 << 12, 2, max_candidates=1000)
+    s.update(dev(pos), 0.1, 100.0)
+    t0 = time.time()
+    s.collect(dev(pos), 0.1, 100.0, oracle.INT32_MIN)
+    with pytest.raises(csk.CskError) as e:
+        s.topk(10)
+    assert e.value.code == csk.CSK_E_CAPACITY
+    s.clear_candidates()
+    s.collect_dictionary(0.1, 100.0, oracle.INT32_MIN)
+    with pytest.raises(csk.CskError) as e:
+        s.topk(10)
+    assert e.value.code == csk.CSK_E_CAPACITY
+    assert time.time() - t0 < 30.0
+    s.close()
+
+
 @pytest.mark.parametrize("d,w,G,theta,variant", [
     (5, 1 << 12, 20, oracle.INT32_MIN, 0),   # every key of the dictionary is a candidate
     (5, 1 << 16, 40, 3, 0),                  # Bloom filter + exact hot set, packed hash fields

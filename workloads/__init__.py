@@ -33,9 +33,9 @@ def _load():
     lib.wl_halo_catalogue.restype = None
     lib.wl_halo_catalogue.argtypes = [u64, u32, f64, f64, f64, f64, P, P]
     lib.wl_gen_exact.restype = i64
-    lib.wl_gen_exact.argtypes = [u64, f64, u32, f64, f64, f64, f64, u64, P]
+    lib.wl_gen_exact.argtypes = [u64, f64, u32, f64, f64, f64, f64, u64, P, C.c_int]
     lib.wl_gen_mixture.restype = i64
-    lib.wl_gen_mixture.argtypes = [u64, u64, f64, u32, f64, f64, f64, f64, f64, u64, P]
+    lib.wl_gen_mixture.argtypes = [u64, u64, f64, u32, f64, f64, f64, f64, f64, u64, P, C.c_int]
     _lib = lib
     return lib
 
@@ -73,8 +73,10 @@ class Workload:
     chunk: int = 0         # particles per generated chunk (0: one piece)
     extra: dict = field(default_factory=dict)
 
-    def generate(self, start: int = 0, count: int | None = None, out: np.ndarray | None = None) -> np.ndarray:
-        """float32 [count][3] positions of particles [start, start + count)."""
+    def generate(self, start: int = 0, count: int | None = None, out: np.ndarray | None = None,
+                 threads: int = 0) -> np.ndarray:
+        """float32 [count][3] positions of particles [start, start + count).  threads > 0 caps
+        the generator's OpenMP threads (1 when several generators run at once)."""
         if count is None:
             count = self.n - start
         if out is None:
@@ -84,10 +86,10 @@ class Workload:
         if self.f_bg < 0:
             assert start == 0 and count == self.n, "exact-count recipe is generated whole"
             lib.wl_gen_exact(self.n, self.L, self.n_halo, self.m_lo, self.m_hi, self.slope, self.a,
-                             self.seed, _p(out))
+                             self.seed, _p(out), threads)
         else:
             lib.wl_gen_mixture(start, count, self.L, self.n_halo, self.m_lo, self.m_hi, self.slope,
-                               self.a, self.f_bg, self.seed, _p(out))
+                               self.a, self.f_bg, self.seed, _p(out), threads)
         return out
 
     def with_(self, **kw) -> "Workload":

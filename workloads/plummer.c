@@ -27,6 +27,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
 
 #define WL_STREAM_HALO 0u
 #define WL_STREAM_PART 1u
@@ -144,10 +145,11 @@ static int cmp_perm(const void *a, const void *b)
 
 /* n particles: halo j gets floor(M_j) particles (halos in index order until n is
  * reached), the rest are uniform in the box, then the stream order is shuffled by
- * sorting on a per-index random 64-bit word (ties by index).  Returns the number
- * of halo particles. */
+ * sorting on a per-index random 64-bit word (ties by index).  threads > 0 caps the
+ * OpenMP threads (1 when the caller runs several generators at once).  Returns the
+ * number of halo particles. */
 int64_t wl_gen_exact(uint64_t n, double L, uint32_t n_halo, double m_lo, double m_hi,
-                     double slope, double a, uint64_t seed, float *pos)
+                     double slope, double a, uint64_t seed, float *pos, int threads)
 {
     double *mass = (double *)malloc(sizeof(double) * (n_halo ? n_halo : 1));
     double *cen = (double *)malloc(sizeof(double) * 3 * (n_halo ? n_halo : 1));
@@ -162,7 +164,7 @@ int64_t wl_gen_exact(uint64_t n, double L, uint32_t n_halo, double m_lo, double 
     uint64_t H = first[n_halo];
     const double u_max = plummer_u_max();
     float *nat = (float *)malloc(sizeof(float) * 3 * (n ? n : 1));
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : omp_get_max_threads())
     for (int64_t ii = 0; ii < (int64_t)n; ++ii) {
         uint64_t i = (uint64_t)ii;
         uint32_t r[4];
@@ -239,9 +241,10 @@ static void alias_build(const double *w, uint32_t m, double *prob, uint32_t *ali
 
 /* Particles with global indices [start, start + n): each is background (uniform)
  * with probability f_bg, otherwise it belongs to a halo drawn with probability
- * proportional to the halo mass.  Returns 0. */
+ * proportional to the halo mass.  threads as for wl_gen_exact.  Returns 0. */
 int64_t wl_gen_mixture(uint64_t start, uint64_t n, double L, uint32_t n_halo, double m_lo,
-                       double m_hi, double slope, double a, double f_bg, uint64_t seed, float *pos)
+                       double m_hi, double slope, double a, double f_bg, uint64_t seed, float *pos,
+                       int threads)
 {
     double *mass = (double *)malloc(sizeof(double) * (n_halo ? n_halo : 1));
     double *cen = (double *)malloc(sizeof(double) * 3 * (n_halo ? n_halo : 1));
@@ -260,7 +263,7 @@ int64_t wl_gen_mixture(uint64_t start, uint64_t n, double L, uint32_t n_halo, do
         }
     }
     const double u_max = plummer_u_max();
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : omp_get_max_threads())
     for (int64_t jj = 0; jj < (int64_t)n; ++jj) {
         uint64_t i = start + (uint64_t)jj;
         uint32_t r[4], q[4];
