@@ -202,7 +202,9 @@ def batched_subvolumes(csk, torch, reps=5):
     pos = [torch.from_numpy(h).cuda() for h in host]
     del host
     log(f"  generated {len(subs)} sub-volumes ({time.time() - t0:.1f} s)")
-    sk = [csk.Sketch(wl.d, wl.w, wl.seed) for wl in subs]
+    # candidate sets sized to each sub-volume (n / 16 keys, 2^16 .. 2^21): clearing and
+    # compacting a set costs time in proportion to its slots
+    sk = [csk.Sketch(wl.d, wl.w, wl.seed, max_candidates=min(1 << 21, max(1 << 16, wl.n // 16))) for wl in subs]
     counts = [wl.n for wl in subs]
     total = sum(counts)
     tuner = autotune.Tuner()
@@ -246,13 +248,22 @@ def batched_subvolumes(csk, torch, reps=5):
     est = [torch.empty(k, dtype=torch.int32, device="cuda") for k in ks]
     outs = [torch.zeros(2, dtype=torch.int32, device="cuda") for _ in ks]
 
-    def pipeline():   # one step of the batch: fresh counters, update, collect, top-k
+    side = [torch.cuda.Stream() for _ in range(8)]   # default priority
+
+    def pipeline():   # one step of the batch: fresh counters, update, then per-sketch chains
+        cur = torch.cuda.current_stream()
         for s in sk:
             s.reset()
         b.update(pos)
-        for j, s in enumerate(sk):
-            s.collect(pos[j], 0.1, 100.0, 8)
-            s.topk_async(ks[j], keys[j], est[j], outs[j])
+        for st in side:
+            st.wait_stream(cur)
+        for j, s in enumerate(sk):   # the 64 collect -> top-k chains run side by side
+            st = side[j % len(side)]
+            with torch.cuda.stream(st):
+                s.collect(pos[j], 0.1, 100.0, 8)
+                s.topk_async(ks[j], keys[j], est[j], outs[j])
+        for st in side:
+            cur.wait_stream(st)
 
     pipeline()
     torch.cuda.synchronize()
