@@ -212,6 +212,65 @@ csk_status csk_batch_update(csk_batch *b, const float *const *pos, const uint64_
 /* Free the batch (the handles stay). */
 csk_status csk_batch_destroy(csk_batch *b);
 
+/* ---- Learned router --------------------------------------------------------------
+ * A small model decides which coarse cells are counted exactly: cells it predicts to
+ * hold heavy cells go to an exact device hash table, every other particle to a Count
+ * Sketch whose width gives the pair the memory of a plain sketch.  The features of a
+ * coarse cell are the counts of a 1 % sample of the stream in it and its 26 neighbours. */
+
+/* Add, for each particle index0 + i (i < n) in the sample, 1 to counts[coarse key]
+ * (device, G_c^3 uint32, G_c = round(L / delta_c)).  Particle g is in the sample when
+ * the first word of Philox4x32-10 at counter (g mod 2^32, g / 2^32, 4, 0) under key
+ * (seed mod 2^32, seed / 2^32) is below `threshold` (1 %: 42949672).  Out-of-domain
+ * particles are skipped.  pos (device). */
+csk_status csk_sample_counts(const float *pos, uint64_t n, uint64_t index0, double delta_c, double L, uint64_t seed,
+                             uint32_t threshold, uint32_t *counts, void *stream);
+
+/* feat[j][q] = log1pf(counts[neighbour q of cells[j]]) for q < 27: the coarse cell and its
+ * 26 periodic neighbours in (dx, dy, dz) lexicographic order over {-1, 0, 1}^3;
+ * feat[j][27..31] = 0.  counts, cells, feat (device); feat is m x 32 float32. */
+csk_status csk_cell_features(const uint32_t *counts, double delta_c, double L, const uint64_t *cells, uint64_t m,
+                             float *feat, void *stream);
+
+/* The router's model: 27 -> 64 -> 64 -> 1 (inputs padded to 32), ReLU, fp32 master weights
+ * used as bf16 operands of v_mfma_f32_16x16x16_bf16 with fp32 accumulation; output layer
+ * on bf16-rounded operands with fp32 sums.  Weights He-uniform from SplitMix64(seed),
+ * biases 0.  max_batch bounds a training batch and the forward chunk. */
+typedef struct csk_mlp csk_mlp;
+csk_status csk_mlp_create(csk_mlp **out, uint64_t seed, uint32_t max_batch);
+csk_status csk_mlp_destroy(csk_mlp *m);
+/* Copy the 6337 fp32 master parameters out to `out` (host), and/or load them from `in`
+ * (host; resets the optimizer).  Layout: W1[64][32], b1[64], W2[64][64], b2[64], w3[64],
+ * b3.  Synchronizes. */
+csk_status csk_mlp_params(csk_mlp *m, float *out, const float *in);
+/* Copy the gradients of the last training step (same layout) to `out` (host).  Synchronizes. */
+csk_status csk_mlp_grads(csk_mlp *m, float *out);
+/* logits[j] (device) of the n feature rows x (device, n x 32). */
+csk_status csk_mlp_forward(csk_mlp *m, const float *x, uint64_t n, float *logits, void *stream);
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the mean binary cross-entropy of
+ * n <= max_batch rows x with labels y (device, 0 or 1); *loss (device, may be NULL) gets
+ * the loss before the step. */
+csk_status csk_mlp_train_step(csk_mlp *m, const float *x, const float *y, uint32_t n, float lr, float *loss,
+                              void *stream);
+
+/* Route a stream: an in-domain particle whose coarse parent (cell index / factor on each
+ * axis) is in `admitted` (device, na <= 512 coarse keys of the mesh G / factor, sorted
+ * ascending) adds 1 to its cell key's count in the exact table (device, table_slots a power
+ * of two, keys all-ones when empty, linear probing from a fixed hash); every other
+ * in-domain particle is appended to rest_pos (device, room for n), *rest_count (device)
+ * counting them.  na * factor^3 <= table_slots / 2, so the table never fills.  Out-of-domain
+ * particles set bit 0 of *err (device). */
+csk_status csk_route_split(const float *pos, uint64_t n, double delta, double L, uint32_t factor,
+                           const uint64_t *admitted, uint32_t na, uint64_t *table_keys, uint32_t *table_counts,
+                           uint32_t table_slots, float *rest_pos, uint64_t *rest_count, uint32_t *err, void *stream);
+
+/* As csk_topk for a sketch of the routed rest: every key of the exact table joins the
+ * candidates, and a candidate found in the table takes its exact count as its estimate.
+ * Synchronizes. */
+csk_status csk_topk_with_table(csk_sketch *s, const uint64_t *table_keys, const uint32_t *table_counts,
+                               uint32_t table_slots, uint32_t k, uint64_t *keys, int32_t *est, uint32_t *k_out,
+                               void *stream);
+
 #ifdef __cplusplus
 }
 #endif

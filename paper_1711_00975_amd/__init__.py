@@ -37,6 +37,8 @@ EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "cs
            "csk_set_update_plan",
            "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
            "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_update", "csk_batch_destroy",
+           "csk_sample_counts", "csk_cell_features", "csk_mlp_create", "csk_mlp_destroy", "csk_mlp_params",
+           "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_route_split", "csk_topk_with_table",
            "csk_get_counters", "csk_set_counters", "csk_reset", "csk_check", "csk_device_bytes",
            "csk_last_error"]
 
@@ -79,6 +81,16 @@ def load_library(path: str = LIB_PATH):
         "csk_batch_create": [PP, P, P, u32, f64, f64, u32],
         "csk_batch_update": [P, P, P, P],
         "csk_batch_destroy": [P],
+        "csk_sample_counts": [P, u64, u64, f64, f64, u64, u32, P, P],
+        "csk_cell_features": [P, f64, f64, P, u64, P, P],
+        "csk_mlp_create": [PP, u64, u32],
+        "csk_mlp_destroy": [P],
+        "csk_mlp_params": [P, P, P],
+        "csk_mlp_grads": [P, P],
+        "csk_mlp_forward": [P, P, u64, P, P],
+        "csk_mlp_train_step": [P, P, P, u32, C.c_float, P, P],
+        "csk_route_split": [P, u64, f64, f64, u32, P, u32, P, P, u32, P, P, P, P],
+        "csk_topk_with_table": [P, P, P, u32, u32, P, P, C.POINTER(C.c_uint32), P],
         "csk_get_counters": [P, P, P],
         "csk_set_counters": [P, P, P],
         "csk_reset": [P, P],
@@ -367,3 +379,100 @@ def cell_keys(pos, delta, L, stream=None):
     keys = torch.empty(pos.shape[0], dtype=torch.int64, device=pos.device)
     csk_cell_keys(pos, delta, L, keys, stream)
     return keys
+
+
+# ------------------------------------------------------------- learned router
+
+SAMPLE_THRESHOLD = 42949672   # floor(0.01 * 2^32): the 1 % sample
+N_PARAMS = 6337
+FEAT = 32
+
+
+def sample_counts(pos, delta_c, L, seed, counts, index0=0, threshold=SAMPLE_THRESHOLD, stream=None):
+    """Add the 1 % sample of pos (particles index0 ..) to counts (device uint32 [G_c^3] as int32)."""
+    import torch
+    _check(load_library().csk_sample_counts(_dev(pos, torch.float32, 3) if pos.shape[0] else None, pos.shape[0],
+                                            index0, delta_c, L, seed, threshold, _dev(counts, torch.int32),
+                                            _stream(stream)))
+
+
+def cell_features(counts, delta_c, L, cells, stream=None):
+    """float32 [m][32] features of the coarse cells `cells` (device int64 keys)."""
+    import torch
+    feat = torch.empty((cells.shape[0], FEAT), dtype=torch.float32, device=cells.device)
+    if cells.shape[0]:
+        _check(load_library().csk_cell_features(_dev(counts, torch.int32), delta_c, L, _dev(cells, torch.int64),
+                                                cells.shape[0], _dev(feat, torch.float32, FEAT), _stream(stream)))
+    return feat
+
+
+class MLP:
+    """The router's 27 -> 64 -> 64 -> 1 model (csk_mlp_*)."""
+
+    def __init__(self, seed=1, max_batch=4096):
+        h = C.c_void_p()
+        _check(load_library().csk_mlp_create(C.byref(h), seed, max_batch))
+        self.h, self.max_batch = h, max_batch
+
+    def params(self):
+        import numpy as np
+        out = np.empty(N_PARAMS, dtype=np.float32)
+        _check(load_library().csk_mlp_params(self.h, out.ctypes.data_as(C.c_void_p), None))
+        return out
+
+    def set_params(self, p):
+        import numpy as np
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        assert a.size == N_PARAMS
+        _check(load_library().csk_mlp_params(self.h, None, a.ctypes.data_as(C.c_void_p)))
+
+    def grads(self):
+        import numpy as np
+        out = np.empty(N_PARAMS, dtype=np.float32)
+        _check(load_library().csk_mlp_grads(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def forward(self, x, stream=None):
+        import torch
+        z = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        if x.shape[0]:
+            _check(load_library().csk_mlp_forward(self.h, _dev(x, torch.float32, FEAT), x.shape[0],
+                                                  _dev(z, torch.float32), _stream(stream)))
+        return z
+
+    def train_step(self, x, y, lr, loss=None, stream=None):
+        import torch
+        _check(load_library().csk_mlp_train_step(self.h, _dev(x, torch.float32, FEAT), _dev(y, torch.float32),
+                                                 x.shape[0], lr, _dev(loss, torch.float32) if loss is not None else None,
+                                                 _stream(stream)))
+
+    def close(self):
+        if self.h is not None:
+            _check(load_library().csk_mlp_destroy(self.h))
+            self.h = None
+
+
+def route_split(pos, delta, L, factor, admitted, table_keys, table_counts, rest_pos, rest_count, err, stream=None):
+    """admitted: sorted device int64 coarse keys; table_keys (int64, all ones when empty) and
+    table_counts (int32) of a power-of-two size; rest_pos float32 [n][3]; rest_count int64 [1];
+    err int32 [1]."""
+    import torch
+    _check(load_library().csk_route_split(_dev(pos, torch.float32, 3) if pos.shape[0] else None, pos.shape[0], delta, L,
+                                          factor, _dev(admitted, torch.int64) if admitted.shape[0] else None,
+                                          admitted.shape[0], _dev(table_keys, torch.int64),
+                                          _dev(table_counts, torch.int32), table_keys.shape[0],
+                                          _dev(rest_pos, torch.float32, 3), _dev(rest_count, torch.int64),
+                                          _dev(err, torch.int32), _stream(stream)))
+
+
+def topk_with_table(sketch, table_keys, table_counts, k, stream=None):
+    import torch
+    dev = table_keys.device
+    keys = torch.empty(max(k, 1), dtype=torch.int64, device=dev)
+    est = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
+    kout = C.c_uint32(0)
+    rc = _check(load_library().csk_topk_with_table(sketch.h, _dev(table_keys, torch.int64),
+                                                   _dev(table_counts, torch.int32), table_keys.shape[0], k,
+                                                   _dev(keys, torch.int64), _dev(est, torch.int32), C.byref(kout),
+                                                   _stream(stream)), allow_warning=True)
+    return keys[:kout.value], est[:kout.value], rc

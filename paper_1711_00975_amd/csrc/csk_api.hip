@@ -12,6 +12,7 @@
 
 #include "csk.h"
 #include "csk_internal.h"
+#include "csk_router.h"
 
 using namespace csk;
 
@@ -744,5 +745,255 @@ csk_status csk_batch_destroy(csk_batch* b) {
   (void)hipDeviceSynchronize();
   batch_free(b);
   delete b;
+  return CSK_OK;
+}
+
+// ------------------------------------------------------------------ learned router
+
+struct csk_mlp {
+  int device = 0;
+  uint32_t max_batch = 0;
+  uint64_t step = 0;
+  float* p = nullptr;     // fp32 master parameters (kParams)
+  float* g = nullptr;     // gradients
+  float* m1 = nullptr;    // Adam moments
+  float* m2 = nullptr;
+  float* H1 = nullptr;    // [max_batch][64]
+  float* H2 = nullptr;
+  float* dA2 = nullptr;
+  float* dA1 = nullptr;
+  float* z = nullptr;     // [max_batch]
+  float* dz = nullptr;
+  float* loss = nullptr;  // [1]
+};
+
+namespace {
+
+void mlp_free(csk_mlp* m) {
+  void* ptrs[] = {m->p, m->g, m->m1, m->m2, m->H1, m->H2, m->dA2, m->dA1, m->z, m->dz, m->loss};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+// forward of rows [0, b) of x into H1, H2 and z (logits)
+hipError_t mlp_forward_rows(csk_mlp* m, const float* x, uint32_t b, float* z, const float* y, hipStream_t st) {
+  const float* P = m->p;
+  hipError_t e = launch_gemm_bf16(b, kHidden, kFeatPad, x, kFeatPad, 1, P + kOffW1, 1, kFeatPad, m->H1, kHidden, 1,
+                                  0.0f, st);
+  if (e == hipSuccess) e = launch_bias_act(m->H1, b, kHidden, P + kOffB1, true, st);
+  if (e == hipSuccess)
+    e = launch_gemm_bf16(b, kHidden, kHidden, m->H1, kHidden, 1, P + kOffW2, 1, kHidden, m->H2, kHidden, 1, 0.0f, st);
+  if (e == hipSuccess) e = launch_bias_act(m->H2, b, kHidden, P + kOffB2, true, st);
+  if (e == hipSuccess) e = launch_head(m->H2, b, P + kOffW3, P + kOffB3, z, y, m->dz, m->loss, st);
+  return e;
+}
+
+}  // namespace
+
+csk_status csk_mlp_create(csk_mlp** out, uint64_t seed, uint32_t max_batch) {
+  if (out == nullptr) return fail(CSK_E_INVALID, "mlp_create: out is NULL");
+  *out = nullptr;
+  if (max_batch < 1 || max_batch > (1u << 22)) return fail(CSK_E_INVALID, "mlp_create: max_batch outside [1, 2^22]");
+  csk_mlp* m = new (std::nothrow) csk_mlp();
+  if (!m) return fail(CSK_E_NOMEM, "mlp_create: host allocation failed");
+  m->max_batch = max_batch;
+  // He-uniform weights U(-sqrt(6 / fan_in), +sqrt(6 / fan_in)) from SplitMix64(seed); biases 0
+  std::vector<float> P(kParams, 0.0f);
+  uint64_t st = seed;
+  auto uni = [&]() { return (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0); };
+  for (uint32_t i = 0; i < 64u * 32u; ++i) P[kOffW1 + i] = (float)((2.0 * uni() - 1.0) * std::sqrt(6.0 / 27.0));
+  for (uint32_t i = 0; i < 64u * 64u; ++i) P[kOffW2 + i] = (float)((2.0 * uni() - 1.0) * std::sqrt(6.0 / 64.0));
+  for (uint32_t i = 0; i < 64u; ++i) P[kOffW3 + i] = (float)((2.0 * uni() - 1.0) * std::sqrt(6.0 / 64.0));
+  for (uint32_t r = 0; r < 64u; ++r)   // the 5 padding inputs carry no weight
+    for (uint32_t c = 27; c < 32u; ++c) P[kOffW1 + r * 32 + c] = 0.0f;
+  hipError_t e = hipGetDevice(&m->device);
+  const uint64_t hb = (uint64_t)max_batch * kHidden;
+  if (e == hipSuccess) e = bmalloc(&m->p, kParams);
+  if (e == hipSuccess) e = bmalloc(&m->g, kParams);
+  if (e == hipSuccess) e = bmalloc(&m->m1, kParams);
+  if (e == hipSuccess) e = bmalloc(&m->m2, kParams);
+  if (e == hipSuccess) e = bmalloc(&m->H1, hb);
+  if (e == hipSuccess) e = bmalloc(&m->H2, hb);
+  if (e == hipSuccess) e = bmalloc(&m->dA2, hb);
+  if (e == hipSuccess) e = bmalloc(&m->dA1, hb);
+  if (e == hipSuccess) e = bmalloc(&m->z, max_batch);
+  if (e == hipSuccess) e = bmalloc(&m->dz, max_batch);
+  if (e == hipSuccess) e = bmalloc(&m->loss, 1);
+  if (e == hipSuccess) e = hipMemcpy(m->p, P.data(), kParams * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->m1, kParams, 0u, nullptr);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->m2, kParams, 0u, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    mlp_free(m);
+    delete m;
+    return hip_fail(e, "mlp_create");
+  }
+  *out = m;
+  return CSK_OK;
+}
+
+csk_status csk_mlp_destroy(csk_mlp* m) {
+  if (m == nullptr) return CSK_OK;
+  (void)hipDeviceSynchronize();
+  mlp_free(m);
+  delete m;
+  return CSK_OK;
+}
+
+csk_status csk_mlp_params(csk_mlp* m, float* out, const float* in) {
+  if (m == nullptr || (out == nullptr && in == nullptr)) return fail(CSK_E_INVALID, "mlp_params: NULL argument");
+  if (in != nullptr) {
+    CSK_HIP(hipMemcpy(m->p, in, kParams * sizeof(float), hipMemcpyHostToDevice), "mlp_params");
+    m->step = 0;
+    CSK_HIP(launch_fill_u32((uint32_t*)m->m1, kParams, 0u, nullptr), "mlp_params");
+    CSK_HIP(launch_fill_u32((uint32_t*)m->m2, kParams, 0u, nullptr), "mlp_params");
+  }
+  if (out != nullptr) CSK_HIP(hipMemcpy(out, m->p, kParams * sizeof(float), hipMemcpyDeviceToHost), "mlp_params");
+  CSK_HIP(hipDeviceSynchronize(), "mlp_params");
+  return CSK_OK;
+}
+
+csk_status csk_mlp_grads(csk_mlp* m, float* out) {
+  if (m == nullptr || out == nullptr) return fail(CSK_E_INVALID, "mlp_grads: NULL argument");
+  CSK_HIP(hipDeviceSynchronize(), "mlp_grads");
+  CSK_HIP(hipMemcpy(out, m->g, kParams * sizeof(float), hipMemcpyDeviceToHost), "mlp_grads");
+  return CSK_OK;
+}
+
+csk_status csk_mlp_forward(csk_mlp* m, const float* x, uint64_t n, float* logits, void* stream) {
+  if (m == nullptr || (n > 0 && (x == nullptr || logits == nullptr))) return fail(CSK_E_INVALID, "mlp_forward: NULL");
+  hipStream_t st = (hipStream_t)stream;
+  for (uint64_t off = 0; off < n; off += m->max_batch) {
+    const uint32_t b = (uint32_t)((n - off < m->max_batch) ? n - off : m->max_batch);
+    CSK_HIP(mlp_forward_rows(m, x + off * kFeatPad, b, logits + off, nullptr, st), "mlp_forward");
+  }
+  return CSK_OK;
+}
+
+csk_status csk_mlp_train_step(csk_mlp* m, const float* x, const float* y, uint32_t n, float lr, float* loss,
+                              void* stream) {
+  if (m == nullptr || x == nullptr || y == nullptr) return fail(CSK_E_INVALID, "mlp_train_step: NULL argument");
+  if (n < 1 || n > m->max_batch) return fail(CSK_E_INVALID, "mlp_train_step: n=%u outside [1, %u]", n, m->max_batch);
+  hipStream_t st = (hipStream_t)stream;
+  float* P = m->p;
+  float* G = m->g;
+  CSK_HIP(launch_fill_u32((uint32_t*)m->loss, 1, 0u, st), "mlp_train_step");
+  CSK_HIP(mlp_forward_rows(m, x, n, m->z, y, st), "mlp_train_step (forward)");
+  // output layer: dw3 = H2^T dz, db3 = sum dz
+  CSK_HIP(launch_colsum(m->H2, n, kHidden, kHidden, m->dz, G + kOffW3, st), "mlp_train_step");
+  CSK_HIP(launch_colsum(m->dz, n, 1, 1, nullptr, G + kOffB3, st), "mlp_train_step");
+  // second layer: dA2 = (dz w3^T) masked by ReLU; dW2 = dA2^T H1; db2 = colsum dA2
+  CSK_HIP(launch_head_back(m->dz, m->H2, P + kOffW3, n, m->dA2, st), "mlp_train_step");
+  CSK_HIP(launch_gemm_bf16(kHidden, kHidden, n, m->dA2, 1, kHidden, m->H1, kHidden, 1, G + kOffW2, kHidden, 1, 0.0f,
+                           st),
+          "mlp_train_step");
+  CSK_HIP(launch_colsum(m->dA2, n, kHidden, kHidden, nullptr, G + kOffB2, st), "mlp_train_step");
+  // first layer: dA1 = (dA2 W2) masked by ReLU; dW1 = dA1^T X; db1 = colsum dA1
+  CSK_HIP(launch_gemm_bf16(n, kHidden, kHidden, m->dA2, kHidden, 1, P + kOffW2, kHidden, 1, m->dA1, kHidden, 1, 0.0f,
+                           st),
+          "mlp_train_step");
+  CSK_HIP(launch_relu_back(m->dA1, m->H1, (uint64_t)n * kHidden, st), "mlp_train_step");
+  CSK_HIP(launch_gemm_bf16(kHidden, kFeatPad, n, m->dA1, 1, kHidden, x, kFeatPad, 1, G + kOffW1, kFeatPad, 1, 0.0f,
+                           st),
+          "mlp_train_step");
+  CSK_HIP(launch_colsum(m->dA1, n, kHidden, kHidden, nullptr, G + kOffB1, st), "mlp_train_step");
+  // Adam
+  m->step += 1;
+  const double b1 = 0.9, b2 = 0.999;
+  const double lr_t = lr * std::sqrt(1.0 - std::pow(b2, (double)m->step)) / (1.0 - std::pow(b1, (double)m->step));
+  CSK_HIP(launch_adam(P, G, m->m1, m->m2, kParams, (float)lr_t, (float)b1, (float)b2, 1e-8f, st), "mlp_train_step");
+  if (loss != nullptr)
+    CSK_HIP(hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToDevice, st), "mlp_train_step");
+  return CSK_OK;
+}
+
+csk_status csk_sample_counts(const float* pos, uint64_t n, uint64_t index0, double delta_c, double L, uint64_t seed,
+                             uint32_t threshold, uint32_t* counts, void* stream) {
+  Mesh coarse;
+  csk_status rc = check_mesh(nullptr, delta_c, L, &coarse);
+  if (rc != CSK_OK) return rc;
+  if (n > 0 && (pos == nullptr || counts == nullptr)) return fail(CSK_E_INVALID, "sample_counts: NULL pointer");
+  if (n == 0) return CSK_OK;
+  CSK_HIP(launch_sample_counts(pos, n, index0, seed, threshold, coarse, counts, (hipStream_t)stream), "sample_counts");
+  return CSK_OK;
+}
+
+csk_status csk_cell_features(const uint32_t* counts, double delta_c, double L, const uint64_t* cells, uint64_t m,
+                             float* feat, void* stream) {
+  Mesh coarse;
+  csk_status rc = check_mesh(nullptr, delta_c, L, &coarse);
+  if (rc != CSK_OK) return rc;
+  if (m > 0 && (counts == nullptr || cells == nullptr || feat == nullptr))
+    return fail(CSK_E_INVALID, "cell_features: NULL pointer");
+  if (m == 0) return CSK_OK;
+  CSK_HIP(launch_features(counts, (uint32_t)coarse.G, cells, m, feat, (hipStream_t)stream), "cell_features");
+  return CSK_OK;
+}
+
+csk_status csk_route_split(const float* pos, uint64_t n, double delta, double L, uint32_t factor,
+                           const uint64_t* admitted, uint32_t na, uint64_t* table_keys, uint32_t* table_counts,
+                           uint32_t table_slots, float* rest_pos, uint64_t* rest_count, uint32_t* err, void* stream) {
+  Mesh mesh;
+  csk_status rc = check_mesh(nullptr, delta, L, &mesh);
+  if (rc != CSK_OK) return rc;
+  if (factor < 1 || (uint32_t)mesh.G % factor != 0)
+    return fail(CSK_E_INVALID, "route_split: factor %u does not divide G=%d", factor, mesh.G);
+  if (na > kMaxAdmitted) return fail(CSK_E_INVALID, "route_split: %u admitted cells above %u", na, kMaxAdmitted);
+  if (table_slots < 2 || (table_slots & (table_slots - 1)) != 0)
+    return fail(CSK_E_INVALID, "route_split: table_slots=%u is not a power of two", table_slots);
+  if ((uint64_t)na * factor * factor * factor > table_slots / 2)
+    return fail(CSK_E_INVALID, "route_split: %u cells of %u^3 children exceed half of %u slots", na, factor,
+                table_slots);
+  if (n > 0 && (pos == nullptr || rest_pos == nullptr || rest_count == nullptr || err == nullptr ||
+                table_keys == nullptr || table_counts == nullptr || (na > 0 && admitted == nullptr)))
+    return fail(CSK_E_INVALID, "route_split: NULL pointer");
+  if (n == 0) return CSK_OK;
+  CSK_HIP(launch_route_split(pos, n, mesh, factor, admitted, na, table_keys, table_counts, table_slots - 1, rest_pos,
+                             (unsigned long long*)rest_count, err, (hipStream_t)stream),
+          "route_split");
+  return CSK_OK;
+}
+
+csk_status csk_topk_with_table(csk_sketch* s, const uint64_t* table_keys, const uint32_t* table_counts,
+                               uint32_t table_slots, uint32_t k, uint64_t* keys, int32_t* est, uint32_t* k_out,
+                               void* stream) {
+  if (s == nullptr || k_out == nullptr || table_keys == nullptr || table_counts == nullptr)
+    return fail(CSK_E_INVALID, "topk_with_table: NULL argument");
+  if (table_slots < 2 || (table_slots & (table_slots - 1)) != 0)
+    return fail(CSK_E_INVALID, "topk_with_table: table_slots=%u is not a power of two", table_slots);
+  *k_out = 0;
+  if (k > 0 && (keys == nullptr || est == nullptr)) return fail(CSK_E_INVALID, "topk_with_table: NULL output");
+  if (k > s->max_cand) return fail(CSK_E_INVALID, "topk_with_table: k=%u above max_candidates", k);
+  hipStream_t st = (hipStream_t)stream;
+  CSK_HIP(launch_table_to_set(table_keys, table_slots, s->set, s->slots - 1, s->set_count(), s->max_cand, s->err(), st),
+          "topk_with_table");
+  if (k > s->sel_cap) {
+    CSK_HIP(hipStreamSynchronize(st), "topk_with_table: grow scratch");
+    if (s->sel_key) (void)hipFree(s->sel_key);
+    if (s->sel_est) (void)hipFree(s->sel_est);
+    s->bytes -= (uint64_t)s->sel_cap * (sizeof(uint64_t) + sizeof(int32_t));
+    s->sel_key = nullptr;
+    s->sel_est = nullptr;
+    s->sel_cap = 0;
+    CSK_HIP(dmalloc(s, &s->sel_key, k), "topk_with_table: scratch");
+    CSK_HIP(dmalloc(s, &s->sel_est, k), "topk_with_table: scratch");
+    s->sel_cap = k;
+  }
+  if (k > 0) {
+    CSK_HIP(launch_topk(s->set, s->slots, s->tables(), s->M, s->max_cand, k, s->sel, s->cand_key, s->cand_est,
+                        s->sel_key, s->sel_est, keys, est, s->err(), st, table_keys, table_counts, table_slots - 1),
+            "topk_with_table");
+  }
+  CSK_HIP(hipMemcpyAsync(s->host_sel, s->sel, sizeof(SelState), hipMemcpyDeviceToHost, st), "topk_with_table");
+  uint32_t bits = 0;
+  csk_status rc = take_latch(s, st, &bits);
+  if (rc != CSK_OK) return rc;
+  rc = latch_status(bits);
+  if (rc != CSK_OK) return rc;
+  const uint32_t m = k ? s->host_sel->m : 0;
+  const uint32_t got = (k < m) ? k : m;
+  *k_out = got;
+  if (got < k && s->partial_set)
+    return fail(CSK_W_INCOMPLETE, "topk_with_table: only %u of %u candidates", got, k);
   return CSK_OK;
 }

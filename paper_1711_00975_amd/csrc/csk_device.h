@@ -311,6 +311,15 @@ __device__ __forceinline__ uint64_t slot_mix(uint64_t k) {
   return k;
 }
 
+// Home slot of a cell key in the router's exact table (linear probing, empty = all ones).
+__device__ __forceinline__ uint32_t table_slot(uint64_t key, uint32_t mask) {
+  uint64_t x = key;
+  x ^= x >> 33;
+  x *= 0xFF51AFD7ED558CCDull;
+  x ^= x >> 33;
+  return (uint32_t)x & mask;
+}
+
 // Hot item (row r < 8, bucket b < 2^28 - 1, sign bit) packed in 32 bits (never kHotEmpty).
 __device__ __forceinline__ uint32_t hot_item(uint32_t r, uint32_t b, uint32_t neg) {
   return (r << 29) | (b << 1) | neg;

@@ -153,9 +153,15 @@ hipError_t launch_collect_children(const uint64_t* coarse_set, uint32_t coarse_s
 hipError_t launch_topk_out(const SelState* st, uint32_t k, uint32_t partial, uint32_t* out, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+// ov_keys / ov_counts / ov_mask: an exact table whose counts replace the estimates of the
+// candidates found in it (NULL: none).
 hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,
                        uint32_t max_cand, uint32_t k, SelState* st, uint64_t* cand_key, int32_t* cand_est,
                        uint64_t* sel_key, int32_t* sel_est, uint64_t* out_key, int32_t* out_est,
-                       const uint32_t* err, hipStream_t s);
+                       const uint32_t* err, hipStream_t s, const uint64_t* ov_keys = nullptr,
+                       const uint32_t* ov_counts = nullptr, uint32_t ov_mask = 0);
+// Insert every non-empty key of an exact table (tslots slots) into a candidate set.
+hipError_t launch_table_to_set(const uint64_t* tk, uint32_t tslots, uint64_t* set, uint32_t slot_mask,
+                               uint32_t* set_count, uint32_t max_cand, uint32_t* err, hipStream_t s);
 
 }  // namespace csk

@@ -1003,6 +1003,23 @@ __global__ __launch_bounds__(256) void set_list_kernel(const uint64_t* __restric
   }
 }
 
+// Every key of the router's exact table joins a candidate set.
+__global__ __launch_bounds__(256) void table_to_set_kernel(const uint64_t* __restrict__ tk, uint32_t tslots, uint64_t* set,
+                                                           uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand,
+                                                           uint32_t* err) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < tslots; i += gridDim.x * blockDim.x) {
+    const uint64_t key = tk[i];
+    if (key != kEmptyKey) set_insert(set, slot_mask, key, set_count, max_cand, err);
+  }
+}
+
+hipError_t launch_table_to_set(const uint64_t* tk, uint32_t tslots, uint64_t* set, uint32_t slot_mask,
+                               uint32_t* set_count, uint32_t max_cand, uint32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(table_to_set_kernel, dim3(grid_for(tslots, 256, 1024)), dim3(256), 0, s, tk, tslots, set,
+                     slot_mask, set_count, max_cand, err);
+  return hipGetLastError();
+}
+
 // Second layer of the hierarchical query (Alg. 3): for each super-item j of the list,
 // every child key of [j R, min((j + 1) R, ncells)) is estimated from the fine counters
 // and goes into the fine set if its estimate is >= theta.  One workgroup per super-item
@@ -1335,11 +1352,27 @@ __global__ void sel_init_kernel(SelState* st) {
 }
 
 // Distinct keys of the set -> (key, estimate from the current counters).
+// Exact count of key in the router's table (linear probing from table_slot), or -1.
+__device__ __forceinline__ int64_t table_count(const uint64_t* __restrict__ tk, const uint32_t* __restrict__ tc,
+                                               uint32_t tmask, uint64_t key) {
+  uint32_t sl = table_slot(key, tmask);
+  for (uint32_t probe = 0; probe <= tmask; ++probe) {
+    const uint64_t k = tk[sl];
+    if (k == key) return (int64_t)tc[sl];
+    if (k == kEmptyKey) return -1;
+    sl = (sl + 1) & tmask;
+  }
+  return -1;
+}
+
+// With an exact table (ov_keys != NULL), a candidate found in it takes its exact count
+// as its estimate (the learned router's table; counts of up to 2^31 - 1).
 template <int MAXD, bool TAB_LDS>
 __global__ __launch_bounds__(256) void compact_kernel(const uint64_t* __restrict__ set, uint32_t slots, Tables t,
                                                       const int32_t* __restrict__ M, uint32_t max_cand,
                                                       SelState* st, uint64_t* __restrict__ ck,
-                                                      int32_t* __restrict__ ce) {
+                                                      int32_t* __restrict__ ce, const uint64_t* __restrict__ ov_keys,
+                                                      const uint32_t* __restrict__ ov_counts, uint32_t ov_mask) {
   __shared__ uint32_t tabs_lds[TAB_LDS ? kTabLdsRows * kTableWords : 1];
   const uint32_t* tabs = t.tab;
   if (TAB_LDS) {
@@ -1354,7 +1387,8 @@ __global__ __launch_bounds__(256) void compact_kernel(const uint64_t* __restrict
     const uint32_t slot = wave_append(&st->m, have);
     if (have && slot < max_cand) {
       ck[slot] = key;
-      ce[slot] = estimate_key<MAXD>(tabs, M, t.d, t.w, t.cm, key);
+      const int64_t exact = ov_keys ? table_count(ov_keys, ov_counts, ov_mask, key) : -1;
+      ce[slot] = exact >= 0 ? (int32_t)exact : estimate_key<MAXD>(tabs, M, t.d, t.w, t.cm, key);
     }
   }
 }
@@ -1513,15 +1547,15 @@ __global__ void sel_finish_kernel(SelState* st, const uint32_t* err) {
 hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,
                        uint32_t max_cand, uint32_t k, SelState* st, uint64_t* ck, int32_t* ce,
                        uint64_t* sk, int32_t* se, uint64_t* ok, int32_t* oe, const uint32_t* err,
-                       hipStream_t s) {
+                       hipStream_t s, const uint64_t* ov_keys, const uint32_t* ov_counts, uint32_t ov_mask) {
   hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, s, st);
   const dim3 cgrid(grid_for(slots, 256, 4096));
   if (t.d <= (uint32_t)kTabLdsRows)
     hipLaunchKernelGGL((compact_kernel<kTabLdsRows, true>), cgrid, dim3(256), 0, s, set, slots, t, M, max_cand, st,
-                       ck, ce);
+                       ck, ce, ov_keys, ov_counts, ov_mask);
   else
     hipLaunchKernelGGL((compact_kernel<32, false>), cgrid, dim3(256), 0, s, set, slots, t, M, max_cand, st, ck,
-                       ce);
+                       ce, ov_keys, ov_counts, ov_mask);
   hipLaunchKernelGGL(clamp_m_kernel, dim3(1), dim3(64), 0, s, st, max_cand);
   const dim3 hgrid(grid_for(max_cand, 256, 1024));
   for (int shift = 24; shift >= 0; shift -= 8) {

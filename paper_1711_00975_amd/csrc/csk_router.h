@@ -1,0 +1,40 @@
+// csk_router.h — launch interface of the learned-router kernels (csk_router.hip).
+// Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "csk_device.h"
+
+namespace csk {
+
+constexpr uint32_t kSampleStream = 4;   // Philox stream of the sampling coin
+constexpr int kFeatPad = 32;            // 27 neighbour features, padded to an MFMA K step
+constexpr int kHidden = 64;             // hidden width of both layers
+constexpr uint32_t kMaxAdmitted = 512;  // coarse cells an exact table takes at most
+// MLP parameter layout (fp32 master copy): W1 [64][32], b1 [64], W2 [64][64], b2 [64],
+// w3 [64], b3 [1]
+constexpr uint32_t kOffW1 = 0, kOffB1 = 2048, kOffW2 = 2112, kOffB2 = 6208, kOffW3 = 6272, kOffB3 = 6336;
+constexpr uint32_t kParams = 6337;
+
+hipError_t launch_sample_counts(const float* pos, uint64_t n, uint64_t index0, uint64_t seed, uint32_t threshold,
+                                const Mesh& coarse, uint32_t* counts, hipStream_t s);
+hipError_t launch_features(const uint32_t* counts, uint32_t Gc, const uint64_t* cells, uint64_t m, float* feat,
+                           hipStream_t s);
+hipError_t launch_gemm_bf16(uint32_t M, uint32_t N, uint32_t K, const float* A, uint64_t sai, uint64_t sak,
+                            const float* B, uint64_t sbk, uint64_t sbj, float* C, uint64_t sci, uint64_t scj,
+                            float beta, hipStream_t s);
+hipError_t launch_bias_act(float* Y, uint32_t M, uint32_t N, const float* bias, bool relu, hipStream_t s);
+hipError_t launch_head(const float* H2, uint32_t M, const float* w3, const float* b3, float* z, const float* y,
+                       float* dz, float* loss, hipStream_t s);
+hipError_t launch_head_back(const float* dz, const float* H2, const float* w3, uint32_t M, float* dA, hipStream_t s);
+hipError_t launch_relu_back(float* dA, const float* H, uint64_t total, hipStream_t s);
+hipError_t launch_colsum(const float* X, uint32_t M, uint32_t N, uint32_t ld, const float* w, float* out, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, uint32_t n, float lr_t, float b1, float b2,
+                       float eps, hipStream_t s);
+hipError_t launch_route_split(const float* pos, uint64_t n, const Mesh& mesh, uint32_t factor, const uint64_t* admitted,
+                              uint32_t na, uint64_t* tkeys, uint32_t* tcounts, uint32_t tmask, float* rest_pos,
+                              unsigned long long* rest_count, uint32_t* err, hipStream_t s);
+
+}  // namespace csk

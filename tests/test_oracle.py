@@ -576,3 +576,79 @@ def test_hierarchical_topk_brute_force():
         b = oracle.topk_dictionary(M2, T2, G, theta2, 200)
         assert all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[2] == b[2]
     assert oracle.topk_hierarchical(M1, T1, M2, T2, G, 0, 0, 0, 5)[2] == oracle.E_INVALID
+
+
+# ------------------------------------------------------------------ learned router reference
+
+def test_router_features_and_sample_by_brute_force():
+    from oracle import router
+    import workloads
+    # features: neighbour counts enumerated one by one on a tiny periodic mesh
+    Gc = 5
+    counts = np.arange(Gc ** 3, dtype=np.uint32) * 7 % 11
+    cells = np.array([0, 62, 124, 31], dtype=np.int64)
+    f = router.features(counts, Gc, cells)
+    for r, c in enumerate(cells):
+        x, y, z = c // 25, (c // 5) % 5, c % 5
+        q = 0
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    nb = (((x + dx) % 5) * 5 + (y + dy) % 5) * 5 + (z + dz) % 5
+                    assert f[r, q] == np.float32(np.log1p(np.float32(counts[nb])))
+                    q += 1
+        assert not f[r, 27:].any()
+    # the sample: about 1 % of the stream, and the coin is the published Philox word
+    m = router.sample_mask(200_000, 9)
+    assert 0.009 < m.mean() < 0.011
+    w = workloads.philox4x32_10([12345, 0, 4, 0], [9, 0])[0]
+    assert m[12345] == (w < router.SAMPLE_THRESHOLD)
+
+
+def test_router_forward_and_gradients_by_loops_and_differences():
+    from oracle import router
+    rng = np.random.default_rng(4)
+    p = rng.normal(0, 0.3, router.N_PARAMS).astype(np.float32)
+    w = router.unpack(p)
+    w["W1"][:, 27:] = 0
+    p = router.pack(w)
+    x = np.zeros((6, 32), np.float32)
+    x[:, :27] = rng.random((6, 27)) * 3
+    z, _, _ = router.forward(p, x)
+    assert np.allclose(z, router.forward_loops(p, x), atol=1e-4)
+    # bf16 rounding: ties to even, and 1 + 2^-8 (a tie) rounds down to 1
+    assert router.bf16(np.float32(1 + 2 ** -8)) == 1.0 and router.bf16(np.float32(1 + 3 * 2 ** -8)) == np.float32(1 + 2 ** -6)
+    # gradients of the loss at float64 without rounding, by central differences, agree with
+    # the rounded analytic gradients to bf16 accuracy
+    y = (rng.random(6) < 0.5).astype(np.float32)
+    g = router.gradients(p, x, y)
+
+    def loss(q):
+        wq = router.unpack(q.astype(np.float32))
+        h1 = np.maximum(x @ wq["W1"].T.astype(np.float64) + wq["b1"], 0)
+        h2 = np.maximum(h1 @ wq["W2"].T.astype(np.float64) + wq["b2"], 0)
+        zz = h2 @ wq["w3"].astype(np.float64) + wq["b3"][0]
+        return np.mean(np.maximum(zz, 0) - zz * y + np.log1p(np.exp(-np.abs(zz))))
+    for idx in [router.OFF["W1"][0] + 3, router.OFF["b1"][0] + 5, router.OFF["W2"][0] + 100,
+                router.OFF["b2"][0] + 7, router.OFF["w3"][0] + 9, router.OFF["b3"][0]]:
+        e = np.zeros(router.N_PARAMS)
+        e[idx] = 1e-3
+        num = (loss(p + e) - loss(p - e)) / 2e-3
+        assert abs(num - g[idx]) < 0.03 * max(1e-3, abs(num)) + 2e-3, (idx, num, g[idx])
+
+
+def test_router_split_invariants():
+    from oracle import router
+    rng = np.random.default_rng(2)
+    pos = (rng.random((20_000, 3)) ** 3 * 10.0).astype(np.float32)     # crowded near the origin
+    admitted = np.array([0, 1, 101, 4444], dtype=np.uint64)            # coarse keys of the 25^3 mesh
+    tk, tc, rest = router.route(pos, 0.1, 10.0, 4, admitted)
+    assert tc.sum() + len(rest) == len(pos)
+    G, Gc = 100, 25
+    for kk in tk:
+        ix, iy, iz = kk // (G * G), (kk // G) % G, kk % G
+        assert ((ix // 4) * Gc + iy // 4) * Gc + iz // 4 in set(admitted.tolist())
+    rk = oracle.keys(rest, 0.1, 10.0)
+    ck = ((rk // np.uint64(G * G) // np.uint64(4)) * np.uint64(Gc) + (rk // np.uint64(G)) % np.uint64(G) // np.uint64(4)) \
+        * np.uint64(Gc) + rk % np.uint64(G) // np.uint64(4)
+    assert not np.isin(ck, admitted).any()

@@ -30,6 +30,8 @@ def _load():
     P, u64, u32, f64, i64 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_double, C.c_int64
     lib.wl_philox4x32_10.restype = None
     lib.wl_philox4x32_10.argtypes = [P, P, P]
+    lib.wl_philox_words.restype = None
+    lib.wl_philox_words.argtypes = [u64, u64, u32, u64, P]
     lib.wl_halo_catalogue.restype = None
     lib.wl_halo_catalogue.argtypes = [u64, u32, f64, f64, f64, f64, P, P]
     lib.wl_gen_exact.restype = i64
@@ -51,6 +53,13 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     out = np.empty(4, dtype=np.uint32)
     _load().wl_philox4x32_10(_p(c), _p(k), _p(out))
     return out
+
+
+def philox_words(index0: int, n: int, stream: int, seed: int) -> np.ndarray:
+    """First Philox4x32-10 word at counter (index, stream, 0) for indices index0 .. index0 + n - 1."""
+    out = np.empty(max(n, 1), dtype=np.uint32)
+    _load().wl_philox_words(index0, n, stream, seed, _p(out))
+    return out[:n]
 
 
 @dataclass(frozen=True)
