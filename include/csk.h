@@ -253,6 +253,15 @@ csk_status csk_mlp_forward(csk_mlp *m, const float *x, uint64_t n, float *logits
 csk_status csk_mlp_train_step(csk_mlp *m, const float *x, const float *y, uint32_t n, float lr, float *loss,
                               void *stream);
 
+/* The router's matrix product: C(i, j) = beta C(i, j) + sum_k A(i, k) B(k, j) for i < M,
+ * j < N, with A(i, k) = A[i sai + k sak], B(k, j) = B[k sbk + j sbj], C(i, j) =
+ * C[i sci + j scj] (device float32, any strides, so transposed operands need no copy).
+ * Operands are rounded to bf16 (nearest even) and the products summed in float32 on the
+ * matrix cores; beta = 0 ignores C's old contents.  M, N <= 2^20; K >= 0. */
+csk_status csk_gemm_bf16(uint32_t M, uint32_t N, uint32_t K, const float *A, uint64_t sai, uint64_t sak,
+                         const float *B, uint64_t sbk, uint64_t sbj, float *C, uint64_t sci, uint64_t scj,
+                         float beta, void *stream);
+
 /* Route a stream: an in-domain particle whose coarse parent (cell index / factor on each
  * axis) is in `admitted` (device, na <= 512 coarse keys of the mesh G / factor, sorted
  * ascending) adds 1 to its cell key's count in the exact table (device, table_slots a power

@@ -38,7 +38,7 @@ EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "cs
            "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
            "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_update", "csk_batch_destroy",
            "csk_sample_counts", "csk_cell_features", "csk_mlp_create", "csk_mlp_destroy", "csk_mlp_params",
-           "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_route_split", "csk_topk_with_table",
+           "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_gemm_bf16", "csk_route_split", "csk_topk_with_table",
            "csk_get_counters", "csk_set_counters", "csk_reset", "csk_check", "csk_device_bytes",
            "csk_last_error"]
 
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "csk_mlp_grads": [P, P],
         "csk_mlp_forward": [P, P, u64, P, P],
         "csk_mlp_train_step": [P, P, P, u32, C.c_float, P, P],
+        "csk_gemm_bf16": [u32, u32, u32, P, u64, u64, P, u64, u64, P, u64, u64, C.c_float, P],
         "csk_route_split": [P, u64, f64, f64, u32, P, u32, P, P, u32, P, P, P, P],
         "csk_topk_with_table": [P, P, P, u32, u32, P, P, C.POINTER(C.c_uint32), P],
         "csk_get_counters": [P, P, P],
@@ -450,6 +451,23 @@ class MLP:
         if self.h is not None:
             _check(load_library().csk_mlp_destroy(self.h))
             self.h = None
+
+
+def gemm_bf16(M, N, K, A, sa, B, sb, C_out, sc, beta=0.0, stream=None):
+    """C = beta C + A B over strided device float32 views (strides in elements: sa = (row,
+    k), sb = (k, col), sc = (row, col)) with bf16 operands and float32 sums."""
+    def span(t, r, c, st):   # every element the kernel reads or writes lies inside t
+        _dev(t, torch.float32)
+        if r and c and (r - 1) * st[0] + (c - 1) * st[1] >= t.numel():
+            raise ValueError("gemm_bf16: strides reach outside the tensor")
+    import torch
+    span(C_out, M, N, sc)
+    if K:
+        span(A, M, K, sa)
+        span(B, K, N, sb)
+    _check(load_library().csk_gemm_bf16(M, N, K, A.data_ptr() if K else None, sa[0], sa[1],
+                                        B.data_ptr() if K else None, sb[0], sb[1], C_out.data_ptr(), sc[0], sc[1],
+                                        beta, _stream(stream)))
 
 
 def route_split(pos, delta, L, factor, admitted, table_keys, table_counts, rest_pos, rest_count, err, stream=None):

@@ -907,6 +907,16 @@ csk_status csk_mlp_train_step(csk_mlp* m, const float* x, const float* y, uint32
   return CSK_OK;
 }
 
+csk_status csk_gemm_bf16(uint32_t M, uint32_t N, uint32_t K, const float* A, uint64_t sai, uint64_t sak,
+                         const float* B, uint64_t sbk, uint64_t sbj, float* C, uint64_t sci, uint64_t scj,
+                         float beta, void* stream) {
+  if (M > (1u << 20) || N > (1u << 20)) return fail(CSK_E_INVALID, "gemm_bf16: M=%u or N=%u above 2^20", M, N);
+  if (M == 0 || N == 0) return CSK_OK;
+  if (C == nullptr || (K > 0 && (A == nullptr || B == nullptr))) return fail(CSK_E_INVALID, "gemm_bf16: NULL pointer");
+  CSK_HIP(launch_gemm_bf16(M, N, K, A, sai, sak, B, sbk, sbj, C, sci, scj, beta, (hipStream_t)stream), "gemm_bf16");
+  return CSK_OK;
+}
+
 csk_status csk_sample_counts(const float* pos, uint64_t n, uint64_t index0, double delta_c, double L, uint64_t seed,
                              uint32_t threshold, uint32_t* counts, void* stream) {
   Mesh coarse;

@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "csk.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(csk_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(csk_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
@@ -46,6 +46,23 @@ def test_argument_errors_are_returned_without_a_device():
     assert lib.csk_batch_update(None, None, None, None) == csk.CSK_E_INVALID
     assert lib.csk_topk_async(None, 1, None, None, None, None) == csk.CSK_E_INVALID
     assert lib.csk_sketch_init_group(C.byref(h), 5, 16, 1, 0, 0, 0) == csk.CSK_E_INVALID
+    # learned router
+    assert lib.csk_mlp_create(C.byref(h), 1, 0) == csk.CSK_E_INVALID
+    assert lib.csk_mlp_create(None, 1, 16) == csk.CSK_E_INVALID
+    assert lib.csk_mlp_train_step(None, None, None, 1, 1e-3, None, None) == csk.CSK_E_INVALID
+    assert lib.csk_gemm_bf16((1 << 20) + 1, 16, 16, None, 0, 0, None, 0, 0, None, 0, 0, 0.0, None) == csk.CSK_E_INVALID
+    assert lib.csk_gemm_bf16(16, 16, 16, None, 0, 0, None, 0, 0, None, 0, 0, 0.0, None) == csk.CSK_E_INVALID
+    assert lib.csk_gemm_bf16(0, 16, 16, None, 0, 0, None, 0, 0, None, 0, 0, 0.0, None) == csk.CSK_OK
+    assert lib.csk_sample_counts(None, 0, 0, 0.3, 100.0, 1, 0, None, None) == csk.CSK_E_INVALID
+    assert lib.csk_cell_features(None, 1.0, 100.0, None, 5, None, None) == csk.CSK_E_INVALID
+    route = lambda factor, na, slots: lib.csk_route_split(None, 0, 0.25, 50.0, factor, None, na, None, None, slots,
+                                                          None, None, None, None)
+    assert route(3, 0, 1024) == csk.CSK_E_INVALID          # 3 does not divide G = 200
+    assert route(4, 513, 1 << 20) == csk.CSK_E_INVALID     # more than 512 admitted cells
+    assert route(4, 1, 1000) == csk.CSK_E_INVALID          # slots not a power of two
+    assert route(4, 8, 512) == csk.CSK_E_INVALID           # 8 * 4^3 children above half of 512 slots
+    assert route(4, 4, 512) == csk.CSK_OK
+    assert lib.csk_topk_with_table(None, None, None, 16, 1, None, None, None, None) == csk.CSK_E_INVALID
     # invalid meshes
     for delta, L in [(0.0, 100.0), (0.3, 100.0), (1e-4, 100.0), (float("nan"), 1.0), (1.0, float("inf"))]:
         assert lib.csk_cell_keys(None, 0, delta, L, None, None) == csk.CSK_E_INVALID
