@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the particle count (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-router", action="store_true",
+                    help="skip the learned router vs plain sketch comparison at equal memory")
+    ap.add_argument("--router-n", type=int, default=1 << 28, help="particles per router snapshot")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched update of 64 uneven sub-volumes")
     ap.add_argument("--no-hierarchy", action="store_true",
@@ -290,6 +293,172 @@ def batched_subvolumes(csk, torch, reps=5):
             "note": "sum over sub-volumes; update counters identical to one-by-one updates"}
 
 
+def learned_router(csk, torch, workloads, n=1 << 28, k=10_000, w_plain=1 << 22, train_seeds=range(2, 10),
+                   eval_seed=1, exact_slots=1 << 29, epochs=4, sweep_widths=(1 << 20, 1 << 18)):
+    """Learned router vs the plain sketch at equal memory on the plain-at-scale recipe cut to
+    n particles.  The model trains on the exact top-k labels of other-seed snapshots; the
+    evaluation snapshot is routed (sample pre-pass -> features -> MLP -> admission ->
+    split -> rest sketch -> merged top-k) and compared with a plain d x w_plain sketch
+    on recall of the exact top-k."""
+    from paper_1711_00975_amd.router import Router, rest_width, TABLE_BYTES_PER_SLOT
+    base = workloads.SCALE.with_(n=n, w=w_plain, k=k, name=f"plummer-2^{n.bit_length() - 1}-L1000-d0.25")
+    r = Router(base.delta, base.L)
+    snaps = []
+    for sd in train_seeds:
+        pos = make_positions(base.with_(seed=sd), n, torch)
+        info = r.add_snapshot(pos, k, exact_slots)
+        del pos
+        snaps.append(info)
+        log(f"  training snapshot seed {sd}: {info}")
+    t0 = time.perf_counter()
+    tr = r.train(epochs=epochs)
+    torch.cuda.synchronize()
+    tr["seconds"] = time.perf_counter() - t0
+    log(f"  trained: {tr}")
+
+    wl = base.with_(seed=eval_seed)
+    pos = make_positions(wl, n, torch)
+    tk, tc = csk.new_table(exact_slots)
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    csk.exact_counts(pos, wl.delta, wl.L, tk, tc, err)
+    ex_keys, ex_counts = csk.table_topk(tk, tc, 2 * k)
+    assert err.item() == 0
+    del tk, tc
+    kth = int(ex_counts[k - 1].item())
+    exact_top = ex_keys[:k]
+    at_least_kth = ex_keys[ex_counts >= kth]
+
+    def score(keys):
+        keys = keys[:k]
+        return {"strict": torch.isin(keys, exact_top).sum().item() / k,
+                "tie_tolerant": torch.isin(keys, at_least_kth).sum().item() / k, "returned": int(keys.numel())}
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best, res = None, None
+        for _ in range(reps):
+            t = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) * 1e3
+            best = dt if best is None else min(best, dt)
+        return best, res
+
+    def search_theta(run):
+        # the top-k is final once k candidates were found and the k-th value is at least
+        # theta (no key left out of the candidate set can beat it); the exact table's keys
+        # are candidates whatever their counts, so the second condition matters there
+        theta = 1 << 22
+        while True:
+            keys, est, rc = run(theta)
+            if rc == csk.CSK_OK and keys.numel() == k and int(est[k - 1].item()) >= theta:
+                return theta
+            if theta <= 1:
+                return csk.INT32_MIN
+            theta //= 2
+
+    # plain sketch: update + collect + top-k
+    plain = csk.Sketch(wl.d, w_plain, wl.seed, max_candidates=1 << 22)
+
+    def plain_run(theta):
+        plain.reset()
+        plain.update(pos, wl.delta, wl.L)
+        plain.collect(pos, wl.delta, wl.L, theta)
+        return plain.topk(k)
+    theta_p = search_theta(plain_run)
+    plain_ms, (plain_keys, _, _) = timed(lambda: plain_run(theta_p))
+    log(f"  plain: theta {theta_p}, {plain_ms:.2f} ms")
+
+    # routed: admission, split, rest sketch, merged top-k
+    w_rest = rest_width(w_plain, wl.d, r.table_slots)
+    rs = csk.Sketch(wl.d, w_rest, wl.seed, max_candidates=1 << 22)
+    ttk, ttc = csk.new_table(r.table_slots)
+    rest = torch.empty_like(pos)
+    rcount = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rerr = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stage = {}
+
+    def routed_run(theta, times=None):
+        marks = [time.perf_counter()]
+
+        def mark():
+            if times is not None:
+                torch.cuda.synchronize()
+                marks.append(time.perf_counter())
+        admitted = r.admit(pos)
+        mark()
+        ttk.fill_(-1)
+        ttc.zero_()
+        rcount.zero_()
+        r.split(pos, admitted, ttk, ttc, rest, rcount, rerr)
+        nrest = int(rcount.item())
+        mark()
+        rs.reset()
+        rs.update(rest[:nrest], wl.delta, wl.L)
+        mark()
+        rs.collect(rest[:nrest], wl.delta, wl.L, theta)
+        keys, est, rc = csk.topk_with_table(rs, ttk, ttc, k)
+        mark()
+        if times is not None:
+            names = ["admit_ms", "split_ms", "rest_update_ms", "collect_topk_ms"]
+            for nm, a, b in zip(names, marks[:-1], marks[1:]):
+                times[nm] = min(times.get(nm, 1e30), (b - a) * 1e3)
+            times["admitted_cells"] = int(admitted.numel())
+            times["table_particles"] = n - nrest
+        return keys, est, rc
+    theta_r = search_theta(routed_run)
+    routed_ms, (routed_keys, _, _) = timed(lambda: routed_run(theta_r))
+    for _ in range(2):
+        routed_run(theta_r, stage)
+    assert rerr.item() == 0
+    log(f"  routed: theta {theta_r}, {routed_ms:.2f} ms, {stage}")
+    # the same trained router at smaller memory: the split is done once, then each width
+    # gets its own plain and rest sketch and threshold search (recall only, untimed)
+    sweep = []
+    for wp in sweep_widths:
+        ps = csk.Sketch(wl.d, wp, wl.seed, max_candidates=1 << 22)
+
+        def small_plain(theta):
+            ps.reset()
+            ps.update(pos, wl.delta, wl.L)
+            ps.collect(pos, wl.delta, wl.L, theta)
+            return ps.topk(k)
+        tp = search_theta(small_plain)
+        pk = small_plain(tp)[0]
+        wr = rest_width(wp, wl.d, r.table_slots)
+        rs2 = csk.Sketch(wl.d, wr, wl.seed, max_candidates=1 << 22)
+        nrest = n - stage["table_particles"]
+
+        def small_routed(theta):
+            rs2.reset()
+            rs2.update(rest[:nrest], wl.delta, wl.L)
+            rs2.collect(rest[:nrest], wl.delta, wl.L, theta)
+            return csk.topk_with_table(rs2, ttk, ttc, k)
+        tr2 = search_theta(small_routed)
+        rk = small_routed(tr2)[0]
+        sweep.append({"w_plain": wp, "w_rest": wr, "plain_theta": tp, "routed_theta": tr2,
+                      "plain_recall": score(pk), "routed_recall": score(rk)})
+        log(f"  width {wp}: plain {sweep[-1]['plain_recall']}, routed {sweep[-1]['routed_recall']}")
+        ps.close()
+        rs2.close()
+    out = {"workload": wl.name, "particles": n, "k": k, "exact_kth_count": kth,
+           "train": {"seeds": list(train_seeds), "snapshots": snaps, **tr},
+           "plain": {"d": wl.d, "w": w_plain, "bytes": wl.d * w_plain * 4, "theta": theta_p, "ms": plain_ms,
+                     "particles_per_s": n / (plain_ms / 1e3), "recall": score(plain_keys)},
+           "routed": {"d": wl.d, "w_rest": w_rest, "table_slots": r.table_slots,
+                      "bytes": wl.d * w_rest * 4 + r.table_slots * TABLE_BYTES_PER_SLOT, "max_admitted": r.max_admit,
+                      "theta": theta_r, "ms": routed_ms, "particles_per_s": n / (routed_ms / 1e3),
+                      "stages": stage, "recall": score(routed_keys)},
+           "smaller_memory": sweep,
+           "note": "times include the host synchronizations of the admission calls; recall against the exact "
+                   "top-k from csk_exact_counts + csk_table_topk"}
+    plain.close()
+    rs.close()
+    r.close()
+    return out
+
+
 def host_threads():
     """Host threads this process may use, capped at the 16 that one GPU's share allows."""
     try:
@@ -427,6 +596,9 @@ def main():
             out["recall"] = recall(pos, wl, keys_top, est_top, csk, torch)
         except RuntimeError as e:   # e.g. not enough device memory for the exact histogram
             out["recall"] = {"error": str(e)[:200]}
+    if not args.no_router:
+        log("learned router vs plain sketch at equal memory ...")
+        out["learned_router"] = learned_router(csk, torch, workloads, n=args.router_n)
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, n)
         log("cpu baseline (oracle, one thread) ...")

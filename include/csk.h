@@ -266,12 +266,51 @@ csk_status csk_gemm_bf16(uint32_t M, uint32_t N, uint32_t K, const float *A, uin
  * axis) is in `admitted` (device, na <= 512 coarse keys of the mesh G / factor, sorted
  * ascending) adds 1 to its cell key's count in the exact table (device, table_slots a power
  * of two, keys all-ones when empty, linear probing from a fixed hash); every other
- * in-domain particle is appended to rest_pos (device, room for n), *rest_count (device)
- * counting them.  na * factor^3 <= table_slots / 2, so the table never fills.  Out-of-domain
- * particles set bit 0 of *err (device). */
+ * in-domain particle is appended, in stream order, to rest_pos (device) after the
+ * *rest_count (device) particles already there, and *rest_count grows by their number
+ * (rest_pos needs room for *rest_count + n).  na * factor^3 <= min(2^15, table_slots / 2),
+ * so the table never fills.  Out-of-domain particles set bit 0 of *err (device).
+ * workspace: device scratch of csk_route_split_workspace bytes, not shared between calls
+ * in flight. */
+csk_status csk_route_split_workspace(uint32_t na, uint32_t factor, uint64_t *bytes);
 csk_status csk_route_split(const float *pos, uint64_t n, double delta, double L, uint32_t factor,
                            const uint64_t *admitted, uint32_t na, uint64_t *table_keys, uint32_t *table_counts,
-                           uint32_t table_slots, float *rest_pos, uint64_t *rest_count, uint32_t *err, void *stream);
+                           uint32_t table_slots, float *rest_pos, uint64_t *rest_count, uint32_t *err,
+                           void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Exact cell counts: every in-domain particle adds 1 to its cell key's count in the table
+ * (device; table_slots a power of two <= 2^31; keys all-ones and counts 0 when empty, as
+ * for csk_route_split).  This is the exact histogram that the sketch approximates (the
+ * router's training labels and the recall reference); n < 2^31 keeps every count below
+ * 2^31.  Out-of-domain particles set bit 0 of *err (device), a key finding no free slot
+ * sets bit 1 (size the table at twice the distinct cells or more). */
+csk_status csk_exact_counts(const float *pos, uint64_t n, double delta, double L, uint64_t *table_keys,
+                            uint32_t *table_counts, uint32_t table_slots, uint32_t *err, void *stream);
+
+/* The k heaviest keys of an exact table (as filled by csk_exact_counts or csk_route_split),
+ * ordered by (count desc, key asc), into keys / counts (device); *k_out (host) = how many,
+ * min(k, keys in the table).  k <= 2^22.  Allocates scratch and synchronizes. */
+csk_status csk_table_topk(const uint64_t *table_keys, const uint32_t *table_counts, uint32_t table_slots, uint32_t k,
+                          uint64_t *keys, uint32_t *counts, uint32_t *k_out, void *stream);
+
+/* The cells j < ncells with counts[j] >= min_count (device), in ascending order, into
+ * cells (device, the first cap of them); *total (host) = how many there are.  Lists the
+ * coarse cells the router scores.  Allocates scratch and synchronizes. */
+csk_status csk_cell_list(const uint32_t *counts, uint64_t ncells, uint32_t min_count, uint64_t *cells, uint64_t cap,
+                         uint64_t *total, void *stream);
+
+/* Router training labels: labels[j] (device float) = 1 if coarse cell cells[j] (mesh
+ * G / factor) is the coarse parent of one of the nk <= 2^17 fine keys (device, mesh of
+ * delta, L), else 0.  Allocates scratch and synchronizes. */
+csk_status csk_cell_labels(const uint64_t *cells, uint64_t m, const uint64_t *fine_keys, uint32_t nk, double delta,
+                           double L, uint32_t factor, float *labels, void *stream);
+
+/* Admission: of the m < 2^31 distinct cells (device keys below 2^48) with their logits
+ * (device float, finite), the min(A, m) highest by (logit desc, key asc) into admitted
+ * (device), in ascending key order as csk_route_split takes them; *na (host) = how many.
+ * A <= 2^16.  Allocates scratch and synchronizes. */
+csk_status csk_route_admit(const uint64_t *cells, const float *logits, uint64_t m, uint32_t A, uint64_t *admitted,
+                           uint32_t *na, void *stream);
 
 /* As csk_topk for a sketch of the routed rest: every key of the exact table joins the
  * candidates, and a candidate found in the table takes its exact count as its estimate.

@@ -148,3 +148,39 @@ def topk_routed(table_keys, table_counts, M_rest, T_rest, rest_pos, delta, L, th
         items += [(-int(v), int(kk)) for kk, v in zip(rk, e) if v >= theta]
     items.sort()
     return [kk for _, kk in items[:k]], [-v for v, _ in items[:k]]
+
+
+# ---------------------------------------------------------------- training labels and admission
+
+def cell_list(counts, min_count=1):
+    """Cells (int64, ascending) whose count is at least min_count."""
+    return np.flatnonzero(np.asarray(counts) >= min_count).astype(np.int64)
+
+
+def parents(fine_keys, G, factor):
+    """Coarse parent keys (mesh G / factor) of fine keys of the mesh G."""
+    k = np.asarray(fine_keys, dtype=np.uint64)
+    G64, f, Gc = np.uint64(G), np.uint64(factor), np.uint64(G // factor)
+    ix, iy, iz = k // (G64 * G64), (k // G64) % G64, k % G64
+    return (((ix // f) * Gc + iy // f) * Gc + iz // f).astype(np.int64)
+
+
+def labels(cells, fine_keys, G, factor):
+    """float32 1 where the coarse cell is the parent of one of the fine keys, else 0."""
+    return np.isin(np.asarray(cells, dtype=np.int64), parents(fine_keys, G, factor)).astype(np.float32)
+
+
+def admit(cells, logits, A):
+    """The min(A, m) cells of highest logit, ties by smaller key, returned in ascending
+    key order (the routing split takes a sorted list)."""
+    c = np.asarray(cells, dtype=np.int64)
+    z = np.asarray(logits, dtype=np.float64)          # -0.0 and +0.0 compare equal
+    order = np.lexsort((c, -z))
+    return np.sort(c[order[:A]])
+
+
+def exact_topk(pos, delta, L, k):
+    """(keys, counts) of the k heaviest cells of the stream by (count desc, key asc)."""
+    from . import histogram, topk_exact
+    uniq, cnt = histogram(keys(pos, delta, L))
+    return topk_exact(uniq, cnt, k)

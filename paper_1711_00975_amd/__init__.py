@@ -38,7 +38,8 @@ EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "cs
            "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
            "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_update", "csk_batch_destroy",
            "csk_sample_counts", "csk_cell_features", "csk_mlp_create", "csk_mlp_destroy", "csk_mlp_params",
-           "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_gemm_bf16", "csk_route_split", "csk_topk_with_table",
+           "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_gemm_bf16", "csk_route_split", "csk_route_split_workspace", "csk_topk_with_table",
+           "csk_exact_counts", "csk_table_topk", "csk_cell_list", "csk_cell_labels", "csk_route_admit",
            "csk_get_counters", "csk_set_counters", "csk_reset", "csk_check", "csk_device_bytes",
            "csk_last_error"]
 
@@ -90,8 +91,14 @@ def load_library(path: str = LIB_PATH):
         "csk_mlp_forward": [P, P, u64, P, P],
         "csk_mlp_train_step": [P, P, P, u32, C.c_float, P, P],
         "csk_gemm_bf16": [u32, u32, u32, P, u64, u64, P, u64, u64, P, u64, u64, C.c_float, P],
-        "csk_route_split": [P, u64, f64, f64, u32, P, u32, P, P, u32, P, P, P, P],
+        "csk_route_split": [P, u64, f64, f64, u32, P, u32, P, P, u32, P, P, P, P, u64, P],
+        "csk_route_split_workspace": [u32, u32, C.POINTER(C.c_uint64)],
         "csk_topk_with_table": [P, P, P, u32, u32, P, P, C.POINTER(C.c_uint32), P],
+        "csk_exact_counts": [P, u64, f64, f64, P, P, u32, P, P],
+        "csk_table_topk": [P, P, u32, u32, P, P, C.POINTER(C.c_uint32), P],
+        "csk_cell_list": [P, u64, u32, P, u64, C.POINTER(C.c_uint64), P],
+        "csk_cell_labels": [P, u64, P, u32, f64, f64, u32, P, P],
+        "csk_route_admit": [P, P, u64, u32, P, C.POINTER(C.c_uint32), P],
         "csk_get_counters": [P, P, P],
         "csk_set_counters": [P, P, P],
         "csk_reset": [P, P],
@@ -470,17 +477,32 @@ def gemm_bf16(M, N, K, A, sa, B, sb, C_out, sc, beta=0.0, stream=None):
                                         beta, _stream(stream)))
 
 
-def route_split(pos, delta, L, factor, admitted, table_keys, table_counts, rest_pos, rest_count, err, stream=None):
+_split_ws = {}
+
+
+def route_split(pos, delta, L, factor, admitted, table_keys, table_counts, rest_pos, rest_count, err, stream=None,
+                workspace=None):
     """admitted: sorted device int64 coarse keys; table_keys (int64, all ones when empty) and
-    table_counts (int32) of a power-of-two size; rest_pos float32 [n][3]; rest_count int64 [1];
-    err int32 [1]."""
+    table_counts (int32) of a power-of-two size; rest_pos float32 [>= rest_count + n][3];
+    rest_count int64 [1] (the rest is appended after it); err int32 [1].  workspace: a
+    device uint8 tensor of csk_route_split_workspace bytes (one kept per device and size
+    class when omitted)."""
     import torch
-    _check(load_library().csk_route_split(_dev(pos, torch.float32, 3) if pos.shape[0] else None, pos.shape[0], delta, L,
-                                          factor, _dev(admitted, torch.int64) if admitted.shape[0] else None,
-                                          admitted.shape[0], _dev(table_keys, torch.int64),
-                                          _dev(table_counts, torch.int32), table_keys.shape[0],
-                                          _dev(rest_pos, torch.float32, 3), _dev(rest_count, torch.int64),
-                                          _dev(err, torch.int32), _stream(stream)))
+    lib = load_library()
+    na = admitted.shape[0]
+    need = C.c_uint64(0)
+    _check(lib.csk_route_split_workspace(na, factor, C.byref(need)))
+    if workspace is None:
+        key = (pos.device.index, factor, max(na, 1).bit_length())
+        workspace = _split_ws.get(key)
+        if workspace is None or workspace.numel() < need.value:
+            workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=pos.device)
+            _split_ws[key] = workspace
+    _check(lib.csk_route_split(_dev(pos, torch.float32, 3) if pos.shape[0] else None, pos.shape[0], delta, L,
+                               factor, _dev(admitted, torch.int64) if na else None, na,
+                               _dev(table_keys, torch.int64), _dev(table_counts, torch.int32), table_keys.shape[0],
+                               _dev(rest_pos, torch.float32, 3), _dev(rest_count, torch.int64),
+                               _dev(err, torch.int32), workspace.data_ptr(), workspace.numel(), _stream(stream)))
 
 
 def topk_with_table(sketch, table_keys, table_counts, k, stream=None):
@@ -494,3 +516,69 @@ def topk_with_table(sketch, table_keys, table_counts, k, stream=None):
                                                    _dev(keys, torch.int64), _dev(est, torch.int32), C.byref(kout),
                                                    _stream(stream)), allow_warning=True)
     return keys[:kout.value], est[:kout.value], rc
+
+
+def exact_counts(pos, delta, L, table_keys, table_counts, err, stream=None):
+    """Add every particle of pos to the exact table (table_keys int64 all ones when empty,
+    table_counts int32, same power-of-two size; err int32 [1])."""
+    import torch
+    _check(load_library().csk_exact_counts(_dev(pos, torch.float32, 3) if pos.shape[0] else None, pos.shape[0], delta,
+                                           L, _dev(table_keys, torch.int64), _dev(table_counts, torch.int32),
+                                           table_keys.shape[0], _dev(err, torch.int32), _stream(stream)))
+
+
+def new_table(slots, device="cuda"):
+    """An empty exact table (keys, counts) of `slots` entries."""
+    import torch
+    return (torch.full((slots,), -1, dtype=torch.int64, device=device),
+            torch.zeros(slots, dtype=torch.int32, device=device))
+
+
+def table_topk(table_keys, table_counts, k, stream=None):
+    """(keys, counts) of the k heaviest table entries, by (count desc, key asc)."""
+    import torch
+    keys = torch.empty(max(k, 1), dtype=torch.int64, device=table_keys.device)
+    counts = torch.empty(max(k, 1), dtype=torch.int32, device=table_keys.device)
+    kout = C.c_uint32(0)
+    _check(load_library().csk_table_topk(_dev(table_keys, torch.int64), _dev(table_counts, torch.int32),
+                                         table_keys.shape[0], k, _dev(keys, torch.int64), _dev(counts, torch.int32),
+                                         C.byref(kout), _stream(stream)))
+    return keys[:kout.value], counts[:kout.value]
+
+
+def cell_list(counts, min_count=1, cap=None, stream=None):
+    """Ascending device int64 list of the cells with counts >= min_count."""
+    import torch
+    total = C.c_uint64(0)
+    lib = load_library()
+    if cap is None:
+        _check(lib.csk_cell_list(_dev(counts, torch.int32), counts.numel(), min_count, None, 0, C.byref(total),
+                                 _stream(stream)))
+        cap = total.value
+    cells = torch.empty(max(cap, 1), dtype=torch.int64, device=counts.device)
+    _check(lib.csk_cell_list(_dev(counts, torch.int32), counts.numel(), min_count, _dev(cells, torch.int64), cap,
+                             C.byref(total), _stream(stream)))
+    return cells[:min(cap, total.value)]
+
+
+def cell_labels(cells, fine_keys, delta, L, factor, stream=None):
+    import torch
+    labels = torch.empty(cells.shape[0], dtype=torch.float32, device=cells.device)
+    if cells.shape[0]:
+        _check(load_library().csk_cell_labels(_dev(cells, torch.int64), cells.shape[0],
+                                              _dev(fine_keys, torch.int64) if fine_keys.shape[0] else None,
+                                              fine_keys.shape[0], delta, L, factor, _dev(labels, torch.float32),
+                                              _stream(stream)))
+    return labels
+
+
+def route_admit(cells, logits, A, stream=None):
+    """Ascending device int64 keys of the min(A, m) cells with the highest logits."""
+    import torch
+    out = torch.empty(max(A, 1), dtype=torch.int64, device=cells.device)
+    na = C.c_uint32(0)
+    m = cells.shape[0]
+    _check(load_library().csk_route_admit(_dev(cells, torch.int64) if m else None,
+                                          _dev(logits, torch.float32) if m else None, m, A,
+                                          _dev(out, torch.int64), C.byref(na), _stream(stream)))
+    return out[:na.value]

@@ -940,27 +940,191 @@ csk_status csk_cell_features(const uint32_t* counts, double delta_c, double L, c
   return CSK_OK;
 }
 
+csk_status csk_route_split_workspace(uint32_t na, uint32_t factor, uint64_t* bytes) {
+  if (bytes == nullptr) return fail(CSK_E_INVALID, "route_split_workspace: bytes is NULL");
+  if (factor < 1 || factor > 32 || na > kMaxAdmitted || (uint64_t)na * factor * factor * factor > kSplitMaxChildren)
+    return fail(CSK_E_INVALID, "route_split_workspace: na=%u, factor=%u outside the limits", na, factor);
+  *bytes = split_workspace_bytes(na, factor);
+  return CSK_OK;
+}
+
 csk_status csk_route_split(const float* pos, uint64_t n, double delta, double L, uint32_t factor,
                            const uint64_t* admitted, uint32_t na, uint64_t* table_keys, uint32_t* table_counts,
-                           uint32_t table_slots, float* rest_pos, uint64_t* rest_count, uint32_t* err, void* stream) {
+                           uint32_t table_slots, float* rest_pos, uint64_t* rest_count, uint32_t* err,
+                           void* workspace, uint64_t workspace_bytes, void* stream) {
+  Mesh mesh;
+  csk_status rc = check_mesh(nullptr, delta, L, &mesh);
+  if (rc != CSK_OK) return rc;
+  if (factor < 1 || factor > 32 || (uint32_t)mesh.G % factor != 0)
+    return fail(CSK_E_INVALID, "route_split: factor %u does not divide G=%d", factor, mesh.G);
+  if (na > kMaxAdmitted) return fail(CSK_E_INVALID, "route_split: %u admitted cells above %u", na, kMaxAdmitted);
+  const uint64_t children = (uint64_t)na * factor * factor * factor;
+  if (children > kSplitMaxChildren)
+    return fail(CSK_E_INVALID, "route_split: %u cells of %u^3 children exceed %u", na, factor, kSplitMaxChildren);
+  if (table_slots < 2 || (table_slots & (table_slots - 1)) != 0)
+    return fail(CSK_E_INVALID, "route_split: table_slots=%u is not a power of two", table_slots);
+  if (children > table_slots / 2)
+    return fail(CSK_E_INVALID, "route_split: %u cells of %u^3 children exceed half of %u slots", na, factor,
+                table_slots);
+  if (n > 0 && workspace_bytes < split_workspace_bytes(na, factor))
+    return fail(CSK_E_INVALID, "route_split: workspace of %llu bytes below the %llu needed",
+                (unsigned long long)workspace_bytes, (unsigned long long)split_workspace_bytes(na, factor));
+  if (n > 0 && (pos == nullptr || rest_pos == nullptr || rest_count == nullptr || err == nullptr ||
+                table_keys == nullptr || table_counts == nullptr || workspace == nullptr ||
+                (na > 0 && admitted == nullptr)))
+    return fail(CSK_E_INVALID, "route_split: NULL pointer");
+  if (n == 0) return CSK_OK;
+  CSK_HIP(launch_route_split(pos, n, mesh, factor, admitted, na, table_keys, table_counts, table_slots - 1, rest_pos,
+                             (unsigned long long*)rest_count, err, workspace, (hipStream_t)stream),
+          "route_split");
+  return CSK_OK;
+}
+
+namespace {
+
+// Device scratch of one call, freed (after the device is idle) when the call returns.
+struct CallScratch {
+  std::vector<void*> ptrs;
+  ~CallScratch() {
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  template <typename T>
+  hipError_t get(T** p, uint64_t count) {
+    hipError_t e = bmalloc(p, count);
+    if (e == hipSuccess) ptrs.push_back((void*)*p);
+    return e;
+  }
+};
+
+}  // namespace
+
+csk_status csk_exact_counts(const float* pos, uint64_t n, double delta, double L, uint64_t* table_keys,
+                            uint32_t* table_counts, uint32_t table_slots, uint32_t* err, void* stream) {
+  Mesh mesh;
+  csk_status rc = check_mesh(nullptr, delta, L, &mesh);
+  if (rc != CSK_OK) return rc;
+  if (table_slots < 2 || table_slots > (1u << 31) || (table_slots & (table_slots - 1)) != 0)
+    return fail(CSK_E_INVALID, "exact_counts: table_slots=%u is not a power of two in [2, 2^31]", table_slots);
+  if (n >= (1ull << 31)) return fail(CSK_E_INVALID, "exact_counts: n=%llu reaches 2^31", (unsigned long long)n);
+  if (n > 0 && (pos == nullptr || table_keys == nullptr || table_counts == nullptr || err == nullptr))
+    return fail(CSK_E_INVALID, "exact_counts: NULL pointer");
+  if (n == 0) return CSK_OK;
+  CSK_HIP(launch_exact_count(pos, n, mesh, table_keys, table_counts, table_slots - 1, err, (hipStream_t)stream),
+          "exact_counts");
+  return CSK_OK;
+}
+
+csk_status csk_table_topk(const uint64_t* table_keys, const uint32_t* table_counts, uint32_t table_slots, uint32_t k,
+                          uint64_t* keys, uint32_t* counts, uint32_t* k_out, void* stream) {
+  if (k_out == nullptr || table_keys == nullptr || table_counts == nullptr)
+    return fail(CSK_E_INVALID, "table_topk: NULL argument");
+  *k_out = 0;
+  if (table_slots < 2 || table_slots > (1u << 31) || (table_slots & (table_slots - 1)) != 0)
+    return fail(CSK_E_INVALID, "table_topk: table_slots=%u is not a power of two in [2, 2^31]", table_slots);
+  if (k > (1u << 22)) return fail(CSK_E_INVALID, "table_topk: k=%u above 2^22", k);
+  if (k == 0) return CSK_OK;
+  if (keys == nullptr || counts == nullptr) return fail(CSK_E_INVALID, "table_topk: NULL output");
+  hipStream_t st = (hipStream_t)stream;
+  CallScratch cs;
+  SelState* sel = nullptr;
+  uint64_t* sk = nullptr;
+  int32_t* se = nullptr;
+  uint32_t* rank = nullptr;
+  uint32_t* err = nullptr;
+  CSK_HIP(cs.get(&sel, 1), "table_topk: scratch");
+  CSK_HIP(cs.get(&sk, k), "table_topk: scratch");
+  CSK_HIP(cs.get(&se, k), "table_topk: scratch");
+  CSK_HIP(cs.get(&rank, k), "table_topk: scratch");
+  CSK_HIP(cs.get(&err, 1), "table_topk: scratch");
+  CSK_HIP(launch_fill_u32(err, 1, 0u, st), "table_topk");
+  // counts below 2^31 order as int32; empty slots (count 0, key all ones) are never gathered
+  CSK_HIP(launch_select_pairs(table_keys, (const int32_t*)table_counts, table_slots, k, sel, sk, se, rank, keys,
+                              (int32_t*)counts, err, st),
+          "table_topk");
+  SelState h;
+  CSK_HIP(hipMemcpyAsync(&h, sel, sizeof(SelState), hipMemcpyDeviceToHost, st), "table_topk");
+  CSK_HIP(hipStreamSynchronize(st), "table_topk");
+  *k_out = h.n_sel < k ? h.n_sel : k;
+  return CSK_OK;
+}
+
+csk_status csk_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t min_count, uint64_t* cells, uint64_t cap,
+                         uint64_t* total, void* stream) {
+  if (total == nullptr) return fail(CSK_E_INVALID, "cell_list: total is NULL");
+  *total = 0;
+  if (ncells > 0 && (counts == nullptr || (cap > 0 && cells == nullptr)))
+    return fail(CSK_E_INVALID, "cell_list: NULL pointer");
+  if (ncells == 0) return CSK_OK;
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t chunk = 0;
+  const uint32_t nb = cell_list_blocks(ncells, &chunk);
+  CallScratch cs;
+  uint64_t* blocks = nullptr;
+  unsigned long long* dtotal = nullptr;
+  CSK_HIP(cs.get(&blocks, nb), "cell_list: scratch");
+  CSK_HIP(cs.get(&dtotal, 1), "cell_list: scratch");
+  CSK_HIP(launch_cell_list(counts, ncells, min_count, blocks, cells, cap, dtotal, st), "cell_list");
+  unsigned long long h = 0;
+  CSK_HIP(hipMemcpyAsync(&h, dtotal, sizeof(h), hipMemcpyDeviceToHost, st), "cell_list");
+  CSK_HIP(hipStreamSynchronize(st), "cell_list");
+  *total = h;
+  return CSK_OK;
+}
+
+csk_status csk_cell_labels(const uint64_t* cells, uint64_t m, const uint64_t* fine_keys, uint32_t nk, double delta,
+                           double L, uint32_t factor, float* labels, void* stream) {
   Mesh mesh;
   csk_status rc = check_mesh(nullptr, delta, L, &mesh);
   if (rc != CSK_OK) return rc;
   if (factor < 1 || (uint32_t)mesh.G % factor != 0)
-    return fail(CSK_E_INVALID, "route_split: factor %u does not divide G=%d", factor, mesh.G);
-  if (na > kMaxAdmitted) return fail(CSK_E_INVALID, "route_split: %u admitted cells above %u", na, kMaxAdmitted);
-  if (table_slots < 2 || (table_slots & (table_slots - 1)) != 0)
-    return fail(CSK_E_INVALID, "route_split: table_slots=%u is not a power of two", table_slots);
-  if ((uint64_t)na * factor * factor * factor > table_slots / 2)
-    return fail(CSK_E_INVALID, "route_split: %u cells of %u^3 children exceed half of %u slots", na, factor,
-                table_slots);
-  if (n > 0 && (pos == nullptr || rest_pos == nullptr || rest_count == nullptr || err == nullptr ||
-                table_keys == nullptr || table_counts == nullptr || (na > 0 && admitted == nullptr)))
-    return fail(CSK_E_INVALID, "route_split: NULL pointer");
-  if (n == 0) return CSK_OK;
-  CSK_HIP(launch_route_split(pos, n, mesh, factor, admitted, na, table_keys, table_counts, table_slots - 1, rest_pos,
-                             (unsigned long long*)rest_count, err, (hipStream_t)stream),
-          "route_split");
+    return fail(CSK_E_INVALID, "cell_labels: factor %u does not divide G=%d", factor, mesh.G);
+  if (nk > (1u << 17)) return fail(CSK_E_INVALID, "cell_labels: %u fine keys above 2^17", nk);
+  if ((m > 0 && (cells == nullptr || labels == nullptr)) || (nk > 0 && fine_keys == nullptr))
+    return fail(CSK_E_INVALID, "cell_labels: NULL pointer");
+  if (m == 0) return CSK_OK;
+  hipStream_t st = (hipStream_t)stream;
+  CallScratch cs;
+  uint64_t* tmp = nullptr;
+  uint64_t* par = nullptr;
+  CSK_HIP(cs.get(&tmp, nk), "cell_labels: scratch");
+  CSK_HIP(cs.get(&par, nk), "cell_labels: scratch");
+  CSK_HIP(launch_parents_sorted(fine_keys, nk, (uint64_t)mesh.G, factor, tmp, par, st), "cell_labels");
+  CSK_HIP(launch_labels(cells, m, par, nk, labels, st), "cell_labels");
+  CSK_HIP(hipStreamSynchronize(st), "cell_labels");
+  return CSK_OK;
+}
+
+csk_status csk_route_admit(const uint64_t* cells, const float* logits, uint64_t m, uint32_t A, uint64_t* admitted,
+                           uint32_t* na, void* stream) {
+  if (na == nullptr) return fail(CSK_E_INVALID, "route_admit: na is NULL");
+  *na = 0;
+  if (m >= (1ull << 31)) return fail(CSK_E_INVALID, "route_admit: m=%llu reaches 2^31", (unsigned long long)m);
+  if (A > (1u << 16)) return fail(CSK_E_INVALID, "route_admit: A=%u above 2^16", A);
+  if (m > 0 && A > 0 && (cells == nullptr || logits == nullptr || admitted == nullptr))
+    return fail(CSK_E_INVALID, "route_admit: NULL pointer");
+  const uint32_t take = (uint32_t)(m < A ? m : A);
+  if (take == 0) return CSK_OK;
+  hipStream_t st = (hipStream_t)stream;
+  CallScratch cs;
+  int32_t* ord = nullptr;
+  SelState* sel = nullptr;
+  uint64_t *sk = nullptr, *ok = nullptr;
+  int32_t *se = nullptr, *oe = nullptr;
+  uint32_t *rank = nullptr, *err = nullptr;
+  CSK_HIP(cs.get(&ord, m), "route_admit: scratch");
+  CSK_HIP(cs.get(&sel, 1), "route_admit: scratch");
+  CSK_HIP(cs.get(&sk, take), "route_admit: scratch");
+  CSK_HIP(cs.get(&se, take), "route_admit: scratch");
+  CSK_HIP(cs.get(&ok, take), "route_admit: scratch");
+  CSK_HIP(cs.get(&oe, take), "route_admit: scratch");
+  CSK_HIP(cs.get(&rank, take), "route_admit: scratch");
+  CSK_HIP(cs.get(&err, 1), "route_admit: scratch");
+  CSK_HIP(launch_fill_u32(err, 1, 0u, st), "route_admit");
+  CSK_HIP(launch_logit_order(logits, m, ord, st), "route_admit");
+  CSK_HIP(launch_select_pairs(cells, ord, (uint32_t)m, take, sel, sk, se, rank, ok, oe, err, st), "route_admit");
+  CSK_HIP(launch_rank_sort(ok, take, admitted, st), "route_admit");
+  CSK_HIP(hipStreamSynchronize(st), "route_admit");
+  *na = take;
   return CSK_OK;
 }
 

@@ -160,6 +160,12 @@ hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, con
                        uint64_t* sel_key, int32_t* sel_est, uint64_t* out_key, int32_t* out_est,
                        const uint32_t* err, hipStream_t s, const uint64_t* ov_keys = nullptr,
                        const uint32_t* ov_counts = nullptr, uint32_t ov_mask = 0);
+// Top k of the m pairs (ck[i], ce[i]) in (ce desc, ck asc) order, keys distinct and below
+// 2^48 (equal keys only where they cannot reach the top k): winners in ok / oe, ranks in
+// `rank` (k words), sk / se (k) scratch.
+hipError_t launch_select_pairs(const uint64_t* ck, const int32_t* ce, uint32_t m, uint32_t k, SelState* st,
+                               uint64_t* sk, int32_t* se, uint32_t* rank, uint64_t* ok, int32_t* oe,
+                               const uint32_t* err, hipStream_t s);
 // Insert every non-empty key of an exact table (tslots slots) into a candidate set.
 hipError_t launch_table_to_set(const uint64_t* tk, uint32_t tslots, uint64_t* set, uint32_t slot_mask,
                                uint32_t* set_count, uint32_t max_cand, uint32_t* err, hipStream_t s);

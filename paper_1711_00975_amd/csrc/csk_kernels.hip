@@ -1544,6 +1544,36 @@ __global__ void sel_finish_kernel(SelState* st, const uint32_t* err) {
   if (threadIdx.x == 0) st->err = *err;
 }
 
+__global__ void sel_set_m_kernel(SelState* st, uint32_t m) {
+  if (threadIdx.x == 0) st->m = m;
+}
+
+// Radix select of the top k of the st->m pairs (ck, ce) in (ce desc, ck asc) order (ck
+// below 2^48), then the winners placed at their ranks in ok / oe.  rank: k words.
+static hipError_t select_stages(const uint64_t* ck, const int32_t* ce, uint32_t m_max, uint32_t k, SelState* st,
+                                uint64_t* sk, int32_t* se, uint32_t* rank, uint64_t* ok, int32_t* oe,
+                                const uint32_t* err, hipStream_t s) {
+  const dim3 hgrid(grid_for(m_max, 256, 1024));
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(sel_hist_kernel<false>, hgrid, dim3(256), 0, s, ck, ce, st, shift);
+    hipLaunchKernelGGL(sel_pick_kernel<false>, dim3(1), dim3(64), 0, s, st, k, shift);
+  }
+  for (int shift = 40; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(sel_hist_kernel<true>, hgrid, dim3(256), 0, s, ck, ce, st, shift);
+    hipLaunchKernelGGL(sel_pick_kernel<true>, dim3(1), dim3(64), 0, s, st, k, shift);
+  }
+  hipLaunchKernelGGL(sel_gather_kernel, hgrid, dim3(256), 0, s, ck, ce, st, k, sk, se);
+  hipError_t e = launch_fill_u32(rank, k, 0u, s);
+  if (e != hipSuccess) return e;
+  uint64_t chunk = kRankChunk;
+  while ((k + chunk - 1) / chunk > kMaxGridY) chunk *= 2;
+  hipLaunchKernelGGL(rank_count_kernel, dim3((k + 255) / 256, (uint32_t)((k + chunk - 1) / chunk)), dim3(256), 0, s,
+                     sk, se, st, k, (uint32_t)chunk, rank);
+  hipLaunchKernelGGL(rank_place_kernel, dim3(grid_for(k, 256, 1024)), dim3(256), 0, s, sk, se, st, k, rank, ok, oe);
+  hipLaunchKernelGGL(sel_finish_kernel, dim3(1), dim3(64), 0, s, st, err);
+  return hipGetLastError();
+}
+
 hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,
                        uint32_t max_cand, uint32_t k, SelState* st, uint64_t* ck, int32_t* ce,
                        uint64_t* sk, int32_t* se, uint64_t* ok, int32_t* oe, const uint32_t* err,
@@ -1557,27 +1587,16 @@ hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, con
     hipLaunchKernelGGL((compact_kernel<32, false>), cgrid, dim3(256), 0, s, set, slots, t, M, max_cand, st, ck,
                        ce, ov_keys, ov_counts, ov_mask);
   hipLaunchKernelGGL(clamp_m_kernel, dim3(1), dim3(64), 0, s, st, max_cand);
-  const dim3 hgrid(grid_for(max_cand, 256, 1024));
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    hipLaunchKernelGGL(sel_hist_kernel<false>, hgrid, dim3(256), 0, s, ck, ce, st, shift);
-    hipLaunchKernelGGL(sel_pick_kernel<false>, dim3(1), dim3(64), 0, s, st, k, shift);
-  }
-  for (int shift = 40; shift >= 0; shift -= 8) {
-    hipLaunchKernelGGL(sel_hist_kernel<true>, hgrid, dim3(256), 0, s, ck, ce, st, shift);
-    hipLaunchKernelGGL(sel_pick_kernel<true>, dim3(1), dim3(64), 0, s, st, k, shift);
-  }
-  hipLaunchKernelGGL(sel_gather_kernel, hgrid, dim3(256), 0, s, ck, ce, st, k, sk, se);
-  // the candidate estimates are no longer needed: their first k words hold the ranks
-  uint32_t* rank = (uint32_t*)ce;
-  hipError_t e = launch_fill_u32(rank, k, 0u, s);
-  if (e != hipSuccess) return e;
-  uint64_t chunk = kRankChunk;
-  while ((k + chunk - 1) / chunk > kMaxGridY) chunk *= 2;
-  hipLaunchKernelGGL(rank_count_kernel, dim3((k + 255) / 256, (uint32_t)((k + chunk - 1) / chunk)), dim3(256), 0, s,
-                     sk, se, st, k, (uint32_t)chunk, rank);
-  hipLaunchKernelGGL(rank_place_kernel, dim3(grid_for(k, 256, 1024)), dim3(256), 0, s, sk, se, st, k, rank, ok, oe);
-  hipLaunchKernelGGL(sel_finish_kernel, dim3(1), dim3(64), 0, s, st, err);
-  return hipGetLastError();
+  // the candidate estimates are no longer needed once gathered: their first k words hold the ranks
+  return select_stages(ck, ce, max_cand, k, st, sk, se, (uint32_t*)ce, ok, oe, err, s);
+}
+
+hipError_t launch_select_pairs(const uint64_t* ck, const int32_t* ce, uint32_t m, uint32_t k, SelState* st,
+                               uint64_t* sk, int32_t* se, uint32_t* rank, uint64_t* ok, int32_t* oe,
+                               const uint32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, s, st);
+  hipLaunchKernelGGL(sel_set_m_kernel, dim3(1), dim3(64), 0, s, st, m);
+  return select_stages(ck, ce, m, k, st, sk, se, rank, ok, oe, err, s);
 }
 
 }  // namespace csk

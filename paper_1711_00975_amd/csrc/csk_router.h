@@ -33,8 +33,32 @@ hipError_t launch_relu_back(float* dA, const float* H, uint64_t total, hipStream
 hipError_t launch_colsum(const float* X, uint32_t M, uint32_t N, uint32_t ld, const float* w, float* out, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, uint32_t n, float lr_t, float b1, float b2,
                        float eps, hipStream_t s);
+// The routing split: workgroups of kSplitThreads, kSplitPPT particles per thread per
+// tile, at most kSplitBlocks workgroups, at most kSplitMaxChildren admitted children (the
+// LDS counters of one workgroup).
+constexpr int kSplitThreads = 1024;
+constexpr int kSplitPPT = 8;
+constexpr uint64_t kSplitTile = (uint64_t)kSplitThreads * kSplitPPT;
+constexpr uint32_t kSplitBlocks = 256;
+constexpr uint32_t kSplitMaxChildren = 32768;
+uint32_t split_blocks(uint64_t n, uint64_t* chunk);
+uint64_t split_workspace_bytes(uint32_t na, uint32_t factor);
 hipError_t launch_route_split(const float* pos, uint64_t n, const Mesh& mesh, uint32_t factor, const uint64_t* admitted,
                               uint32_t na, uint64_t* tkeys, uint32_t* tcounts, uint32_t tmask, float* rest_pos,
-                              unsigned long long* rest_count, uint32_t* err, hipStream_t s);
+                              unsigned long long* rest_count, uint32_t* err, void* workspace, hipStream_t s);
+
+
+constexpr uint32_t kCellListBlocks = 65536;   // workgroups of the ordered cell listing
+hipError_t launch_exact_count(const float* pos, uint64_t n, const Mesh& mesh, uint64_t* tkeys, uint32_t* tcounts,
+                              uint32_t tmask, uint32_t* err, hipStream_t s);
+uint32_t cell_list_blocks(uint64_t ncells, uint64_t* chunk);
+hipError_t launch_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t min_count, uint64_t* block_scratch,
+                            uint64_t* cells, uint64_t cap, unsigned long long* total, hipStream_t s);
+hipError_t launch_parents_sorted(const uint64_t* keys, uint32_t n, uint64_t G, uint32_t factor, uint64_t* tmp,
+                                 uint64_t* out, hipStream_t s);
+hipError_t launch_rank_sort(const uint64_t* in, uint32_t n, uint64_t* out, hipStream_t s);
+hipError_t launch_labels(const uint64_t* cells, uint64_t m, const uint64_t* par, uint32_t np, float* labels,
+                         hipStream_t s);
+hipError_t launch_logit_order(const float* z, uint64_t m, int32_t* out, hipStream_t s);
 
 }  // namespace csk

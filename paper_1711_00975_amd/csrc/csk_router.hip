@@ -202,75 +202,359 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const 
 
 // ------------------------------------------------------------------ routing
 
-// Every in-domain particle whose coarse parent (fine index / factor on each axis) is in
-// the sorted list `admitted` adds 1 to its fine key's entry of the exact table; every
-// other in-domain particle is appended to rest_pos (count in *rest_count).  Particles
-// outside the domain latch kErrDomain in *err and go nowhere.
-__global__ __launch_bounds__(256) void route_split_kernel(const float* __restrict__ pos, uint64_t n, Mesh mesh,
-                                                          uint32_t factor, const uint64_t* __restrict__ admitted,
-                                                          uint32_t na, uint64_t* __restrict__ tkeys,
-                                                          uint32_t* __restrict__ tcounts, uint32_t tmask,
-                                                          float* __restrict__ rest_pos,
-                                                          unsigned long long* __restrict__ rest_count,
-                                                          uint32_t* __restrict__ err) {
+// The split runs in two passes over the same contiguous chunks of the stream, one chunk
+// per workgroup: pass 1 counts each chunk's rest particles, a scan turns the counts into
+// output offsets, pass 2 writes the rest in stream order and counts the admitted
+// particles in a workgroup-private LDS array of the admitted cells' children.  The
+// per-workgroup arrays are summed and inserted into the exact table once.
+
+struct SplitArgs {
+  const float* pos;
+  uint64_t n;
+  Mesh mesh;
+  uint32_t factor;      // fine cells per coarse cell along an axis
+  uint32_t f3;          // factor^3
+  const uint64_t* admitted;
+  uint32_t na;
+  uint64_t chunk;       // particles per workgroup (a multiple of kSplitTile)
+};
+
+// Index of the admitted coarse parent of (x, y, z) in the sorted list, or -1; -2 outside
+// the domain.  child = position of the fine cell inside its coarse cell.
+__device__ __forceinline__ int32_t split_class(float x, float y, float z, const SplitArgs& a,
+                                               const uint64_t* __restrict__ adm, uint32_t& child) {
+  int32_t ix, iy, iz;
+  const bool ok = (int)cell_index(x, a.mesh, ix) & (int)cell_index(y, a.mesh, iy) & (int)cell_index(z, a.mesh, iz);
+  if (!ok) return -2;
+  const uint32_t f = a.factor;
+  const uint32_t cx = (uint32_t)ix / f, cy = (uint32_t)iy / f, cz = (uint32_t)iz / f;
+  const uint64_t Gc = (uint64_t)((uint32_t)a.mesh.G / f);
+  const uint64_t ckey = ((uint64_t)cx * Gc + cy) * Gc + cz;
+  uint32_t lo = 0, hi = a.na;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (adm[mid] < ckey) lo = mid + 1;
+    else hi = mid;
+  }
+  child = (((uint32_t)ix - cx * f) * f + ((uint32_t)iy - cy * f)) * f + ((uint32_t)iz - cz * f);
+  return (lo < a.na && adm[lo] == ckey) ? (int32_t)lo : -1;
+}
+
+// Loads of one tile: kSplitPPT particles per thread, all issued before the first use
+// (indices clamped to the last particle; the caller masks by validity).
+__device__ __forceinline__ void split_load(const SplitArgs& a, uint64_t t0, float (&p)[kSplitPPT][3]) {
+  const uint64_t last = a.n - 1;
+#pragma unroll
+  for (int j = 0; j < kSplitPPT; ++j) {
+    uint64_t i = t0 + (uint64_t)j * kSplitThreads + threadIdx.x;
+    i = i < last ? i : last;
+    p[j][0] = a.pos[3 * i];
+    p[j][1] = a.pos[3 * i + 1];
+    p[j][2] = a.pos[3 * i + 2];
+  }
+}
+
+__global__ __launch_bounds__(kSplitThreads) void split_count_kernel(SplitArgs a, uint64_t* __restrict__ block_rest,
+                                                                    uint32_t* __restrict__ err) {
   __shared__ uint64_t adm[kMaxAdmitted];
-  for (uint32_t i = threadIdx.x; i < na; i += blockDim.x) adm[i] = admitted[i];
+  __shared__ uint32_t part[kSplitThreads / 64];
+  for (uint32_t i = threadIdx.x; i < a.na; i += blockDim.x) adm[i] = a.admitted[i];
   __syncthreads();
-  const uint64_t G = (uint64_t)mesh.G, Gc = G / factor;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t n_round = (n + blockDim.x - 1) / blockDim.x * blockDim.x;   // whole waves for the append
-  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n_round; i0 += stride) {
-    const uint64_t i = i0 + threadIdx.x;
-    bool rest = false;
-    float x = 0.0f, y = 0.0f, z = 0.0f;
-    if (i < n) {
-      x = pos[3 * i];
-      y = pos[3 * i + 1];
-      z = pos[3 * i + 2];
-      uint64_t key;
-      if (!cell_key(x, y, z, mesh, key)) {
-        atomicOr(err, 1u);
-      } else {
-        const uint64_t ix = key / (G * G), iy = (key / G) % G, iz = key % G;
-        const uint64_t ckey = ((ix / factor) * Gc + iy / factor) * Gc + iz / factor;
-        uint32_t lo = 0, hi = na;   // binary search in the sorted admitted list
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (adm[mid] < ckey) lo = mid + 1;
-          else hi = mid;
-        }
-        if (lo < na && adm[lo] == ckey) {
-          uint32_t sl = table_slot(key, tmask);
-          for (uint32_t probe = 0; probe <= tmask; ++probe) {
-            const unsigned long long old = atomicCAS((unsigned long long*)&tkeys[sl], ~0ull, (unsigned long long)key);
-            if (old == ~0ull || old == key) {
-              atomicAdd(&tcounts[sl], 1u);
-              break;
-            }
-            sl = (sl + 1) & tmask;
-            if (probe == tmask) atomicOr(err, 2u);   // table full (admission keeps it at most half full)
-          }
-        } else {
-          rest = true;
-        }
+  const uint64_t lo = (uint64_t)blockIdx.x * a.chunk;
+  const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+  uint32_t rest = 0;
+  bool bad = false;
+  for (uint64_t t0 = lo; t0 < hi; t0 += kSplitTile) {
+    float p[kSplitPPT][3];
+    split_load(a, t0, p);
+#pragma unroll
+    for (int j = 0; j < kSplitPPT; ++j) {
+      const uint64_t i = t0 + (uint64_t)j * kSplitThreads + threadIdx.x;
+      uint32_t child;
+      const int32_t c = split_class(p[j][0], p[j][1], p[j][2], a, adm, child);
+      if (i < hi) {
+        rest += c == -1;
+        bad |= c == -2;
       }
     }
-    // wave-aggregated append of the rest
-    const uint64_t mask = __ballot(rest);
-    if (mask) {
-      const uint32_t lane = threadIdx.x & 63u;
-      const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(rest_count, (unsigned long long)__popcll(mask));
-      base = __shfl(base, (int)leader, 64);
+  }
+  if (bad) atomicOr(err, 1u);
+  // block sum
+  uint32_t v = rest;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t sum = 0;
+    for (uint32_t w = 0; w < kSplitThreads / 64; ++w) sum += part[w];
+    block_rest[blockIdx.x] = sum;
+  }
+}
+
+// Exclusive scan of the nb <= 1024 block counts, offset by *rest_count; *rest_count grows
+// by the total.
+__global__ __launch_bounds__(1024) void split_scan_kernel(uint64_t* __restrict__ v, uint32_t nb,
+                                                          unsigned long long* __restrict__ rest_count) {
+  __shared__ uint64_t part[1024];
+  const uint64_t x = threadIdx.x < nb ? v[threadIdx.x] : 0;
+  part[threadIdx.x] = x;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024; off <<= 1) {
+    const uint64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const uint64_t base = *rest_count;
+  if (threadIdx.x < nb) v[threadIdx.x] = base + part[threadIdx.x] - x;
+  __syncthreads();
+  if (threadIdx.x == 0) *rest_count = base + part[1023];
+}
+
+__global__ __launch_bounds__(kSplitThreads) void split_write_kernel(SplitArgs a, const uint64_t* __restrict__ block_off,
+                                                                    float* __restrict__ rest_pos,
+                                                                    uint32_t* __restrict__ dense_part) {
+  extern __shared__ uint32_t dense[];          // na * f3 counters of this chunk
+  __shared__ uint64_t adm[kMaxAdmitted];
+  __shared__ uint32_t wave_n[kSplitThreads / 64];
+  const uint32_t nd = a.na * a.f3;
+  for (uint32_t i = threadIdx.x; i < a.na; i += blockDim.x) adm[i] = a.admitted[i];
+  for (uint32_t i = threadIdx.x; i < nd; i += blockDim.x) dense[i] = 0;
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint64_t lo = (uint64_t)blockIdx.x * a.chunk;
+  const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+  uint64_t base = block_off[blockIdx.x];
+  for (uint64_t t0 = lo; t0 < hi; t0 += kSplitTile) {   // uniform over the block
+    float p[kSplitPPT][3];
+    split_load(a, t0, p);
+#pragma unroll
+    for (int j = 0; j < kSplitPPT; ++j) {
+      const uint64_t i = t0 + (uint64_t)j * kSplitThreads + threadIdx.x;
+      uint32_t child = 0;
+      const int32_t c = split_class(p[j][0], p[j][1], p[j][2], a, adm, child);
+      const bool valid = i < hi;
+      if (valid && c >= 0) atomicAdd(&dense[(uint32_t)c * a.f3 + child], 1u);
+      const bool rest = valid && c == -1;
+      const uint64_t mask = __ballot(rest);
+      if (lane == 0) wave_n[wave] = (uint32_t)__popcll(mask);
+      __syncthreads();
+      uint64_t off = base;
+      for (uint32_t q = 0; q < wave; ++q) off += wave_n[q];
+      off += (uint64_t)__popcll(lane ? (mask & (~0ull >> (64 - lane))) : 0ull);
       if (rest) {
-        const uint64_t below = (lane == 0) ? 0ull : (mask & ((~0ull) >> (64 - lane)));
-        const uint64_t o = base + (uint64_t)__popcll(below);
-        rest_pos[3 * o] = x;
-        rest_pos[3 * o + 1] = y;
-        rest_pos[3 * o + 2] = z;
+        rest_pos[3 * off] = p[j][0];
+        rest_pos[3 * off + 1] = p[j][1];
+        rest_pos[3 * off + 2] = p[j][2];
       }
+      for (uint32_t q = 0; q < kSplitThreads / 64; ++q) base += wave_n[q];
+      __syncthreads();
     }
+  }
+  uint32_t* out = dense_part + (uint64_t)blockIdx.x * nd;
+  for (uint32_t i = threadIdx.x; i < nd; i += blockDim.x) out[i] = dense[i];
+}
+
+// Sum of the nb partial arrays, and every child with a nonzero count added to the exact
+// table under its fine key (linear probing from table_slot; bit 1 of *err if full).
+__global__ __launch_bounds__(256) void split_table_kernel(SplitArgs a, const uint32_t* __restrict__ dense_part,
+                                                          uint32_t nb, uint64_t* __restrict__ tkeys,
+                                                          uint32_t* __restrict__ tcounts, uint32_t tmask,
+                                                          uint32_t* __restrict__ err) {
+  const uint32_t nd = a.na * a.f3;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nd; e += gridDim.x * blockDim.x) {
+    uint32_t cnt = 0;
+    for (uint32_t b = 0; b < nb; ++b) cnt += dense_part[(uint64_t)b * nd + e];
+    if (cnt == 0) continue;
+    const uint32_t f = a.factor, ai = e / a.f3, c = e % a.f3;
+    const uint64_t G = (uint64_t)(uint32_t)a.mesh.G, Gc = G / f;
+    const uint64_t P = a.admitted[ai];
+    const uint64_t px = P / (Gc * Gc), py = (P / Gc) % Gc, pz = P % Gc;
+    const uint64_t ix = px * f + c / (f * f), iy = py * f + (c / f) % f, iz = pz * f + c % f;
+    const uint64_t key = (ix * G + iy) * G + iz;
+    uint32_t sl = table_slot(key, tmask);
+    bool placed = false;
+    for (uint32_t probe = 0; probe <= tmask; ++probe) {
+      uint64_t cur = __hip_atomic_load(&tkeys[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (cur == ~0ull) {
+        cur = atomicCAS((unsigned long long*)&tkeys[sl], ~0ull, (unsigned long long)key);
+        if (cur == ~0ull) cur = key;
+      }
+      if (cur == key) {
+        atomicAdd(&tcounts[sl], cnt);
+        placed = true;
+        break;
+      }
+      sl = (sl + 1) & tmask;
+    }
+    if (!placed) atomicOr(err, 2u);
+  }
+}
+
+// ------------------------------------------------------------------ exact counting
+
+// Every in-domain particle adds 1 to its cell key's entry of the table (linear probing
+// from table_slot; keys all-ones when empty).  Out-of-domain particles set bit 0 of *err;
+// a key that finds no free slot after probing the whole table sets bit 1.
+__global__ __launch_bounds__(256) void exact_count_kernel(const float* __restrict__ pos, uint64_t n, Mesh mesh,
+                                                          uint64_t* __restrict__ tkeys, uint32_t* __restrict__ tcounts,
+                                                          uint32_t tmask, uint32_t* __restrict__ err) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint64_t key;
+    if (!cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mesh, key)) {
+      atomicOr(err, 1u);
+      continue;
+    }
+    uint32_t sl = table_slot(key, tmask);
+    bool placed = false;
+    for (uint32_t probe = 0; probe <= tmask; ++probe) {
+      // a slot's key only ever changes from empty to its final value
+      uint64_t cur = __hip_atomic_load(&tkeys[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (cur == ~0ull) {
+        cur = atomicCAS((unsigned long long*)&tkeys[sl], ~0ull, (unsigned long long)key);
+        if (cur == ~0ull) cur = key;
+      }
+      if (cur == key) {
+        atomicAdd(&tcounts[sl], 1u);
+        placed = true;
+        break;
+      }
+      sl = (sl + 1) & tmask;
+    }
+    if (!placed) atomicOr(err, 2u);
+  }
+}
+
+// ------------------------------------------------------------------ cell lists
+
+// Cells with count >= min_count, in ascending order: block b owns cells [b chunk,
+// (b + 1) chunk); pass 1 counts per block, pass 2 scans the block counts, pass 3 writes.
+__global__ __launch_bounds__(256) void cell_list_count_kernel(const uint32_t* __restrict__ counts, uint64_t ncells,
+                                                              uint64_t chunk, uint32_t min_count,
+                                                              uint64_t* __restrict__ block_count) {
+  __shared__ uint64_t part[256];
+  const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+  const uint64_t hi = lo + chunk < ncells ? lo + chunk : ncells;
+  uint64_t c = 0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) c += counts[i] >= min_count;
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (uint32_t h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) block_count[blockIdx.x] = part[0];
+}
+
+// Exclusive scan of nb block counts in place (one workgroup of 1024); total in *total.
+__global__ __launch_bounds__(1024) void scan_blocks_kernel(uint64_t* __restrict__ v, uint32_t nb,
+                                                           unsigned long long* __restrict__ total) {
+  __shared__ uint64_t part[1024];
+  const uint32_t per = (nb + 1023) / 1024;
+  const uint32_t lo = threadIdx.x * per, hi = lo + per < nb ? lo + per : nb;
+  uint64_t s = 0;
+  for (uint32_t i = lo; i < hi; ++i) s += v[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
+    const uint64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  uint64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint64_t c = v[i];
+    v[i] = run;
+    run += c;
+  }
+  if (threadIdx.x == 1023) *total = part[1023];
+}
+
+__global__ __launch_bounds__(256) void cell_list_write_kernel(const uint32_t* __restrict__ counts, uint64_t ncells,
+                                                              uint64_t chunk, uint32_t min_count,
+                                                              const uint64_t* __restrict__ block_off,
+                                                              uint64_t* __restrict__ cells, uint64_t cap) {
+  __shared__ uint32_t wave_n[4];
+  const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+  const uint64_t hi = lo + chunk < ncells ? lo + chunk : ncells;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint64_t base = block_off[blockIdx.x];
+  for (uint64_t t0 = lo; t0 < hi; t0 += blockDim.x) {   // uniform over the block
+    const uint64_t i = t0 + threadIdx.x;
+    const bool take = i < hi && counts[i] >= min_count;
+    const uint64_t mask = __ballot(take);
+    if (lane == 0) wave_n[wave] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    uint64_t off = base;
+    for (uint32_t q = 0; q < wave; ++q) off += wave_n[q];
+    const uint64_t below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
+    off += (uint64_t)__popcll(below);
+    if (take && off < cap) cells[off] = i;
+    for (uint32_t q = 0; q < 4; ++q) base += wave_n[q];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ labels and admission
+
+// out[i] = coarse parent (fine cell index / factor per axis on the mesh G / factor) of keys[i]
+__global__ __launch_bounds__(256) void parent_kernel(const uint64_t* __restrict__ keys, uint32_t n, uint64_t G,
+                                                     uint32_t factor, uint64_t* __restrict__ out) {
+  const uint64_t Gc = G / factor;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    const uint64_t ix = k / (G * G), iy = (k / G) % G, iz = k % G;
+    out[i] = ((ix / factor) * Gc + iy / factor) * Gc + iz / factor;
+  }
+}
+
+// out[rank(i)] = in[i] with rank(i) = #{j : in[j] < in[i]} + #{j < i : in[j] == in[i]}:
+// an ascending stable sort for short lists (quadratic work).
+__global__ __launch_bounds__(256) void rank_sort_kernel(const uint64_t* __restrict__ in, uint32_t n,
+                                                        uint64_t* __restrict__ out) {
+  __shared__ uint64_t tile[256];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t v = i < n ? in[i] : 0;
+  uint32_t r = 0;
+  for (uint32_t j0 = 0; j0 < n; j0 += 256) {
+    __syncthreads();
+    if (j0 + threadIdx.x < n) tile[threadIdx.x] = in[j0 + threadIdx.x];
+    __syncthreads();
+    const uint32_t lim = n - j0 < 256 ? n - j0 : 256;
+    for (uint32_t t = 0; t < lim; ++t) r += (tile[t] < v) || (tile[t] == v && j0 + t < i);
+  }
+  if (i < n) out[r] = v;
+}
+
+// labels[j] = 1 if cells[j] is in the ascending list par[0 .. np), else 0
+__global__ __launch_bounds__(256) void label_kernel(const uint64_t* __restrict__ cells, uint64_t m,
+                                                    const uint64_t* __restrict__ par, uint32_t np,
+                                                    float* __restrict__ labels) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    const uint64_t c = cells[j];
+    uint32_t lo = 0, hi = np;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (par[mid] < c) lo = mid + 1;
+      else hi = mid;
+    }
+    labels[j] = (lo < np && par[lo] == c) ? 1.0f : 0.0f;
+  }
+}
+
+// An int32 whose signed order is the order of the float logits (-0 taken as +0), so that
+// the radix select of the top-k ranks cells by logit.
+__global__ __launch_bounds__(256) void logit_order_kernel(const float* __restrict__ z, uint64_t m,
+                                                          int32_t* __restrict__ out) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    uint32_t u = __float_as_uint(z[j]);
+    if (u == 0x80000000u) u = 0u;
+    const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);   // unsigned order of the floats
+    out[j] = (int32_t)(ord ^ 0x80000000u);
   }
 }
 
@@ -339,11 +623,92 @@ hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, uint32_t 
   return hipGetLastError();
 }
 
+uint32_t split_blocks(uint64_t n, uint64_t* chunk) {
+  uint64_t tiles = (n + kSplitTile - 1) / kSplitTile;
+  uint64_t nb = tiles < kSplitBlocks ? tiles : kSplitBlocks;
+  if (nb < 1) nb = 1;
+  *chunk = (tiles + nb - 1) / nb * kSplitTile;
+  return (uint32_t)nb;
+}
+
+uint64_t split_workspace_bytes(uint32_t na, uint32_t factor) {
+  return kSplitBlocks * sizeof(uint64_t) + (uint64_t)kSplitBlocks * na * factor * factor * factor * sizeof(uint32_t);
+}
+
 hipError_t launch_route_split(const float* pos, uint64_t n, const Mesh& mesh, uint32_t factor, const uint64_t* admitted,
                               uint32_t na, uint64_t* tkeys, uint32_t* tcounts, uint32_t tmask, float* rest_pos,
-                              unsigned long long* rest_count, uint32_t* err, hipStream_t s) {
-  hipLaunchKernelGGL(route_split_kernel, dim3(grid_of(n, 256, 8192)), dim3(256), 0, s, pos, n, mesh, factor, admitted,
-                     na, tkeys, tcounts, tmask, rest_pos, rest_count, err);
+                              unsigned long long* rest_count, uint32_t* err, void* workspace, hipStream_t s) {
+  SplitArgs a;
+  a.pos = pos;
+  a.n = n;
+  a.mesh = mesh;
+  a.factor = factor;
+  a.f3 = factor * factor * factor;
+  a.admitted = admitted;
+  a.na = na;
+  const uint32_t nb = split_blocks(n, &a.chunk);
+  uint64_t* block = (uint64_t*)workspace;
+  uint32_t* dense_part = (uint32_t*)(block + kSplitBlocks);
+  const uint32_t nd = na * a.f3;
+  hipLaunchKernelGGL(split_count_kernel, dim3(nb), dim3(kSplitThreads), 0, s, a, block, err);
+  hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(1024), 0, s, block, nb, rest_count);
+  hipLaunchKernelGGL(split_write_kernel, dim3(nb), dim3(kSplitThreads), (size_t)nd * sizeof(uint32_t), s, a, block,
+                     rest_pos, dense_part);
+  if (nd > 0)
+    hipLaunchKernelGGL(split_table_kernel, dim3(grid_of(nd, 256, 1024)), dim3(256), 0, s, a, dense_part, nb, tkeys,
+                       tcounts, tmask, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_exact_count(const float* pos, uint64_t n, const Mesh& mesh, uint64_t* tkeys, uint32_t* tcounts,
+                              uint32_t tmask, uint32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(exact_count_kernel, dim3(grid_of(n, 256, 16384)), dim3(256), 0, s, pos, n, mesh, tkeys, tcounts,
+                     tmask, err);
+  return hipGetLastError();
+}
+
+uint32_t cell_list_blocks(uint64_t ncells, uint64_t* chunk) {
+  uint64_t nb = (ncells + 4095) / 4096;
+  if (nb > kCellListBlocks) nb = kCellListBlocks;
+  if (nb < 1) nb = 1;
+  *chunk = (ncells + nb - 1) / nb;
+  return (uint32_t)nb;
+}
+
+hipError_t launch_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t min_count, uint64_t* block_scratch,
+                            uint64_t* cells, uint64_t cap, unsigned long long* total, hipStream_t s) {
+  uint64_t chunk = 0;
+  const uint32_t nb = cell_list_blocks(ncells, &chunk);
+  hipLaunchKernelGGL(cell_list_count_kernel, dim3(nb), dim3(256), 0, s, counts, ncells, chunk, min_count,
+                     block_scratch);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, block_scratch, nb, total);
+  hipLaunchKernelGGL(cell_list_write_kernel, dim3(nb), dim3(256), 0, s, counts, ncells, chunk, min_count,
+                     block_scratch, cells, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_parents_sorted(const uint64_t* keys, uint32_t n, uint64_t G, uint32_t factor, uint64_t* tmp,
+                                 uint64_t* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(parent_kernel, dim3(grid_of(n, 256, 1024)), dim3(256), 0, s, keys, n, G, factor, tmp);
+  hipLaunchKernelGGL(rank_sort_kernel, dim3((n + 255) / 256), dim3(256), 0, s, tmp, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_sort(const uint64_t* in, uint32_t n, uint64_t* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_sort_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_labels(const uint64_t* cells, uint64_t m, const uint64_t* par, uint32_t np, float* labels,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(label_kernel, dim3(grid_of(m, 256, 8192)), dim3(256), 0, s, cells, m, par, np, labels);
+  return hipGetLastError();
+}
+
+hipError_t launch_logit_order(const float* z, uint64_t m, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(logit_order_kernel, dim3(grid_of(m, 256, 8192)), dim3(256), 0, s, z, m, out);
   return hipGetLastError();
 }
 

@@ -652,3 +652,49 @@ def test_router_split_invariants():
     ck = ((rk // np.uint64(G * G) // np.uint64(4)) * np.uint64(Gc) + (rk // np.uint64(G)) % np.uint64(G) // np.uint64(4)) \
         * np.uint64(Gc) + rk % np.uint64(G) // np.uint64(4)
     assert not np.isin(ck, admitted).any()
+
+
+def test_router_lists_labels_and_admission_by_brute_force():
+    from oracle import router
+    rng = np.random.default_rng(6)
+    counts = rng.integers(0, 4, 300).astype(np.uint32)
+    for mc in (0, 1, 3, 5):
+        assert router.cell_list(counts, mc).tolist() == [j for j in range(300) if counts[j] >= mc]
+    # labels: a coarse cell is positive iff one of its factor^3 children, enumerated one by
+    # one, is among the fine keys
+    G, f = 12, 3
+    Gc = G // f
+    fine = rng.choice(G ** 3, 40, replace=False).astype(np.uint64)
+    fs = set(fine.tolist())
+    cells = np.arange(Gc ** 3, dtype=np.int64)
+    lab = router.labels(cells, fine, G, f)
+    for c in cells:
+        cx, cy, cz = c // (Gc * Gc), (c // Gc) % Gc, c % Gc
+        kids = {((cx * f + a) * G + cy * f + b) * G + cz * f + e for a in range(f) for b in range(f) for e in range(f)}
+        assert lab[c] == (1.0 if kids & fs else 0.0)
+    # admission: A cells, ascending, and no cell left out outranks one taken by (logit, -key)
+    m = 60
+    cells = rng.choice(10 ** 6, m, replace=False).astype(np.int64)
+    z = rng.integers(-3, 4, m).astype(np.float32) / 2      # many ties
+    z[:4] = [0.0, -0.0, 0.0, -0.0]
+    for A in (1, 7, 25, 60, 80):
+        adm = router.admit(cells, z, A)
+        assert len(adm) == min(A, m) and np.all(np.diff(adm) > 0)
+        taken = set(adm.tolist())
+        for j in range(m):
+            for i in range(m):
+                if cells[i] in taken and cells[j] not in taken:
+                    assert (z[i] > z[j]) or (z[i] == z[j] and cells[i] < cells[j])
+
+
+def test_exact_topk_by_counting():
+    from oracle import router
+    rng = np.random.default_rng(3)
+    pos = (rng.random((5000, 3)) ** 2 * 10).astype(np.float32)
+    keys, cnt = router.exact_topk(pos, 1.0, 10.0, 15)
+    tally = {}
+    for p in pos:
+        k = (int(p[0]) * 10 + int(p[1])) * 10 + int(p[2])
+        tally[k] = tally.get(k, 0) + 1
+    want = sorted(tally.items(), key=lambda kv: (-kv[1], kv[0]))[:15]
+    assert keys.tolist() == [k for k, _ in want] and cnt.tolist() == [c for _, c in want]

@@ -65,12 +65,33 @@ def test_mfma_gemm_matches_numpy(M, N, K, trans_a, trans_b):
         assert np.allclose(Cd.cpu().numpy(), want, rtol=1e-5, atol=2e-4)
 
 
+def he_uniform_params(seed):
+    """The documented initialisation of csk_mlp_create: He-uniform weights from the
+    SplitMix64 sequence of the seed (W1, W2, w3 in turn; padding inputs zero), zero biases."""
+    u = (oracle.splitmix64(seed, 64 * 32 + 64 * 64 + 64) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    w = {"W1": (2 * u[:2048] - 1) * np.sqrt(6 / 27), "W2": (2 * u[2048:6144] - 1) * np.sqrt(6 / 64),
+         "w3": (2 * u[6144:] - 1) * np.sqrt(6 / 64), "b1": np.zeros(64), "b2": np.zeros(64), "b3": np.zeros(1)}
+    w = {k: v.astype(np.float32) for k, v in w.items()}
+    w["W1"] = w["W1"].reshape(64, 32)
+    w["W1"][:, 27:] = 0
+    return ref.pack(w)
+
+
+def test_mlp_initialisation_follows_its_recipe():
+    m = csk.MLP(seed=5, max_batch=16)
+    assert np.array_equal(m.params(), he_uniform_params(5))
+    m.close()
+
+
 def test_mlp_logits_and_gradients_match_reference():
     import torch
     rng = np.random.default_rng(8)
+    w = ref.unpack(rng.normal(0, 0.25, ref.N_PARAMS).astype(np.float32))
+    w["W1"][:, 27:] = 0
+    p = ref.pack(w)
     m = csk.MLP(seed=5, max_batch=512)
-    p = m.params()
-    assert not ref.unpack(p)["W1"][:, 27:].any()          # padding inputs carry no weight
+    m.set_params(p)
+    assert np.array_equal(m.params(), p)
     x = np.zeros((700, 32), np.float32)
     x[:, :27] = np.log1p(rng.poisson(3.0, (700, 27))).astype(np.float32)
     z = m.forward(dev(x)).cpu().numpy()                   # two chunks of at most 512 rows
@@ -125,7 +146,9 @@ def test_route_split_and_routed_topk_match_oracle():
     rest = torch.empty((len(pos), 3), dtype=torch.float32, device="cuda")
     rcount = torch.zeros(1, dtype=torch.int64, device="cuda")
     err = torch.zeros(1, dtype=torch.int32, device="cuda")
-    csk.route_split(dev(pos), delta, L, factor, dev(admitted), tkeys, tcounts, rest, rcount, err)
+    cut = 123_457                              # two calls: the table adds up, the rest appends
+    csk.route_split(dev(pos[:cut]), delta, L, factor, dev(admitted), tkeys, tcounts, rest, rcount, err)
+    csk.route_split(dev(pos[cut:]), delta, L, factor, dev(admitted), tkeys, tcounts, rest, rcount, err)
     torch.cuda.synchronize()
     assert err.item() == 0
     tk_ref, tc_ref, rest_ref = ref.route(pos, delta, L, factor, admitted.astype(np.uint64))
@@ -135,9 +158,8 @@ def test_route_split_and_routed_topk_match_oracle():
     order = np.argsort(tk[full])
     assert np.array_equal(tk[full][order], tk_ref) and np.array_equal(tc[full][order], tc_ref)
     nrest = int(rcount.item())
-    got_rest = rest[:nrest].cpu().numpy()
     assert nrest == len(rest_ref)
-    assert np.array_equal(got_rest[np.lexsort(got_rest.T)], rest_ref[np.lexsort(rest_ref.T)])
+    assert np.array_equal(rest[:nrest].cpu().numpy(), rest_ref)    # stream order kept
     # the rest goes to a sketch; the top-k merges the table's exact counts with its estimates
     w, seed, theta, k = 9973, 4, 3, 400
     s = csk.Sketch(5, w, seed)
@@ -150,3 +172,102 @@ def test_route_split_and_routed_topk_match_oracle():
     assert keys.cpu().numpy().view(np.uint64).tolist() == kr
     assert est.cpu().numpy().tolist() == er
     s.close()
+
+
+@pytest.mark.parametrize("n", [0, 1, 777, 300_000])
+def test_exact_counts_and_table_topk_match_oracle(n):
+    import torch
+    L, delta = 50.0, 0.25
+    pos = clustered(n, L, 11 + n, frac=0.7, sigma=0.15)
+    if n > 10:
+        pos[5] = (3 * L, 1.0, 1.0)             # beyond the periodic wrap (|p| < 2L): skipped and flagged
+    tk, tc = csk.new_table(1 << 20)
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cut = n // 3                               # two calls add into one table
+    csk.exact_counts(dev(pos[:cut]), delta, L, tk, tc, err)
+    csk.exact_counts(dev(pos[cut:]), delta, L, tk, tc, err)
+    torch.cuda.synchronize()
+    assert err.item() == (1 if n > 10 else 0)
+    uniq, cnt = oracle.histogram(oracle.keys(pos, delta, L))
+    keys = tk.cpu().numpy().view(np.uint64)
+    full = keys != np.uint64(2 ** 64 - 1)
+    order = np.argsort(keys[full])
+    assert np.array_equal(keys[full][order], uniq) and np.array_equal(tc.cpu().numpy()[full][order], cnt)
+    for k in (1, 100, 5000, len(uniq) + 5):
+        gk, gc = csk.table_topk(tk, tc, k)
+        rk, rc = oracle.topk_exact(uniq, cnt, k)
+        assert gk.cpu().numpy().view(np.uint64).tolist() == rk.tolist()
+        assert gc.cpu().numpy().tolist() == rc.tolist()
+
+
+def test_exact_counts_flag_a_full_table():
+    import torch
+    pos = clustered(5000, 50.0, 2)
+    tk, tc = csk.new_table(16)
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    csk.exact_counts(dev(pos), 0.25, 50.0, tk, tc, err)
+    torch.cuda.synchronize()
+    assert err.item() == 2 and (tk.cpu().numpy() != -1).all()
+
+
+def test_cell_list_and_labels_match_reference():
+    import torch
+    rng = np.random.default_rng(5)
+    counts = np.where(rng.random(10 ** 6) < 0.02, rng.integers(1, 9, 10 ** 6), 0).astype(np.uint32)
+    cd = dev(counts.view(np.int32))
+    for mc in (1, 3, 9):
+        got = csk.cell_list(cd, mc).cpu().numpy()
+        assert np.array_equal(got, ref.cell_list(counts, mc))
+    part = csk.cell_list(cd, 1, cap=1000).cpu().numpy()          # only the first cap are written
+    assert np.array_equal(part, ref.cell_list(counts, 1)[:1000])
+    assert csk.cell_list(dev(np.zeros(1000, np.int32)), 1).numel() == 0
+    # labels of coarse cells (mesh 100, factor 4 of the fine mesh 400) from fine keys
+    cells = ref.cell_list(counts, 1)
+    fine = rng.choice(400 ** 3, 3000, replace=False).astype(np.int64)
+    fine[:50] = ref.parents(fine[:50], 400, 4) * 0     # a few keys share the first parent
+    got = csk.cell_labels(dev(cells), dev(fine), 0.25, 100.0, 4).cpu().numpy()
+    assert np.array_equal(got, ref.labels(cells, fine.astype(np.uint64), 400, 4))
+    assert got.sum() > 0
+
+
+@pytest.mark.parametrize("A", [1, 100, 512, 5003])
+def test_route_admit_matches_reference(A):
+    rng = np.random.default_rng(A)
+    m = 5000
+    cells = rng.choice(2 ** 40, m, replace=False).astype(np.int64)
+    z = (rng.integers(-400, 400, m) / 64).astype(np.float32)    # many exact ties
+    z[:10] = 0.0
+    z[10:20] = -0.0
+    z[20] = np.float32(3e38)
+    z[21] = np.float32(-3e38)
+    got = csk.route_admit(dev(cells), dev(z), A).cpu().numpy()
+    assert np.array_equal(got, ref.admit(cells, z, A))
+
+
+@pytest.mark.parametrize("n,na,factor", [(1, 3, 4), (8191, 0, 4), (8193, 17, 2), (2_000_000, 512, 4)])
+def test_route_split_edges_match_oracle(n, na, factor):
+    # ragged tiles, no admitted cells, another factor, and the largest admitted set
+    import torch
+    L, delta = 50.0, 0.25
+    G = 200
+    pos = clustered(n, L, 20 + na, frac=0.8, sigma=0.2)
+    Gc = G // factor
+    ck = ref.parents(oracle.keys(pos, delta, L), G, factor)
+    cu, cc = np.unique(ck, return_counts=True)
+    admitted = np.sort(cu[np.argsort(-cc, kind="stable")[:na]]).astype(np.int64)
+    slots = 1 << 16
+    tkeys, tcounts = csk.new_table(slots)
+    rest = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    rcount = torch.zeros(1, dtype=torch.int64, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    csk.route_split(dev(pos), delta, L, factor, dev(admitted), tkeys, tcounts, rest, rcount, err)
+    torch.cuda.synchronize()
+    assert err.item() == 0
+    tk_ref, tc_ref, rest_ref = ref.route(pos, delta, L, factor, admitted.astype(np.uint64))
+    tk = tkeys.cpu().numpy().view(np.uint64)
+    full = tk != np.uint64(0xFFFFFFFFFFFFFFFF)
+    order = np.argsort(tk[full])
+    assert np.array_equal(tk[full][order], tk_ref)
+    assert np.array_equal(tcounts.cpu().numpy()[full][order], tc_ref)
+    assert int(rcount.item()) == len(rest_ref)
+    assert np.array_equal(rest[:len(rest_ref)].cpu().numpy(), rest_ref)
