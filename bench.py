@@ -27,9 +27,9 @@ BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
 # rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) scaled by a 1 GiB device copy
 # (profiles/update_kernels_plummer_2e30.md).  Reported only while the kernel sources hash
 # to what was profiled; any change to them makes `traffic` null until measured again.
-TRAFFIC = {"bytes": 46_066_504_752, "particles": 1 << 30,
-           "sources_sha256": "9bd6d711d860ab752b618df64201337f39072ed6bae98cf8892fec51aa59b167"}
-TRAFFIC_SOURCES = ["csk_kernels.hip", "csk_device.h", "csk_internal.h", "csk_api.hip"]
+TRAFFIC = {"bytes": 46_061_779_751, "particles": 1 << 30,
+           "sources_sha256": "c416c2d5883090edaf16bc9808a16e7a821cc61af3624cf2ded11c159af83801"}
+TRAFFIC_SOURCES = ["csk_update.hip", "csk_kernel_util.h", "csk_device.h", "csk_internal.h"]
 
 
 def sources_sha256():

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcsk.so")
-SOURCES = ["csk_api.hip", "csk_kernels.hip", "csk_router.hip"]
+SOURCES = ["csk_api.hip", "csk_update.hip", "csk_kernels.hip", "csk_router.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -337,7 +337,7 @@ csk_status csk_sketch_update(csk_sketch* s, const float* pos, uint64_t n, double
     const uint64_t m = (n - off < piece_max) ? n - off : piece_max;
     const float* p = pos + 3 * off;
     BinPlan plan;
-    const uint64_t max_wg = s->upd_max_wg ? s->upd_max_wg : ((s->d <= (uint32_t)kTabLdsRows) ? 256u : 512u);
+    const uint64_t max_wg = bin_wg_cap(s->d, s->upd_max_wg);
     if (s->upd_mode == CSK_UPDATE_DIRECT || !plan_bin_wg(m, s->d, s->w, max_wg, plan)) {
       CSK_HIP(launch_update_direct(p, m, mesh, t, s->M, s->err(), st), "update (direct)");
       continue;

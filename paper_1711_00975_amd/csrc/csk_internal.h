@@ -71,6 +71,7 @@ constexpr uint32_t kMaxLds = 160 * 1024;
 bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& plan);
 // The same with at most max_wg workgroups (>= 1) for the bin kernel.
 bool plan_bin_wg(uint64_t n, uint32_t d, uint32_t w, uint64_t max_wg, BinPlan& plan);
+uint32_t bin_wg_cap(uint32_t d, uint32_t requested);
 
 // Everything the bin kernel needs for one sketch and one stream.
 struct BinArgs {

@@ -1,0 +1,110 @@
+// csk_kernel_util.h — device helpers shared by the update kernels and the query,
+// collect and top-k kernels (wave scans, appends, tabulated estimates, table staging).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "csk_internal.h"
+
+namespace csk {
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= (uint32_t)o) v += t;
+  }
+  return v;
+}
+
+// Wave-aggregated append: every lane of the wave must call it.  Returns the slot of a
+// lane with pred set.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return 0;
+  const uint32_t lane = lane_id();
+  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = __shfl(base, (int)leader, 64);
+  const uint64_t below = (lane == 0) ? 0ull : (mask & ((~0ull) >> (64 - lane)));
+  return base + (uint32_t)__popcll(below);
+}
+
+// Exclusive scan of in[0..n) into out[0..n) by a block of NT threads; total -> *total.
+// Contains barriers: every thread of the block must call it.
+template <int NT>
+__device__ __forceinline__ void block_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t n,
+                                                     uint32_t* wsum, uint32_t* total) {
+  constexpr int NW = NT / 64;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (n + NT - 1) / NT;
+  const uint32_t lo = min(n, tid * per), hi = min(n, lo + per);
+  uint32_t s = 0;
+  for (uint32_t i = lo; i < hi; ++i) s += in[i];
+  const uint32_t incl = wave_incl_scan(s);
+  const uint32_t wave = tid >> 6;
+  if (lane_id() == 63) wsum[wave] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t t = wsum[w];
+      wsum[w] = acc;
+      acc += t;
+    }
+    *total = acc;
+  }
+  __syncthreads();
+  uint32_t run = wsum[wave] + incl - s;
+  for (uint32_t i = lo; i < hi; ++i) {
+    out[i] = run;
+    run += in[i];
+  }
+  __syncthreads();
+}
+
+// Signed estimate of one row: M * sign (Count-Min: M), modulo 2^32.
+__device__ __forceinline__ int32_t row_estimate(const uint32_t* tab_r, const int32_t* __restrict__ Mr,
+                                                uint32_t w, uint32_t cm, uint64_t key) {
+  const uint32_t h = row_hash(tab_r, key);
+  const uint32_t c = (uint32_t)Mr[bucket_of(h, w)];
+  const uint32_t neg = (h >> 31) & (cm ^ 1u);
+  return (int32_t)(neg ? (0u - c) : c);
+}
+
+template <int MAXD>
+__device__ __forceinline__ int32_t estimate_key(const uint32_t* tabs, const int32_t* __restrict__ M,
+                                                uint32_t d, uint32_t w, uint32_t cm, uint64_t key) {
+  int32_t v[MAXD];
+#pragma unroll
+  for (int r = 0; r < MAXD; ++r) {
+    v[r] = ((uint32_t)r < d) ? row_estimate(tabs + r * kTableWords, M + (uint64_t)r * w, w, cm, key) : 0;
+  }
+  if (cm) {
+    int32_t mn = v[0];
+#pragma unroll
+    for (int r = 1; r < MAXD; ++r)
+      if ((uint32_t)r < d) mn = min(mn, v[r]);
+    return mn;
+  }
+  return lower_median<MAXD>(v, (int)d);
+}
+
+// Stage the tables of the first `rows` rows in LDS.
+__device__ __forceinline__ void load_tables(uint32_t* dst, const uint32_t* __restrict__ src, uint32_t rows) {
+  for (uint32_t i = threadIdx.x; i < rows * kTableWords; i += blockDim.x) dst[i] = src[i];
+}
+
+static inline uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t max_blocks) {
+  uint64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return (uint32_t)b;
+}
+
+}  // namespace csk
