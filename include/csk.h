@@ -222,9 +222,11 @@ csk_status csk_batch_destroy(csk_batch *b);
  * (device, G_c^3 uint32, G_c = round(L / delta_c)).  Particle g is in the sample when
  * the first word of Philox4x32-10 at counter (g mod 2^32, g / 2^32, 4, 0) under key
  * (seed mod 2^32, seed / 2^32) is below `threshold` (1 %: 42949672).  Out-of-domain
- * particles are skipped.  pos (device). */
+ * particles are skipped.  pos (device).  bitmap (device, ceil(G_c^3 / 32) words, or NULL):
+ * a cell's bit (word key / 32, bit key mod 32) is set when its count leaves 0, so that
+ * csk_cell_list and csk_cells_clear touch only the sampled cells. */
 csk_status csk_sample_counts(const float *pos, uint64_t n, uint64_t index0, double delta_c, double L, uint64_t seed,
-                             uint32_t threshold, uint32_t *counts, void *stream);
+                             uint32_t threshold, uint32_t *counts, uint32_t *bitmap, void *stream);
 
 /* feat[j][q] = log1pf(counts[neighbour q of cells[j]]) for q < 27: the coarse cell and its
  * 26 periodic neighbours in (dx, dy, dz) lexicographic order over {-1, 0, 1}^3;
@@ -295,9 +297,14 @@ csk_status csk_table_topk(const uint64_t *table_keys, const uint32_t *table_coun
 
 /* The cells j < ncells with counts[j] >= min_count (device), in ascending order, into
  * cells (device, the first cap of them); *total (host) = how many there are.  Lists the
- * coarse cells the router scores.  Allocates scratch and synchronizes. */
-csk_status csk_cell_list(const uint32_t *counts, uint64_t ncells, uint32_t min_count, uint64_t *cells, uint64_t cap,
-                         uint64_t *total, void *stream);
+ * coarse cells the router scores.  With the bitmap of csk_sample_counts (device, or NULL)
+ * only the cells whose bit is set are examined (every cell with a nonzero count has
+ * one).  Allocates scratch and synchronizes. */
+csk_status csk_cell_list(const uint32_t *counts, uint64_t ncells, uint32_t min_count, const uint32_t *bitmap,
+                         uint64_t *cells, uint64_t cap, uint64_t *total, void *stream);
+/* Zero counts[j] for every cell j whose bit is set, then the bitmap (both device): the
+ * state of csk_sample_counts back to empty without writing all G_c^3 counters. */
+csk_status csk_cells_clear(uint32_t *counts, uint32_t *bitmap, uint64_t ncells, void *stream);
 
 /* Router training labels: labels[j] (device float) = 1 if coarse cell cells[j] (mesh
  * G / factor) is the coarse parent of one of the nk <= 2^17 fine keys (device, mesh of

@@ -39,7 +39,8 @@ EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "cs
            "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_update", "csk_batch_destroy",
            "csk_sample_counts", "csk_cell_features", "csk_mlp_create", "csk_mlp_destroy", "csk_mlp_params",
            "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_gemm_bf16", "csk_route_split", "csk_route_split_workspace", "csk_topk_with_table",
-           "csk_exact_counts", "csk_table_topk", "csk_cell_list", "csk_cell_labels", "csk_route_admit",
+           "csk_exact_counts", "csk_table_topk", "csk_cell_list", "csk_cells_clear", "csk_cell_labels",
+           "csk_route_admit",
            "csk_get_counters", "csk_set_counters", "csk_reset", "csk_check", "csk_device_bytes",
            "csk_last_error"]
 
@@ -82,7 +83,7 @@ def load_library(path: str = LIB_PATH):
         "csk_batch_create": [PP, P, P, u32, f64, f64, u32],
         "csk_batch_update": [P, P, P, P],
         "csk_batch_destroy": [P],
-        "csk_sample_counts": [P, u64, u64, f64, f64, u64, u32, P, P],
+        "csk_sample_counts": [P, u64, u64, f64, f64, u64, u32, P, P, P],
         "csk_cell_features": [P, f64, f64, P, u64, P, P],
         "csk_mlp_create": [PP, u64, u32],
         "csk_mlp_destroy": [P],
@@ -96,7 +97,8 @@ def load_library(path: str = LIB_PATH):
         "csk_topk_with_table": [P, P, P, u32, u32, P, P, C.POINTER(C.c_uint32), P],
         "csk_exact_counts": [P, u64, f64, f64, P, P, u32, P, P],
         "csk_table_topk": [P, P, u32, u32, P, P, C.POINTER(C.c_uint32), P],
-        "csk_cell_list": [P, u64, u32, P, u64, C.POINTER(C.c_uint64), P],
+        "csk_cell_list": [P, u64, u32, P, P, u64, C.POINTER(C.c_uint64), P],
+        "csk_cells_clear": [P, P, u64, P],
         "csk_cell_labels": [P, u64, P, u32, f64, f64, u32, P, P],
         "csk_route_admit": [P, P, u64, u32, P, C.POINTER(C.c_uint32), P],
         "csk_get_counters": [P, P, P],
@@ -396,11 +398,13 @@ N_PARAMS = 6337
 FEAT = 32
 
 
-def sample_counts(pos, delta_c, L, seed, counts, index0=0, threshold=SAMPLE_THRESHOLD, stream=None):
-    """Add the 1 % sample of pos (particles index0 ..) to counts (device uint32 [G_c^3] as int32)."""
+def sample_counts(pos, delta_c, L, seed, counts, index0=0, threshold=SAMPLE_THRESHOLD, stream=None, bitmap=None):
+    """Add the 1 % sample of pos (particles index0 ..) to counts (device uint32 [G_c^3] as int32);
+    bitmap (device int32 [ceil(G_c^3 / 32)]) marks the cells first touched."""
     import torch
     _check(load_library().csk_sample_counts(_dev(pos, torch.float32, 3) if pos.shape[0] else None, pos.shape[0],
                                             index0, delta_c, L, seed, threshold, _dev(counts, torch.int32),
+                                            _dev(bitmap, torch.int32) if bitmap is not None else None,
                                             _stream(stream)))
 
 
@@ -546,19 +550,37 @@ def table_topk(table_keys, table_counts, k, stream=None):
     return keys[:kout.value], counts[:kout.value]
 
 
-def cell_list(counts, min_count=1, cap=None, stream=None):
-    """Ascending device int64 list of the cells with counts >= min_count."""
+def cell_list(counts, min_count=1, cap=None, stream=None, out=None, bitmap=None):
+    """Ascending device int64 list of the cells with counts >= min_count (only the cells
+    marked in `bitmap` are examined when it is given).  With `out` (a device int64 buffer)
+    the list is written there and a larger buffer is made only when it is too small;
+    otherwise cap (default: count first) bounds the list."""
     import torch
     total = C.c_uint64(0)
     lib = load_library()
-    if cap is None:
-        _check(lib.csk_cell_list(_dev(counts, torch.int32), counts.numel(), min_count, None, 0, C.byref(total),
-                                 _stream(stream)))
-        cap = total.value
-    cells = torch.empty(max(cap, 1), dtype=torch.int64, device=counts.device)
-    _check(lib.csk_cell_list(_dev(counts, torch.int32), counts.numel(), min_count, _dev(cells, torch.int64), cap,
+    bm = _dev(bitmap, torch.int32) if bitmap is not None else None
+    grow = out is not None
+    if out is None:
+        if cap is None:
+            _check(lib.csk_cell_list(_dev(counts, torch.int32), counts.numel(), min_count, bm, None, 0,
+                                     C.byref(total), _stream(stream)))
+            cap = total.value
+        out = torch.empty(max(cap, 1), dtype=torch.int64, device=counts.device)
+    else:
+        cap = out.numel()
+    _check(lib.csk_cell_list(_dev(counts, torch.int32), counts.numel(), min_count, bm, _dev(out, torch.int64), cap,
                              C.byref(total), _stream(stream)))
-    return cells[:min(cap, total.value)]
+    if grow and total.value > cap:
+        out = torch.empty(total.value, dtype=torch.int64, device=counts.device)
+        return cell_list(counts, min_count, stream=stream, out=out, bitmap=bitmap)
+    return out[:min(cap, total.value)]
+
+
+def cells_clear(counts, bitmap, stream=None):
+    """Zero the counts of the cells marked in bitmap, then the bitmap."""
+    import torch
+    _check(load_library().csk_cells_clear(_dev(counts, torch.int32), _dev(bitmap, torch.int32), counts.numel(),
+                                          _stream(stream)))
 
 
 def cell_labels(cells, fine_keys, delta, L, factor, stream=None):

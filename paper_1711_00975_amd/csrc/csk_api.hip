@@ -765,12 +765,14 @@ struct csk_mlp {
   float* z = nullptr;     // [max_batch]
   float* dz = nullptr;
   float* loss = nullptr;  // [1]
+  float* part = nullptr;  // split-k partial products of the weight gradients
+  uint64_t part_floats = 0;
 };
 
 namespace {
 
 void mlp_free(csk_mlp* m) {
-  void* ptrs[] = {m->p, m->g, m->m1, m->m2, m->H1, m->H2, m->dA2, m->dA1, m->z, m->dz, m->loss};
+  void* ptrs[] = {m->p, m->g, m->m1, m->m2, m->H1, m->H2, m->dA2, m->dA1, m->z, m->dz, m->loss, m->part};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -819,6 +821,8 @@ csk_status csk_mlp_create(csk_mlp** out, uint64_t seed, uint32_t max_batch) {
   if (e == hipSuccess) e = bmalloc(&m->z, max_batch);
   if (e == hipSuccess) e = bmalloc(&m->dz, max_batch);
   if (e == hipSuccess) e = bmalloc(&m->loss, 1);
+  m->part_floats = ((uint64_t)max_batch + kSplitK - 1) / kSplitK * kHidden * kHidden;
+  if (e == hipSuccess) e = bmalloc(&m->part, m->part_floats);
   if (e == hipSuccess) e = hipMemcpy(m->p, P.data(), kParams * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->m1, kParams, 0u, nullptr);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->m2, kParams, 0u, nullptr);
@@ -885,7 +889,7 @@ csk_status csk_mlp_train_step(csk_mlp* m, const float* x, const float* y, uint32
   // second layer: dA2 = (dz w3^T) masked by ReLU; dW2 = dA2^T H1; db2 = colsum dA2
   CSK_HIP(launch_head_back(m->dz, m->H2, P + kOffW3, n, m->dA2, st), "mlp_train_step");
   CSK_HIP(launch_gemm_bf16(kHidden, kHidden, n, m->dA2, 1, kHidden, m->H1, kHidden, 1, G + kOffW2, kHidden, 1, 0.0f,
-                           st),
+                           st, m->part, m->part_floats),
           "mlp_train_step");
   CSK_HIP(launch_colsum(m->dA2, n, kHidden, kHidden, nullptr, G + kOffB2, st), "mlp_train_step");
   // first layer: dA1 = (dA2 W2) masked by ReLU; dW1 = dA1^T X; db1 = colsum dA1
@@ -894,7 +898,7 @@ csk_status csk_mlp_train_step(csk_mlp* m, const float* x, const float* y, uint32
           "mlp_train_step");
   CSK_HIP(launch_relu_back(m->dA1, m->H1, (uint64_t)n * kHidden, st), "mlp_train_step");
   CSK_HIP(launch_gemm_bf16(kHidden, kFeatPad, n, m->dA1, 1, kHidden, x, kFeatPad, 1, G + kOffW1, kFeatPad, 1, 0.0f,
-                           st),
+                           st, m->part, m->part_floats),
           "mlp_train_step");
   CSK_HIP(launch_colsum(m->dA1, n, kHidden, kHidden, nullptr, G + kOffB1, st), "mlp_train_step");
   // Adam
@@ -918,13 +922,14 @@ csk_status csk_gemm_bf16(uint32_t M, uint32_t N, uint32_t K, const float* A, uin
 }
 
 csk_status csk_sample_counts(const float* pos, uint64_t n, uint64_t index0, double delta_c, double L, uint64_t seed,
-                             uint32_t threshold, uint32_t* counts, void* stream) {
+                             uint32_t threshold, uint32_t* counts, uint32_t* bitmap, void* stream) {
   Mesh coarse;
   csk_status rc = check_mesh(nullptr, delta_c, L, &coarse);
   if (rc != CSK_OK) return rc;
   if (n > 0 && (pos == nullptr || counts == nullptr)) return fail(CSK_E_INVALID, "sample_counts: NULL pointer");
   if (n == 0) return CSK_OK;
-  CSK_HIP(launch_sample_counts(pos, n, index0, seed, threshold, coarse, counts, (hipStream_t)stream), "sample_counts");
+  CSK_HIP(launch_sample_counts(pos, n, index0, seed, threshold, coarse, counts, bitmap, (hipStream_t)stream),
+          "sample_counts");
   return CSK_OK;
 }
 
@@ -1048,8 +1053,8 @@ csk_status csk_table_topk(const uint64_t* table_keys, const uint32_t* table_coun
   return CSK_OK;
 }
 
-csk_status csk_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t min_count, uint64_t* cells, uint64_t cap,
-                         uint64_t* total, void* stream) {
+csk_status csk_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t min_count, const uint32_t* bitmap,
+                         uint64_t* cells, uint64_t cap, uint64_t* total, void* stream) {
   if (total == nullptr) return fail(CSK_E_INVALID, "cell_list: total is NULL");
   *total = 0;
   if (ncells > 0 && (counts == nullptr || (cap > 0 && cells == nullptr)))
@@ -1057,17 +1062,24 @@ csk_status csk_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t min_c
   if (ncells == 0) return CSK_OK;
   hipStream_t st = (hipStream_t)stream;
   uint64_t chunk = 0;
-  const uint32_t nb = cell_list_blocks(ncells, &chunk);
+  const uint32_t nb = cell_list_blocks(ncells, &chunk);   // at least the bitmap path's count
   CallScratch cs;
   uint64_t* blocks = nullptr;
   unsigned long long* dtotal = nullptr;
   CSK_HIP(cs.get(&blocks, nb), "cell_list: scratch");
   CSK_HIP(cs.get(&dtotal, 1), "cell_list: scratch");
-  CSK_HIP(launch_cell_list(counts, ncells, min_count, blocks, cells, cap, dtotal, st), "cell_list");
+  CSK_HIP(launch_cell_list(counts, ncells, min_count, bitmap, blocks, cells, cap, dtotal, st), "cell_list");
   unsigned long long h = 0;
   CSK_HIP(hipMemcpyAsync(&h, dtotal, sizeof(h), hipMemcpyDeviceToHost, st), "cell_list");
   CSK_HIP(hipStreamSynchronize(st), "cell_list");
   *total = h;
+  return CSK_OK;
+}
+
+csk_status csk_cells_clear(uint32_t* counts, uint32_t* bitmap, uint64_t ncells, void* stream) {
+  if (ncells > 0 && (counts == nullptr || bitmap == nullptr)) return fail(CSK_E_INVALID, "cells_clear: NULL pointer");
+  if (ncells == 0) return CSK_OK;
+  CSK_HIP(launch_bitmap_clear(bitmap, ncells, counts, (hipStream_t)stream), "cells_clear");
   return CSK_OK;
 }
 

@@ -19,12 +19,16 @@ constexpr uint32_t kOffW1 = 0, kOffB1 = 2048, kOffW2 = 2112, kOffB2 = 6208, kOff
 constexpr uint32_t kParams = 6337;
 
 hipError_t launch_sample_counts(const float* pos, uint64_t n, uint64_t index0, uint64_t seed, uint32_t threshold,
-                                const Mesh& coarse, uint32_t* counts, hipStream_t s);
+                                const Mesh& coarse, uint32_t* counts, uint32_t* bitmap, hipStream_t s);
 hipError_t launch_features(const uint32_t* counts, uint32_t Gc, const uint64_t* cells, uint64_t m, float* feat,
                            hipStream_t s);
+// C = beta C + A B with bf16 operands and fp32 sums.  With `partial` (device scratch of
+// partial_floats floats), products with k >= 2 kSplitK and fewer than 256 tiles are split
+// over k in chunks of about kSplitK and the chunks summed in a fixed order.
+constexpr uint32_t kSplitK = 256;
 hipError_t launch_gemm_bf16(uint32_t M, uint32_t N, uint32_t K, const float* A, uint64_t sai, uint64_t sak,
                             const float* B, uint64_t sbk, uint64_t sbj, float* C, uint64_t sci, uint64_t scj,
-                            float beta, hipStream_t s);
+                            float beta, hipStream_t s, float* partial = nullptr, uint64_t partial_floats = 0);
 hipError_t launch_bias_act(float* Y, uint32_t M, uint32_t N, const float* bias, bool relu, hipStream_t s);
 hipError_t launch_head(const float* H2, uint32_t M, const float* w3, const float* b3, float* z, const float* y,
                        float* dz, float* loss, hipStream_t s);
@@ -33,15 +37,16 @@ hipError_t launch_relu_back(float* dA, const float* H, uint64_t total, hipStream
 hipError_t launch_colsum(const float* X, uint32_t M, uint32_t N, uint32_t ld, const float* w, float* out, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, uint32_t n, float lr_t, float b1, float b2,
                        float eps, hipStream_t s);
-// The routing split: workgroups of kSplitThreads, kSplitPPT particles per thread per
-// tile, at most kSplitBlocks workgroups, at most kSplitMaxChildren admitted children (the
-// LDS counters of one workgroup).
+// The routing split: workgroups of kSplitThreads, kSplitPPT particles per lane per wave
+// tile, at most kSplitMaxWaves waves (each with one contiguous range of the stream), at
+// most kSplitMaxChildren admitted children (the LDS counters of one workgroup).
 constexpr int kSplitThreads = 1024;
-constexpr int kSplitPPT = 8;
-constexpr uint64_t kSplitTile = (uint64_t)kSplitThreads * kSplitPPT;
-constexpr uint32_t kSplitBlocks = 256;
+constexpr int kSplitPPT = 8;        // count pass
+constexpr int kSplitWritePPT = 4;   // write pass (divides kSplitPPT: same wave ranges)
+constexpr uint64_t kSplitWaveTile = 64ull * kSplitPPT;
+constexpr uint32_t kSplitMaxWaves = 4096;
 constexpr uint32_t kSplitMaxChildren = 32768;
-uint32_t split_blocks(uint64_t n, uint64_t* chunk);
+uint32_t split_waves(uint64_t n, uint64_t* wchunk);
 uint64_t split_workspace_bytes(uint32_t na, uint32_t factor);
 hipError_t launch_route_split(const float* pos, uint64_t n, const Mesh& mesh, uint32_t factor, const uint64_t* admitted,
                               uint32_t na, uint64_t* tkeys, uint32_t* tcounts, uint32_t tmask, float* rest_pos,
@@ -52,8 +57,10 @@ constexpr uint32_t kCellListBlocks = 65536;   // workgroups of the ordered cell 
 hipError_t launch_exact_count(const float* pos, uint64_t n, const Mesh& mesh, uint64_t* tkeys, uint32_t* tcounts,
                               uint32_t tmask, uint32_t* err, hipStream_t s);
 uint32_t cell_list_blocks(uint64_t ncells, uint64_t* chunk);
-hipError_t launch_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t min_count, uint64_t* block_scratch,
-                            uint64_t* cells, uint64_t cap, unsigned long long* total, hipStream_t s);
+hipError_t launch_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t min_count, const uint32_t* bitmap,
+                            uint64_t* block_scratch, uint64_t* cells, uint64_t cap, unsigned long long* total,
+                            hipStream_t s);
+hipError_t launch_bitmap_clear(uint32_t* bitmap, uint64_t ncells, uint32_t* counts, hipStream_t s);
 hipError_t launch_parents_sorted(const uint64_t* keys, uint32_t n, uint64_t G, uint32_t factor, uint64_t* tmp,
                                  uint64_t* out, hipStream_t s);
 hipError_t launch_rank_sort(const uint64_t* in, uint32_t n, uint64_t* out, hipStream_t s);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "csk_kernel_util.h"
 #include "csk_router.h"
 
 namespace csk {
@@ -29,10 +30,12 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 }
 
 // Particle index0 + i is in the sample when the first Philox word of counter
-// (index lo, index hi, kSampleStream, 0) under the seed is below `threshold`.
+// (index lo, index hi, kSampleStream, 0) under the seed is below `threshold`.  With a
+// bitmap, a cell's bit is set when its count leaves 0.
 __global__ __launch_bounds__(256) void sample_counts_kernel(const float* __restrict__ pos, uint64_t n, uint64_t index0,
                                                             uint64_t seed, uint32_t threshold, Mesh coarse,
-                                                            uint32_t* __restrict__ counts) {
+                                                            uint32_t* __restrict__ counts,
+                                                            uint32_t* __restrict__ bitmap) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const uint64_t g = index0 + i;
@@ -40,7 +43,10 @@ __global__ __launch_bounds__(256) void sample_counts_kernel(const float* __restr
     philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
     if (c[0] >= threshold) continue;
     uint64_t key;
-    if (cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], coarse, key)) atomicAdd(&counts[key], 1u);
+    if (cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], coarse, key)) {
+      const uint32_t old = atomicAdd(&counts[key], 1u);
+      if (bitmap != nullptr && old == 0) atomicOr(&bitmap[key >> 5], 1u << (key & 31u));   // first touch
+    }
   }
 }
 
@@ -80,12 +86,33 @@ __device__ __forceinline__ short to_bf16(float x) {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// C[i][j] = beta * C[i][j] + sum_k A(i, k) * B(k, j) for i < M, j < N, with
-// A(i, k) = A[i * sai + k * sak], B(k, j) = B[k * sbk + j * sbj] read as fp32 and rounded
-// to bf16, products accumulated in fp32 by v_mfma_f32_16x16x16_bf16.  One wave per 16x16
-// tile of C; elements outside the matrices read as 0 and are not written.
+// Partial product of one 16x16 tile of C over k in [k_lo, k_hi): A(i, k) = A[i * sai + k * sak],
+// B(k, j) = B[k * sbk + j * sbj] read as fp32 and rounded to bf16, products accumulated in
+// fp32 by v_mfma_f32_16x16x16_bf16; elements outside the matrices read as 0.
 // Lane l of the MFMA holds A rows l % 16, k = 4 (l / 16) .. +3; B columns l % 16 at the
 // same k; the result rows 4 (l / 16) .. +3 of column l % 16.
+__device__ __forceinline__ f32x4 gemm_tile(uint32_t M, uint32_t N, uint32_t k_lo, uint32_t k_hi,
+                                           const float* __restrict__ A, uint64_t sai, uint64_t sak,
+                                           const float* __restrict__ B, uint64_t sbk, uint64_t sbj, uint32_t i0,
+                                           uint32_t j0, uint32_t lane) {
+  const uint32_t r = lane & 15u, kq = (lane >> 4) * 4;
+  const uint32_t ia = i0 + r, jb = j0 + r;
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (uint32_t k0 = k_lo; k0 < k_hi; k0 += 16) {
+    bf16x4 a, b;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t k = k0 + kq + (uint32_t)e;
+      a[e] = to_bf16((ia < M && k < k_hi) ? A[ia * sai + k * sak] : 0.0f);
+      b[e] = to_bf16((jb < N && k < k_hi) ? B[k * sbk + jb * sbj] : 0.0f);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// C[i][j] = beta * C[i][j] + sum_k A(i, k) * B(k, j) for i < M, j < N.  One wave per 16x16
+// tile of C; elements outside C are not written.
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(uint32_t M, uint32_t N, uint32_t K, const float* __restrict__ A,
                                                         uint64_t sai, uint64_t sak, const float* __restrict__ B,
                                                         uint64_t sbk, uint64_t sbj, float* __restrict__ C,
@@ -96,19 +123,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(uint32_t M, uint32_t N, 
   const uint64_t tiles = (uint64_t)((M + 15) / 16) * tiles_n;
   if (tile >= tiles) return;   // whole waves only: every lane of a wave shares its tile
   const uint32_t i0 = (uint32_t)(tile / tiles_n) * 16, j0 = (uint32_t)(tile % tiles_n) * 16;
+  const f32x4 acc = gemm_tile(M, N, 0, K, A, sai, sak, B, sbk, sbj, i0, j0, lane);
   const uint32_t r = lane & 15u, kq = (lane >> 4) * 4;
-  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (uint32_t k0 = 0; k0 < K; k0 += 16) {
-    bf16x4 a, b;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t k = k0 + kq + (uint32_t)e;
-      const uint32_t ia = i0 + r, jb = j0 + r;
-      a[e] = to_bf16((ia < M && k < K) ? A[ia * sai + k * sak] : 0.0f);
-      b[e] = to_bf16((jb < N && k < K) ? B[k * sbk + jb * sbj] : 0.0f);
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-  }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const uint32_t i = i0 + kq + (uint32_t)e, j = j0 + r;
@@ -116,6 +132,43 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(uint32_t M, uint32_t N, 
       float* c = C + i * sci + j * scj;
       *c = (beta != 0.0f ? beta * *c : 0.0f) + acc[e];
     }
+  }
+}
+
+// Split over k for products with a long k and few tiles (the weight gradients, k = batch
+// rows): chunk y = blockIdx.y covers k in [y kc, (y + 1) kc) and writes its partial tile to
+// P[y][i][j] (M x N row-major); splitk_reduce_kernel sums the chunks in order.
+__global__ __launch_bounds__(256) void gemm_bf16_splitk_kernel(uint32_t M, uint32_t N, uint32_t K, uint32_t kc,
+                                                               const float* __restrict__ A, uint64_t sai, uint64_t sak,
+                                                               const float* __restrict__ B, uint64_t sbk, uint64_t sbj,
+                                                               float* __restrict__ P) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t tiles_n = (N + 15) / 16;
+  const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const uint64_t tiles = (uint64_t)((M + 15) / 16) * tiles_n;
+  if (tile >= tiles) return;
+  const uint32_t i0 = (uint32_t)(tile / tiles_n) * 16, j0 = (uint32_t)(tile % tiles_n) * 16;
+  const uint32_t k_lo = blockIdx.y * kc, k_hi = (k_lo + kc < K) ? k_lo + kc : K;
+  const f32x4 acc = gemm_tile(M, N, k_lo, k_hi, A, sai, sak, B, sbk, sbj, i0, j0, lane);
+  float* out = P + (uint64_t)blockIdx.y * M * N;
+  const uint32_t r = lane & 15u, kq = (lane >> 4) * 4;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t i = i0 + kq + (uint32_t)e, j = j0 + r;
+    if (i < M && j < N) out[(uint64_t)i * N + j] = acc[e];
+  }
+}
+
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ P, uint32_t nsplit, uint32_t M,
+                                                            uint32_t N, float* __restrict__ C, uint64_t sci,
+                                                            uint64_t scj, float beta) {
+  const uint64_t total = (uint64_t)M * N;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (uint32_t y = 0; y < nsplit; ++y) s += P[(uint64_t)y * total + t];
+    const uint32_t i = (uint32_t)(t / N), j = (uint32_t)(t % N);
+    float* c = C + i * sci + j * scj;
+    *c = (beta != 0.0f ? beta * *c : 0.0f) + s;
   }
 }
 
@@ -202,51 +255,121 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, const 
 
 // ------------------------------------------------------------------ routing
 
-// The split runs in two passes over the same contiguous chunks of the stream, one chunk
-// per workgroup: pass 1 counts each chunk's rest particles, a scan turns the counts into
-// output offsets, pass 2 writes the rest in stream order and counts the admitted
-// particles in a workgroup-private LDS array of the admitted cells' children.  The
-// per-workgroup arrays are summed and inserted into the exact table once.
+// The split runs in two passes over the same contiguous ranges of the stream, one range
+// per wave: pass 1 counts each range's rest particles, a scan turns the counts into output
+// offsets, pass 2 writes each range's rest in stream order (a wave ballot orders the
+// appends, no workgroup barrier) and counts the admitted particles in a workgroup-private
+// LDS array of the admitted cells' children.  The per-workgroup arrays are summed and
+// inserted into the exact table once.  Admitted cells are found through an LDS hash of
+// their keys (one probe or two), not a search.
 
 struct SplitArgs {
   const float* pos;
   uint64_t n;
   Mesh mesh;
   uint32_t factor;      // fine cells per coarse cell along an axis
+  uint32_t fmagic;      // ceil(2^32 / factor): i / factor = umulhi(i, fmagic) for i < 2^16
   uint32_t f3;          // factor^3
   const uint64_t* admitted;
   uint32_t na;
-  uint64_t chunk;       // particles per workgroup (a multiple of kSplitTile)
+  uint32_t nwaves;      // waves with a range
+  uint64_t wchunk;      // particles per wave (a multiple of kSplitWaveTile)
 };
 
-// Index of the admitted coarse parent of (x, y, z) in the sorted list, or -1; -2 outside
-// the domain.  child = position of the fine cell inside its coarse cell.
-__device__ __forceinline__ int32_t split_class(float x, float y, float z, const SplitArgs& a,
-                                               const uint64_t* __restrict__ adm, uint32_t& child) {
-  int32_t ix, iy, iz;
-  const bool ok = (int)cell_index(x, a.mesh, ix) & (int)cell_index(y, a.mesh, iy) & (int)cell_index(z, a.mesh, iz);
-  if (!ok) return -2;
-  const uint32_t f = a.factor;
-  const uint32_t cx = (uint32_t)ix / f, cy = (uint32_t)iy / f, cz = (uint32_t)iz / f;
-  const uint64_t Gc = (uint64_t)((uint32_t)a.mesh.G / f);
-  const uint64_t ckey = ((uint64_t)cx * Gc + cy) * Gc + cz;
-  uint32_t lo = 0, hi = a.na;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (adm[mid] < ckey) lo = mid + 1;
-    else hi = mid;
-  }
-  child = (((uint32_t)ix - cx * f) * f + ((uint32_t)iy - cy * f)) * f + ((uint32_t)iz - cz * f);
-  return (lo < a.na && adm[lo] == ckey) ? (int32_t)lo : -1;
+constexpr uint32_t kAdmHashSlots = 2 * kMaxAdmitted;   // load <= 1/2
+constexpr uint64_t kEmptySlot = ~0ull;
+
+__device__ __forceinline__ uint32_t adm_hash(uint64_t key) {
+  return ((uint32_t)(key ^ (key >> 32)) * 0x9E3779B9u) >> 22;   // top 10 bits
 }
 
-// Loads of one tile: kSplitPPT particles per thread, all issued before the first use
-// (indices clamped to the last particle; the caller masks by validity).
-__device__ __forceinline__ void split_load(const SplitArgs& a, uint64_t t0, float (&p)[kSplitPPT][3]) {
+// Fill the LDS hash (key -> position in the admitted list); ends with a barrier.
+__device__ __forceinline__ void adm_hash_build(const SplitArgs& a, uint64_t* hkey, uint16_t* hidx) {
+  for (uint32_t i = threadIdx.x; i < kAdmHashSlots; i += blockDim.x) hkey[i] = kEmptySlot;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < a.na; i += blockDim.x) {
+    const uint64_t key = a.admitted[i];
+    uint32_t sl = adm_hash(key);
+    for (uint32_t probe = 0; probe < kAdmHashSlots; ++probe) {
+      if (atomicCAS((unsigned long long*)&hkey[sl], kEmptySlot, (unsigned long long)key) == kEmptySlot) {
+        hidx[sl] = (uint16_t)i;
+        break;
+      }
+      sl = (sl + 1) & (kAdmHashSlots - 1);
+    }
+  }
+  __syncthreads();
+}
+
+// Classes of a wave tile's PPT particles: cls[j] = position of the admitted coarse
+// parent in the sorted list, -1 (rest) or -2 (outside the domain); child[j] = position of
+// the fine cell inside its coarse cell.  The two first probes of every particle are
+// loaded before any is used, so that the LDS latencies overlap; a longer probe run
+// (rare at load 1/2) finishes in a loop.
+template <uint32_t MODE, int PPT>
+__device__ __forceinline__ void split_classes(const float (&p)[PPT][3], const SplitArgs& a, const uint64_t* hkey,
+                                              const uint16_t* hidx, int32_t (&cls)[PPT], uint32_t (&child)[PPT]) {
+  const uint32_t f = a.factor;
+  const uint64_t Gc = (uint64_t)((uint32_t)a.mesh.G / f);
+  uint64_t ckey[PPT];
+  uint32_t sl[PPT];
+  bool ok[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    int32_t ix, iy, iz;
+    ok[j] = (int)cell_index_m<MODE>(p[j][0], a.mesh, ix) & (int)cell_index_m<MODE>(p[j][1], a.mesh, iy) &
+            (int)cell_index_m<MODE>(p[j][2], a.mesh, iz);
+    const uint32_t cx = __umulhi((uint32_t)ix, a.fmagic), cy = __umulhi((uint32_t)iy, a.fmagic),
+                   cz = __umulhi((uint32_t)iz, a.fmagic);
+    ckey[j] = ((uint64_t)cx * Gc + cy) * Gc + cz;
+    child[j] = (((uint32_t)ix - cx * f) * f + ((uint32_t)iy - cy * f)) * f + ((uint32_t)iz - cz * f);
+    sl[j] = adm_hash(ckey[j]);
+  }
+  uint64_t k0[PPT], k1[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    k0[j] = hkey[sl[j]];
+    k1[j] = hkey[(sl[j] + 1) & (kAdmHashSlots - 1)];
+  }
+  bool slow_any = false;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const bool h0 = k0[j] == ckey[j], e0 = k0[j] == kEmptySlot;
+    const bool h1 = k1[j] == ckey[j], e1 = k1[j] == kEmptySlot;
+    const bool found = h0 || (!e0 && h1);
+    const uint32_t at = h0 ? sl[j] : ((sl[j] + 1) & (kAdmHashSlots - 1));
+    const int32_t c = found ? (int32_t)hidx[at] : -1;
+    cls[j] = ok[j] ? c : -2;
+    const bool slow = !h0 && !e0 && !h1 && !e1;   // both probes held other keys
+    slow_any |= slow;
+    sl[j] = slow ? ((sl[j] + 2) & (kAdmHashSlots - 1)) : kAdmHashSlots;
+  }
+  if (slow_any) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (sl[j] == kAdmHashSlots || !ok[j]) continue;
+      uint32_t q = sl[j];
+      for (uint32_t probe = 2; probe < kAdmHashSlots; ++probe) {
+        const uint64_t k = hkey[q];
+        if (k == ckey[j]) {
+          cls[j] = (int32_t)hidx[q];
+          break;
+        }
+        if (k == kEmptySlot) break;
+        q = (q + 1) & (kAdmHashSlots - 1);
+      }
+    }
+  }
+}
+
+// Loads of one wave tile: PPT particles per lane (j * 64 + lane), all issued before
+// the first use (indices clamped to the last particle; the caller masks by validity).
+template <int PPT>
+__device__ __forceinline__ void split_load(const SplitArgs& a, uint64_t t0, uint32_t lane, float (&p)[PPT][3]) {
   const uint64_t last = a.n - 1;
 #pragma unroll
-  for (int j = 0; j < kSplitPPT; ++j) {
-    uint64_t i = t0 + (uint64_t)j * kSplitThreads + threadIdx.x;
+  for (int j = 0; j < PPT; ++j) {
+    uint64_t i = t0 + (uint64_t)j * 64 + lane;
     i = i < last ? i : last;
     p[j][0] = a.pos[3 * i];
     p[j][1] = a.pos[3 * i + 1];
@@ -254,103 +377,112 @@ __device__ __forceinline__ void split_load(const SplitArgs& a, uint64_t t0, floa
   }
 }
 
-__global__ __launch_bounds__(kSplitThreads) void split_count_kernel(SplitArgs a, uint64_t* __restrict__ block_rest,
+template <uint32_t MODE>
+__global__ __launch_bounds__(kSplitThreads) void split_count_kernel(SplitArgs a, uint64_t* __restrict__ wave_rest,
                                                                     uint32_t* __restrict__ err) {
-  __shared__ uint64_t adm[kMaxAdmitted];
-  __shared__ uint32_t part[kSplitThreads / 64];
-  for (uint32_t i = threadIdx.x; i < a.na; i += blockDim.x) adm[i] = a.admitted[i];
-  __syncthreads();
-  const uint64_t lo = (uint64_t)blockIdx.x * a.chunk;
-  const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+  __shared__ uint64_t hkey[kAdmHashSlots];
+  __shared__ uint16_t hidx[kAdmHashSlots];
+  adm_hash_build(a, hkey, hidx);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wid = blockIdx.x * (kSplitThreads / 64) + (threadIdx.x >> 6);
+  if (wid >= a.nwaves) return;   // whole waves; no barrier follows
+  const uint64_t lo = (uint64_t)wid * a.wchunk;
+  const uint64_t hi = lo + a.wchunk < a.n ? lo + a.wchunk : a.n;
   uint32_t rest = 0;
   bool bad = false;
-  for (uint64_t t0 = lo; t0 < hi; t0 += kSplitTile) {
+  for (uint64_t t0 = lo; t0 < hi; t0 += kSplitWaveTile) {
     float p[kSplitPPT][3];
-    split_load(a, t0, p);
+    split_load(a, t0, lane, p);
+    int32_t cls[kSplitPPT];
+    uint32_t child[kSplitPPT];
+    split_classes<MODE>(p, a, hkey, hidx, cls, child);
 #pragma unroll
     for (int j = 0; j < kSplitPPT; ++j) {
-      const uint64_t i = t0 + (uint64_t)j * kSplitThreads + threadIdx.x;
-      uint32_t child;
-      const int32_t c = split_class(p[j][0], p[j][1], p[j][2], a, adm, child);
+      const uint64_t i = t0 + (uint64_t)j * 64 + lane;
       if (i < hi) {
-        rest += c == -1;
-        bad |= c == -2;
+        rest += cls[j] == -1;
+        bad |= cls[j] == -2;
       }
     }
   }
   if (bad) atomicOr(err, 1u);
-  // block sum
-  uint32_t v = rest;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t sum = 0;
-    for (uint32_t w = 0; w < kSplitThreads / 64; ++w) sum += part[w];
-    block_rest[blockIdx.x] = sum;
-  }
+  for (int off = 32; off > 0; off >>= 1) rest += __shfl_down(rest, off, 64);
+  if (lane == 0) wave_rest[wid] = rest;
 }
 
-// Exclusive scan of the nb <= 1024 block counts, offset by *rest_count; *rest_count grows
-// by the total.
-__global__ __launch_bounds__(1024) void split_scan_kernel(uint64_t* __restrict__ v, uint32_t nb,
+// Exclusive scan of the nw <= 4096 wave counts, offset by *rest_count; *rest_count grows by
+// the total.
+__global__ __launch_bounds__(1024) void split_scan_kernel(uint64_t* __restrict__ v, uint32_t nw,
                                                           unsigned long long* __restrict__ rest_count) {
   __shared__ uint64_t part[1024];
-  const uint64_t x = threadIdx.x < nb ? v[threadIdx.x] : 0;
-  part[threadIdx.x] = x;
+  const uint32_t lo = threadIdx.x * 4;
+  uint64_t x[4], s = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    x[q] = lo + q < nw ? v[lo + q] : 0;
+    s += x[q];
+  }
+  part[threadIdx.x] = s;
   __syncthreads();
-  for (uint32_t off = 1; off < 1024; off <<= 1) {
+  for (uint32_t off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
     const uint64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
     __syncthreads();
     part[threadIdx.x] += add;
     __syncthreads();
   }
   const uint64_t base = *rest_count;
-  if (threadIdx.x < nb) v[threadIdx.x] = base + part[threadIdx.x] - x;
+  uint64_t run = base + part[threadIdx.x] - s;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (lo + q < nw) {
+      v[lo + q] = run;
+      run += x[q];
+    }
   __syncthreads();
   if (threadIdx.x == 0) *rest_count = base + part[1023];
 }
 
-__global__ __launch_bounds__(kSplitThreads) void split_write_kernel(SplitArgs a, const uint64_t* __restrict__ block_off,
+template <uint32_t MODE>
+__global__ __launch_bounds__(kSplitThreads) void split_write_kernel(SplitArgs a, const uint64_t* __restrict__ wave_off,
                                                                     float* __restrict__ rest_pos,
                                                                     uint32_t* __restrict__ dense_part) {
-  extern __shared__ uint32_t dense[];          // na * f3 counters of this chunk
-  __shared__ uint64_t adm[kMaxAdmitted];
-  __shared__ uint32_t wave_n[kSplitThreads / 64];
+  extern __shared__ uint32_t dense[];          // na * f3 counters of this workgroup
+  __shared__ uint64_t hkey[kAdmHashSlots];
+  __shared__ uint16_t hidx[kAdmHashSlots];
   const uint32_t nd = a.na * a.f3;
-  for (uint32_t i = threadIdx.x; i < a.na; i += blockDim.x) adm[i] = a.admitted[i];
   for (uint32_t i = threadIdx.x; i < nd; i += blockDim.x) dense[i] = 0;
-  __syncthreads();
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const uint64_t lo = (uint64_t)blockIdx.x * a.chunk;
-  const uint64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-  uint64_t base = block_off[blockIdx.x];
-  for (uint64_t t0 = lo; t0 < hi; t0 += kSplitTile) {   // uniform over the block
-    float p[kSplitPPT][3];
-    split_load(a, t0, p);
+  adm_hash_build(a, hkey, hidx);               // ends with a barrier
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wid = blockIdx.x * (kSplitThreads / 64) + (threadIdx.x >> 6);
+  if (wid < a.nwaves) {
+    const uint64_t lo = (uint64_t)wid * a.wchunk;
+    const uint64_t hi = lo + a.wchunk < a.n ? lo + a.wchunk : a.n;
+    uint64_t base = wave_off[wid];
+    for (uint64_t t0 = lo; t0 < hi; t0 += 64ull * kSplitWritePPT) {
+      float p[kSplitWritePPT][3];
+      split_load(a, t0, lane, p);
+      int32_t cls[kSplitWritePPT];
+      uint32_t child[kSplitWritePPT];
+      split_classes<MODE>(p, a, hkey, hidx, cls, child);
 #pragma unroll
-    for (int j = 0; j < kSplitPPT; ++j) {
-      const uint64_t i = t0 + (uint64_t)j * kSplitThreads + threadIdx.x;
-      uint32_t child = 0;
-      const int32_t c = split_class(p[j][0], p[j][1], p[j][2], a, adm, child);
-      const bool valid = i < hi;
-      if (valid && c >= 0) atomicAdd(&dense[(uint32_t)c * a.f3 + child], 1u);
-      const bool rest = valid && c == -1;
-      const uint64_t mask = __ballot(rest);
-      if (lane == 0) wave_n[wave] = (uint32_t)__popcll(mask);
-      __syncthreads();
-      uint64_t off = base;
-      for (uint32_t q = 0; q < wave; ++q) off += wave_n[q];
-      off += (uint64_t)__popcll(lane ? (mask & (~0ull >> (64 - lane))) : 0ull);
-      if (rest) {
-        rest_pos[3 * off] = p[j][0];
-        rest_pos[3 * off + 1] = p[j][1];
-        rest_pos[3 * off + 2] = p[j][2];
+      for (int j = 0; j < kSplitWritePPT; ++j) {
+        const uint64_t i = t0 + (uint64_t)j * 64 + lane;
+        const int32_t c = cls[j];
+        const bool valid = i < hi;
+        if (valid && c >= 0) atomicAdd(&dense[(uint32_t)c * a.f3 + child[j]], 1u);
+        const bool rest = valid && c == -1;
+        const uint64_t mask = __ballot(rest);
+        if (rest) {
+          const uint64_t o = base + (uint64_t)__popcll(lane ? (mask & (~0ull >> (64 - lane))) : 0ull);
+          rest_pos[3 * o] = p[j][0];
+          rest_pos[3 * o + 1] = p[j][1];
+          rest_pos[3 * o + 2] = p[j][2];
+        }
+        base += (uint64_t)__popcll(mask);
       }
-      for (uint32_t q = 0; q < kSplitThreads / 64; ++q) base += wave_n[q];
-      __syncthreads();
     }
   }
+  __syncthreads();
   uint32_t* out = dense_part + (uint64_t)blockIdx.x * nd;
   for (uint32_t i = threadIdx.x; i < nd; i += blockDim.x) out[i] = dense[i];
 }
@@ -497,6 +629,95 @@ __global__ __launch_bounds__(256) void cell_list_write_kernel(const uint32_t* __
   }
 }
 
+// The same listing from the bitmap of touched cells: word w's bits are cells 32 w .. +31.
+// Block b owns words [b chunk, (b + 1) chunk).
+__device__ __forceinline__ uint32_t bits_taken(uint32_t bits, uint64_t w, const uint32_t* __restrict__ counts,
+                                               uint32_t min_count) {
+  if (min_count <= 1) return (uint32_t)__popc(bits);
+  uint32_t q = 0;
+  while (bits) {
+    const uint32_t b = (uint32_t)__ffs(bits) - 1u;
+    bits &= bits - 1u;
+    q += counts[w * 32 + b] >= min_count;
+  }
+  return q;
+}
+
+__global__ __launch_bounds__(256) void bitmap_list_count_kernel(const uint32_t* __restrict__ bitmap, uint64_t nwords,
+                                                                uint64_t chunk, const uint32_t* __restrict__ counts,
+                                                                uint32_t min_count,
+                                                                uint64_t* __restrict__ block_count) {
+  __shared__ uint64_t part[256];
+  const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+  const uint64_t hi = lo + chunk < nwords ? lo + chunk : nwords;
+  uint64_t c = 0;
+  for (uint64_t w = lo + threadIdx.x; w < hi; w += blockDim.x) {
+    const uint32_t bits = bitmap[w];
+    if (bits) c += bits_taken(bits, w, counts, min_count);
+  }
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (uint32_t h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) block_count[blockIdx.x] = part[0];
+}
+
+__global__ __launch_bounds__(256) void bitmap_list_write_kernel(const uint32_t* __restrict__ bitmap, uint64_t nwords,
+                                                                uint64_t chunk, const uint32_t* __restrict__ counts,
+                                                                uint32_t min_count,
+                                                                const uint64_t* __restrict__ block_off,
+                                                                uint64_t* __restrict__ cells, uint64_t cap) {
+  __shared__ uint32_t wsum[4];
+  const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+  const uint64_t hi = lo + chunk < nwords ? lo + chunk : nwords;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint64_t base = block_off[blockIdx.x];
+  for (uint64_t t0 = lo; t0 < hi; t0 += blockDim.x) {   // uniform over the block
+    const uint64_t w = t0 + threadIdx.x;
+    const uint32_t bits = w < hi ? bitmap[w] : 0u;
+    const uint32_t q = bits ? bits_taken(bits, w, counts, min_count) : 0u;
+    const uint32_t incl = wave_incl_scan(q);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint64_t off = base + incl - q;
+    uint64_t tile = 0;
+    for (uint32_t v = 0; v < 4; ++v) {
+      if (v < wave) off += wsum[v];
+      tile += wsum[v];
+    }
+    uint32_t rem = bits;
+    while (rem) {
+      const uint32_t b = (uint32_t)__ffs(rem) - 1u;
+      rem &= rem - 1u;
+      const uint64_t cell = w * 32 + b;
+      if (min_count <= 1 || counts[cell] >= min_count) {
+        if (off < cap) cells[off] = cell;
+        ++off;
+      }
+    }
+    base += tile;
+    __syncthreads();
+  }
+}
+
+// Zero the counts of every touched cell and the bitmap itself.
+__global__ __launch_bounds__(256) void bitmap_clear_kernel(uint32_t* __restrict__ bitmap, uint64_t nwords,
+                                                           uint32_t* __restrict__ counts) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
+    uint32_t bits = bitmap[w];
+    if (!bits) continue;
+    while (bits) {
+      const uint32_t b = (uint32_t)__ffs(bits) - 1u;
+      bits &= bits - 1u;
+      counts[w * 32 + b] = 0u;
+    }
+    bitmap[w] = 0u;
+  }
+}
+
 // ------------------------------------------------------------------ labels and admission
 
 // out[i] = coarse parent (fine cell index / factor per axis on the mesh G / factor) of keys[i]
@@ -568,9 +789,9 @@ static uint32_t grid_of(uint64_t n, uint32_t threads, uint32_t max_blocks) {
 }
 
 hipError_t launch_sample_counts(const float* pos, uint64_t n, uint64_t index0, uint64_t seed, uint32_t threshold,
-                                const Mesh& coarse, uint32_t* counts, hipStream_t s) {
+                                const Mesh& coarse, uint32_t* counts, uint32_t* bitmap, hipStream_t s) {
   hipLaunchKernelGGL(sample_counts_kernel, dim3(grid_of(n, 256, 8192)), dim3(256), 0, s, pos, n, index0, seed,
-                     threshold, coarse, counts);
+                     threshold, coarse, counts, bitmap);
   return hipGetLastError();
 }
 
@@ -582,10 +803,22 @@ hipError_t launch_features(const uint32_t* counts, uint32_t Gc, const uint64_t* 
 
 hipError_t launch_gemm_bf16(uint32_t M, uint32_t N, uint32_t K, const float* A, uint64_t sai, uint64_t sak,
                             const float* B, uint64_t sbk, uint64_t sbj, float* C, uint64_t sci, uint64_t scj,
-                            float beta, hipStream_t s) {
+                            float beta, hipStream_t s, float* partial, uint64_t partial_floats) {
   const uint64_t tiles = (uint64_t)((M + 15) / 16) * ((N + 15) / 16);
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3((uint32_t)((tiles + 3) / 4)), dim3(256), 0, s, M, N, K, A, sai, sak, B,
-                     sbk, sbj, C, sci, scj, beta);
+  uint64_t nsplit = (K + kSplitK - 1) / kSplitK;
+  if (partial != nullptr && (uint64_t)M * N > 0 && nsplit * (uint64_t)M * N > partial_floats)
+    nsplit = partial_floats / ((uint64_t)M * N);
+  if (partial == nullptr || K < 2 * kSplitK || tiles >= 256 || nsplit < 2) {
+    hipLaunchKernelGGL(gemm_bf16_kernel, dim3((uint32_t)((tiles + 3) / 4)), dim3(256), 0, s, M, N, K, A, sai, sak, B,
+                       sbk, sbj, C, sci, scj, beta);
+    return hipGetLastError();
+  }
+  const uint32_t kc = (uint32_t)(((K + nsplit - 1) / nsplit + 15) / 16 * 16);
+  nsplit = (K + kc - 1) / kc;
+  hipLaunchKernelGGL(gemm_bf16_splitk_kernel, dim3((uint32_t)((tiles + 3) / 4), (uint32_t)nsplit), dim3(256), 0, s, M,
+                     N, K, kc, A, sai, sak, B, sbk, sbj, partial);
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_of((uint64_t)M * N, 256, 1024)), dim3(256), 0, s, partial,
+                     (uint32_t)nsplit, M, N, C, sci, scj, beta);
   return hipGetLastError();
 }
 
@@ -623,16 +856,18 @@ hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, uint32_t 
   return hipGetLastError();
 }
 
-uint32_t split_blocks(uint64_t n, uint64_t* chunk) {
-  uint64_t tiles = (n + kSplitTile - 1) / kSplitTile;
-  uint64_t nb = tiles < kSplitBlocks ? tiles : kSplitBlocks;
-  if (nb < 1) nb = 1;
-  *chunk = (tiles + nb - 1) / nb * kSplitTile;
-  return (uint32_t)nb;
+// Waves and particles per wave of a split of n particles.
+uint32_t split_waves(uint64_t n, uint64_t* wchunk) {
+  const uint64_t tiles = (n + kSplitWaveTile - 1) / kSplitWaveTile;
+  uint64_t nw = tiles < kSplitMaxWaves ? tiles : kSplitMaxWaves;
+  if (nw < 1) nw = 1;
+  *wchunk = (tiles + nw - 1) / nw * kSplitWaveTile;
+  return (uint32_t)nw;
 }
 
 uint64_t split_workspace_bytes(uint32_t na, uint32_t factor) {
-  return kSplitBlocks * sizeof(uint64_t) + (uint64_t)kSplitBlocks * na * factor * factor * factor * sizeof(uint32_t);
+  const uint64_t blocks = kSplitMaxWaves / (kSplitThreads / 64);
+  return kSplitMaxWaves * sizeof(uint64_t) + blocks * na * factor * factor * factor * sizeof(uint32_t);
 }
 
 hipError_t launch_route_split(const float* pos, uint64_t n, const Mesh& mesh, uint32_t factor, const uint64_t* admitted,
@@ -643,17 +878,32 @@ hipError_t launch_route_split(const float* pos, uint64_t n, const Mesh& mesh, ui
   a.n = n;
   a.mesh = mesh;
   a.factor = factor;
+  a.fmagic = (uint32_t)(((1ull << 32) + factor - 1) / factor);
   a.f3 = factor * factor * factor;
   a.admitted = admitted;
   a.na = na;
-  const uint32_t nb = split_blocks(n, &a.chunk);
-  uint64_t* block = (uint64_t*)workspace;
-  uint32_t* dense_part = (uint32_t*)(block + kSplitBlocks);
+  a.nwaves = split_waves(n, &a.wchunk);
+  const uint32_t nb = (a.nwaves + kSplitThreads / 64 - 1) / (kSplitThreads / 64);
+  uint64_t* wave = (uint64_t*)workspace;
+  uint32_t* dense_part = (uint32_t*)(wave + kSplitMaxWaves);
   const uint32_t nd = na * a.f3;
-  hipLaunchKernelGGL(split_count_kernel, dim3(nb), dim3(kSplitThreads), 0, s, a, block, err);
-  hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(1024), 0, s, block, nb, rest_count);
-  hipLaunchKernelGGL(split_write_kernel, dim3(nb), dim3(kSplitThreads), (size_t)nd * sizeof(uint32_t), s, a, block,
-                     rest_pos, dense_part);
+  const size_t lds = (size_t)nd * sizeof(uint32_t);
+  if (mesh.mode == kMeshPow2Ratio) {
+    hipLaunchKernelGGL(split_count_kernel<kMeshPow2Ratio>, dim3(nb), dim3(kSplitThreads), 0, s, a, wave, err);
+    hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(1024), 0, s, wave, a.nwaves, rest_count);
+    hipLaunchKernelGGL(split_write_kernel<kMeshPow2Ratio>, dim3(nb), dim3(kSplitThreads), lds, s, a, wave, rest_pos,
+                       dense_part);
+  } else if (mesh.mode == kMeshExactRatio) {
+    hipLaunchKernelGGL(split_count_kernel<kMeshExactRatio>, dim3(nb), dim3(kSplitThreads), 0, s, a, wave, err);
+    hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(1024), 0, s, wave, a.nwaves, rest_count);
+    hipLaunchKernelGGL(split_write_kernel<kMeshExactRatio>, dim3(nb), dim3(kSplitThreads), lds, s, a, wave, rest_pos,
+                       dense_part);
+  } else {
+    hipLaunchKernelGGL(split_count_kernel<kMeshGeneral>, dim3(nb), dim3(kSplitThreads), 0, s, a, wave, err);
+    hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(1024), 0, s, wave, a.nwaves, rest_count);
+    hipLaunchKernelGGL(split_write_kernel<kMeshGeneral>, dim3(nb), dim3(kSplitThreads), lds, s, a, wave, rest_pos,
+                       dense_part);
+  }
   if (nd > 0)
     hipLaunchKernelGGL(split_table_kernel, dim3(grid_of(nd, 256, 1024)), dim3(256), 0, s, a, dense_part, nb, tkeys,
                        tcounts, tmask, err);
@@ -675,15 +925,32 @@ uint32_t cell_list_blocks(uint64_t ncells, uint64_t* chunk) {
   return (uint32_t)nb;
 }
 
-hipError_t launch_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t min_count, uint64_t* block_scratch,
-                            uint64_t* cells, uint64_t cap, unsigned long long* total, hipStream_t s) {
+hipError_t launch_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t min_count, const uint32_t* bitmap,
+                            uint64_t* block_scratch, uint64_t* cells, uint64_t cap, unsigned long long* total,
+                            hipStream_t s) {
   uint64_t chunk = 0;
+  if (bitmap != nullptr) {
+    const uint64_t nwords = (ncells + 31) / 32;
+    const uint32_t nb = cell_list_blocks(nwords, &chunk);
+    hipLaunchKernelGGL(bitmap_list_count_kernel, dim3(nb), dim3(256), 0, s, bitmap, nwords, chunk, counts, min_count,
+                       block_scratch);
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, block_scratch, nb, total);
+    hipLaunchKernelGGL(bitmap_list_write_kernel, dim3(nb), dim3(256), 0, s, bitmap, nwords, chunk, counts, min_count,
+                       block_scratch, cells, cap);
+    return hipGetLastError();
+  }
   const uint32_t nb = cell_list_blocks(ncells, &chunk);
   hipLaunchKernelGGL(cell_list_count_kernel, dim3(nb), dim3(256), 0, s, counts, ncells, chunk, min_count,
                      block_scratch);
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, block_scratch, nb, total);
   hipLaunchKernelGGL(cell_list_write_kernel, dim3(nb), dim3(256), 0, s, counts, ncells, chunk, min_count,
                      block_scratch, cells, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_bitmap_clear(uint32_t* bitmap, uint64_t ncells, uint32_t* counts, hipStream_t s) {
+  const uint64_t nwords = (ncells + 31) / 32;
+  hipLaunchKernelGGL(bitmap_clear_kernel, dim3(grid_of(nwords, 256, 8192)), dim3(256), 0, s, bitmap, nwords, counts);
   return hipGetLastError();
 }
 

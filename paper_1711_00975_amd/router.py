@@ -19,8 +19,8 @@ from __future__ import annotations
 
 import math
 
-from . import (FEAT, MLP, Sketch, cell_features, cell_labels, cell_list, exact_counts, new_table, route_admit,
-               route_split, sample_counts, table_topk, topk_with_table)
+from . import (FEAT, MLP, Sketch, cell_features, cell_labels, cell_list, cells_clear, exact_counts, new_table,
+               route_admit, route_split, sample_counts, table_topk, topk_with_table)
 
 TABLE_BYTES_PER_SLOT = 12     # 8-byte key + 4-byte count
 
@@ -44,16 +44,21 @@ class Router:
         self.table_slots, self.min_count, self.sample_seed = table_slots, min_count, sample_seed
         self.max_admit = min(max_admit, table_slots // (2 * self.factor ** 3))
         self.counts = torch.zeros(Gc ** 3, dtype=torch.int32, device="cuda")
+        self.bitmap = torch.zeros((Gc ** 3 + 31) // 32, dtype=torch.int32, device="cuda")
         self.mlp = MLP(seed=model_seed, max_batch=max_batch)
+        self.cells = torch.empty(1 << 20, dtype=torch.int64, device="cuda")
         self.X, self.Y = [], []
 
     # ---- the sample pre-pass and features
     def features(self, pos):
         """(coarse cells with >= min_count sampled particles, their features)."""
-        self.counts.zero_()
-        sample_counts(pos, self.delta_c, self.L, self.sample_seed, self.counts)
-        cells = cell_list(self.counts, self.min_count)
-        return cells, cell_features(self.counts, self.delta_c, self.L, cells)
+        sample_counts(pos, self.delta_c, self.L, self.sample_seed, self.counts, bitmap=self.bitmap)
+        cells = cell_list(self.counts, self.min_count, out=self.cells, bitmap=self.bitmap)
+        if cells.data_ptr() != self.cells.data_ptr():      # the buffer grew
+            self.cells = cells
+        x = cell_features(self.counts, self.delta_c, self.L, cells)
+        cells_clear(self.counts, self.bitmap)              # back to empty for the next stream
+        return cells, x
 
     # ---- training
     def add_snapshot(self, pos, k: int, exact_slots: int):

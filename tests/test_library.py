@@ -53,7 +53,8 @@ def test_argument_errors_are_returned_without_a_device():
     assert lib.csk_gemm_bf16((1 << 20) + 1, 16, 16, None, 0, 0, None, 0, 0, None, 0, 0, 0.0, None) == csk.CSK_E_INVALID
     assert lib.csk_gemm_bf16(16, 16, 16, None, 0, 0, None, 0, 0, None, 0, 0, 0.0, None) == csk.CSK_E_INVALID
     assert lib.csk_gemm_bf16(0, 16, 16, None, 0, 0, None, 0, 0, None, 0, 0, 0.0, None) == csk.CSK_OK
-    assert lib.csk_sample_counts(None, 0, 0, 0.3, 100.0, 1, 0, None, None) == csk.CSK_E_INVALID
+    assert lib.csk_sample_counts(None, 0, 0, 0.3, 100.0, 1, 0, None, None, None) == csk.CSK_E_INVALID
+    assert lib.csk_cells_clear(None, None, 5, None) == csk.CSK_E_INVALID
     assert lib.csk_cell_features(None, 1.0, 100.0, None, 5, None, None) == csk.CSK_E_INVALID
     route = lambda factor, na, slots: lib.csk_route_split(None, 0, 0.25, 50.0, factor, None, na, None, None, slots,
                                                           None, None, None, None, 0, None)
@@ -76,8 +77,8 @@ def test_argument_errors_are_returned_without_a_device():
     kout = C.c_uint32(7)
     assert lib.csk_table_topk(None, None, 1024, 1, None, None, C.byref(kout), None) == csk.CSK_E_INVALID
     tot = C.c_uint64(7)
-    assert lib.csk_cell_list(None, 5, 1, None, 0, None, None) == csk.CSK_E_INVALID
-    assert lib.csk_cell_list(None, 0, 1, None, 0, C.byref(tot), None) == csk.CSK_OK and tot.value == 0
+    assert lib.csk_cell_list(None, 5, 1, None, None, 0, None, None) == csk.CSK_E_INVALID
+    assert lib.csk_cell_list(None, 0, 1, None, None, 0, C.byref(tot), None) == csk.CSK_OK and tot.value == 0
     assert lib.csk_cell_labels(None, 5, None, (1 << 17) + 1, 0.25, 50.0, 4, None, None) == csk.CSK_E_INVALID
     assert lib.csk_cell_labels(None, 5, None, 3, 0.25, 50.0, 3, None, None) == csk.CSK_E_INVALID
     na = C.c_uint32(7)

@@ -41,6 +41,19 @@ def test_sample_counts_and_features_match_reference():
     cells = np.unique(np.nonzero(want)[0]).astype(np.int64)[:5000]
     feat = csk.cell_features(counts, dc, L, dev(cells)).cpu().numpy()
     assert np.allclose(feat, ref.features(want, 100, cells), rtol=2e-7, atol=0)
+    # the same pass with the touched-cell bitmap: bits mark exactly the nonzero cells, the
+    # listing from the bitmap equals the reference, and clearing empties both
+    counts.zero_()
+    bitmap = torch.zeros((100 ** 3 + 31) // 32, dtype=torch.int32, device="cuda")
+    csk.sample_counts(dev(pos), dc, L, 17, counts, bitmap=bitmap)
+    assert np.array_equal(counts.cpu().numpy().view(np.uint32), want)
+    bits = np.unpackbits(bitmap.cpu().numpy().view(np.uint8), bitorder="little")[:100 ** 3]
+    assert np.array_equal(bits.astype(bool), want > 0)
+    for mc in (1, 2, 4):
+        got = csk.cell_list(counts, mc, bitmap=bitmap).cpu().numpy()
+        assert np.array_equal(got, ref.cell_list(want, mc))
+    csk.cells_clear(counts, bitmap)
+    assert not counts.any().item() and not bitmap.any().item()
 
 
 @pytest.mark.parametrize("M,N,K,trans_a,trans_b", [(16, 16, 16, False, False), (37, 64, 27, False, True),
@@ -221,6 +234,13 @@ def test_cell_list_and_labels_match_reference():
     part = csk.cell_list(cd, 1, cap=1000).cpu().numpy()          # only the first cap are written
     assert np.array_equal(part, ref.cell_list(counts, 1)[:1000])
     assert csk.cell_list(dev(np.zeros(1000, np.int32)), 1).numel() == 0
+    words = np.packbits(counts > 0, bitorder="little").view(np.uint32)   # 10^6 cells: whole words
+    bm = dev(words.view(np.int32))
+    for mc in (1, 3, 9):
+        assert np.array_equal(csk.cell_list(cd, mc, bitmap=bm).cpu().numpy(), ref.cell_list(counts, mc))
+    assert np.array_equal(csk.cell_list(cd, 2, cap=777, bitmap=bm).cpu().numpy(), ref.cell_list(counts, 2)[:777])
+    buf = torch.empty(10, dtype=torch.int64, device="cuda")         # a caller's buffer grows as needed
+    assert np.array_equal(csk.cell_list(cd, 3, out=buf).cpu().numpy(), ref.cell_list(counts, 3))
     # labels of coarse cells (mesh 100, factor 4 of the fine mesh 400) from fine keys
     cells = ref.cell_list(counts, 1)
     fine = rng.choice(400 ** 3, 3000, replace=False).astype(np.int64)
