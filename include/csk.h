@@ -126,6 +126,26 @@ csk_status csk_cell_keys(const float *pos, uint64_t n, double delta, double L, u
 csk_status csk_collect(csk_sketch *s, const float *pos, uint64_t n, double delta, double L,
                        int32_t theta, void *stream);
 
+/* The packed particle stream (Sec. 4.1: the three coordinates of a particle share 64
+ * bits).  Word of a particle: qx | qy << 21 | qz << 42, q = floor(p * 2^21 / L) on the
+ * exact values after the periodic wrap (the same exact floor as the cell index, on 2^21
+ * cells), or UINT64_MAX when the particle is outside the domain (|p| >= 2L or not
+ * finite; bit 0 of *err, device, is then set).  Its cell index on a mesh of G cells is
+ * floor(q * G / 2^21), integer arithmetic, so a packed stream defines its own cells: for
+ * G dividing 2^21 they are those of the float stream, otherwise a particle within L/2^21
+ * of a cell boundary may move to the neighbouring cell.  pos, packed (device). */
+csk_status csk_pack_positions(const float *pos, uint64_t n, double L, uint64_t *packed, uint32_t *err,
+                              void *stream);
+/* csk_sketch_update, csk_collect and csk_cell_keys for a packed stream (n words,
+ * device), 8 bytes per particle instead of 12.  Outside-domain words are skipped and
+ * latched as for float positions.  Float and packed calls may be mixed on one handle. */
+csk_status csk_sketch_update_packed(csk_sketch *s, const uint64_t *packed, uint64_t n, double delta, double L,
+                                   void *stream);
+csk_status csk_collect_packed(csk_sketch *s, const uint64_t *packed, uint64_t n, double delta, double L,
+                              int32_t theta, void *stream);
+csk_status csk_cell_keys_packed(const uint64_t *packed, uint64_t n, double delta, double L, uint64_t *keys,
+                                void *stream);
+
 /* Candidate pass over the whole dictionary (Count Sketch with Full Search: Sec. 2.2
  * item 1, Alg. 1): every cell key of the G^3 mesh, G = round(L / delta), occupied or
  * not, whose estimate is >= theta is added to the candidate set; no positions are

@@ -116,6 +116,45 @@ def keys(pos, delta: float, L: float) -> np.ndarray:
     return out[:m].copy()
 
 
+PACK_BITS = 21
+PACK_OUTSIDE = np.uint64(2 ** 64 - 1)
+
+
+def pack(pos, L: float) -> np.ndarray:
+    """The packed stream (Sec. 4.1: three coordinates in 64 bits): word = qx | qy << 21 |
+    qz << 42 with q = floor(p * 2^21 / L) exactly, wrapped as for the cell index (the cell
+    index of a mesh of 2^21 cells); all ones when the particle is outside the domain.
+    orc_cell_index's 128-bit arithmetic covers G = 2^21: |mantissa * G| < 2^45."""
+    a = _pos(pos)
+    q = cell_index_many(a.ravel(), 1 << PACK_BITS, L).reshape(-1, 3)
+    out = np.full(a.shape[0], PACK_OUTSIDE, dtype=np.uint64)
+    ok = (q >= 0).all(axis=1)
+    qq = q[ok].astype(np.uint64)
+    out[ok] = qq[:, 0] | (qq[:, 1] << np.uint64(PACK_BITS)) | (qq[:, 2] << np.uint64(2 * PACK_BITS))
+    return out
+
+
+def keys_packed(words, delta: float, L: float) -> np.ndarray:
+    """Cell keys of the in-domain packed particles, in stream order: i = floor(q G / 2^21)."""
+    G = np.uint64(grid(delta, L))
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    w = w[(w >> np.uint64(63)) == 0]
+    mask = np.uint64((1 << PACK_BITS) - 1)
+    i = [(((w >> np.uint64(sh)) & mask) * G) >> np.uint64(PACK_BITS) for sh in (0, PACK_BITS, 2 * PACK_BITS)]
+    return (i[0] * G + i[1]) * G + i[2]
+
+
+def topk_keys(M, T, keys_, theta, k, variant: int = VARIANT_CS):
+    """Top-k over the distinct keys of a key stream: those with estimate >= theta, ordered by
+    (estimate desc, key asc).  Returns (keys, est)."""
+    uniq = np.unique(np.ascontiguousarray(keys_, dtype=np.uint64))
+    est = estimate(M, T, uniq, variant) if uniq.size else np.empty(0, np.int32)
+    sel = est.astype(np.int64) >= theta
+    u, e = uniq[sel], est[sel]
+    order = np.lexsort((u, -e.astype(np.int64)))[:k]
+    return u[order], e[order]
+
+
 def splitmix64(seed: int, count: int) -> np.ndarray:
     st = C.c_uint64(seed)
     lib = _load()

@@ -35,7 +35,8 @@ INT32_MIN = -(2 ** 31)
 
 EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "csk_sketch_destroy", "csk_sketch_update",
            "csk_set_update_plan",
-           "csk_sketch_query", "csk_cell_keys", "csk_collect", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
+           "csk_sketch_query", "csk_cell_keys", "csk_collect",
+           "csk_pack_positions", "csk_sketch_update_packed", "csk_collect_packed", "csk_cell_keys_packed", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
            "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_update", "csk_batch_destroy",
            "csk_sample_counts", "csk_cell_features", "csk_mlp_create", "csk_mlp_destroy", "csk_mlp_params",
            "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_gemm_bf16", "csk_route_split", "csk_route_split_workspace", "csk_topk_with_table",
@@ -75,6 +76,10 @@ def load_library(path: str = LIB_PATH):
         "csk_sketch_query": [P, P, u64, P, P],
         "csk_cell_keys": [P, u64, f64, f64, P, P],
         "csk_collect": [P, P, u64, f64, f64, i32, P],
+        "csk_pack_positions": [P, u64, f64, P, P, P],
+        "csk_sketch_update_packed": [P, P, u64, f64, f64, P],
+        "csk_collect_packed": [P, P, u64, f64, f64, i32, P],
+        "csk_cell_keys_packed": [P, u64, f64, f64, P, P],
         "csk_collect_dictionary": [P, f64, f64, i32, P],
         "csk_collect_children": [P, P, i32, P],
         "csk_candidates_clear": [P, P],
@@ -207,6 +212,40 @@ def csk_collect(h, pos, delta: float, L: float, theta: int, stream=None) -> None
                                       _stream(stream)))
 
 
+def pack_positions(pos, L: float, err=None, stream=None):
+    """The packed stream (int64 words holding uint64: qx | qy << 21 | qz << 42, q =
+    floor(p 2^21 / L); all ones outside the domain, which sets err[0] bit 0)."""
+    import torch
+    out = torch.empty(pos.shape[0], dtype=torch.int64, device=pos.device)
+    if err is None:
+        err = torch.zeros(1, dtype=torch.int32, device=pos.device)
+    if pos.shape[0]:
+        _check(load_library().csk_pack_positions(_dev(pos, torch.float32, 3), pos.shape[0], L, _dev(out, torch.int64),
+                                                 _dev(err, torch.int32), _stream(stream)))
+    return out
+
+
+def csk_sketch_update_packed(h, words, delta: float, L: float, stream=None) -> None:
+    import torch
+    _check(load_library().csk_sketch_update_packed(h, _dev(words, torch.int64) if words.numel() else None,
+                                                   words.numel(), delta, L, _stream(stream)))
+
+
+def csk_collect_packed(h, words, delta: float, L: float, theta: int, stream=None) -> None:
+    import torch
+    _check(load_library().csk_collect_packed(h, _dev(words, torch.int64) if words.numel() else None, words.numel(),
+                                             delta, L, theta, _stream(stream)))
+
+
+def cell_keys_packed(words, delta: float, L: float, stream=None):
+    import torch
+    keys = torch.empty(words.numel(), dtype=torch.int64, device=words.device)
+    if words.numel():
+        _check(load_library().csk_cell_keys_packed(_dev(words, torch.int64), words.numel(), delta, L,
+                                                   _dev(keys, torch.int64), _stream(stream)))
+    return keys
+
+
 def csk_collect_dictionary(h, delta: float, L: float, theta: int, stream=None) -> None:
     _check(load_library().csk_collect_dictionary(h, delta, L, theta, _stream(stream)))
 
@@ -337,6 +376,12 @@ class Sketch:
 
     def collect(self, pos, delta, L, theta=INT32_MIN, stream=None):
         csk_collect(self.h, pos, delta, L, theta, stream)
+
+    def update_packed(self, words, delta, L, stream=None):
+        csk_sketch_update_packed(self.h, words, delta, L, stream)
+
+    def collect_packed(self, words, delta, L, theta=INT32_MIN, stream=None):
+        csk_collect_packed(self.h, words, delta, L, theta, stream)
 
     def collect_dictionary(self, delta, L, theta=INT32_MIN, stream=None):
         csk_collect_dictionary(self.h, delta, L, theta, stream)

@@ -163,26 +163,16 @@ void free_all(csk_sketch* s) {
   if (s->host_ctl) (void)hipHostFree(s->host_ctl);
 }
 
-csk_status check_mesh(csk_sketch* s, double delta, double L, Mesh* out) {
-  if (!(delta > 0.0) || !(L > 0.0) || !std::isfinite(delta) || !std::isfinite(L))
-    return fail(CSK_E_INVALID, "mesh: delta and L must be finite and positive (delta=%g, L=%g)", delta, L);
-  const double q = L / delta;
-  if (!(q >= 0.5) || !(q < 65535.5))
-    return fail(CSK_E_INVALID, "mesh: L/delta = %g outside [1, 65535]", q);
-  const long long G = std::llround(q);
-  if (G < 1 || G > 65535 || std::fabs(q - (double)G) > 1e-6 * (double)G)
-    return fail(CSK_E_INVALID, "mesh: L/delta = %.17g is not within 1e-6 of an integer in [1, 65535]", q);
-  if (s != nullptr && s->mesh_set && (s->delta != delta || s->L != L))
-    return fail(CSK_E_STATE, "mesh (delta=%g, L=%g) differs from the one latched on this handle (%g, %g)", delta,
-                L, s->delta, s->L);
+// The mesh of G cells per side over [0, L) and its floor path.
+void classify_mesh(Mesh* out, long long G, double L) {
   out->L = L;
   out->invL = 1.0 / L;
   out->twoL = 2.0 * L;
   out->Gd = (double)G;
   out->G = (int32_t)G;
-  out->nch = key_chars((int32_t)G);
-  out->group = (s != nullptr) ? s->group : 1u;
-  out->ginv = 1.0 / (double)out->group;
+  out->nch = key_chars((int32_t)(G < 65535 ? G : 65535));
+  out->group = 1u;
+  out->ginv = 1.0;
   // exact-ratio modes: R = G/L exactly representable with <= 29 significant bits
   out->mode = kMeshGeneral;
   out->R = (double)G / L;
@@ -195,6 +185,23 @@ csk_status check_mesh(csk_sketch* s, double delta, double L, Mesh* out) {
     if (scaled == std::floor(scaled)) out->mode = kMeshExactRatio;
     if (mant == 0.5 && ex >= 1 && (double)out->twoLf == 2.0 * L) out->mode = kMeshPow2Ratio;
   }
+}
+
+csk_status check_mesh(csk_sketch* s, double delta, double L, Mesh* out) {
+  if (!(delta > 0.0) || !(L > 0.0) || !std::isfinite(delta) || !std::isfinite(L))
+    return fail(CSK_E_INVALID, "mesh: delta and L must be finite and positive (delta=%g, L=%g)", delta, L);
+  const double q = L / delta;
+  if (!(q >= 0.5) || !(q < 65535.5))
+    return fail(CSK_E_INVALID, "mesh: L/delta = %g outside [1, 65535]", q);
+  const long long G = std::llround(q);
+  if (G < 1 || G > 65535 || std::fabs(q - (double)G) > 1e-6 * (double)G)
+    return fail(CSK_E_INVALID, "mesh: L/delta = %.17g is not within 1e-6 of an integer in [1, 65535]", q);
+  if (s != nullptr && s->mesh_set && (s->delta != delta || s->L != L))
+    return fail(CSK_E_STATE, "mesh (delta=%g, L=%g) differs from the one latched on this handle (%g, %g)", delta,
+                L, s->delta, s->L);
+  classify_mesh(out, G, L);
+  out->group = (s != nullptr) ? s->group : 1u;
+  out->ginv = 1.0 / (double)out->group;
   return CSK_OK;
 }
 
@@ -321,21 +328,26 @@ csk_status csk_set_update_plan(csk_sketch* s, int32_t mode, uint32_t max_wg) {
   return CSK_OK;
 }
 
-csk_status csk_sketch_update(csk_sketch* s, const float* pos, uint64_t n, double delta, double L, void* stream) {
+namespace {
+
+// The update of a float (x, y, z) stream, or of a packed stream (src = 64-bit words).
+csk_status update_impl(csk_sketch* s, const void* src, bool packed, uint64_t n, double delta, double L,
+                       void* stream) {
   if (s == nullptr) return fail(CSK_E_INVALID, "update: NULL handle");
   Mesh mesh;
   csk_status rc = check_mesh(s, delta, L, &mesh);
   if (rc != CSK_OK) return rc;
-  if (n > 0 && pos == nullptr) return fail(CSK_E_INVALID, "update: NULL positions");
+  if (n > 0 && src == nullptr) return fail(CSK_E_INVALID, "update: NULL positions");
   if (n > (1ull << 40)) return fail(CSK_E_INVALID, "update: n above 2^40");
   latch_mesh(s, delta, L, mesh);
   if (n == 0) return CSK_OK;
+  if (packed) mesh.mode = kMeshPacked;
   hipStream_t st = (hipStream_t)stream;
   const Tables t = s->tables();
   const uint64_t piece_max = 1ull << 30;
   for (uint64_t off = 0; off < n; off += piece_max) {
     const uint64_t m = (n - off < piece_max) ? n - off : piece_max;
-    const float* p = pos + 3 * off;
+    const float* p = packed ? (const float*)((const uint64_t*)src + off) : (const float*)src + 3 * off;
     BinPlan plan;
     const uint64_t max_wg = bin_wg_cap(s->d, s->upd_max_wg);
     if (s->upd_mode == CSK_UPDATE_DIRECT || !plan_bin_wg(m, s->d, s->w, max_wg, plan)) {
@@ -369,6 +381,17 @@ csk_status csk_sketch_update(csk_sketch* s, const float* pos, uint64_t n, double
   return CSK_OK;
 }
 
+}  // namespace
+
+csk_status csk_sketch_update(csk_sketch* s, const float* pos, uint64_t n, double delta, double L, void* stream) {
+  return update_impl(s, pos, false, n, delta, L, stream);
+}
+
+csk_status csk_sketch_update_packed(csk_sketch* s, const uint64_t* packed, uint64_t n, double delta, double L,
+                                   void* stream) {
+  return update_impl(s, packed, true, n, delta, L, stream);
+}
+
 csk_status csk_sketch_query(csk_sketch* s, const uint64_t* keys, uint64_t m, int32_t* est, void* stream) {
   if (s == nullptr) return fail(CSK_E_INVALID, "query: NULL handle");
   if (m > 0 && (keys == nullptr || est == nullptr)) return fail(CSK_E_INVALID, "query: NULL keys or est");
@@ -387,16 +410,41 @@ csk_status csk_cell_keys(const float* pos, uint64_t n, double delta, double L, u
   return CSK_OK;
 }
 
-csk_status csk_collect(csk_sketch* s, const float* pos, uint64_t n, double delta, double L, int32_t theta,
-                       void* stream) {
+csk_status csk_cell_keys_packed(const uint64_t* packed, uint64_t n, double delta, double L, uint64_t* keys,
+                                void* stream) {
+  Mesh mesh;
+  csk_status rc = check_mesh(nullptr, delta, L, &mesh);
+  if (rc != CSK_OK) return rc;
+  if (n > 0 && (packed == nullptr || keys == nullptr)) return fail(CSK_E_INVALID, "cell_keys_packed: NULL pointer");
+  if (n == 0) return CSK_OK;
+  mesh.mode = kMeshPacked;
+  CSK_HIP(launch_keys((const float*)packed, n, mesh, keys, (hipStream_t)stream), "cell_keys_packed");
+  return CSK_OK;
+}
+
+csk_status csk_pack_positions(const float* pos, uint64_t n, double L, uint64_t* packed, uint32_t* err, void* stream) {
+  if (!(L > 0.0) || !std::isfinite(L)) return fail(CSK_E_INVALID, "pack: L=%g must be finite and positive", L);
+  if (n > 0 && (pos == nullptr || packed == nullptr || err == nullptr)) return fail(CSK_E_INVALID, "pack: NULL pointer");
+  if (n == 0) return CSK_OK;
+  Mesh pm;
+  classify_mesh(&pm, 1ll << kPackBits, L);
+  CSK_HIP(launch_pack(pos, n, pm, packed, err, (hipStream_t)stream), "pack");
+  return CSK_OK;
+}
+
+namespace {
+
+csk_status collect_impl(csk_sketch* s, const void* src, bool packed, uint64_t n, double delta, double L,
+                        int32_t theta, void* stream) {
   if (s == nullptr) return fail(CSK_E_INVALID, "collect: NULL handle");
   Mesh mesh;
   csk_status rc = check_mesh(s, delta, L, &mesh);
   if (rc != CSK_OK) return rc;
-  if (n > 0 && pos == nullptr) return fail(CSK_E_INVALID, "collect: NULL positions");
+  if (n > 0 && src == nullptr) return fail(CSK_E_INVALID, "collect: NULL positions");
   latch_mesh(s, delta, L, mesh);
   if (theta != INT32_MIN) s->partial_set = true;
   if (n == 0) return CSK_OK;
+  if (packed) mesh.mode = kMeshPacked;
   hipStream_t st = (hipStream_t)stream;
   const Tables t = s->tables();
   const uint32_t* filter = nullptr;
@@ -407,10 +455,22 @@ csk_status csk_collect(csk_sketch* s, const float* pos, uint64_t n, double delta
     filter = s->filter;
     hot = s->filter + kFilterWords;
   }
-  CSK_HIP(launch_collect(pos, n, mesh, t, s->M, theta, filter, hot, filter ? s->hot_table : nullptr, s->set,
+  CSK_HIP(launch_collect((const float*)src, n, mesh, t, s->M, theta, filter, hot, filter ? s->hot_table : nullptr, s->set,
                          s->slots - 1, s->set_count(), s->max_cand, s->err(), st),
           "collect");
   return CSK_OK;
+}
+
+}  // namespace
+
+csk_status csk_collect(csk_sketch* s, const float* pos, uint64_t n, double delta, double L, int32_t theta,
+                       void* stream) {
+  return collect_impl(s, pos, false, n, delta, L, theta, stream);
+}
+
+csk_status csk_collect_packed(csk_sketch* s, const uint64_t* packed, uint64_t n, double delta, double L, int32_t theta,
+                              void* stream) {
+  return collect_impl(s, packed, true, n, delta, L, theta, stream);
 }
 
 csk_status csk_collect_dictionary(csk_sketch* s, double delta, double L, int32_t theta, void* stream) {

@@ -61,6 +61,12 @@ __device__ __forceinline__ uint64_t group_key(uint64_t key, const Mesh& m) {
 constexpr uint32_t kMeshGeneral = 0;
 constexpr uint32_t kMeshExactRatio = 1;
 constexpr uint32_t kMeshPow2Ratio = 2;
+// The stream is packed: one 64-bit word per particle holding three 21-bit fixed-point
+// coordinates q = floor(p * 2^21 / L) (x in bits 0-20, y in 21-41, z in 42-62; all ones:
+// outside the domain).  The cell index on a mesh of G cells is floor(q * G / 2^21).
+constexpr uint32_t kMeshPacked = 3;
+constexpr uint32_t kPackBits = 21;
+constexpr uint64_t kPackedOutside = ~0ull;
 
 // Exact cell index along one axis: floor(p * G / L) on the exact values, wrapped into
 // [0, G).  p*G is exact in binary64 (24-bit significand times a 16-bit integer).  The
@@ -122,6 +128,27 @@ __device__ __forceinline__ bool cell_key(float x, float y, float z, const Mesh& 
   const uint32_t xy = (uint32_t)ix * (uint32_t)m.G + (uint32_t)iy;  // < G^2 <= 2^32
   key = group_key((uint64_t)xy * (uint64_t)(uint32_t)m.G + (uint64_t)(uint32_t)iz, m);
   return ok;
+}
+
+// Cell key of a packed particle: i = floor(q * G / 2^21) = umulhi(q * 2^11, G) exactly
+// (q < 2^21, G < 2^16); false for the outside marker (the key is then still a key of
+// the mesh, so table lookups stay in range).
+__device__ __forceinline__ bool packed_key(uint64_t w, const Mesh& m, uint64_t& key) {
+  constexpr uint32_t mask = (1u << kPackBits) - 1u;
+  const uint32_t G = (uint32_t)m.G;
+  const uint32_t ix = __umulhi(((uint32_t)w & mask) << (32 - kPackBits), G);
+  const uint32_t iy = __umulhi(((uint32_t)(w >> kPackBits) & mask) << (32 - kPackBits), G);
+  const uint32_t iz = __umulhi(((uint32_t)(w >> (2 * kPackBits)) & mask) << (32 - kPackBits), G);
+  key = group_key((uint64_t)(ix * G + iy) * G + iz, m);
+  return (w >> 63) == 0;
+}
+
+// Cell key of particle i of a stream in the mesh's form: float (x, y, z) triples, or
+// packed words when the mesh mode says so.
+__device__ __forceinline__ bool particle_key(const float* __restrict__ pos, uint64_t i, const Mesh& m,
+                                             uint64_t& key) {
+  if (m.mode == kMeshPacked) return packed_key(((const uint64_t*)pos)[i], m, key);
+  return cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], m, key);
 }
 
 // Tabulated word of row r: XOR over the six key bytes of T[r][c][byte_c].

@@ -124,6 +124,7 @@ hipError_t launch_accumulate(const uint16_t* tok, const uint32_t* cnt, const Bin
 hipError_t launch_update_direct(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, int32_t* M,
                                 uint32_t* err, hipStream_t s);
 hipError_t launch_keys(const float* pos, uint64_t n, const Mesh& mesh, uint64_t* keys, hipStream_t s);
+hipError_t launch_pack(const float* pos, uint64_t n, const Mesh& pm, uint64_t* out, uint32_t* err, hipStream_t s);
 hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const int32_t* M, int32_t* est,
                         hipStream_t s);
 // Bloom filter of the (row, bucket, sign) items whose signed counter is >= theta

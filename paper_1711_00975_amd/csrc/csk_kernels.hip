@@ -18,12 +18,35 @@ __global__ __launch_bounds__(256) void keys_kernel(const float* __restrict__ pos
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     uint64_t key;
-    keys[i] = cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mesh, key) ? key : kEmptyKey;
+    keys[i] = particle_key(pos, i, mesh, key) ? key : kEmptyKey;
   }
 }
 
 hipError_t launch_keys(const float* pos, uint64_t n, const Mesh& mesh, uint64_t* keys, hipStream_t s) {
   hipLaunchKernelGGL(keys_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, pos, n, mesh, keys);
+  return hipGetLastError();
+}
+
+// Packing: word = qx | qy << 21 | qz << 42 with q = floor(p * 2^21 / L) exactly (the cell
+// index of a mesh of 2^21 cells, wrapped), or all ones outside the domain (bit 0 of *err).
+__global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ pos, uint64_t n, Mesh pm,
+                                                   uint64_t* __restrict__ out, uint32_t* __restrict__ err) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    int32_t qx, qy, qz;
+    const bool ok = (int)cell_index(pos[3 * i], pm, qx) & (int)cell_index(pos[3 * i + 1], pm, qy) &
+                    (int)cell_index(pos[3 * i + 2], pm, qz);
+    out[i] = ok ? ((uint64_t)(uint32_t)qx | (uint64_t)(uint32_t)qy << kPackBits |
+                   (uint64_t)(uint32_t)qz << (2 * kPackBits))
+                : kPackedOutside;
+    bad |= !ok;
+  }
+  if (bad) atomicOr(err, 1u);
+}
+
+hipError_t launch_pack(const float* pos, uint64_t n, const Mesh& pm, uint64_t* out, uint32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(pack_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, pos, n, pm, out, err);
   return hipGetLastError();
 }
 
@@ -119,7 +142,7 @@ __global__ __launch_bounds__(256) void collect_kernel(const float* __restrict__ 
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     uint64_t key;
-    if (!cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mesh, key)) {
+    if (!particle_key(pos, i, mesh, key)) {
       atomicOr(err, kErrDomain);
       continue;
     }
@@ -171,14 +194,19 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
     // all PPT position loads are issued before any is used (a clamped index keeps the
     // loads unconditional; particles beyond the stream are masked below)
     float px[PPT], py[PPT], pz[PPT];
+    uint64_t pw[PPT];
     const uint64_t last = n - 1;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       uint64_t i = first + (uint64_t)j * NT + threadIdx.x;
       i = i < last ? i : last;
-      px[j] = __builtin_nontemporal_load(pos + 3 * i);
-      py[j] = __builtin_nontemporal_load(pos + 3 * i + 1);
-      pz[j] = __builtin_nontemporal_load(pos + 3 * i + 2);
+      if constexpr (MODE == kMeshPacked) {
+        pw[j] = __builtin_nontemporal_load((const uint64_t*)pos + i);
+      } else {
+        px[j] = __builtin_nontemporal_load(pos + 3 * i);
+        py[j] = __builtin_nontemporal_load(pos + 3 * i + 1);
+        pz[j] = __builtin_nontemporal_load(pos + 3 * i + 2);
+      }
     }
     // keys and the filter verdict of all PPT particles, without branches
     uint64_t keys[PPT];
@@ -186,7 +214,9 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const bool in = full || (first + (uint64_t)j * NT + threadIdx.x) < n;
-      const bool ok = cell_key_m<MODE>(px[j], py[j], pz[j], mesh, keys[j]);
+      bool ok;
+      if constexpr (MODE == kMeshPacked) ok = packed_key(pw[j], mesh, keys[j]);
+      else ok = cell_key_m<MODE>(px[j], py[j], pz[j], mesh, keys[j]);
       bad |= in && !ok;
       bool go = in && ok;
       if (uf) {
@@ -584,7 +614,8 @@ static void launch_collect2_m(int hm, dim3 grid, dim3 block, size_t lds, hipStre
 template <int D>
 static void launch_collect2_dm(uint32_t mode, int hm, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                                const CollectArgs& c) {
-  if (mode == kMeshPow2Ratio) launch_collect2_m<D, kMeshPow2Ratio>(hm, grid, block, lds, s, c);
+  if (mode == kMeshPacked) launch_collect2_m<D, kMeshPacked>(hm, grid, block, lds, s, c);
+  else if (mode == kMeshPow2Ratio) launch_collect2_m<D, kMeshPow2Ratio>(hm, grid, block, lds, s, c);
   else if (mode == kMeshExactRatio) launch_collect2_m<D, kMeshExactRatio>(hm, grid, block, lds, s, c);
   else launch_collect2_m<D, kMeshGeneral>(hm, grid, block, lds, s, c);
 }

@@ -49,8 +49,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
       const uint64_t i = first + (uint64_t)j * kBinThreads + tid;
       key[j] = 0;
       if (i < a.n) {
-        const float x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
-        if (cell_key(x, y, z, a.mesh, key[j])) valid |= 1u << j;
+        if (particle_key(a.pos, i, a.mesh, key[j])) valid |= 1u << j;
         else bad = true;
       }
     }
@@ -171,14 +170,19 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
     // all PPT position loads are issued before any is used (a clamped index keeps the
     // loads unconditional; particles beyond the stream are masked below)
     float px[PPT], py[PPT], pz[PPT];
+    uint64_t pw[PPT];
     const uint64_t last = n - 1;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       uint64_t i = first + (uint64_t)j * NT + tid;
       i = i < last ? i : last;
-      px[j] = __builtin_nontemporal_load(pos + 3 * i);
-      py[j] = __builtin_nontemporal_load(pos + 3 * i + 1);
-      pz[j] = __builtin_nontemporal_load(pos + 3 * i + 2);
+      if constexpr (MODE == kMeshPacked) {
+        pw[j] = __builtin_nontemporal_load((const uint64_t*)pos + i);
+      } else {
+        px[j] = __builtin_nontemporal_load(pos + 3 * i);
+        py[j] = __builtin_nontemporal_load(pos + 3 * i + 1);
+        pz[j] = __builtin_nontemporal_load(pos + 3 * i + 2);
+      }
     }
     // sv = (bin in its sort pass) << 16 | token; bin = (row % RP) * Pr + slice, or the dummy
     // bin for a particle outside the stream or the domain
@@ -188,7 +192,9 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
     for (int j = 0; j < PPT; ++j) {
       const bool in = full || (first + (uint64_t)j * NT + tid) < n;
       uint64_t key;   // always a key of the mesh, so the table lookups stay in range
-      const bool ok = cell_key_m<MODE>(px[j], py[j], pz[j], a.mesh, key) && in;
+      bool ok;
+      if constexpr (MODE == kMeshPacked) ok = packed_key(pw[j], a.mesh, key) && in;
+      else ok = cell_key_m<MODE>(px[j], py[j], pz[j], a.mesh, key) && in;
       inside |= (uint32_t)in << j;
       valid |= (uint32_t)ok << j;
       uint32_t bk[D], sg[D];
@@ -344,7 +350,8 @@ static void launch_bin3_m(int hm, dim3 grid, dim3 block, uint32_t lds, hipStream
 template <int D>
 static void launch_bin3_dm(uint32_t mode, int hm, dim3 grid, dim3 block, uint32_t lds, hipStream_t s,
                            const BinArgs& a) {
-  if (mode == kMeshPow2Ratio) launch_bin3_m<D, kMeshPow2Ratio>(hm, grid, block, lds, s, a);
+  if (mode == kMeshPacked) launch_bin3_m<D, kMeshPacked>(hm, grid, block, lds, s, a);
+  else if (mode == kMeshPow2Ratio) launch_bin3_m<D, kMeshPow2Ratio>(hm, grid, block, lds, s, a);
   else if (mode == kMeshExactRatio) launch_bin3_m<D, kMeshExactRatio>(hm, grid, block, lds, s, a);
   else launch_bin3_m<D, kMeshGeneral>(hm, grid, block, lds, s, a);
 }
@@ -531,7 +538,7 @@ __global__ __launch_bounds__(256) void update_direct_kernel(const float* __restr
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     uint64_t key;
-    if (!cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], mesh, key)) {
+    if (!particle_key(pos, i, mesh, key)) {
       atomicOr(err, kErrDomain);
       continue;
     }

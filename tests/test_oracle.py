@@ -698,3 +698,64 @@ def test_exact_topk_by_counting():
         tally[k] = tally.get(k, 0) + 1
     want = sorted(tally.items(), key=lambda kv: (-kv[1], kv[0]))[:15]
     assert keys.tolist() == [k for k, _ in want] and cnt.tolist() == [c for _, c in want]
+
+
+# ------------------------------------------------------------------ packed particle input
+
+def test_pack_by_exact_rationals():
+    from fractions import Fraction
+    rng = np.random.default_rng(12)
+    for L in (100.0, 1000.0, 64.0, 3.7):
+        p = np.concatenate([rng.uniform(-1.9 * L, 1.9 * L, 300),
+                            [0.0, -0.0, L, -L, np.nextafter(np.float32(L), np.float32(0)), 2 * L, -2 * L, np.inf,
+                             np.nan, 1e-30]]).astype(np.float32)
+        pos = np.stack([p, p[::-1], np.roll(p, 7)], axis=1)
+        words = oracle.pack(pos, L)
+        for row, wd in zip(pos, words):
+            qs = []
+            for c in row:
+                c = float(c)
+                if not np.isfinite(c) or abs(c) >= 2 * L:
+                    qs = None
+                    break
+                q = (Fraction(c) * 2 ** 21 // Fraction(L)) % (2 ** 21)
+                qs.append(int(q))
+            if qs is None:
+                assert wd == oracle.PACK_OUTSIDE
+            else:
+                assert int(wd) == qs[0] | qs[1] << 21 | qs[2] << 42
+
+
+def test_packed_keys_by_integer_formula_and_nesting():
+    rng = np.random.default_rng(13)
+    pos = rng.uniform(0, 64.0, (3000, 3)).astype(np.float32)
+    words = oracle.pack(pos, 64.0)
+    for delta in (0.25, 0.256, 1.0):            # G = 256, 250, 64
+        G = oracle.grid(delta, 64.0)
+        keys = oracle.keys_packed(words, delta, 64.0)
+        want = []
+        for wd in words.tolist():
+            i = [((wd >> sh) & (2 ** 21 - 1)) * G >> 21 for sh in (0, 21, 42)]
+            want.append((i[0] * G + i[1]) * G + i[2])
+        assert keys.tolist() == want
+    # G dividing 2^21 (here 256 = 64 / 0.25): floor(floor(p 2^21 / L) G / 2^21) = floor(p G / L),
+    # so the packed stream has the float stream's cells
+    assert np.array_equal(oracle.keys_packed(words, 0.25, 64.0), oracle.keys(pos, 0.25, 64.0))
+    # outside-domain words are dropped like out-of-domain particles
+    pos[5] = (200.0, 1.0, 1.0)
+    assert len(oracle.keys_packed(oracle.pack(pos, 64.0), 0.25, 64.0)) == len(pos) - 1
+
+
+def test_topk_keys_matches_exact_top_without_collisions():
+    rng = np.random.default_rng(14)
+    keys = rng.zipf(1.6, 20000).astype(np.uint64) % np.uint64(5000)
+    M = oracle.sketch_keys(keys, 5, 1 << 22, 3)
+    T = oracle.hash_tables(3, 5)
+    uniq, cnt = oracle.histogram(keys)
+    # a wide sketch estimates every key exactly here, so the top-k is the exact one
+    assert np.array_equal(oracle.estimate(M, T, uniq), cnt.astype(np.int32))
+    k_keys, k_est = oracle.topk_keys(M, T, keys, oracle.INT32_MIN, 50)
+    e_keys, e_cnt = oracle.topk_exact(uniq, cnt, 50)
+    assert np.array_equal(k_keys, e_keys) and np.array_equal(k_est, e_cnt.astype(np.int32))
+    k2, e2 = oracle.topk_keys(M, T, keys, int(e_cnt[9]), 50)         # theta cuts at the 10th count
+    assert np.array_equal(k2, k_keys[k_est >= e_cnt[9]])
