@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--no-dictionary", action="store_true",
                     help="skip the full-dictionary search (every cell of the mesh estimated once)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
+    ap.add_argument("--large", action="store_true",
+                    help="run the large combined workload (2^34 particles, three grids, router) instead")
+    ap.add_argument("--large-n", type=int, default=0, help="particles of the large run (default 2^34)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device three times (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -504,6 +507,214 @@ def packed_input(pos, wl, theta, keys_top, csk, torch, steps):
             "topk_overlap_with_float_stream": overlap}
 
 
+def large_run(args, csk, torch, workloads):
+    """The large combined run: 2^34 particles generated on the device in 2^27-particle
+    chunks (L = 3000, 2^24 halos), streamed into three grids (0.25, 0.5, 1.0) as one batch
+    of w = 2^24 sketches, with the learned router on the 0.25 grid (its table and rest
+    sketch take the memory of one plain sketch), top-10^5 per sketch.
+
+    Passes over the stream (each regenerates its chunks): a 1 % sample pass for the router,
+    the update pass, and the candidate pass (repeated with half the threshold if fewer than
+    k candidates pass).  The router's model is trained first on eight boxes of the same
+    density and recipe at 1/64 of the volume (L = 750, 2^28 particles, 2^18 halos, exact
+    top-1563 labels)."""
+    from paper_1711_00975_amd.router import Router, rest_width
+    wl = workloads.LARGE
+    n = args.large_n or wl.n
+    chunk = min(wl.chunk, n)
+    k = wl.k
+    L = wl.L
+    deltas = [0.25, 0.5, 1.0]
+    out = {"metric": "particles/s sketched into three grids (update pass) + top-10^5 per grid; learned router "
+                     "vs plain at equal memory on the 0.25 grid",
+           "unit": "particles/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int32",
+           "data": "synthetic (seeded Plummer halos + uniform background, generated on the device)",
+           "config": {"workload": wl.name, "particles": n, "chunk": chunk, "L": L, "deltas": deltas, "d": wl.d,
+                      "w": wl.w, "k": k, "halos": wl.n_halo}}
+    # ---- the router's model, trained on small boxes of the same density
+    t0 = time.perf_counter()
+    scale = 4
+    tw = wl.with_(L=L / scale, n=1 << 28, n_halo=wl.n_halo // scale ** 3, chunk=0)
+    k_train = round(k / scale ** 3)
+    rt = Router(wl.delta, tw.L)
+    for sd in range(2, 10):
+        pos = workloads.DeviceGenerator(tw.with_(seed=sd)).generate(0, tw.n)
+        info = rt.add_snapshot(pos, k_train, 1 << 29)
+        del pos
+        log(f"  training box seed {sd}: {info}")
+    tr = rt.train()
+    params = rt.mlp.params()
+    rt.close()
+    del rt
+    torch.cuda.empty_cache()
+    out["router_training"] = {"box_L": tw.L, "particles": tw.n, "halos": tw.n_halo, "k": k_train, **tr,
+                              "seconds": time.perf_counter() - t0}
+    log(f"  router trained: {tr}")
+
+    gen = workloads.DeviceGenerator(wl)
+    buf = torch.empty((chunk, 3), dtype=torch.float32, device="cuda")
+    nchunks = (n + chunk - 1) // chunk
+
+    def chunks():
+        for c in range(nchunks):
+            a = c * chunk
+            m = min(chunk, n - a)
+            yield a, gen.generate(a, m, buf)
+
+    # ---- pass 0: the 1 % sample of the whole stream, admission
+    r = Router(wl.delta, L)
+    r.mlp.set_params(params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, pos in chunks():
+        csk.sample_counts(pos, r.delta_c, L, r.sample_seed, r.counts, index0=a, bitmap=r.bitmap)
+    cells = csk.cell_list(r.counts, r.min_count, bitmap=r.bitmap)
+    x = csk.cell_features(r.counts, r.delta_c, L, cells)
+    admitted = csk.route_admit(cells, r.mlp.forward(x), r.max_admit)
+    torch.cuda.synchronize()
+    t_sample = time.perf_counter() - t0
+    scored = int(cells.numel())
+    del cells, x
+    r.counts = r.bitmap = None            # the 108 GB of coarse counts are not needed again
+    torch.cuda.empty_cache()
+    log(f"  sample pass: {t_sample:.1f} s, {scored} cells scored, {admitted.numel()} admitted")
+
+    # ---- pass 1: updates (three grids batched; the routed rest separately)
+    mc = 1 << 23
+    plain = [csk.Sketch(wl.d, wl.w, wl.seed, max_candidates=mc) for _ in deltas]
+    w_rest = rest_width(wl.w, wl.d, r.table_slots)
+    rest_sk = csk.Sketch(wl.d, w_rest, wl.seed, max_candidates=mc)
+    batch = csk.Batch(plain, [chunk] * 3, deltas, [L] * 3)
+    ttk, ttc = csk.new_table(r.table_slots)
+    rest = torch.empty((chunk, 3), dtype=torch.float32, device="cuda")
+    rcount = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rerr = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t_gen = t_batch = t_route = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, (a, pos) in enumerate(chunks()):
+        ev[0].record()
+        batch.update([pos, pos, pos])
+        ev[1].record()
+        rcount.zero_()
+        r.split(pos, admitted, ttk, ttc, rest, rcount, rerr)
+        nr = int(rcount.item())
+        rest_sk.update(rest[:nr], wl.delta, L)
+        torch.cuda.synchronize()
+        t_batch += ev[0].elapsed_time(ev[1])
+        if c % 16 == 15:
+            log(f"  update pass: {a + pos.shape[0]}/{n} particles ({time.perf_counter() - t0:.1f} s)")
+    t_update = time.perf_counter() - t0
+    batch.close()
+    for sk in plain + [rest_sk]:
+        sk.check()
+    assert rerr.item() == 0
+    # generation alone, for the split of the update pass's time
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(4):
+        gen.generate(0, chunk, buf)
+    torch.cuda.synchronize()
+    t_gen = (time.perf_counter() - g0) / 4 * nchunks
+    log(f"  update pass: {t_update:.1f} s (batched three-grid update {t_batch / 1e3:.2f} s, generation about "
+        f"{t_gen:.2f} s)")
+
+    # ---- pass 2: candidates, threshold from chunk 0, halved until k pass everywhere
+    names = ["plain_0.25", "plain_0.5", "plain_1.0", "routed_0.25"]
+    sketches = plain + [rest_sk]
+    dl = deltas + [wl.delta]
+
+    def collect_pass(thetas):
+        for sk in sketches:
+            sk.clear_candidates()
+        for a, pos in chunks():
+            for sk, dd, th in zip(sketches[:3], dl[:3], thetas[:3]):
+                sk.collect(pos, dd, L, th)
+            rcount.zero_()
+            ttk2, ttc2 = scratch_table
+            ttk2.fill_(-1)
+            ttc2.zero_()
+            r.split(pos, admitted, ttk2, ttc2, rest, rcount, rerr)
+            nr = int(rcount.item())
+            rest_sk.collect(rest[:nr], wl.delta, L, thetas[3])
+
+    scratch_table = csk.new_table(r.table_slots)   # the split's table of pass 2 is discarded
+    g0 = time.perf_counter()
+    pos0 = gen.generate(0, chunk, buf)
+    thetas = []
+    for i, sk in enumerate(sketches[:3]):
+        th = 1 << 22
+        while th > 1:
+            sk.clear_candidates()
+            sk.collect(pos0, dl[i], L, th)
+            kk, ee, rc = sk.topk(k)
+            if kk.numel() == k:
+                break
+            th //= 2
+        thetas.append(th)
+    th = 1 << 22
+    while th > 1:
+        rcount.zero_()
+        ttk2, ttc2 = scratch_table
+        ttk2.fill_(-1)
+        ttc2.zero_()
+        r.split(pos0, admitted, ttk2, ttc2, rest, rcount, rerr)
+        rest_sk.clear_candidates()
+        rest_sk.collect(rest[:int(rcount.item())], wl.delta, L, th)
+        kk, ee, rc = csk.topk_with_table(rest_sk, ttk, ttc, k)
+        if kk.numel() == k and int(ee[k - 1].item()) >= th:
+            break
+        th //= 2
+    thetas.append(th)
+    results = {}
+    for attempt in range(6):
+        collect_pass(thetas)
+        done = True
+        for i, (nm, sk) in enumerate(zip(names, sketches)):
+            if nm.startswith("routed"):
+                kk, ee, rc = csk.topk_with_table(sk, ttk, ttc, k)
+            else:
+                kk, ee, rc = sk.topk(k)
+            ok = kk.numel() == k and int(ee[k - 1].item()) >= thetas[i]
+            results[nm] = (kk, ee, rc)
+            if not ok:
+                thetas[i] //= 2
+                done = False
+        log(f"  candidate pass {attempt + 1}: thetas {thetas}, complete {done}")
+        if done:
+            break
+    t_collect = time.perf_counter() - g0
+    grids = {}
+    for i, nm in enumerate(names):
+        kk, ee, rc = results[nm]
+        grids[nm] = {"theta": thetas[i], "returned": int(kk.numel()), "kth_estimate": int(ee[-1].item()),
+                     "max_estimate": int(ee[0].item()), "status": rc}
+    pk, rk = results["plain_0.25"][0], results["routed_0.25"][0]
+    # coarse consistency: the 0.5 cell of each 0.25 top cell (floor nesting) among the 0.5 top cells
+    G1, G2 = round(L / 0.25), round(L / 0.5)
+    ix, iy, iz = pk // (G1 * G1), (pk // G1) % G1, pk % G1
+    parent = ((ix // 2) * G2 + iy // 2) * G2 + iz // 2
+    out.update({
+        "value": n / t_update, "ms_per_step": t_update * 1e3, "steps": 1, "warmup": 0, "scaling": "weak",
+        "vs_baseline": None,
+        "passes_s": {"sample": t_sample, "update": t_update, "candidates": t_collect},
+        "update_pass": {"batched_three_grid_update_s": t_batch / 1e3,
+                        "three_grid_particles_per_s": 3 * n / (t_batch / 1e3),
+                        "generation_s_estimate": t_gen},
+        "router": {"scored_cells": scored, "admitted": int(admitted.numel()), "w_rest": w_rest,
+                   "table_slots": r.table_slots,
+                   "table_particles": int(ttc.to(torch.int64).sum().item())},
+        "grids": grids,
+        "routed_vs_plain_top_overlap": torch.isin(rk, pk).sum().item() / k,
+        "fine_top_parents_in_0.5_top": torch.isin(parent, results["plain_0.5"][0]).sum().item() / k,
+    })
+    for sk in sketches:
+        sk.close()
+    r.close()
+    return out
+
+
 def host_threads():
     """Host threads this process may use, capped at the 16 that one GPU's share allows."""
     try:
@@ -557,6 +768,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read_per_copy": src.numel() * 4}), flush=True)
+        return
+
+    if args.large:
+        torch.cuda.set_device(0)
+        print(json.dumps(large_run(args, csk, torch, workloads)), flush=True)
         return
 
     wl = workloads.SCALE if args.workload == "scale" else workloads.SMALL

@@ -222,6 +222,11 @@ typedef struct csk_batch csk_batch;
  * batch.  Allocates device memory and synchronizes. */
 csk_status csk_batch_create(csk_batch **out, csk_sketch *const *sketches, const uint64_t *max_n, uint32_t count,
                             double delta, double L, uint32_t wg_budget);
+/* As csk_batch_create with a mesh per sketch (delta[i], L[i], host arrays): sketches of
+ * different grids over the same particles (the meshes must share one cell-index path, e.g.
+ * all power-of-two ratios) form one batch. */
+csk_status csk_batch_create_meshes(csk_batch **out, csk_sketch *const *sketches, const uint64_t *max_n,
+                                   uint32_t count, const double *delta, const double *L, uint32_t wg_budget);
 
 /* Add n[i] particles at pos[i] (device pointers; host arrays of the batch's count) to
  * sketch i for every i, n[i] <= max_n[i].  Allocates nothing and does not synchronize,

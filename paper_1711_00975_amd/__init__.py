@@ -37,7 +37,7 @@ EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "cs
            "csk_set_update_plan",
            "csk_sketch_query", "csk_cell_keys", "csk_collect",
            "csk_pack_positions", "csk_sketch_update_packed", "csk_collect_packed", "csk_cell_keys_packed", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
-           "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_update", "csk_batch_destroy",
+           "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_create_meshes", "csk_batch_update", "csk_batch_destroy",
            "csk_sample_counts", "csk_cell_features", "csk_mlp_create", "csk_mlp_destroy", "csk_mlp_params",
            "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_gemm_bf16", "csk_route_split", "csk_route_split_workspace", "csk_topk_with_table",
            "csk_exact_counts", "csk_table_topk", "csk_cell_list", "csk_cells_clear", "csk_cell_labels",
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "csk_topk": [P, u32, P, P, C.POINTER(C.c_uint32), P],
         "csk_topk_async": [P, u32, P, P, P, P],
         "csk_batch_create": [PP, P, P, u32, f64, f64, u32],
+        "csk_batch_create_meshes": [PP, P, P, u32, P, P, u32],
         "csk_batch_update": [P, P, P, P],
         "csk_batch_destroy": [P],
         "csk_sample_counts": [P, u64, u64, f64, f64, u64, u32, P, P, P],
@@ -309,12 +310,19 @@ class Batch:
     """Up to 64 sketches updated by one bin and one accumulate launch (csk_batch_*)."""
 
     def __init__(self, sketches, max_n, delta, L, wg_budget: int = 0):
+        """delta and L: one mesh for every sketch, or one per sketch (sequences)."""
         lib = load_library()
         m = len(sketches)
         arr = (C.c_void_p * m)(*[s.h.value if isinstance(s.h, C.c_void_p) else s.h for s in sketches])
         mx = (C.c_uint64 * m)(*[int(x) for x in max_n])
         h = C.c_void_p()
-        _check(lib.csk_batch_create(C.byref(h), arr, mx, m, delta, L, wg_budget))
+        if isinstance(delta, (list, tuple)) or isinstance(L, (list, tuple)):
+            ds = list(delta) if isinstance(delta, (list, tuple)) else [delta] * m
+            ls = list(L) if isinstance(L, (list, tuple)) else [L] * m
+            _check(lib.csk_batch_create_meshes(C.byref(h), arr, mx, m, (C.c_double * m)(*ds), (C.c_double * m)(*ls),
+                                               wg_budget))
+        else:
+            _check(lib.csk_batch_create(C.byref(h), arr, mx, m, delta, L, wg_budget))
         self.h, self.sketches, self.count = h, list(sketches), m
 
     def update(self, positions, stream=None):

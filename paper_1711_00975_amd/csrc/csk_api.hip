@@ -666,8 +666,10 @@ hipError_t bmalloc(T** p, uint64_t count) {
 
 }  // namespace
 
-csk_status csk_batch_create(csk_batch** out, csk_sketch* const* sketches, const uint64_t* max_n, uint32_t count,
-                            double delta, double L, uint32_t wg_budget) {
+namespace {
+
+csk_status batch_create_impl(csk_batch** out, csk_sketch* const* sketches, const uint64_t* max_n, uint32_t count,
+                             const double* delta, const double* L, uint32_t wg_budget) {
   if (out == nullptr) return fail(CSK_E_INVALID, "batch_create: out is NULL");
   *out = nullptr;
   if (sketches == nullptr || max_n == nullptr) return fail(CSK_E_INVALID, "batch_create: NULL array");
@@ -688,14 +690,16 @@ csk_status csk_batch_create(csk_batch** out, csk_sketch* const* sketches, const 
     if (s->tables().hash_mode() != hm)
       return fail(CSK_E_INVALID, "batch_create: widths need different hash forms (sketch %u, w=%u)", i, s->w);
     Mesh m;
-    csk_status rc = check_mesh(sketches[i], delta, L, &m);
+    csk_status rc = check_mesh(sketches[i], delta[i], L[i], &m);
     if (rc != CSK_OK) return rc;
     if (i == 0) mesh0 = m;
+    if (m.mode != mesh0.mode)
+      return fail(CSK_E_INVALID, "batch_create: meshes need different cell-index paths (sketch %u)", i);
   }
   for (uint32_t i = 0; i < count; ++i) {
     Mesh m;
-    (void)check_mesh(sketches[i], delta, L, &m);
-    latch_mesh(sketches[i], delta, L, m);
+    (void)check_mesh(sketches[i], delta[i], L[i], &m);
+    latch_mesh(sketches[i], delta[i], L[i], m);
   }
   const uint32_t d = s0->d;
   const uint64_t tile = (uint64_t)kBin2Threads * bin2_ppt((int)d);
@@ -755,7 +759,7 @@ csk_status csk_batch_create(csk_batch** out, csk_sketch* const* sketches, const 
     for (uint32_t i = 0; i < count; ++i) {
       csk_sketch* s = sketches[i];
       Mesh m;
-      (void)check_mesh(s, delta, L, &m);
+      (void)check_mesh(s, delta[i], L[i], &m);
       hb[i] = make_bin_args(nullptr, 0, m, s->tables(), plans[i], b->tok + tok_off[i], b->cnt + cnt_off[i], s->M,
                             s->err());
       ha[i].tok = b->tok + tok_off[i];
@@ -779,6 +783,27 @@ csk_status csk_batch_create(csk_batch** out, csk_sketch* const* sketches, const 
   }
   *out = b;
   return CSK_OK;
+}
+
+}  // namespace
+
+csk_status csk_batch_create(csk_batch** out, csk_sketch* const* sketches, const uint64_t* max_n, uint32_t count,
+                            double delta, double L, uint32_t wg_budget) {
+  if (count < 1 || count > kMaxBatch) {
+    if (out != nullptr) *out = nullptr;
+    return fail(CSK_E_INVALID, "batch_create: count=%u outside [1, %u]", count, kMaxBatch);
+  }
+  std::vector<double> d(count, delta), l(count, L);
+  return batch_create_impl(out, sketches, max_n, count, d.data(), l.data(), wg_budget);
+}
+
+csk_status csk_batch_create_meshes(csk_batch** out, csk_sketch* const* sketches, const uint64_t* max_n,
+                                   uint32_t count, const double* delta, const double* L, uint32_t wg_budget) {
+  if (delta == nullptr || L == nullptr) {
+    if (out != nullptr) *out = nullptr;
+    return fail(CSK_E_INVALID, "batch_create_meshes: NULL mesh arrays");
+  }
+  return batch_create_impl(out, sketches, max_n, count, delta, L, wg_budget);
 }
 
 csk_status csk_batch_update(csk_batch* b, const float* const* pos, const uint64_t* n, void* stream) {

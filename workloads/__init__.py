@@ -16,7 +16,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcsk_workloads.so")
+GPU_LIB_PATH = os.path.join(HERE, "libcsk_workloads_gpu.so")
 _lib = None
+_gpu_lib = None
 
 
 def _load():
@@ -38,6 +40,8 @@ def _load():
     lib.wl_gen_exact.argtypes = [u64, f64, u32, f64, f64, f64, f64, u64, P, C.c_int]
     lib.wl_gen_mixture.restype = i64
     lib.wl_gen_mixture.argtypes = [u64, u64, f64, u32, f64, f64, f64, f64, f64, u64, P, C.c_int]
+    lib.wl_alias_records.restype = i64
+    lib.wl_alias_records.argtypes = [u64, u32, f64, f64, f64, f64, P]
     _lib = lib
     return lib
 
@@ -144,3 +148,52 @@ def batch_subvolumes(count: int = 64, seed: int = 1) -> list:
         out.append(Workload(name=f"subvolume-{s}", n=n, L=100.0, delta=0.1, d=5, w=w, k=max(1, w // 100),
                             seed=1 + s, n_halo=max(1, int(round(256 * n / 2 ** 20))), m_lo=100.0, m_hi=1.0e4))
     return out
+
+
+def _load_gpu():
+    global _gpu_lib
+    if _gpu_lib is None:
+        if not os.path.exists(GPU_LIB_PATH):
+            raise RuntimeError(f"{GPU_LIB_PATH} is missing: build the workloads first")
+        lib = C.CDLL(GPU_LIB_PATH)
+        lib.wl_gen_mixture_device.restype = C.c_int
+        lib.wl_gen_mixture_device.argtypes = [C.c_uint64, C.c_uint64, C.c_double, C.c_uint32, C.c_double,
+                                              C.c_double, C.c_uint64, C.c_double, C.c_void_p, C.c_void_p,
+                                              C.c_void_p]
+        _gpu_lib = lib
+    return _gpu_lib
+
+
+class DeviceGenerator:
+    """The mixture recipe generated on the GPU, chunk by chunk (plummer_gpu.hip): the same
+    draws and alias records as Workload.generate, written straight into device memory."""
+
+    def __init__(self, wl: Workload):
+        import torch
+        if wl.f_bg < 0:
+            raise ValueError("the device generator implements the mixture recipe only")
+        self.wl = wl
+        rec = np.zeros((max(wl.n_halo, 1), 8), dtype=np.float64)
+        _load().wl_alias_records(wl.seed, wl.n_halo, wl.L, wl.m_lo, wl.m_hi, wl.slope, _p(rec))
+        self.rec = torch.from_numpy(rec).cuda()
+        self.u_max = 1.01 ** -1.5
+
+    def generate(self, start: int, count: int, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((count, 3), dtype=torch.float32, device="cuda")
+        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.shape[0] >= count
+        s = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        rc = _load_gpu().wl_gen_mixture_device(start, count, self.wl.L, self.wl.n_halo, self.wl.a, self.wl.f_bg,
+                                               self.wl.seed, self.u_max, self.rec.data_ptr(), out.data_ptr(), s)
+        if rc != 0:
+            raise RuntimeError(f"device generator launch failed ({rc})")
+        return out[:count]
+
+
+# 2^34 particles in 2^27-particle chunks, L = 3000 Mpc/h, 2^24 halos (masses ~ M^-1.9 on
+# [50, 1e6]), 30 % uniform background; three meshes 0.25 / 0.5 / 1.0 Mpc/h, d = 5,
+# w = 2^24 each, k = 1e5.  Generated on the device.
+LARGE = Workload(name="plummer-2^34-L3000-d0.25/0.5/1.0-w2^24", n=1 << 34, L=3000.0, delta=0.25, d=5,
+                 w=1 << 24, k=100_000, seed=1, n_halo=1 << 24, m_lo=50.0, m_hi=1.0e6, f_bg=0.3,
+                 chunk=1 << 27)

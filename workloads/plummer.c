@@ -290,6 +290,36 @@ int64_t wl_gen_mixture(uint64_t start, uint64_t n, double L, uint32_t n_halo, do
     return 0;
 }
 
+/* The mixture recipe's per-column records for a device generator: rec[j] = {own centre
+ * x, y, z, alias centre x, y, z, cut, 0} (8 doubles), built exactly as wl_gen_mixture
+ * builds them.  Returns 0. */
+int64_t wl_alias_records(uint64_t seed, uint32_t n_halo, double L, double m_lo, double m_hi, double slope,
+                         double *rec_out)
+{
+    if (n_halo == 0)
+        return 0;
+    double *mass = (double *)malloc(sizeof(double) * n_halo);
+    double *cen = (double *)malloc(sizeof(double) * 3 * n_halo);
+    double *prob = (double *)malloc(sizeof(double) * n_halo);
+    uint32_t *alias = (uint32_t *)malloc(sizeof(uint32_t) * n_halo);
+    wl_halo_catalogue(seed, n_halo, L, m_lo, m_hi, slope, mass, cen);
+    alias_build(mass, n_halo, prob, alias);
+    wl_alias_rec *rec = (wl_alias_rec *)rec_out;
+    for (uint32_t j = 0; j < n_halo; ++j) {
+        rec[j].prob = prob[j];
+        rec[j].pad = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            rec[j].own[c] = cen[3 * j + c];
+            rec[j].alt[c] = cen[3 * (uint64_t)alias[j] + c];
+        }
+    }
+    free(alias);
+    free(prob);
+    free(cen);
+    free(mass);
+    return 0;
+}
+
 /* out[i] = first word of Philox4x32-10 at counter ((index0 + i) mod 2^32, (index0 + i) / 2^32,
  * stream, 0) under key (seed mod 2^32, seed / 2^32), for i < n. */
 void wl_philox_words(uint64_t index0, uint64_t n, uint32_t stream, uint64_t seed, uint32_t *out)
