@@ -27,8 +27,8 @@ BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
 # rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) scaled by a 1 GiB device copy
 # (profiles/update_kernels_plummer_2e30.md).  Reported only while the kernel sources hash
 # to what was profiled; any change to them makes `traffic` null until measured again.
-TRAFFIC = {"bytes": 46_061_779_751, "particles": 1 << 30,
-           "sources_sha256": "c416c2d5883090edaf16bc9808a16e7a821cc61af3624cf2ded11c159af83801"}
+TRAFFIC = {"bytes": 46_061_269_927, "particles": 1 << 30,
+           "sources_sha256": "89212efc1dd9c58c0b22c0cd1ed6f554ea5ab6cae9fa781ef3b31205f01c4cb7"}
 TRAFFIC_SOURCES = ["csk_update.hip", "csk_kernel_util.h", "csk_device.h", "csk_internal.h"]
 
 
