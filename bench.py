@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the particle count (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the measured ceilings (stream read, LDS and global atomic rates)")
+    ap.add_argument("--no-small", action="store_true", help="skip the 2^20-particle warm/cold update")
     ap.add_argument("--no-packed", action="store_true",
                     help="skip the packed 8-byte particle stream")
     ap.add_argument("--no-router", action="store_true",
@@ -715,6 +718,110 @@ def large_run(args, csk, torch, workloads):
     return out
 
 
+def ceilings(pos, torch, reps=5):
+    """Measured ceilings (libcsk_probe.so): the read bandwidth of the 12-byte particle
+    records with the update's own load pattern, the LDS atomic rate (128 KiB array, random
+    addresses), and the device-scope global atomic rate into tables of 64 KiB, 64 MiB and
+    1 GiB.  Each is the best of `reps` timed launches after one warm-up."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_1711_00975_amd", "libcsk_probe.so"))
+    P, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+    lib.probe_stream_read.argtypes = [P, u64, P, u32, P]
+    lib.probe_lds_atomics.argtypes = [u64, u32, P, P]
+    lib.probe_global_atomics.argtypes = [P, u32, u64, u32, P]
+    for f in (lib.probe_stream_read, lib.probe_lds_atomics, lib.probe_global_atomics):
+        f.restype = C.c_int
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def timed(launch):
+        assert launch() == 0
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            assert launch() == 0
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    n = pos.shape[0]
+    blocks = 1024
+    sink = torch.empty(blocks * 1024, dtype=torch.int32, device="cuda")
+    read_ms = timed(lambda: lib.probe_stream_read(pos.data_ptr(), n, sink.data_ptr(), blocks, st))
+    lds_iters, lds_blocks = 2048, 512
+    lds_ms = timed(lambda: lib.probe_lds_atomics(lds_iters, lds_blocks, sink.data_ptr(), st))
+    glob = {}
+    g_iters, g_blocks = 64, 4096
+    for lw, label in ((14, "64KiB"), (24, "64MiB"), (28, "1GiB")):
+        table = torch.zeros(1 << lw, dtype=torch.int32, device="cuda")
+        ms = timed(lambda: lib.probe_global_atomics(table.data_ptr(), lw, g_iters, g_blocks, st))
+        glob[label] = g_iters * g_blocks * 256 / (ms / 1e3)
+        del table
+    return {"stream_read_GBs": 12 * n / (read_ms / 1e3) / 1e9,
+            "lds_atomics_per_s": lds_iters * lds_blocks * 1024 / (lds_ms / 1e3),
+            "global_atomics_per_s": glob,
+            "note": "libcsk_probe.so: 12-byte records read with eight dwordx3 loads in flight per thread; random "
+                    "ds_add on 2^15 LDS words; random device-scope atomicAdd into 2^14, 2^24 and 2^28 words"}
+
+
+def small_workload(csk, torch, workloads, reps=1000, cold_reps=20):
+    """The 2^20-particle configuration: the update warm (1000 updates replayed from one HIP
+    graph; positions and counters stay on chip) and cold (a 512 MiB write before each
+    update flushes the MALL), and recall@100 against the exact histogram."""
+    import numpy as np
+    wl = workloads.SMALL
+    pos = torch.from_numpy(wl.generate()).cuda()
+    n = pos.shape[0]
+    s = csk.Sketch(wl.d, wl.w, wl.seed)
+    s.update(pos, wl.delta, wl.L)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            s.update(pos, wl.delta, wl.L)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    warm_us = e0.elapsed_time(e1) * 1e3 / reps
+    del g
+    flush = torch.empty(1 << 27, dtype=torch.int32, device="cuda")
+    cold = []
+    for r in range(cold_reps):
+        flush.fill_(r)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        s.update(pos, wl.delta, wl.L)
+        b.record()
+        torch.cuda.synchronize()
+        cold.append(a.elapsed_time(b) * 1e3)
+    del flush
+    cold_us = float(np.median(cold))
+    s.reset()
+    s.update(pos, wl.delta, wl.L)
+    s.collect(pos, wl.delta, wl.L, csk.INT32_MIN)
+    keys, est, rc = s.topk(wl.k)
+    s.close()
+    ck = csk.cell_keys(pos, wl.delta, wl.L)
+    uniq, counts = torch.unique(ck, sorted=True, return_counts=True)
+    order = np.lexsort((uniq.cpu().numpy(), -counts.cpu().numpy()))
+    u, c = uniq.cpu().numpy()[order], counts.cpu().numpy()[order]
+    kth = c[wl.k - 1]
+    got = keys.cpu().numpy()
+    return {"workload": wl.name, "particles": n,
+            "warm_update_us": warm_us, "warm_particles_per_s": n / (warm_us / 1e6),
+            "warm_roofline_frac": 12 * n / (warm_us / 1e6) / (HBM_PEAK_GBS * 1e9),
+            "cold_update_us_median": cold_us, "cold_particles_per_s": n / (cold_us / 1e6),
+            "recall": {"k": wl.k, "strict": float(np.isin(got, u[:wl.k]).mean()),
+                       "tie_tolerant": float(np.isin(got, u[c >= kth]).mean())},
+            "note": "warm: one HIP graph of 1000 updates, per update; cold: median of 20 updates, each after "
+                    "writing 512 MiB"}
+
+
 def host_threads():
     """Host threads this process may use, capped at the 16 that one GPU's share allows."""
     try:
@@ -842,6 +949,13 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n)},
     }
+    if not args.no_ceilings:
+        log("measured ceilings ...")
+        out["ceilings"] = c = ceilings(pos, torch)
+        out["roofline"]["frac_of_measured_stream_read"] = achieved / c["stream_read_GBs"]
+    if not args.no_small:
+        log("2^20-particle workload, warm and cold ...")
+        out["small_workload"] = small_workload(csk, torch, workloads)
     if not args.no_packed:
         log("packed 8-byte stream ...")
         out["packed_input"] = packed_input(pos, wl, theta, keys_top, csk, torch, args.steps)

@@ -7,6 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcsk.so")
+PROBE_LIB = os.path.join(HERE, "libcsk_probe.so")   # measurement probes for the benchmark
 SOURCES = ["csk_api.hip", "csk_update.hip", "csk_kernels.hip", "csk_router.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -29,6 +30,16 @@ def build(verbose: bool = False) -> str:
     if verbose and err.strip():
         sys.stderr.write(err + "\n")
     os.replace(LIB + ".tmp", LIB)
+    pcmd = [HIPCC, "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-o", PROBE_LIB + ".tmp", os.path.join(CSRC, "csk_probe.hip")]
+    if verbose:
+        print(" ".join(pcmd), flush=True)
+    r = subprocess.run(pcmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stderr + "\n")
+        raise RuntimeError("hipcc failed building libcsk_probe.so")
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     return LIB
 
 
