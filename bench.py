@@ -213,9 +213,11 @@ def batched_subvolumes(csk, torch, reps=5):
     pos = [torch.from_numpy(h).cuda() for h in host]
     del host
     log(f"  generated {len(subs)} sub-volumes ({time.time() - t0:.1f} s)")
-    # candidate sets sized to each sub-volume (n / 16 keys, 2^16 .. 2^21): clearing and
-    # compacting a set costs time in proportion to its slots
-    sk = [csk.Sketch(wl.d, wl.w, wl.seed, max_candidates=min(1 << 21, max(1 << 16, wl.n // 16))) for wl in subs]
+    # candidate sets sized to each sub-volume (8 k keys, or all n when n <= 2^18, so that a
+    # small stream cannot overflow): clearing and compacting a set costs time in proportion
+    # to its slots
+    sk = [csk.Sketch(wl.d, wl.w, wl.seed, max_candidates=max(1 << 14, 8 * wl.k, min(wl.n, 1 << 18)))
+          for wl in subs]
     counts = [wl.n for wl in subs]
     total = sum(counts)
     tuner = autotune.Tuner()
@@ -253,8 +255,31 @@ def batched_subvolumes(csk, torch, reps=5):
     t_batch = timed(lambda: b.update(pos))
     t_seq = timed(sequential)
     log(f"  batched update {t_batch:.3f} ms, one by one {t_seq:.3f} ms")
-    # the whole pipeline: batched update, then per sketch a filtered collect and top-k
+    # a threshold per sub-volume, as for the main stream: halved from 2^16 until k cells pass
+    # (the paper's geometric threshold, Sec. 3.1 item 4), on fresh counters
     ks = [wl.k for wl in subs]
+    for s_ in sk:
+        s_.reset()
+    b.update(pos)
+    thetas = []
+    for s_, p, k_ in zip(sk, pos, ks):
+        th = 1 << 16
+        while th > 1:
+            s_.clear_candidates()
+            s_.collect(p, 0.1, 100.0, th)
+            try:
+                kk, ee, rc = s_.topk(k_)
+            except csk.CskError:      # the set overflowed: the previous threshold is the lowest that fits
+                th *= 2
+                s_.reset()
+                s_.update(p, 0.1, 100.0)
+                break
+            if kk.numel() == k_ and int(ee[k_ - 1].item()) >= th:
+                break
+            th //= 2
+        thetas.append(th)
+    log(f"  thresholds per sub-volume: {min(thetas)} .. {max(thetas)}")
+    # the whole pipeline: batched update, then per sketch a filtered collect and top-k
     keys = [torch.empty(k, dtype=torch.int64, device="cuda") for k in ks]
     est = [torch.empty(k, dtype=torch.int32, device="cuda") for k in ks]
     outs = [torch.zeros(2, dtype=torch.int32, device="cuda") for _ in ks]
@@ -271,7 +296,7 @@ def batched_subvolumes(csk, torch, reps=5):
         for j, s in enumerate(sk):   # the 64 collect -> top-k chains run side by side
             st = side[j % len(side)]
             with torch.cuda.stream(st):
-                s.collect(pos[j], 0.1, 100.0, 8)
+                s.collect(pos[j], 0.1, 100.0, thetas[j])
                 s.topk_async(ks[j], keys[j], est[j], outs[j])
         for st in side:
             cur.wait_stream(st)
@@ -289,6 +314,7 @@ def batched_subvolumes(csk, torch, reps=5):
     del g
     for s in sk:   # surfaces a latched device error (capacity, domain) of the last replay
         s.check()
+    complete = sum(int(o[0].item()) == k_ for o, k_ in zip(outs, ks))   # k returned by the last replay
     b.close()
     for s in sk:
         s.close()
@@ -298,6 +324,7 @@ def batched_subvolumes(csk, torch, reps=5):
             "particles_per_s": total / (t_batch / 1e3),
             "roofline_frac": BYTES_PER_PARTICLE * total / (t_batch / 1e3) / 1e9 / HBM_PEAK_GBS,
             "pipeline_eager_ms": t_eager, "pipeline_graph_ms": t_graph,
+            "thresholds": [min(thetas), max(thetas)], "complete_topk": complete,
             "note": "sum over sub-volumes; update counters identical to one-by-one updates"}
 
 
