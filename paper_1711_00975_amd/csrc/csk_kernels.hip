@@ -811,32 +811,49 @@ __global__ __launch_bounds__(256) void sel_hist_kernel(const uint64_t* __restric
 }
 
 // Pick the digit holding the k_rem-th item: descending for estimates, ascending for keys.
+// One wave: position q of the scan order is digit 255 - q (estimates) or q (keys); lane l
+// holds positions 4l .. 4l + 3.  The chosen position is the first whose inclusive prefix
+// count reaches k_rem, or the last one (255) when none does; k_rem becomes k_rem minus the
+// count before it.  The histogram is cleared for the next pass.
 template <bool KEYS>
-__global__ void sel_pick_kernel(SelState* st, uint32_t k, int shift) {
-  if (threadIdx.x != 0) return;
-  if (!KEYS && shift == 24) st->k_rem = min(k, st->m);
+__global__ __launch_bounds__(64) void sel_pick_kernel(SelState* st, uint32_t k, int shift) {
+  const uint32_t lane = threadIdx.x;
+  if (!KEYS && shift == 24 && lane == 0) st->k_rem = min(k, st->m);
+  __syncthreads();
   const uint32_t need = st->k_rem;
-  if (need > 0) {
-    uint32_t cum = 0;
-    int dg;
-    if (!KEYS) {
-      for (dg = 255; dg > 0; --dg) {
-        if (cum + st->hist[dg] >= need) break;
-        cum += st->hist[dg];
-      }
-      st->est_prefix |= (uint32_t)dg << shift;
-      st->est_mask |= 255u << shift;
-    } else {
-      for (dg = 0; dg < 255; ++dg) {
-        if (cum + st->hist[dg] >= need) break;
-        cum += st->hist[dg];
-      }
-      st->key_prefix |= (uint64_t)dg << shift;
-      st->key_mask |= 255ull << shift;
-    }
-    st->k_rem = need - cum;
+  uint32_t h[4], sum = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t q = lane * 4 + (uint32_t)e;
+    h[e] = st->hist[KEYS ? q : 255u - q];
+    sum += h[e];
   }
-  for (int i = 0; i < 256; ++i) st->hist[i] = 0;
+  const uint32_t incl = wave_incl_scan(sum);
+  if (need > 0) {
+    const uint64_t hit = __ballot(incl >= need);
+    const uint32_t lead = hit ? (uint32_t)__ffsll((unsigned long long)hit) - 1u : 63u;
+    if (lane == lead) {
+      uint32_t cum = incl - sum, q = lane * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        q = lane * 4 + (uint32_t)e;
+        if (q == 255u || cum + h[e] >= need) break;
+        cum += h[e];
+      }
+      const uint32_t dg = KEYS ? q : 255u - q;
+      if (!KEYS) {
+        st->est_prefix |= dg << shift;
+        st->est_mask |= 255u << shift;
+      } else {
+        st->key_prefix |= (uint64_t)dg << shift;
+        st->key_mask |= 255ull << shift;
+      }
+      st->k_rem = need - cum;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 4; ++e) st->hist[lane * 4 + (uint32_t)e] = 0;
 }
 
 // Winners: est > T, or est == T and key <= K (T, K from the two stages).
