@@ -631,6 +631,15 @@ __global__ __launch_bounds__(256) void cell_list_write_kernel(const uint32_t* __
 
 // The same listing from the bitmap of touched cells: word w's bits are cells 32 w .. +31.
 // Block b owns words [b chunk, (b + 1) chunk).
+// Bits of word w that name cells below ncells (a caller's bitmap may carry stray bits in
+// its last word or beyond).
+__device__ __forceinline__ uint32_t valid_bits(uint32_t bits, uint64_t w, uint64_t ncells) {
+  const uint64_t lo = w * 32;
+  if (lo >= ncells) return 0u;
+  const uint64_t left = ncells - lo;
+  return left >= 32 ? bits : bits & ((1u << left) - 1u);
+}
+
 __device__ __forceinline__ uint32_t bits_taken(uint32_t bits, uint64_t w, const uint32_t* __restrict__ counts,
                                                uint32_t min_count) {
   if (min_count <= 1) return (uint32_t)__popc(bits);
@@ -644,7 +653,8 @@ __device__ __forceinline__ uint32_t bits_taken(uint32_t bits, uint64_t w, const 
 }
 
 __global__ __launch_bounds__(256) void bitmap_list_count_kernel(const uint32_t* __restrict__ bitmap, uint64_t nwords,
-                                                                uint64_t chunk, const uint32_t* __restrict__ counts,
+                                                                uint64_t ncells, uint64_t chunk,
+                                                                const uint32_t* __restrict__ counts,
                                                                 uint32_t min_count,
                                                                 uint64_t* __restrict__ block_count) {
   __shared__ uint64_t part[256];
@@ -652,7 +662,7 @@ __global__ __launch_bounds__(256) void bitmap_list_count_kernel(const uint32_t* 
   const uint64_t hi = lo + chunk < nwords ? lo + chunk : nwords;
   uint64_t c = 0;
   for (uint64_t w = lo + threadIdx.x; w < hi; w += blockDim.x) {
-    const uint32_t bits = bitmap[w];
+    const uint32_t bits = valid_bits(bitmap[w], w, ncells);
     if (bits) c += bits_taken(bits, w, counts, min_count);
   }
   part[threadIdx.x] = c;
@@ -665,7 +675,8 @@ __global__ __launch_bounds__(256) void bitmap_list_count_kernel(const uint32_t* 
 }
 
 __global__ __launch_bounds__(256) void bitmap_list_write_kernel(const uint32_t* __restrict__ bitmap, uint64_t nwords,
-                                                                uint64_t chunk, const uint32_t* __restrict__ counts,
+                                                                uint64_t ncells, uint64_t chunk,
+                                                                const uint32_t* __restrict__ counts,
                                                                 uint32_t min_count,
                                                                 const uint64_t* __restrict__ block_off,
                                                                 uint64_t* __restrict__ cells, uint64_t cap) {
@@ -676,7 +687,7 @@ __global__ __launch_bounds__(256) void bitmap_list_write_kernel(const uint32_t* 
   uint64_t base = block_off[blockIdx.x];
   for (uint64_t t0 = lo; t0 < hi; t0 += blockDim.x) {   // uniform over the block
     const uint64_t w = t0 + threadIdx.x;
-    const uint32_t bits = w < hi ? bitmap[w] : 0u;
+    const uint32_t bits = w < hi ? valid_bits(bitmap[w], w, ncells) : 0u;
     const uint32_t q = bits ? bits_taken(bits, w, counts, min_count) : 0u;
     const uint32_t incl = wave_incl_scan(q);
     if (lane == 63) wsum[wave] = incl;
@@ -704,11 +715,12 @@ __global__ __launch_bounds__(256) void bitmap_list_write_kernel(const uint32_t* 
 
 // Zero the counts of every touched cell and the bitmap itself.
 __global__ __launch_bounds__(256) void bitmap_clear_kernel(uint32_t* __restrict__ bitmap, uint64_t nwords,
-                                                           uint32_t* __restrict__ counts) {
+                                                           uint64_t ncells, uint32_t* __restrict__ counts) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
-    uint32_t bits = bitmap[w];
-    if (!bits) continue;
+    const uint32_t raw = bitmap[w];
+    if (!raw) continue;
+    uint32_t bits = valid_bits(raw, w, ncells);
     while (bits) {
       const uint32_t b = (uint32_t)__ffs(bits) - 1u;
       bits &= bits - 1u;
@@ -932,11 +944,11 @@ hipError_t launch_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t mi
   if (bitmap != nullptr) {
     const uint64_t nwords = (ncells + 31) / 32;
     const uint32_t nb = cell_list_blocks(nwords, &chunk);
-    hipLaunchKernelGGL(bitmap_list_count_kernel, dim3(nb), dim3(256), 0, s, bitmap, nwords, chunk, counts, min_count,
-                       block_scratch);
+    hipLaunchKernelGGL(bitmap_list_count_kernel, dim3(nb), dim3(256), 0, s, bitmap, nwords, ncells, chunk, counts,
+                       min_count, block_scratch);
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, block_scratch, nb, total);
-    hipLaunchKernelGGL(bitmap_list_write_kernel, dim3(nb), dim3(256), 0, s, bitmap, nwords, chunk, counts, min_count,
-                       block_scratch, cells, cap);
+    hipLaunchKernelGGL(bitmap_list_write_kernel, dim3(nb), dim3(256), 0, s, bitmap, nwords, ncells, chunk, counts,
+                       min_count, block_scratch, cells, cap);
     return hipGetLastError();
   }
   const uint32_t nb = cell_list_blocks(ncells, &chunk);
@@ -950,7 +962,8 @@ hipError_t launch_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t mi
 
 hipError_t launch_bitmap_clear(uint32_t* bitmap, uint64_t ncells, uint32_t* counts, hipStream_t s) {
   const uint64_t nwords = (ncells + 31) / 32;
-  hipLaunchKernelGGL(bitmap_clear_kernel, dim3(grid_of(nwords, 256, 8192)), dim3(256), 0, s, bitmap, nwords, counts);
+  hipLaunchKernelGGL(bitmap_clear_kernel, dim3(grid_of(nwords, 256, 8192)), dim3(256), 0, s, bitmap, nwords, ncells,
+                     counts);
   return hipGetLastError();
 }
 
