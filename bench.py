@@ -955,7 +955,9 @@ def main():
     value = n / (ms / 1e3)
     achieved = BYTES_PER_PARTICLE * n / (upd_ms / 1e3) / 1e9
     out = {
-        "metric": "particles/s sketched (update + collect + top-k per step)",
+        "metric": "particles/s sketched + top-10^4 recall; learned router vs plain at equal memory",
+        "value_is": "particles per second of whole steps (update + candidate pass + top-10^4) on the scale "
+                    "workload; recall is in `recall`, the router comparison in `learned_router`",
         "value": value,
         "unit": "particles/s",
         "n_gpus": 1,
