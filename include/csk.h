@@ -234,6 +234,15 @@ csk_status csk_batch_create_meshes(csk_batch **out, csk_sketch *const *sketches,
  * Asynchronous on `stream`. */
 csk_status csk_batch_update(csk_batch *b, const float *const *pos, const uint64_t *n, void *stream);
 
+/* The top-k of every sketch of the batch (Sec. 2.2 UpdateHeap; as csk_topk_async for each
+ * sketch i with k[i], keys[i], est[i], out[i], all host arrays of the batch's count holding
+ * device pointers) in one set of launches.  out[i][0] = how many, out[i][1] = 1 when fewer
+ * than k[i] came from a partial candidate set.  The first call, and a call after a
+ * sketch's selection scratch grew, allocates and synchronizes; later calls allocate
+ * nothing and do not synchronize, so they can be captured in a HIP graph. */
+csk_status csk_batch_topk(csk_batch *b, const uint32_t *k, uint64_t *const *keys, int32_t *const *est,
+                          uint32_t *const *out, void *stream);
+
 /* Free the batch (the handles stay). */
 csk_status csk_batch_destroy(csk_batch *b);
 

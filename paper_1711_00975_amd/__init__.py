@@ -37,7 +37,7 @@ EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "cs
            "csk_set_update_plan",
            "csk_sketch_query", "csk_cell_keys", "csk_collect",
            "csk_pack_positions", "csk_sketch_update_packed", "csk_collect_packed", "csk_cell_keys_packed", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
-           "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_create_meshes", "csk_batch_update", "csk_batch_destroy",
+           "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_create_meshes", "csk_batch_update", "csk_batch_topk", "csk_batch_destroy",
            "csk_sample_counts", "csk_cell_features", "csk_mlp_create", "csk_mlp_destroy", "csk_mlp_params",
            "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_gemm_bf16", "csk_route_split", "csk_route_split_workspace", "csk_topk_with_table",
            "csk_exact_counts", "csk_table_topk", "csk_cell_list", "csk_cells_clear", "csk_cell_labels",
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "csk_topk_async": [P, u32, P, P, P, P],
         "csk_batch_create": [PP, P, P, u32, f64, f64, u32],
         "csk_batch_create_meshes": [PP, P, P, u32, P, P, u32],
+        "csk_batch_topk": [P, P, P, P, P, P],
         "csk_batch_update": [P, P, P, P],
         "csk_batch_destroy": [P],
         "csk_sample_counts": [P, u64, u64, f64, f64, u64, u32, P, P, P],
@@ -333,6 +334,22 @@ class Batch:
         ptrs = (C.c_void_p * self.count)(*[_dev(t, torch.float32, 3) if t.shape[0] else None for t in positions])
         ns = (C.c_uint64 * self.count)(*[int(t.shape[0]) for t in positions])
         _check(load_library().csk_batch_update(self.h, ptrs, ns, _stream(stream)))
+
+    def topk(self, ks, keys, est, outs, stream=None):
+        """Top-k of every sketch in one set of launches: ks (ints), keys / est (device int64 /
+        int32 tensors of at least k each), outs (device int32 [2] each: count, incomplete)."""
+        import torch
+        m = self.count
+        if not (len(ks) == len(keys) == len(est) == len(outs) == m):
+            raise ValueError("one k and one output per sketch")
+        kk = (C.c_uint32 * m)(*[int(k) for k in ks])
+        kp = (C.c_void_p * m)(*[_dev(t, torch.int64) if k else None for t, k in zip(keys, ks)])
+        ep = (C.c_void_p * m)(*[_dev(t, torch.int32) if k else None for t, k in zip(est, ks)])
+        op = (C.c_void_p * m)(*[_dev(t, torch.int32) for t in outs])
+        for t, k in zip(keys, ks):
+            if k and t.numel() < k:
+                raise ValueError("an output holds fewer than k entries")
+        _check(load_library().csk_batch_topk(self.h, kk, kp, ep, op, _stream(stream)))
 
     def close(self):
         if self.h is not None:

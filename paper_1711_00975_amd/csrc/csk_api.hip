@@ -649,12 +649,14 @@ struct csk_batch {
   uint32_t* acc_first = nullptr;
   uint16_t* tok = nullptr;       // every sketch's token regions
   uint32_t* cnt = nullptr;
+  TopkDesc* topk = nullptr;      // per-sketch top-k descriptors (device), built on first use
+  std::vector<TopkDesc> topk_host;
 };
 
 namespace {
 
 void batch_free(csk_batch* b) {
-  void* ptrs[] = {b->bin, b->acc, b->wg_sketch, b->wg_first, b->acc_sketch, b->acc_first, b->tok, b->cnt};
+  void* ptrs[] = {b->bin, b->acc, b->wg_sketch, b->wg_first, b->acc_sketch, b->acc_first, b->tok, b->cnt, b->topk};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -822,6 +824,66 @@ csk_status csk_batch_update(csk_batch* b, const float* const* pos, const uint64_
                            st),
           "batch_update (bin)");
   CSK_HIP(launch_accumulate_batch(b->acc, b->acc_sketch, b->acc_first, b->nacc_total, st), "batch_update (accumulate)");
+  return CSK_OK;
+}
+
+csk_status csk_batch_topk(csk_batch* b, const uint32_t* k, uint64_t* const* keys, int32_t* const* est,
+                          uint32_t* const* out, void* stream) {
+  if (b == nullptr || k == nullptr || out == nullptr) return fail(CSK_E_INVALID, "batch_topk: NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t k_max = 0, slots_max = 0, mc_max = 0;
+  for (uint32_t i = 0; i < b->count; ++i) {
+    const csk_sketch* s = b->sk[i];
+    if (k[i] > s->max_cand)
+      return fail(CSK_E_INVALID, "batch_topk: k[%u]=%u above max_candidates=%u", i, k[i], s->max_cand);
+    if (k[i] > 0 && (keys == nullptr || est == nullptr || keys[i] == nullptr || est[i] == nullptr))
+      return fail(CSK_E_INVALID, "batch_topk: NULL output of sketch %u", i);
+    if (out[i] == nullptr) return fail(CSK_E_INVALID, "batch_topk: out[%u] is NULL", i);
+    k_max = k[i] > k_max ? k[i] : k_max;
+    slots_max = s->slots > slots_max ? s->slots : slots_max;
+    mc_max = s->max_cand > mc_max ? s->max_cand : mc_max;
+  }
+  // the selection scratch of each sketch holds its k (grown here, synchronizing, as by csk_topk_async)
+  for (uint32_t i = 0; i < b->count; ++i) {
+    csk_sketch* s = b->sk[i];
+    if (k[i] <= s->sel_cap) continue;
+    CSK_HIP(hipStreamSynchronize(st), "batch_topk: grow scratch");
+    if (s->sel_key) (void)hipFree(s->sel_key);
+    if (s->sel_est) (void)hipFree(s->sel_est);
+    s->bytes -= (uint64_t)s->sel_cap * (sizeof(uint64_t) + sizeof(int32_t));
+    s->sel_key = nullptr;
+    s->sel_est = nullptr;
+    s->sel_cap = 0;
+    CSK_HIP(dmalloc(s, &s->sel_key, k[i]), "batch_topk: scratch");
+    CSK_HIP(dmalloc(s, &s->sel_est, k[i]), "batch_topk: scratch");
+    s->sel_cap = k[i];
+  }
+  // descriptors: built once, rebuilt when a sketch's selection scratch moved
+  bool stale = b->topk == nullptr || b->topk_host.size() != b->count;
+  for (uint32_t i = 0; !stale && i < b->count; ++i)
+    stale = b->topk_host[i].sk != b->sk[i]->sel_key || b->topk_host[i].se != b->sk[i]->sel_est;
+  if (stale) {
+    std::vector<TopkDesc> h(b->count);
+    for (uint32_t i = 0; i < b->count; ++i) {
+      csk_sketch* s = b->sk[i];
+      h[i] = TopkDesc{s->set, s->slots, s->max_cand, s->tables(), s->M, s->sel, s->cand_key, s->cand_est,
+                      s->sel_key, s->sel_est, s->err()};
+    }
+    CSK_HIP(hipStreamSynchronize(st), "batch_topk: descriptors");
+    if (b->topk == nullptr) CSK_HIP(bmalloc(&b->topk, b->count), "batch_topk: descriptors");
+    CSK_HIP(hipMemcpy(b->topk, h.data(), sizeof(TopkDesc) * b->count, hipMemcpyHostToDevice),
+            "batch_topk: descriptors");
+    b->topk_host = h;
+  }
+  TopkCall call{};
+  for (uint32_t i = 0; i < b->count; ++i) {
+    call.keys[i] = k[i] ? keys[i] : nullptr;
+    call.est[i] = k[i] ? est[i] : nullptr;
+    call.out[i] = out[i];
+    call.k[i] = k[i];
+    call.partial[i] = b->sk[i]->partial_set ? 1u : 0u;
+  }
+  CSK_HIP(launch_topk_batch(b->topk, b->count, b->d, slots_max, mc_max, k_max, call, st), "batch_topk");
   return CSK_OK;
 }
 

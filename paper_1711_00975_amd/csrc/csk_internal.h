@@ -165,6 +165,32 @@ hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, con
 // Top k of the m pairs (ck[i], ce[i]) in (ce desc, ck asc) order, keys distinct and below
 // 2^48 (equal keys only where they cannot reach the top k): winners in ok / oe, ranks in
 // `rank` (k words), sk / se (k) scratch.
+// One sketch of a batched top-k (device array, built once per batch).
+struct TopkDesc {
+  const uint64_t* set;
+  uint32_t slots;
+  uint32_t max_cand;
+  Tables t;
+  const int32_t* M;
+  SelState* st;
+  uint64_t* ck;
+  int32_t* ce;
+  uint64_t* sk;
+  int32_t* se;
+  const uint32_t* err;
+};
+// Per-call arguments of a batched top-k (kernel arguments): k, outputs and the partial-set
+// flag of each sketch.
+struct TopkCall {
+  uint64_t* keys[kMaxBatch];
+  int32_t* est[kMaxBatch];
+  uint32_t* out[kMaxBatch];
+  uint32_t k[kMaxBatch];
+  uint32_t partial[kMaxBatch];
+};
+hipError_t launch_topk_batch(const TopkDesc* D, uint32_t count, uint32_t d, uint32_t slots_max,
+                             uint32_t max_cand_max, uint32_t k_max, const TopkCall& call, hipStream_t s);
+
 hipError_t launch_select_pairs(const uint64_t* ck, const int32_t* ce, uint32_t m, uint32_t k, SelState* st,
                                uint64_t* sk, int32_t* se, uint32_t* rank, uint64_t* ok, int32_t* oe,
                                const uint32_t* err, hipStream_t s);

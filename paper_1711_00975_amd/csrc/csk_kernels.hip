@@ -735,10 +735,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
 
 // ------------------------------------------------------------------ top-k
 
-__global__ void sel_init_kernel(SelState* st) {
+__device__ __forceinline__ void sel_init_body(SelState* st) {
   uint32_t* w = (uint32_t*)st;
   for (uint32_t i = threadIdx.x; i < sizeof(SelState) / 4; i += blockDim.x) w[i] = 0;
 }
+__global__ void sel_init_kernel(SelState* st) { sel_init_body(st); }
 
 // Distinct keys of the set -> (key, estimate from the current counters).
 // Exact count of key in the router's table (linear probing from table_slot), or -1.
@@ -757,7 +758,7 @@ __device__ __forceinline__ int64_t table_count(const uint64_t* __restrict__ tk, 
 // With an exact table (ov_keys != NULL), a candidate found in it takes its exact count
 // as its estimate (the learned router's table; counts of up to 2^31 - 1).
 template <int MAXD, bool TAB_LDS>
-__global__ __launch_bounds__(256) void compact_kernel(const uint64_t* __restrict__ set, uint32_t slots, Tables t,
+__device__ __forceinline__ void compact_body(const uint64_t* __restrict__ set, uint32_t slots, Tables t,
                                                       const int32_t* __restrict__ M, uint32_t max_cand,
                                                       SelState* st, uint64_t* __restrict__ ck,
                                                       int32_t* __restrict__ ce, const uint64_t* __restrict__ ov_keys,
@@ -781,15 +782,24 @@ __global__ __launch_bounds__(256) void compact_kernel(const uint64_t* __restrict
     }
   }
 }
+template <int MAXD, bool TAB_LDS>
+__global__ __launch_bounds__(256) void compact_kernel(const uint64_t* __restrict__ set, uint32_t slots, Tables t,
+                                                      const int32_t* __restrict__ M, uint32_t max_cand,
+                                                      SelState* st, uint64_t* __restrict__ ck,
+                                                      int32_t* __restrict__ ce, const uint64_t* __restrict__ ov_keys,
+                                                      const uint32_t* __restrict__ ov_counts, uint32_t ov_mask) {
+  compact_body<MAXD, TAB_LDS>(set, slots, t, M, max_cand, st, ck, ce, ov_keys, ov_counts, ov_mask);
+}
 
-__global__ void clamp_m_kernel(SelState* st, uint32_t max_cand) {
+__device__ __forceinline__ void clamp_m_body(SelState* st, uint32_t max_cand) {
   if (threadIdx.x == 0 && st->m > max_cand) st->m = max_cand;
 }
+__global__ void clamp_m_kernel(SelState* st, uint32_t max_cand) { clamp_m_body(st, max_cand); }
 
 // Histogram of one 8-bit digit over the current class (stage 1: est; stage 2: key
 // among est == T).
 template <bool KEYS>
-__global__ __launch_bounds__(256) void sel_hist_kernel(const uint64_t* __restrict__ ck, const int32_t* __restrict__ ce,
+__device__ __forceinline__ void sel_hist_body(const uint64_t* __restrict__ ck, const int32_t* __restrict__ ce,
                                                        SelState* st, int shift) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
@@ -809,6 +819,11 @@ __global__ __launch_bounds__(256) void sel_hist_kernel(const uint64_t* __restric
   __syncthreads();
   if (h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], h[threadIdx.x]);
 }
+template <bool KEYS>
+__global__ __launch_bounds__(256) void sel_hist_kernel(const uint64_t* __restrict__ ck, const int32_t* __restrict__ ce,
+                                                       SelState* st, int shift) {
+  sel_hist_body<KEYS>(ck, ce, st, shift);
+}
 
 // Pick the digit holding the k_rem-th item: descending for estimates, ascending for keys.
 // One wave: position q of the scan order is digit 255 - q (estimates) or q (keys); lane l
@@ -816,7 +831,7 @@ __global__ __launch_bounds__(256) void sel_hist_kernel(const uint64_t* __restric
 // count reaches k_rem, or the last one (255) when none does; k_rem becomes k_rem minus the
 // count before it.  The histogram is cleared for the next pass.
 template <bool KEYS>
-__global__ __launch_bounds__(64) void sel_pick_kernel(SelState* st, uint32_t k, int shift) {
+__device__ __forceinline__ void sel_pick_body(SelState* st, uint32_t k, int shift) {
   const uint32_t lane = threadIdx.x;
   if (!KEYS && shift == 24 && lane == 0) st->k_rem = min(k, st->m);
   __syncthreads();
@@ -855,9 +870,13 @@ __global__ __launch_bounds__(64) void sel_pick_kernel(SelState* st, uint32_t k, 
 #pragma unroll
   for (int e = 0; e < 4; ++e) st->hist[lane * 4 + (uint32_t)e] = 0;
 }
+template <bool KEYS>
+__global__ __launch_bounds__(64) void sel_pick_kernel(SelState* st, uint32_t k, int shift) {
+  sel_pick_body<KEYS>(st, k, shift);
+}
 
 // Winners: est > T, or est == T and key <= K (T, K from the two stages).
-__global__ __launch_bounds__(256) void sel_gather_kernel(const uint64_t* __restrict__ ck, const int32_t* __restrict__ ce,
+__device__ __forceinline__ void sel_gather_body(const uint64_t* __restrict__ ck, const int32_t* __restrict__ ce,
                                                          SelState* st, uint32_t k, uint64_t* __restrict__ sk,
                                                          int32_t* __restrict__ se) {
   const uint32_t m = st->m;
@@ -882,6 +901,11 @@ __global__ __launch_bounds__(256) void sel_gather_kernel(const uint64_t* __restr
     }
   }
 }
+__global__ __launch_bounds__(256) void sel_gather_kernel(const uint64_t* __restrict__ ck, const int32_t* __restrict__ ce,
+                                                         SelState* st, uint32_t k, uint64_t* __restrict__ sk,
+                                                         int32_t* __restrict__ se) {
+  sel_gather_body(ck, ce, st, k, sk, se);
+}
 
 // Place each winner at its rank in (est desc, key asc); keys are distinct.
 // Rank of winner i = number of winners ahead of it in (estimate desc, key asc) order.
@@ -890,14 +914,14 @@ __global__ __launch_bounds__(256) void sel_gather_kernel(const uint64_t* __restr
 // so the ranks are a permutation of [0, n).
 constexpr uint32_t kRankChunk = 1024;      // smallest chunk
 constexpr uint32_t kMaxGridY = 65535;
-__global__ __launch_bounds__(256) void rank_count_kernel(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
-                                                         const SelState* st, uint32_t k, uint32_t chunk,
-                                                         uint32_t* __restrict__ rank) {
+__device__ __forceinline__ void rank_count_body(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
+                                                const SelState* st, uint32_t k, uint32_t chunk,
+                                                uint32_t* __restrict__ rank, uint32_t cy = blockIdx.y) {
   __shared__ uint64_t tk[256];
   __shared__ int32_t te[256];
   const uint32_t n = min(st->n_sel, k);
   const uint32_t i0 = blockIdx.x * 256;
-  const uint64_t j_lo64 = (uint64_t)blockIdx.y * chunk;
+  const uint64_t j_lo64 = (uint64_t)cy * chunk;
   if (i0 >= n || j_lo64 >= n) return;   // uniform over the block
   const uint32_t j_lo = (uint32_t)j_lo64;
   const uint32_t j_hi = (uint32_t)min((uint64_t)n, j_lo64 + chunk);
@@ -918,8 +942,13 @@ __global__ __launch_bounds__(256) void rank_count_kernel(const uint64_t* __restr
   }
   if (act && cnt) atomicAdd(&rank[i], cnt);
 }
+__global__ __launch_bounds__(256) void rank_count_kernel(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
+                                                         const SelState* st, uint32_t k, uint32_t chunk,
+                                                         uint32_t* __restrict__ rank) {
+  rank_count_body(sk, se, st, k, chunk, rank);
+}
 
-__global__ __launch_bounds__(256) void rank_place_kernel(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
+__device__ __forceinline__ void rank_place_body(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
                                                          const SelState* st, uint32_t k,
                                                          const uint32_t* __restrict__ rank, uint64_t* __restrict__ ok,
                                                          int32_t* __restrict__ oe) {
@@ -930,15 +959,24 @@ __global__ __launch_bounds__(256) void rank_place_kernel(const uint64_t* __restr
     oe[r] = se[i];
   }
 }
+__global__ __launch_bounds__(256) void rank_place_kernel(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
+                                                         const SelState* st, uint32_t k,
+                                                         const uint32_t* __restrict__ rank, uint64_t* __restrict__ ok,
+                                                         int32_t* __restrict__ oe) {
+  rank_place_body(sk, se, st, k, rank, ok, oe);
+}
 
 // Number written and status of a top-k, for callers that do not synchronize: out[0] =
 // min(k, m); out[1] = 1 (incomplete) when fewer than k were found from a partial set.
-__global__ void topk_out_kernel(const SelState* st, uint32_t k, uint32_t partial, uint32_t* out) {
+__device__ __forceinline__ void topk_out_body(const SelState* st, uint32_t k, uint32_t partial, uint32_t* out) {
   if (threadIdx.x == 0) {
     const uint32_t got = min(k, st->m);
     out[0] = got;
     out[1] = (got < k && partial) ? 1u : 0u;
   }
+}
+__global__ void topk_out_kernel(const SelState* st, uint32_t k, uint32_t partial, uint32_t* out) {
+  topk_out_body(st, k, partial, out);
 }
 
 hipError_t launch_topk_out(const SelState* st, uint32_t k, uint32_t partial, uint32_t* out, hipStream_t s) {
@@ -946,9 +984,10 @@ hipError_t launch_topk_out(const SelState* st, uint32_t k, uint32_t partial, uin
   return hipGetLastError();
 }
 
-__global__ void sel_finish_kernel(SelState* st, const uint32_t* err) {
+__device__ __forceinline__ void sel_finish_body(SelState* st, const uint32_t* err) {
   if (threadIdx.x == 0) st->err = *err;
 }
+__global__ void sel_finish_kernel(SelState* st, const uint32_t* err) { sel_finish_body(st, err); }
 
 __global__ void sel_set_m_kernel(SelState* st, uint32_t m) {
   if (threadIdx.x == 0) st->m = m;
@@ -977,6 +1016,93 @@ static hipError_t select_stages(const uint64_t* ck, const int32_t* ce, uint32_t 
                      sk, se, st, k, (uint32_t)chunk, rank);
   hipLaunchKernelGGL(rank_place_kernel, dim3(grid_for(k, 256, 1024)), dim3(256), 0, s, sk, se, st, k, rank, ok, oe);
   hipLaunchKernelGGL(sel_finish_kernel, dim3(1), dim3(64), 0, s, st, err);
+  return hipGetLastError();
+}
+
+// ---- the top-k of many sketches at once: block row blockIdx.y (blockIdx.z for the rank
+// count) serves sketch y of the descriptors; per-call k and outputs come by value.
+__global__ void sel_init_batch_kernel(const TopkDesc* __restrict__ D) { sel_init_body(D[blockIdx.y].st); }
+
+template <int MAXD, bool TAB_LDS>
+__global__ __launch_bounds__(256) void compact_batch_kernel(const TopkDesc* __restrict__ D) {
+  const TopkDesc& d = D[blockIdx.y];
+  compact_body<MAXD, TAB_LDS>(d.set, d.slots, d.t, d.M, d.max_cand, d.st, d.ck, d.ce, nullptr, nullptr, 0u);
+}
+
+__global__ void clamp_m_batch_kernel(const TopkDesc* __restrict__ D) {
+  clamp_m_body(D[blockIdx.y].st, D[blockIdx.y].max_cand);
+}
+
+template <bool KEYS>
+__global__ __launch_bounds__(256) void sel_hist_batch_kernel(const TopkDesc* __restrict__ D, int shift) {
+  const TopkDesc& d = D[blockIdx.y];
+  sel_hist_body<KEYS>(d.ck, d.ce, d.st, shift);
+}
+
+template <bool KEYS>
+__global__ __launch_bounds__(64) void sel_pick_batch_kernel(const TopkDesc* __restrict__ D, TopkCall call, int shift) {
+  sel_pick_body<KEYS>(D[blockIdx.y].st, call.k[blockIdx.y], shift);
+}
+
+__global__ __launch_bounds__(256) void sel_gather_batch_kernel(const TopkDesc* __restrict__ D, TopkCall call) {
+  const TopkDesc& d = D[blockIdx.y];
+  sel_gather_body(d.ck, d.ce, d.st, call.k[blockIdx.y], d.sk, d.se);
+}
+
+// ranks live in the first k words of each sketch's candidate estimates (no longer needed)
+__global__ __launch_bounds__(256) void rank_clear_batch_kernel(const TopkDesc* __restrict__ D, TopkCall call) {
+  uint32_t* r = (uint32_t*)D[blockIdx.y].ce;
+  const uint32_t k = call.k[blockIdx.y];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) r[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void rank_count_batch_kernel(const TopkDesc* __restrict__ D, TopkCall call,
+                                                               uint32_t chunk) {
+  const TopkDesc& d = D[blockIdx.z];
+  rank_count_body(d.sk, d.se, d.st, call.k[blockIdx.z], chunk, (uint32_t*)d.ce, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void rank_place_batch_kernel(const TopkDesc* __restrict__ D, TopkCall call) {
+  const TopkDesc& d = D[blockIdx.y];
+  rank_place_body(d.sk, d.se, d.st, call.k[blockIdx.y], (const uint32_t*)d.ce, call.keys[blockIdx.y],
+                  call.est[blockIdx.y]);
+}
+
+__global__ void sel_finish_out_batch_kernel(const TopkDesc* __restrict__ D, TopkCall call) {
+  const TopkDesc& d = D[blockIdx.y];
+  sel_finish_body(d.st, d.err);
+  topk_out_body(d.st, call.k[blockIdx.y], call.partial[blockIdx.y], call.out[blockIdx.y]);
+}
+
+hipError_t launch_topk_batch(const TopkDesc* D, uint32_t count, uint32_t d, uint32_t slots_max,
+                             uint32_t max_cand_max, uint32_t k_max, const TopkCall& call, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(sel_init_batch_kernel, dim3(1, count), dim3(256), 0, s, D);
+  const dim3 cgrid(grid_for(slots_max, 256, 4096), count);
+  if (d <= (uint32_t)kTabLdsRows)
+    hipLaunchKernelGGL((compact_batch_kernel<kTabLdsRows, true>), cgrid, dim3(256), 0, s, D);
+  else
+    hipLaunchKernelGGL((compact_batch_kernel<32, false>), cgrid, dim3(256), 0, s, D);
+  hipLaunchKernelGGL(clamp_m_batch_kernel, dim3(1, count), dim3(64), 0, s, D);
+  const dim3 hgrid(grid_for(max_cand_max, 256, 1024), count);
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(sel_hist_batch_kernel<false>, hgrid, dim3(256), 0, s, D, shift);
+    hipLaunchKernelGGL(sel_pick_batch_kernel<false>, dim3(1, count), dim3(64), 0, s, D, call, shift);
+  }
+  for (int shift = 40; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL(sel_hist_batch_kernel<true>, hgrid, dim3(256), 0, s, D, shift);
+    hipLaunchKernelGGL(sel_pick_batch_kernel<true>, dim3(1, count), dim3(64), 0, s, D, call, shift);
+  }
+  hipLaunchKernelGGL(sel_gather_batch_kernel, hgrid, dim3(256), 0, s, D, call);
+  if (k_max > 0) {
+    hipLaunchKernelGGL(rank_clear_batch_kernel, dim3(grid_for(k_max, 256, 1024), count), dim3(256), 0, s, D, call);
+    uint64_t chunk = kRankChunk;
+    while ((k_max + chunk - 1) / chunk > kMaxGridY) chunk *= 2;
+    hipLaunchKernelGGL(rank_count_batch_kernel, dim3((k_max + 255) / 256, (uint32_t)((k_max + chunk - 1) / chunk), count),
+                       dim3(256), 0, s, D, call, (uint32_t)chunk);
+    hipLaunchKernelGGL(rank_place_batch_kernel, dim3(grid_for(k_max, 256, 1024), count), dim3(256), 0, s, D, call);
+  }
+  hipLaunchKernelGGL(sel_finish_out_batch_kernel, dim3(1, count), dim3(64), 0, s, D, call);
   return hipGetLastError();
 }
 

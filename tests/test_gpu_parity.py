@@ -528,6 +528,68 @@ def test_batch_update_matches_oracle_per_sketch():
         s.close()
 
 
+def test_batch_topk_matches_oracle_and_replays_in_a_graph():
+    # the top-k of all sketches of a batch in one set of launches equals the oracle's top-k
+    # of each (counts, incomplete flags, keys, estimates), for uneven k (0 included) and
+    # thresholds, eagerly and from three replays of a captured graph
+    import torch
+    say("batch top-k", len(BATCH_SHAPES))
+    sk, pos1, _ = batch_case(BATCH_SHAPES)
+    pos = [dev(p) for p in pos1]
+    b = csk.Batch(sk, [max(1, p.shape[0]) for p in pos1], 0.1, 100.0)
+    ks = [7, 0, 64, 300, 1000, 2500, 1]
+    thetas = [3, 2, oracle.INT32_MIN, 4, 3, oracle.INT32_MIN, 2]
+    keys = [torch.empty(max(k, 1), dtype=torch.int64, device="cuda") for k in ks]
+    est = [torch.empty(max(k, 1), dtype=torch.int32, device="cuda") for k in ks]
+    outs = [torch.zeros(2, dtype=torch.int32, device="cuda") for _ in ks]
+
+    def pipeline():
+        b.update(pos)
+        for j, s in enumerate(sk):
+            s.clear_candidates()
+            s.collect(pos[j], 0.1, 100.0, thetas[j])
+        b.topk(ks, keys, est, outs)
+
+    for s in sk:
+        s.reset()
+    pipeline()
+    torch.cuda.synchronize()
+    want = []
+    for j, (n1, _, w, seed) in enumerate(BATCH_SHAPES):
+        Mo, _ = oracle.sketch(pos1[j], 5, w, seed, 0.1, 100.0, threads=8)
+        ko, eo, st = oracle.topk_sketch(Mo, oracle.hash_tables(seed, 5), pos1[j], 0.1, 100.0, thetas[j], ks[j])
+        o = outs[j].cpu().numpy()
+        got = int(o[0])
+        assert got == len(ko), (j, got, len(ko))
+        assert o[1] == (1 if (st == oracle.W_INCOMPLETE and ks[j] > 0) else 0), (j, o, st)
+        assert np.array_equal(keys[j].cpu().numpy()[:got].view(np.uint64), ko), j
+        assert np.array_equal(est[j].cpu().numpy()[:got], eo), j
+        want.append((o.copy(), keys[j].cpu().numpy()[:got].copy(), est[j].cpu().numpy()[:got].copy()))
+    for s in sk:
+        s.reset()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pipeline()
+    for rep in range(3):
+        for s in sk:
+            s.reset()
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for j, (o, kk, e) in enumerate(want):
+            got = int(o[0])
+            assert np.array_equal(outs[j].cpu().numpy(), o), (rep, j)
+            assert np.array_equal(keys[j].cpu().numpy()[:got], kk), (rep, j)
+            assert np.array_equal(est[j].cpu().numpy()[:got], e), (rep, j)
+    del g
+    b.close()
+    for s in sk:
+        s.close()
+
+
 def test_batch_create_rejects_mixed_sketches():
     a, c = csk.Sketch(5, 1 << 14, 1), csk.Sketch(4, 1 << 14, 2)
     with pytest.raises(csk.CskError) as e:
