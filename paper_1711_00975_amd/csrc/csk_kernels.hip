@@ -233,52 +233,103 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
       }
       cand |= (uint32_t)go << j;
     }
-    // the particles that may pass: exact test, unless the key is known to be in the set
+    // The particles that may pass.  A key seen recently by this workgroup, or already in the
+    // set, needs no exact test: heavy cells repeat thousands of times, and the set only ever
+    // gains keys.  The first set slot of every candidate is loaded before any is compared,
+    // so that the thread waits on one round trip for all its keys rather than one per key.
+    auto cache_slot = [](uint64_t key) { return (uint32_t)(key ^ (key >> 21)) & (kCollectCache - 1); };
+    uint32_t todo = cand;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      if (!(cand & (1u << j))) continue;
-      const uint64_t key = keys[j];
-      // a key seen recently by this workgroup, or already in the set, needs no exact test:
-      // heavy cells repeat thousands of times, and the set only ever gains keys
-      const uint32_t ci = (uint32_t)(key ^ (key >> 21)) & (kCollectCache - 1);
-      if (__hip_atomic_load(&cache[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == key) continue;
-      if (set_contains(set, slot_mask, key)) {
-        __hip_atomic_store(&cache[ci], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        continue;
+      if ((todo >> j) & 1u)
+        if (__hip_atomic_load(&cache[cache_slot(keys[j])], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == keys[j])
+          todo &= ~(1u << j);
+    }
+    // the first slot of each key's probe sequence in the set
+    uint64_t s0[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      s0[j] = kEmptyKey;
+      if ((todo >> j) & 1u) s0[j] = set[(uint32_t)slot_mix(keys[j]) & slot_mask];
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (!((todo >> j) & 1u)) continue;
+      bool in = s0[j] == keys[j];
+      if (!in && s0[j] != kEmptyKey) in = set_contains(set, slot_mask, keys[j]);   // a longer probe run
+      if (in) {
+        __hip_atomic_store(&cache[cache_slot(keys[j])], keys[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        todo &= ~(1u << j);
       }
-      uint32_t bk[D], ng[D];
-      rows_bucket_sign<D, HM>(ti, key, mesh.nch, t.w, t.wshift, bk, ng);
+    }
+    // The exact test of the rest.  With the hot-item set (2 MiB, resident in L2) the first
+    // slot of every row of four keys is loaded before any is compared.  Without it the
+    // counters are read row by row until the answer is known: in a large table those reads
+    // go to HBM, and stopping early saves more than overlapping them gains.
+    if (uh) {
+      constexpr int GQ = D <= 5 ? 4 : 2;
+      static_assert(PPT % GQ == 0, "whole groups of keys");
 #pragma unroll
-      for (int r = 0; r < D; ++r) ng[r] &= t.cm ^ 1u;
-      uint32_t pass = 0;
-      if (uh) {
-        // row r passes (sign * M >= theta) exactly when its item is in the hot set
+      for (int j0 = 0; j0 < PPT; j0 += GQ) {
+        if (!((todo >> j0) & ((1u << GQ) - 1u))) continue;
+        uint32_t item[GQ][D], v[GQ][D];
 #pragma unroll
-        for (int r = 0; r < D; ++r) {
-          if (pass >= need || pass + (uint32_t)(D - r) < need) break;
-          const uint32_t item = hot_item((uint32_t)r, bk[r], ng[r]);
-          uint32_t sl = hot_slot(item);
-          for (uint32_t probe = 0; probe < kHotSlots; ++probe) {
-            const uint32_t v = hot_table[sl];
-            if (v == item) {
-              ++pass;
-              break;
-            }
-            if (v == kHotEmpty) break;
-            sl = (sl + 1) & (kHotSlots - 1);
+        for (int q = 0; q < GQ; ++q) {
+          if (!((todo >> (j0 + q)) & 1u)) continue;
+          uint32_t bk[D], ng[D];
+          rows_bucket_sign<D, HM>(ti, keys[j0 + q], mesh.nch, t.w, t.wshift, bk, ng);
+#pragma unroll
+          for (int r = 0; r < D; ++r) {
+            item[q][r] = hot_item((uint32_t)r, bk[r], ng[r] & (t.cm ^ 1u));
+            v[q][r] = hot_table[hot_slot(item[q][r])];
           }
         }
-      } else {
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) {
+          const int j = j0 + q;
+          if (!((todo >> j) & 1u)) continue;
+          // row r passes (sign * M >= theta) exactly when its item is in the hot set
+          uint32_t pass = 0;
+#pragma unroll
+          for (int r = 0; r < D; ++r) {
+            bool hit = v[q][r] == item[q][r];
+            if (!hit && v[q][r] != kHotEmpty) {
+              uint32_t sl = (hot_slot(item[q][r]) + 1) & (kHotSlots - 1);
+              for (uint32_t probe = 1; probe < kHotSlots; ++probe) {
+                const uint32_t x = hot_table[sl];
+                if (x == item[q][r]) {
+                  hit = true;
+                  break;
+                }
+                if (x == kHotEmpty) break;
+                sl = (sl + 1) & (kHotSlots - 1);
+              }
+            }
+            pass += hit ? 1u : 0u;
+          }
+          if (pass >= need) {
+            set_insert(set, slot_mask, keys[j], set_count, max_cand, err);
+            __hip_atomic_store(&cache[cache_slot(keys[j])], keys[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        if (!((todo >> j) & 1u)) continue;
+        uint32_t bk[D], ng[D];
+        rows_bucket_sign<D, HM>(ti, keys[j], mesh.nch, t.w, t.wshift, bk, ng);
+        uint32_t pass = 0;
 #pragma unroll
         for (int r = 0; r < D; ++r) {
           if (pass >= need || pass + (uint32_t)(D - r) < need) break;
           const uint32_t c = (uint32_t)M[(uint64_t)r * t.w + bk[r]];
-          if ((int32_t)(ng[r] ? 0u - c : c) >= theta) ++pass;
+          if ((int32_t)((ng[r] & (t.cm ^ 1u)) ? 0u - c : c) >= theta) ++pass;
         }
-      }
-      if (pass >= need) {
-        set_insert(set, slot_mask, key, set_count, max_cand, err);
-        __hip_atomic_store(&cache[ci], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (pass >= need) {
+          set_insert(set, slot_mask, keys[j], set_count, max_cand, err);
+          __hip_atomic_store(&cache[cache_slot(keys[j])], keys[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
       }
     }
   }

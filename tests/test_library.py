@@ -44,6 +44,7 @@ def test_argument_errors_are_returned_without_a_device():
     assert lib.csk_collect_children(None, None, 0, None) == csk.CSK_E_INVALID
     assert lib.csk_batch_create(None, None, None, 1, 0.1, 100.0, 0) == csk.CSK_E_INVALID
     assert lib.csk_batch_update(None, None, None, None) == csk.CSK_E_INVALID
+    assert lib.csk_batch_topk(None, None, None, None, None, None) == csk.CSK_E_INVALID
     assert lib.csk_topk_async(None, 1, None, None, None, None) == csk.CSK_E_INVALID
     assert lib.csk_sketch_init_group(C.byref(h), 5, 16, 1, 0, 0, 0) == csk.CSK_E_INVALID
     # learned router
