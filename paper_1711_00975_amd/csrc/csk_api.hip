@@ -613,10 +613,22 @@ csk_status csk_set_counters(csk_sketch* s, const int32_t* in, void* stream) {
 csk_status csk_reset(csk_sketch* s, void* stream) {
   if (s == nullptr) return fail(CSK_E_INVALID, "reset: NULL handle");
   hipStream_t st = (hipStream_t)stream;
-  CSK_HIP(launch_fill_u32((uint32_t*)s->M, (uint64_t)s->d * s->w, 0u, st), "reset");
-  CSK_HIP(launch_fill_u32(s->err(), 1, 0u, st), "reset");
+  // counters, latch, candidate set (empty slots are all-ones words) and its count in one launch
+  FillSpans f{};
+  f.p[0] = (uint32_t*)s->M;
+  f.n[0] = (uint64_t)s->d * s->w;
+  f.p[1] = s->err();
+  f.n[1] = 1;
+  f.p[2] = (uint32_t*)s->set;
+  f.n[2] = 2ull * s->slots;
+  f.v[2] = 0xFFFFFFFFu;
+  f.p[3] = s->set_count();
+  f.n[3] = 1;
+  static_assert(kEmptyKey == ~0ull, "an empty slot is two all-ones words");
+  CSK_HIP(launch_fill_spans(f, st), "reset");
   s->mesh_set = false;
-  return clear_candidates(s, st);
+  s->partial_set = false;
+  return CSK_OK;
 }
 
 csk_status csk_check(csk_sketch* s, void* stream) {

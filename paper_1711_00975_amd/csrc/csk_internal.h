@@ -155,6 +155,15 @@ hipError_t launch_collect_children(const uint64_t* coarse_set, uint32_t coarse_s
 hipError_t launch_topk_out(const SelState* st, uint32_t k, uint32_t partial, uint32_t* out, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+// Up to kFillSpans spans of 32-bit words, span r set to v[r], in one launch (the clears of a
+// handle's state).  A span with n[r] = 0 is skipped and its pointer is not used.
+constexpr int kFillSpans = 4;
+struct FillSpans {
+  uint32_t* p[kFillSpans];
+  uint64_t n[kFillSpans];
+  uint32_t v[kFillSpans];
+};
+hipError_t launch_fill_spans(const FillSpans& f, hipStream_t s);
 // ov_keys / ov_counts / ov_mask: an exact table whose counts replace the estimates of the
 // candidates found in it (NULL: none).
 hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,

@@ -615,9 +615,15 @@ __global__ __launch_bounds__(256) void hot_build_kernel(const int32_t* __restric
 
 hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta, uint32_t* filter, uint32_t* hot,
                                uint32_t* hot_table, hipStream_t s) {
-  hipError_t e = launch_fill_u32(filter, kFilterWords, 0u, s);
-  if (e == hipSuccess) e = launch_fill_u32(hot, 1, 0u, s);
-  if (e == hipSuccess && hot_table != nullptr) e = launch_fill_u32(hot_table, kHotSlots, kHotEmpty, s);
+  FillSpans f{};   // the three clears in one launch
+  f.p[0] = filter;
+  f.n[0] = kFilterWords;
+  f.p[1] = hot;
+  f.n[1] = 1;
+  f.p[2] = hot_table;
+  f.n[2] = hot_table != nullptr ? kHotSlots : 0;
+  f.v[2] = kHotEmpty;
+  hipError_t e = launch_fill_spans(f, s);
   if (e != hipSuccess) return e;
   const dim3 grid(grid_for((t.w + 4 * kFilterVec - 1) / (4 * kFilterVec), 256, 8192));
   hipLaunchKernelGGL(filter_build_kernel, grid, dim3(256), 0, s, M, t.d, t.w, t.cm, t.bnorm, theta, filter, hot);
@@ -781,6 +787,28 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// Word i of the concatenated spans goes to the span it falls in (spans of length 0 are skipped).
+__global__ void fill_spans_kernel(FillSpans f) {
+  const uint64_t total = f.n[0] + f.n[1] + f.n[2] + f.n[3];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    uint64_t j = i;
+    int r = 0;
+    while (r < kFillSpans - 1 && j >= f.n[r]) {
+      j -= f.n[r];
+      ++r;
+    }
+    f.p[r][j] = f.v[r];
+  }
+}
+hipError_t launch_fill_spans(const FillSpans& f, hipStream_t s) {
+  uint64_t total = 0;
+  for (int r = 0; r < kFillSpans; ++r) total += f.n[r];
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_spans_kernel, dim3(grid_for(total, 256, 4096)), dim3(256), 0, s, f);
   return hipGetLastError();
 }
 
