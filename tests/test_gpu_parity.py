@@ -242,6 +242,35 @@ def test_domain_errors_latch_and_skip():
     s.close()
 
 
+def test_reset_gives_a_fresh_handle():
+    # reset clears counters, latch, candidate set and its count in one launch: after it the
+    # handle must behave exactly like a new one, for the update and for a filtered collect
+    a = clustered(120_000, 100.0, 71)
+    a[::997, 0] = np.nan                      # latches a domain error before the reset
+    b = clustered(90_000, 100.0, 72)
+    s = csk.Sketch(5, 1 << 14, 4, max_candidates=1 << 15)
+    s.update(dev(a), 0.1, 100.0)
+    s.collect(dev(a), 0.1, 100.0, 5)
+    s.reset()
+    assert not s.counters().cpu().numpy().any()
+    s.check()                                 # the latch is clear
+    kk, ee, rc = s.topk(10)                   # the set is empty and not partial
+    assert kk.numel() == 0 and rc == csk.CSK_OK
+    s.update(dev(b), 0.1, 100.0)
+    M = oracle.sketch(b, 5, 1 << 14, 4, 0.1, 100.0)[0]
+    assert np.array_equal(s.counters().cpu().numpy(), M)
+    T = oracle.hash_tables(4, 5)
+    keys = oracle.keys(b, 0.1, 100.0)
+    for theta in (6, 40):                     # the filter and hot set are rebuilt per collect
+        s.clear_candidates()
+        s.collect(dev(b), 0.1, 100.0, theta)
+        got_k, got_e, rc = s.topk(200)
+        want_k, want_e = oracle.topk_keys(M, T, keys, theta, 200)
+        assert got_k.cpu().numpy().view(np.uint64).tolist() == want_k.tolist()
+        assert got_e.cpu().numpy().tolist() == want_e.tolist()
+    s.close()
+
+
 # ------------------------------------------------------------------ estimates, top-k
 
 def test_query_matches_oracle():
