@@ -263,9 +263,9 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
       }
     }
     // The exact test of the rest.  With the hot-item set (2 MiB, resident in L2) the first
-    // slot of every row of four keys is loaded before any is compared.  Without it the
-    // counters are read row by row until the answer is known: in a large table those reads
-    // go to HBM, and stopping early saves more than overlapping them gains.
+    // slot of every row of a group of keys (four for d <= 5, else two) is loaded before any
+    // is compared.  Without it the counters are read row by row until the answer is known;
+    // in a large table those reads go to HBM, and reading all d rows at once was no faster.
     if (uh) {
       constexpr int GQ = D <= 5 ? 4 : 2;
       static_assert(PPT % GQ == 0, "whole groups of keys");
