@@ -262,6 +262,11 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
         todo &= ~(1u << j);
       }
     }
+    // Other threads of the workgroup may have inserted a key since the first cache check;
+    // looking again before the exact test spares it (one LDS read).
+    auto recheck = [&](uint64_t key) {
+      return __hip_atomic_load(&cache[cache_slot(key)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == key;
+    };
     // The exact test of the rest.  With the hot-item set (2 MiB, resident in L2) the first
     // slot of every row of a group of keys (four for d <= 5, else two) is loaded before any
     // is compared.  Without it the counters are read row by row until the answer is known;
@@ -276,6 +281,10 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
 #pragma unroll
         for (int q = 0; q < GQ; ++q) {
           if (!((todo >> (j0 + q)) & 1u)) continue;
+          if (recheck(keys[j0 + q])) {
+            todo &= ~(1u << (j0 + q));
+            continue;
+          }
           uint32_t bk[D], ng[D];
           rows_bucket_sign<D, HM>(ti, keys[j0 + q], mesh.nch, t.w, t.wshift, bk, ng);
 #pragma unroll
@@ -316,7 +325,7 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
     } else {
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        if (!((todo >> j) & 1u)) continue;
+        if (!((todo >> j) & 1u) || recheck(keys[j])) continue;
         uint32_t bk[D], ng[D];
         rows_bucket_sign<D, HM>(ti, keys[j], mesh.nch, t.w, t.wshift, bk, ng);
         uint32_t pass = 0;
