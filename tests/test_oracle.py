@@ -759,3 +759,105 @@ def test_topk_keys_matches_exact_top_without_collisions():
     assert np.array_equal(k_keys, e_keys) and np.array_equal(k_est, e_cnt.astype(np.int32))
     k2, e2 = oracle.topk_keys(M, T, keys, int(e_cnt[9]), 50)         # theta cuts at the 10th count
     assert np.array_equal(k2, k_keys[k_est >= e_cnt[9]])
+
+
+# ------------------------------------------------------------ router reference pins
+
+@pytest.fixture(scope="module")
+def torch_philox(tmp_path_factory):
+    """PyTorch's own Philox4x32-10 engine (Salmon et al., SC'11), built from its header:
+    an implementation that shares nothing with the workload generator's."""
+    import ctypes
+    import subprocess
+    import torch
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    src = os.path.join(os.path.dirname(__file__), "torch_philox_ref.cpp")
+    so = str(tmp_path_factory.mktemp("philox") / "torch_philox_ref.so")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-I", inc, "-o", so, src], check=True)
+    lib = ctypes.CDLL(so)
+
+    def words(ctr, key):
+        c = np.ascontiguousarray(ctr, dtype=np.uint32)
+        k = np.ascontiguousarray(key, dtype=np.uint32)
+        out = np.zeros(4, dtype=np.uint32)
+        lib.torch_philox4x32_10(c.ctypes.data_as(ctypes.c_void_p), k.ctypes.data_as(ctypes.c_void_p),
+                                out.ctypes.data_as(ctypes.c_void_p))
+        return out
+    return words
+
+
+def test_philox_matches_an_independent_engine(torch_philox):
+    import workloads
+    rng = np.random.default_rng(77)
+    cases = [([0, 0, 0, 0], [0, 0]), ([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2), ([1, 0, 0, 0], [0, 0]),
+             ([0, 0, 0, 1], [1, 0]), ([12345, 0, 4, 0], [9, 0])]
+    cases += [(rng.integers(0, 2 ** 32, 4, dtype=np.uint64), rng.integers(0, 2 ** 32, 2, dtype=np.uint64))
+              for _ in range(500)]
+    for ctr, key in cases:
+        assert np.array_equal(workloads.philox4x32_10(ctr, key), torch_philox(ctr, key)), (ctr, key)
+    # the batch form: word 0 at counter (index mod 2^32, index / 2^32, stream, 0), key = seed
+    for index0, stream, seed in [(0, 1, 1), (2 ** 32 - 3, 4, 2 ** 40 + 5), (10 ** 12, 2, 9)]:
+        got = workloads.philox_words(index0, 6, stream, seed)
+        for i in range(6):
+            g = index0 + i
+            want = torch_philox([g & 0xFFFFFFFF, g >> 32, stream, 0], [seed & 0xFFFFFFFF, seed >> 32])[0]
+            assert got[i] == want, (index0, stream, seed, i)
+
+
+def test_router_sample_counts_by_particle_loop(torch_philox):
+    # One particle at a time: the coin is word 0 of the independent engine at counter
+    # (index, stream 4), the cell is the exact floor by rationals, and a particle outside the
+    # domain is never counted.
+    from oracle import router
+    rng = np.random.default_rng(31)
+    L, dc, seed = 10.0, 2.5, 2 ** 33 + 17
+    Gc = 4
+    pos = (rng.random((3000, 3)) ** 2 * L).astype(np.float32)
+    pos[5] = [np.nan, 1.0, 1.0]
+    pos[6] = [1.0, 2 * L, 1.0]
+    pos[7] = [-1.0, 0.0, np.float32(L)]        # wraps into the box
+    for index0, threshold in [(0, 2 ** 31), (2 ** 32 - 1000, 2 ** 30), (123, router.SAMPLE_THRESHOLD)]:
+        want = np.zeros(Gc ** 3, dtype=np.int64)
+        for i, p in enumerate(pos):
+            g = index0 + i
+            coin = torch_philox([g & 0xFFFFFFFF, g >> 32, router.SAMPLE_STREAM, 0],
+                                [seed & 0xFFFFFFFF, seed >> 32])[0]
+            if coin >= threshold:
+                continue
+            if not all(math.isfinite(float(c)) and abs(float(c)) < 2 * L for c in p):
+                continue
+            ix, iy, iz = (exact_index(float(c), Gc, L) for c in p)
+            want[(ix * Gc + iy) * Gc + iz] += 1
+        got = router.sample_counts(pos, dc, L, seed, index0, threshold)
+        assert got.dtype == np.uint32 and np.array_equal(got.astype(np.int64), want), (index0, threshold)
+
+
+def test_router_topk_routed_by_dict_merge():
+    # The merged top-k of the routed pair, rebuilt with a dictionary: table keys enter with
+    # their exact counts whatever theta is; a rest cell enters with the lower median of its
+    # per-row estimates (computed row by row here) when that is >= theta; the order is
+    # (value desc, key asc) and at most k come out.
+    from oracle import router
+    rng = np.random.default_rng(12)
+    L, delta, d, w, seed = 10.0, 0.5, 5, 64, 3           # w = 64: many collisions
+    G = 20
+    rest = small_stream(4000, L, seed=4)
+    rk_all = oracle.keys(rest, delta, L)
+    present = set(int(x) for x in np.unique(rk_all))
+    absent = [c for c in range(G ** 3) if c not in present]
+    tkeys = np.sort(rng.choice(absent, 30, replace=False)).astype(np.uint64)
+    tcounts = rng.integers(1, 40, 30).astype(np.int64)
+    tcounts[:6] = [7, 7, 7, 1, 1, 300]                     # ties, and counts below theta
+    M, _ = oracle.sketch(rest, d, w, seed, delta, L)
+    T = oracle.hash_tables(seed, d)
+    uniq = np.unique(rk_all)
+    E = np.sort(per_row_estimates(M, T, uniq), axis=0)[(d - 1) // 2]
+    for theta, k in [(oracle.INT32_MIN, 50), (5, 40), (20, 10 ** 4), (10 ** 6, 12), (8, 1)]:
+        cand = {int(kk): int(c) for kk, c in zip(tkeys, tcounts)}
+        for kk, e in zip(uniq, E):
+            if e >= theta:
+                cand[int(kk)] = int(e)
+        want = sorted(cand.items(), key=lambda kv: (-kv[1], kv[0]))[:k]
+        gk, gv = router.topk_routed(tkeys, tcounts, M, T, rest, delta, L, theta, k)
+        assert list(gk) == [kk for kk, _ in want] and list(gv) == [v for _, v in want], (theta, k)
+        assert len(gk) == min(k, len(cand))
