@@ -688,3 +688,42 @@ def test_batch_pipeline_in_a_hip_graph():
     b.close()
     for s in sk:
         s.close()
+
+
+# ------------------------------------------------------------------ headline configuration
+
+def test_headline_config_prefix_update_collect_topk():
+    # The 2^30-particle configuration (L = 1000, delta = 0.25, 4000^3 cells, d = 5, w = 2^24,
+    # k = 10^4) on the first 2^24 particles of its own stream: one update call of 2048 tiles of
+    # 8192 particles over 256 bin workgroups (8 tiles each), then the candidate pass through
+    # the Bloom filter and the exact hot-item set (w = 2^24: 24-bit buckets in the packed
+    # fields) and the top-10^4, each against the oracle (Sec. 2.2 Add, Estimate, UpdateHeap;
+    # Sec. 3.1 item 4).  theta is the oracle's own 10^4-th estimate, so the result is complete;
+    # theta = 1024 leaves about a thousand candidates: an incomplete result.
+    wl = workloads.SCALE
+    n = 1 << 24
+    say("headline prefix", wl.name, n)
+    pos = wl.generate(0, n)
+    s, M = gpu_counters(pos, wl.d, wl.w, wl.seed, wl.delta, wl.L)
+    Mo, skipped = oracle.sketch(pos, wl.d, wl.w, wl.seed, wl.delta, wl.L, threads=16)
+    assert skipped == 0
+    assert np.array_equal(M, Mo)
+    T = oracle.hash_tables(wl.seed, wl.d)
+    uniq, _ = oracle.histogram(oracle.keys(pos, wl.delta, wl.L))
+    est_all = oracle.estimate(Mo, T, uniq)
+    kth = int(np.sort(est_all)[::-1][wl.k - 1])
+    hot = int((np.abs(Mo.astype(np.int64)) >= kth).sum())
+    say("10^4-th estimate", kth, "rows x buckets at or above it", hot)
+    assert 1 <= kth and hot <= 131072          # the filter and the hot-item set are both in use
+    t = dev(pos)
+    for theta, complete in ((kth, True), (1024, False)):
+        s.clear_candidates()
+        s.collect(t, wl.delta, wl.L, theta)
+        keys, est, rc = s.topk(wl.k)
+        ko, eo, st = oracle.topk_sketch(Mo, T, pos, wl.delta, wl.L, theta, wl.k)
+        say("theta", theta, "returned", len(ko))
+        assert (st == oracle.OK) == complete and (len(ko) == wl.k) == complete
+        assert np.array_equal(keys.cpu().numpy().view(np.uint64), ko)
+        assert np.array_equal(est.cpu().numpy(), eo)
+        assert rc == (csk.CSK_OK if complete else csk.CSK_W_INCOMPLETE)
+    s.close()
