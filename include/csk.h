@@ -94,6 +94,20 @@ csk_status csk_sketch_destroy(csk_sketch *s);
 csk_status csk_sketch_update(csk_sketch *s, const float *pos, uint64_t n, double delta, double L,
                              void *stream);
 
+/* csk_sketch_update for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, hosts that forbid hipMalloc.  The same counters
+ * come out, but the token scratch is a fixed 64 MiB array that the library holds on
+ * each device for the life of the process (set up by csk_sketch_init on that device),
+ * so this call never allocates or frees.  A stream whose scratch need exceeds 64 MiB
+ * (about 3.5e6 particles at d = 5; fewer on very wide rows) returns CSK_E_CAPACITY at
+ * once, before anything is launched or latched: split it into smaller calls.  Every
+ * call on one device shares that device's scratch: calls that overlap in time (on
+ * different streams, or from different threads) race and must be serialised by the
+ * caller.  Nothing in the scratch needs clearing between calls: each call writes the
+ * counts it reads.  Arguments, errors and ordering as csk_sketch_update. */
+csk_status csk_sketch_update_noalloc(csk_sketch *s, const float *pos, uint64_t n, double delta, double L,
+                                     void *stream);
+
 #define CSK_UPDATE_AUTO   0 /* LDS-binned when the rows fit it, else global atomics  */
 #define CSK_UPDATE_BINNED 1 /* LDS-binned tokens, summed per counter slice          */
 #define CSK_UPDATE_DIRECT 2 /* one global atomic add per row and particle           */

@@ -34,6 +34,7 @@ CSK_DEFAULT_CANDIDATES = 1 << 21
 INT32_MIN = -(2 ** 31)
 
 EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "csk_sketch_destroy", "csk_sketch_update",
+           "csk_sketch_update_noalloc",
            "csk_set_update_plan",
            "csk_sketch_query", "csk_cell_keys", "csk_collect",
            "csk_pack_positions", "csk_sketch_update_packed", "csk_collect_packed", "csk_cell_keys_packed", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
@@ -72,6 +73,7 @@ def load_library(path: str = LIB_PATH):
         "csk_sketch_init_group": [PP, u32, u32, u64, i32, u64, u32],
         "csk_sketch_destroy": [P],
         "csk_sketch_update": [P, P, u64, f64, f64, P],
+        "csk_sketch_update_noalloc": [P, P, u64, f64, f64, P],
         "csk_set_update_plan": [P, i32, u32],
         "csk_sketch_query": [P, P, u64, P, P],
         "csk_cell_keys": [P, u64, f64, f64, P, P],
@@ -190,6 +192,12 @@ def csk_sketch_update(h, pos, delta: float, L: float, stream=None) -> None:
     import torch
     _check(load_library().csk_sketch_update(h, _dev(pos, torch.float32, 3), pos.shape[0], delta, L,
                                             _stream(stream)))
+
+
+def csk_sketch_update_noalloc(h, pos, delta: float, L: float, stream=None) -> None:
+    import torch
+    _check(load_library().csk_sketch_update_noalloc(h, _dev(pos, torch.float32, 3), pos.shape[0], delta, L,
+                                                    _stream(stream)))
 
 
 def csk_sketch_query(h, keys, est, stream=None) -> None:
@@ -392,6 +400,9 @@ class Sketch:
 
     def update(self, pos, delta, L, stream=None):
         csk_sketch_update(self.h, pos, delta, L, stream)
+
+    def update_noalloc(self, pos, delta, L, stream=None):
+        csk_sketch_update_noalloc(self.h, pos, delta, L, stream)
 
     def query(self, keys, stream=None):
         import torch

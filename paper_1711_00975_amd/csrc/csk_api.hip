@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -85,6 +86,34 @@ std::vector<uint32_t> pack_tables(const std::vector<uint32_t>& T, uint32_t d) {
     }
   }
   return P;
+}
+
+// Scratch of csk_sketch_update_noalloc: the token regions of one bin plan, then their
+// counts.  Each device holds its own copy for the life of the process; host code never
+// uses the array's name as an address, only the per-device pointer that
+// hipGetSymbolAddress returns for it (noalloc_scratch()).
+constexpr uint64_t kNoAllocScratchBytes = 64ull << 20;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+uint8_t* g_scratch_ptr[kNoAllocMaxDevices] = {};
+std::mutex g_scratch_mutex;
+
+// Looks up this device's copy of `scratch` once per device (the device is current).
+hipError_t noalloc_scratch_setup(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[device] != nullptr) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = (uint8_t*)ptr;
+  return hipSuccess;
+}
+
+uint8_t* noalloc_scratch(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace
@@ -268,6 +297,7 @@ csk_status csk_sketch_init_group(csk_sketch** out, uint32_t d, uint32_t w, uint6
   while (slots < 2 * max_candidates) slots <<= 1;
   s->slots = (uint32_t)slots;
   hipError_t e = hipGetDevice(&s->device);
+  if (e == hipSuccess) e = noalloc_scratch_setup(s->device);
   const auto T = make_tables(seed, d);
   s->dp = (d <= 4) ? 4u : (d <= 6 ? 6u : (d <= (uint32_t)kTabLdsRows ? 8u : 0u));
   std::vector<uint32_t> Ti;
@@ -331,19 +361,57 @@ csk_status csk_set_update_plan(csk_sketch* s, int32_t mode, uint32_t max_wg) {
 namespace {
 
 // The update of a float (x, y, z) stream, or of a packed stream (src = 64-bit words).
+// noalloc: tokens go to the device's static scratch, never to memory allocated here;
+// a stream whose bin plan does not fit it is refused before anything runs.
 csk_status update_impl(csk_sketch* s, const void* src, bool packed, uint64_t n, double delta, double L,
-                       void* stream) {
+                       void* stream, bool noalloc = false) {
   if (s == nullptr) return fail(CSK_E_INVALID, "update: NULL handle");
   Mesh mesh;
   csk_status rc = check_mesh(s, delta, L, &mesh);
   if (rc != CSK_OK) return rc;
   if (n > 0 && src == nullptr) return fail(CSK_E_INVALID, "update: NULL positions");
   if (n > (1ull << 40)) return fail(CSK_E_INVALID, "update: n above 2^40");
+  hipStream_t st = (hipStream_t)stream;
+  const Tables t = s->tables();
+  if (noalloc) {
+    uint8_t* base = noalloc_scratch(s->device);
+    if (base == nullptr) return fail(CSK_E_STATE, "update_noalloc: no scratch for device %d", s->device);
+    if (n > (1ull << 30)) return fail(CSK_E_CAPACITY, "update_noalloc: n=%llu above 2^30", (unsigned long long)n);
+    BinPlan plan;
+    bool binned = false;
+    uint64_t tok_need = 0, need = 0;
+    if (s->upd_mode != CSK_UPDATE_DIRECT) {
+      // the usual plan, else fewer workgroups (shorter regions), until the regions fit
+      for (uint64_t max_wg = bin_wg_cap(s->d, s->upd_max_wg); max_wg >= 1; max_wg /= 2) {
+        if (!plan_bin_wg(n, s->d, s->w, max_wg, plan)) break;
+        binned = true;
+        tok_need = ((uint64_t)plan.P * plan.nwg * plan.cap * sizeof(uint16_t) + 255) & ~255ull;
+        need = tok_need + (uint64_t)plan.P * plan.nwg * sizeof(uint32_t);
+        if (need <= kNoAllocScratchBytes || max_wg == 1) break;
+      }
+    }
+    if (binned && need > kNoAllocScratchBytes)
+      return fail(CSK_E_CAPACITY,
+                  "update_noalloc: %llu particles at d=%u, w=%u need %llu bytes of token scratch; the "
+                  "no-allocation update holds %llu: split the stream",
+                  (unsigned long long)n, s->d, s->w, (unsigned long long)need,
+                  (unsigned long long)kNoAllocScratchBytes);
+    latch_mesh(s, delta, L, mesh);
+    if (n == 0) return CSK_OK;
+    if (packed) mesh.mode = kMeshPacked;
+    if (!binned) {
+      CSK_HIP(launch_update_direct((const float*)src, n, mesh, t, s->M, s->err(), st), "update_noalloc (direct)");
+      return CSK_OK;
+    }
+    uint16_t* tok = (uint16_t*)base;
+    uint32_t* cnt = (uint32_t*)(base + tok_need);
+    CSK_HIP(launch_bin((const float*)src, n, mesh, t, plan, tok, cnt, s->M, s->err(), st), "update_noalloc (bin)");
+    CSK_HIP(launch_accumulate(tok, cnt, plan, s->w, s->M, st), "update_noalloc (accumulate)");
+    return CSK_OK;
+  }
   latch_mesh(s, delta, L, mesh);
   if (n == 0) return CSK_OK;
   if (packed) mesh.mode = kMeshPacked;
-  hipStream_t st = (hipStream_t)stream;
-  const Tables t = s->tables();
   const uint64_t piece_max = 1ull << 30;
   for (uint64_t off = 0; off < n; off += piece_max) {
     const uint64_t m = (n - off < piece_max) ? n - off : piece_max;
@@ -390,6 +458,11 @@ csk_status csk_sketch_update(csk_sketch* s, const float* pos, uint64_t n, double
 csk_status csk_sketch_update_packed(csk_sketch* s, const uint64_t* packed, uint64_t n, double delta, double L,
                                    void* stream) {
   return update_impl(s, packed, true, n, delta, L, stream);
+}
+
+csk_status csk_sketch_update_noalloc(csk_sketch* s, const float* pos, uint64_t n, double delta, double L,
+                                     void* stream) {
+  return update_impl(s, pos, false, n, delta, L, stream, true);
 }
 
 csk_status csk_sketch_query(csk_sketch* s, const uint64_t* keys, uint64_t m, int32_t* est, void* stream) {
