@@ -29,7 +29,7 @@ BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
 # to what was profiled; any change to them makes `traffic` null until measured again.
 TRAFFIC = {"bytes": 46_061_014_467, "particles": 1 << 30,
            "sources_sha256": "13c2f8bbc9bca67b74d885a32b1ad22fae0772f452e836a31e39d4110b40a9f1"}
-TRAFFIC_SOURCES = ["csk_update.hip", "csk_kernel_util.h", "csk_device.h", "csk_internal.h"]
+TRAFFIC_SOURCES = ["csk_update.hip", "csk_sortbin.hip", "csk_kernel_util.h", "csk_device.h", "csk_internal.h"]
 
 
 def sources_sha256():
@@ -75,6 +75,10 @@ def parse():
     ap.add_argument("--no-dictionary", action="store_true",
                     help="skip the full-dictionary search (every cell of the mesh estimated once)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
+    ap.add_argument("--no-protocols", action="store_true",
+                    help="skip the per-2^26-chunk update timing and the 2^28-particle w = 2^22 update")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="time the oracle on the whole stream on every host core (minutes; own JSON line)")
     ap.add_argument("--large", action="store_true",
                     help="run the large combined workload (2^34 particles, three grids, router) instead")
     ap.add_argument("--large-n", type=int, default=0, help="particles of the large run (default 2^34)")
@@ -119,6 +123,24 @@ def calibrate_theta(s, pos, wl, csk):
         theta //= 2
 
 
+def host_info():
+    """The host the oracle runs on: logical CPUs, the ones this process may use, the model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = None
+    return {"nproc": os.cpu_count(), "usable": aff, "cpu_model": model}
+
+
 def cpu_baseline(pos_dev, wl, sample, threads):
     """The oracle as it stands on the first `sample` particles.  With threads > 1 the Add
     phase runs on that many threads (one sketch per thread, summed); the estimates of
@@ -131,9 +153,81 @@ def cpu_baseline(pos_dev, wl, sample, threads):
     oracle.topk_sketch(M, oracle.hash_tables(wl.seed, wl.d), pos, wl.delta, wl.L, oracle.INT32_MIN, wl.k)
     t2 = time.perf_counter()
     return {"value": sample / (t2 - t0), "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "host": host_info(),
             "sample": f"first {sample} particles of the same stream; keys + Add ({t1 - t0:.1f} s on {threads} "
                       f"thread{'s' if threads > 1 else ''}), estimates of every distinct cell + top-{wl.k} "
                       f"({t2 - t1:.1f} s, one thread)"}
+
+
+def oracle_full(pos_dev, wl, threads):
+    """The oracle on the whole stream: keys + Add on `threads` host threads (one sketch per
+    thread, summed), then the estimates of every distinct cell and the top-k on one thread,
+    and the exact histogram by sort (the recall reference)."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    pos = pos_dev.cpu().numpy()
+    t1 = time.perf_counter()
+    M, skipped = oracle.sketch(pos, wl.d, wl.w, wl.seed, wl.delta, wl.L, threads=threads)
+    t2 = time.perf_counter()
+    ko, eo, st = oracle.topk_sketch(M, oracle.hash_tables(wl.seed, wl.d), pos, wl.delta, wl.L, oracle.INT32_MIN, wl.k)
+    t3 = time.perf_counter()
+    n = pos.shape[0]
+    return {"oracle_full": {"particles": n, "threads_add": threads, "host": host_info(),
+                            "copy_to_host_s": t1 - t0, "keys_add_s": t2 - t1, "estimates_topk_s": t3 - t2,
+                            "add_particles_per_s": n / (t2 - t1), "whole_particles_per_s": n / (t3 - t1),
+                            "skipped": int(skipped), "kth_estimate": int(eo[-1]) if len(eo) else None}}
+
+
+def update_protocols(pos, wl, csk, torch, reps=10):
+    """The update under the stream's own chunking (2^26 particles per csk_sketch_update call,
+    each call complete: bin + accumulate), and the 2^28-particle stream into w = 2^22
+    counters (80 MiB, MALL-resident): per call, median of `reps`."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    out = {}
+    n = pos.shape[0]
+    chunk = wl.chunk or n
+    s = csk.Sketch(wl.d, wl.w, wl.seed)
+    s.update(pos[:chunk], wl.delta, wl.L)
+    per_call, whole = [], []
+    for _ in range(3):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(n // chunk + 1)]
+        torch.cuda.synchronize()
+        evs[0].record(stream)
+        for i, a in enumerate(range(0, n, chunk)):
+            s.update(pos[a:a + chunk], wl.delta, wl.L)
+            evs[i + 1].record(stream)
+        torch.cuda.synchronize()
+        per_call += [evs[i].elapsed_time(evs[i + 1]) for i in range(len(evs) - 1)]
+        whole.append(evs[0].elapsed_time(evs[-1]))
+    s.close()
+    ms = float(np.median(whole))
+    out["chunked"] = {"chunk": chunk, "calls": n // chunk, "stream_ms": ms,
+                      "call_ms_median": float(np.median(per_call)),
+                      "particles_per_s": n / (ms / 1e3),
+                      "roofline_frac": BYTES_PER_PARTICLE * n / (ms / 1e3) / (HBM_PEAK_GBS * 1e9),
+                      "note": "median of 3 passes over the stream, one csk_sketch_update per chunk; each call "
+                              "adds its tokens to the counters (a read-modify-write of all d w counters)"}
+    m = min(n, 1 << 28)
+    w4 = 1 << 22
+    s = csk.Sketch(wl.d, w4, wl.seed)
+    s.update(pos[:m], wl.delta, wl.L)
+    t = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.update(pos[:m], wl.delta, wl.L)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t.append(e0.elapsed_time(e1))
+    s.close()
+    ms4 = float(np.median(t))
+    out["w2e22_2e28"] = {"particles": m, "w": w4, "update_ms": ms4, "particles_per_s": m / (ms4 / 1e3),
+                         "roofline_frac": BYTES_PER_PARTICLE * m / (ms4 / 1e3) / (HBM_PEAK_GBS * 1e9),
+                         "note": "the first 2^28 particles of the stream into d = 5, w = 2^22 (80 MiB of "
+                                 "counters, MALL-resident): the learned-router configuration's plain sketch"}
+    return out
 
 
 def dictionary_search(s, wl, theta, keys_top, torch):
@@ -930,10 +1024,18 @@ def main():
         keys, est, rc = s.topk(wl.k)
         return rc, keys, est
 
+    if args.oracle_full:
+        log(f"oracle on all {n} particles, {host_threads()} threads for Add ...")
+        print(json.dumps(oracle_full(pos, wl, host_threads())), flush=True)
+        return
+
     # warm-up: first update allocates scratch; then find theta
     s.update(pos, wl.delta, wl.L)
+    torch.cuda.synchronize()
+    t_theta = time.perf_counter()
     theta, kth = calibrate_theta(s, pos, wl, csk)
-    log(f"theta = {theta} (k-th estimate {kth})")
+    theta_ms = (time.perf_counter() - t_theta) * 1e3
+    log(f"theta = {theta} (k-th estimate {kth}; search {theta_ms:.1f} ms)")
     for _ in range(args.warmup):
         step(theta)
     torch.cuda.synchronize()
@@ -971,10 +1073,13 @@ def main():
         "data": "synthetic (seeded Plummer halos + uniform background, generated on the host)",
         "config": {"workload": wl.name, "particles": n, "L": wl.L, "delta": wl.delta, "d": wl.d, "w": wl.w,
                    "k": wl.k, "seed": wl.seed, "theta": theta, "parallelism": "single GPU"},
+        "theta_search": {"ms": theta_ms, "theta": theta,
+                         "note": "untimed: halving from 2^22, one collect + top-k per try, on the counters of "
+                                 "the warm-up update of the same stream, before the timed steps"},
         "update_ms": upd_ms,
         "update_particles_per_s": n / (upd_ms / 1e3),
         "collect_ms": col_ms,
-        "roofline": {"kernel": "csk_sketch_update (bin3_kernel + accumulate_kernel)", "bound": "hbm",
+        "roofline": {"kernel": "csk_sketch_update (sortbin_kernel + accumulate_kernel)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n)},
     }
@@ -982,6 +1087,9 @@ def main():
         log("measured ceilings ...")
         out["ceilings"] = c = ceilings(pos, torch)
         out["roofline"]["frac_of_measured_stream_read"] = achieved / c["stream_read_GBs"]
+    if not args.no_protocols:
+        log("chunked update and the 2^28-particle w = 2^22 update ...")
+        out["update_protocols"] = update_protocols(pos, wl, csk, torch)
     if not args.no_small:
         log("2^20-particle workload, warm and cold ...")
         out["small_workload"] = small_workload(csk, torch, workloads)

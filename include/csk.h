@@ -118,6 +118,20 @@ csk_status csk_sketch_update_noalloc(csk_sketch *s, const float *pos, uint64_t n
  * for the binned path behaves as CSK_UPDATE_AUTO. */
 csk_status csk_set_update_plan(csk_sketch *s, int32_t mode, uint32_t max_wg);
 
+#define CSK_BIN_AUTO      0 /* the sort-word kernel where it applies, else the general one */
+#define CSK_BIN_GENERAL   1 /* row-interleaved hashing, bucket and sign taken apart per row */
+#define CSK_BIN_SORT_WORD 2 /* packed tables whose fields already are the LDS sort words:
+                               d = 5..8, w = 2^lw <= 2^24 with lw + 1 <= floor(128 / d),
+                               a mesh that is neither grouped nor packed (else: general) */
+
+/* The tiling of the binned update (an autotuner's axes); the counters come out the same
+ * for every choice.  form: CSK_BIN_*.  threads: workgroup size of the sort-word kernel,
+ * 512 or 1024 (0: automatic); rows_per_pass: rows counting-sorted per LDS pass, 2 or 3
+ * (0: as many as LDS holds); prefetch: 1 off, 2 on (load the next tile's positions while
+ * the current one is sorted; 512 threads only), 0 automatic. */
+csk_status csk_set_update_tiling(csk_sketch *s, int32_t form, uint32_t threads, uint32_t rows_per_pass,
+                                 int32_t prefetch);
+
 /* Estimates of m cell keys: est[j] = the element at index floor((d-1)/2) of the
  * ascending sort of { M[r][bucket_r(key_j)] * sign_r(key_j) } (Count-Min: the
  * minimum of M[r][bucket_r(key_j)]).  Sec. 2.2 Estimate; Alg. 4 Estimate.

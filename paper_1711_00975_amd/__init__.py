@@ -35,7 +35,7 @@ INT32_MIN = -(2 ** 31)
 
 EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "csk_sketch_destroy", "csk_sketch_update",
            "csk_sketch_update_noalloc",
-           "csk_set_update_plan",
+           "csk_set_update_plan", "csk_set_update_tiling",
            "csk_sketch_query", "csk_cell_keys", "csk_collect",
            "csk_pack_positions", "csk_sketch_update_packed", "csk_collect_packed", "csk_cell_keys_packed", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
            "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_create_meshes", "csk_batch_update", "csk_batch_topk", "csk_batch_destroy",
@@ -74,6 +74,7 @@ def load_library(path: str = LIB_PATH):
         "csk_sketch_destroy": [P],
         "csk_sketch_update": [P, P, u64, f64, f64, P],
         "csk_sketch_update_noalloc": [P, P, u64, f64, f64, P],
+        "csk_set_update_tiling": [P, i32, u32, u32, i32],
         "csk_set_update_plan": [P, i32, u32],
         "csk_sketch_query": [P, P, u64, P, P],
         "csk_cell_keys": [P, u64, f64, f64, P, P],
@@ -178,10 +179,15 @@ def csk_sketch_init_group(d: int, w: int, seed: int, variant: int = CSK_VARIANT_
 
 
 CSK_UPDATE_AUTO, CSK_UPDATE_BINNED, CSK_UPDATE_DIRECT = 0, 1, 2
+CSK_BIN_AUTO, CSK_BIN_GENERAL, CSK_BIN_SORT_WORD = 0, 1, 2
 
 
 def csk_set_update_plan(h, mode: int, max_wg: int = 0) -> None:
     _check(load_library().csk_set_update_plan(h, mode, max_wg))
+
+
+def csk_set_update_tiling(h, form: int = 0, threads: int = 0, rows_per_pass: int = 0, prefetch: int = 0) -> None:
+    _check(load_library().csk_set_update_tiling(h, form, threads, rows_per_pass, prefetch))
 
 
 def csk_sketch_destroy(h) -> None:
@@ -440,6 +446,9 @@ class Sketch:
 
     def set_update_plan(self, mode, max_wg=0):
         csk_set_update_plan(self.h, mode, max_wg)
+
+    def set_update_tiling(self, form=0, threads=0, rows_per_pass=0, prefetch=0):
+        csk_set_update_tiling(self.h, form, threads, rows_per_pass, prefetch)
 
     def topk_async(self, k, keys, est, out, stream=None):
         """Top-k into preallocated device tensors without synchronizing (graph-capturable)."""

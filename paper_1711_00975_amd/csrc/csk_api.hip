@@ -88,6 +88,62 @@ std::vector<uint32_t> pack_tables(const std::vector<uint32_t>& T, uint32_t d) {
   return P;
 }
 
+// The packed fields of pack_tables() with each row's bits rearranged into the sort word
+// of the update kernel for w = 2^lw: (slice << 16) | (sign << 15) | (offset in the
+// 2^15-counter slice).  Bits below the bucket are dropped; Count-Min drops the sign.  A
+// fixed rearrangement of every entry's bits commutes with the XOR of the tabulation, so
+// the XOR of these entries is the rearranged field of the full row word.
+std::vector<uint32_t> sort_tables(const std::vector<uint32_t>& T, uint32_t d, uint32_t lw, bool count_min) {
+  const uint32_t F = (uint32_t)packed_bits((int)d);
+  std::vector<uint32_t> S((size_t)kTableWords * 4, 0u);
+  for (uint32_t e = 0; e < (uint32_t)kTableWords; ++e) {
+    for (uint32_t r = 0; r < d; ++r) {
+      const uint32_t f = T[(size_t)r * kTableWords + e] >> (32u - F);
+      const uint32_t sign = count_min ? 0u : (f >> (F - 1u));
+      const uint32_t b = (f >> (F - 1u - lw)) & ((1u << lw) - 1u);
+      const uint32_t v = ((b >> kSliceBits) << 16) | (sign << 15) | (b & (kSlice - 1u));
+      const uint32_t o = r * F, wi = o / 32u, sh = o % 32u;
+      S[(size_t)e * 4 + wi] |= v << sh;
+      if (sh + F > 32u) S[(size_t)e * 4 + wi + 1] |= v >> (32u - sh);
+    }
+  }
+  return S;
+}
+
+// The row maps of the field-probe filter: kFieldCols words per row (25 random 25-bit
+// columns, then a 25-bit salt) from a SplitMix64 stream of its own.
+std::vector<uint32_t> probe_columns(uint64_t seed, uint32_t d) {
+  std::vector<uint32_t> C((size_t)d * kFieldCols);
+  uint64_t st = seed ^ 0x243F6A8885A308D3ull;
+  for (auto& c : C) c = (uint32_t)splitmix64(st) & ((1u << kFieldBits) - 1u);
+  return C;
+}
+
+// Probe tables of the field-probe filter for w = 2^lw: entry (c, v) holds, for every row r
+// at bit 25 r, L_r applied to the (sign, bucket) bits of T[r][c][v] (a bit selection, so
+// the XOR over a key's bytes gives L_r of the key's own (sign, bucket)), with the salt
+// added to the entries of byte 0 only, so that every key's XOR holds it exactly once.
+std::vector<uint32_t> probe_tables(const std::vector<uint32_t>& T, uint32_t d, uint32_t lw, bool count_min,
+                                   const std::vector<uint32_t>& C) {
+  std::vector<uint32_t> Q((size_t)kTableWords * 4, 0u);
+  for (uint32_t e = 0; e < (uint32_t)kTableWords; ++e) {
+    for (uint32_t r = 0; r < d; ++r) {
+      const uint32_t H = T[(size_t)r * kTableWords + e];
+      const uint32_t b = (H << 1) >> (32u - lw);
+      const uint32_t sign = count_min ? 0u : (H >> 31);
+      const uint32_t x = (sign << lw) | b;
+      const uint32_t* col = &C[(size_t)r * kFieldCols];
+      uint32_t f = (e < 256u) ? col[kFieldBits] : 0u;
+      for (uint32_t i = 0; i < (uint32_t)kFieldBits; ++i)
+        if ((x >> i) & 1u) f ^= col[i];
+      const uint32_t o = r * (uint32_t)kFieldBits, wi = o / 32u, sh = o % 32u;
+      Q[(size_t)e * 4 + wi] |= f << sh;
+      if (sh + kFieldBits > 32u) Q[(size_t)e * 4 + wi + 1] |= f >> (32u - sh);
+    }
+  }
+  return Q;
+}
+
 // Scratch of csk_sketch_update_noalloc: the token regions of one bin plan, then their
 // counts.  Each device holds its own copy for the life of the process; host code never
 // uses the array's name as an address, only the per-device pointer that
@@ -124,14 +180,19 @@ struct csk_sketch {
   uint32_t group = 1;        // items are cell keys / group (hierarchical coarse layer)
   int32_t upd_mode = CSK_UPDATE_AUTO;  // how csk_sketch_update adds (csk_set_update_plan)
   uint32_t upd_max_wg = 0;             // most bin workgroups (0: the default)
+  uint32_t upd_form = kFormAuto;       // bin kernel form, threads, rows per pass, prefetch
+  uint32_t upd_nt = 0, upd_rp = 0, upd_pf = 0;   // (csk_set_update_tiling; 0: automatic)
   uint64_t seed = 0;
   int32_t variant = CSK_VARIANT_COUNT_SKETCH;
   int32_t* M = nullptr;
   uint32_t* tab = nullptr;
   uint32_t* tabi = nullptr;  // row-interleaved tables (d <= 8)
   uint32_t* tabp = nullptr;  // packed top-bit tables (d = 5..8)
+  uint32_t* tabs = nullptr;  // the packed fields as sort words (d = 5..8, w = 2^lw <= 2^24)
+  uint32_t* tabq = nullptr;  // probe tables of the field-probe filter (d = 5, w = 2^lw <= 2^24)
+  uint32_t* fcols = nullptr; // the columns and salts of its row maps
   uint32_t dp = 0;
-  uint32_t* filter = nullptr; // Bloom filter of hot items + [kFilterWords] item count
+  uint32_t* filter = nullptr; // Bloom filter of hot items + [kFilterAllocWords] item count
   uint32_t* hot_table = nullptr; // exact set of hot items (kHotSlots words)
   uint64_t* set = nullptr;
   uint32_t slots = 0;
@@ -162,6 +223,10 @@ struct csk_sketch {
     t.tab = tab;
     t.tabi = tabi;
     t.tabp = tabp;
+    t.tabs = tabs;
+    t.tabq = tabq;
+    t.fcols = fcols;
+    t.lw = (w >= 2 && (w & (w - 1)) == 0) ? (uint32_t)__builtin_ctz(w) : 0u;
     t.dp = dp;
     t.d = d;
     t.w = w;
@@ -184,7 +249,7 @@ hipError_t dmalloc(csk_sketch* s, T** p, uint64_t count) {
 }
 
 void free_all(csk_sketch* s) {
-  void* ptrs[] = {s->M, s->tab, s->tabi, s->tabp, s->filter, s->hot_table, s->set, s->ctl, s->sel, s->cand_key, s->cand_est, s->sel_key, s->sel_est,
+  void* ptrs[] = {s->M, s->tab, s->tabi, s->tabp, s->tabs, s->tabq, s->fcols, s->filter, s->hot_table, s->set, s->ctl, s->sel, s->cand_key, s->cand_est, s->sel_key, s->sel_est,
                   s->tok, s->cnt};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -304,11 +369,25 @@ csk_status csk_sketch_init_group(csk_sketch** out, uint32_t d, uint32_t w, uint6
   if (s->dp) Ti = interleave_tables(T, d, s->dp);
   std::vector<uint32_t> Tp;
   if (d >= 5 && d <= (uint32_t)kTabLdsRows) Tp = pack_tables(T, d);
+  std::vector<uint32_t> Ts;
+  if (!Tp.empty() && w >= 2 && (w & (w - 1)) == 0) {
+    const uint32_t lw = (uint32_t)__builtin_ctz(w);
+    if (lw <= 24 && lw + 1 <= (uint32_t)packed_bits((int)d))
+      Ts = sort_tables(T, d, lw, variant == CSK_VARIANT_COUNT_MIN);
+  }
+  std::vector<uint32_t> Fc, Tq;
+  if (d == 5 && !Tp.empty() && w >= 2 && (w & (w - 1)) == 0 && __builtin_ctz(w) <= 24) {
+    Fc = probe_columns(seed, d);
+    Tq = probe_tables(T, d, (uint32_t)__builtin_ctz(w), variant == CSK_VARIANT_COUNT_MIN, Fc);
+  }
   if (e == hipSuccess) e = dmalloc(s, &s->M, (uint64_t)d * w);
   if (e == hipSuccess) e = dmalloc(s, &s->tab, T.size());
   if (e == hipSuccess && s->dp) e = dmalloc(s, &s->tabi, Ti.size());
   if (e == hipSuccess && !Tp.empty()) e = dmalloc(s, &s->tabp, Tp.size());
-  if (e == hipSuccess && s->dp) e = dmalloc(s, &s->filter, (uint64_t)kFilterWords + 1);
+  if (e == hipSuccess && !Ts.empty()) e = dmalloc(s, &s->tabs, Ts.size());
+  if (e == hipSuccess && !Tq.empty()) e = dmalloc(s, &s->tabq, Tq.size());
+  if (e == hipSuccess && !Fc.empty()) e = dmalloc(s, &s->fcols, Fc.size());
+  if (e == hipSuccess && s->dp) e = dmalloc(s, &s->filter, (uint64_t)kFilterAllocWords + 1);
   // items pack the bucket in 28 bits, so the exact hot set needs w < 2^28
   if (e == hipSuccess && s->dp && w < (1u << 28)) e = dmalloc(s, &s->hot_table, (uint64_t)kHotSlots);
   if (e == hipSuccess) e = dmalloc(s, &s->set, slots);
@@ -323,6 +402,12 @@ csk_status csk_sketch_init_group(csk_sketch** out, uint32_t d, uint32_t w, uint6
     e = hipMemcpy(s->tabi, Ti.data(), Ti.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess && !Tp.empty())
     e = hipMemcpy(s->tabp, Tp.data(), Tp.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !Ts.empty())
+    e = hipMemcpy(s->tabs, Ts.data(), Ts.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !Tq.empty())
+    e = hipMemcpy(s->tabq, Tq.data(), Tq.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !Fc.empty())
+    e = hipMemcpy(s->fcols, Fc.data(), Fc.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)s->M, (uint64_t)d * w, 0u, nullptr);
   if (e == hipSuccess) e = launch_fill_u32(s->ctl, 4, 0u, nullptr);
   if (e == hipSuccess) e = launch_fill_u64(s->set, slots, kEmptyKey, nullptr);
@@ -355,6 +440,25 @@ csk_status csk_set_update_plan(csk_sketch* s, int32_t mode, uint32_t max_wg) {
   if (max_wg > 65535) return fail(CSK_E_INVALID, "set_update_plan: max_wg=%u above 65535", max_wg);
   s->upd_mode = mode;
   s->upd_max_wg = max_wg;
+  return CSK_OK;
+}
+
+csk_status csk_set_update_tiling(csk_sketch* s, int32_t form, uint32_t threads, uint32_t rows_per_pass,
+                                 int32_t prefetch) {
+  if (s == nullptr) return fail(CSK_E_INVALID, "set_update_tiling: NULL handle");
+  if (form != CSK_BIN_AUTO && form != CSK_BIN_GENERAL && form != CSK_BIN_SORT_WORD)
+    return fail(CSK_E_INVALID, "set_update_tiling: unknown form %d", form);
+  if (threads != 0 && threads != 512 && threads != 1024)
+    return fail(CSK_E_INVALID, "set_update_tiling: threads=%u not 0, 512 or 1024", threads);
+  if (rows_per_pass != 0 && rows_per_pass != 2 && rows_per_pass != 3)
+    return fail(CSK_E_INVALID, "set_update_tiling: rows_per_pass=%u not 0, 2 or 3", rows_per_pass);
+  if (prefetch < 0 || prefetch > 2) return fail(CSK_E_INVALID, "set_update_tiling: prefetch=%d not 0, 1 or 2", prefetch);
+  if (prefetch == 2 && threads == 1024)
+    return fail(CSK_E_INVALID, "set_update_tiling: the 1024-thread form has no registers for a prefetched tile");
+  s->upd_form = (uint32_t)form;
+  s->upd_nt = threads;
+  s->upd_rp = rows_per_pass;
+  s->upd_pf = (uint32_t)prefetch;
   return CSK_OK;
 }
 
@@ -399,6 +503,7 @@ csk_status update_impl(csk_sketch* s, const void* src, bool packed, uint64_t n, 
     latch_mesh(s, delta, L, mesh);
     if (n == 0) return CSK_OK;
     if (packed) mesh.mode = kMeshPacked;
+    if (binned) (void)plan_sortbin(plan, s->d, mesh, t.tabs != nullptr, s->upd_form, s->upd_nt, s->upd_rp, s->upd_pf);
     if (!binned) {
       CSK_HIP(launch_update_direct((const float*)src, n, mesh, t, s->M, s->err(), st), "update_noalloc (direct)");
       return CSK_OK;
@@ -422,6 +527,7 @@ csk_status update_impl(csk_sketch* s, const void* src, bool packed, uint64_t n, 
       CSK_HIP(launch_update_direct(p, m, mesh, t, s->M, s->err(), st), "update (direct)");
       continue;
     }
+    (void)plan_sortbin(plan, s->d, mesh, t.tabs != nullptr, s->upd_form, s->upd_nt, s->upd_rp, s->upd_pf);
     const uint64_t tok_need = (uint64_t)plan.P * plan.nwg * plan.cap * sizeof(uint16_t);
     const uint64_t cnt_need = (uint64_t)plan.P * plan.nwg * sizeof(uint32_t);
     if (tok_need > s->tok_bytes || cnt_need > s->cnt_bytes) {
@@ -523,13 +629,13 @@ csk_status collect_impl(csk_sketch* s, const void* src, bool packed, uint64_t n,
   const uint32_t* filter = nullptr;
   const uint32_t* hot = nullptr;
   if (s->filter != nullptr && theta > 0) {
-    CSK_HIP(launch_filter_build(t, s->M, theta, s->filter, s->filter + kFilterWords, s->hot_table, st),
+    CSK_HIP(launch_filter_build(t, s->M, theta, s->filter, s->filter + kFilterAllocWords, s->hot_table, true, st),
             "collect (filter)");
     filter = s->filter;
-    hot = s->filter + kFilterWords;
+    hot = s->filter + kFilterAllocWords;
   }
   CSK_HIP(launch_collect((const float*)src, n, mesh, t, s->M, theta, filter, hot, filter ? s->hot_table : nullptr, s->set,
-                         s->slots - 1, s->set_count(), s->max_cand, s->err(), st),
+                         s->slots - 1, s->set_count(), s->max_cand, s->err(), true, st),
           "collect");
   return CSK_OK;
 }
@@ -558,10 +664,10 @@ csk_status csk_collect_dictionary(csk_sketch* s, double delta, double L, int32_t
   const uint32_t* filter = nullptr;
   const uint32_t* hot = nullptr;
   if (s->filter != nullptr && theta > 0) {
-    CSK_HIP(launch_filter_build(t, s->M, theta, s->filter, s->filter + kFilterWords, s->hot_table, st),
+    CSK_HIP(launch_filter_build(t, s->M, theta, s->filter, s->filter + kFilterAllocWords, s->hot_table, false, st),
             "collect_dictionary (filter)");
     filter = s->filter;
-    hot = s->filter + kFilterWords;
+    hot = s->filter + kFilterAllocWords;
   }
   const uint64_t ncells = (uint64_t)mesh.G * mesh.G * mesh.G;
   const uint64_t nkeys = (ncells + s->group - 1) / s->group;   // the items: cell keys / group
@@ -724,6 +830,7 @@ struct csk_batch {
   int device = 0;
   uint32_t count = 0, d = 0, mode = 0, nwg_total = 0, nacc_total = 0, lds_bytes = 0;
   int hm = 0;
+  BinPlan form{};                // the sort-word kernel's form when form.sort (the same for all)
   std::vector<csk_sketch*> sk;
   std::vector<uint64_t> max_n;
   BinArgs* bin = nullptr;        // per-sketch bin arguments (device)
@@ -820,6 +927,28 @@ csk_status batch_create_impl(csk_batch** out, csk_sketch* const* sketches, const
     acc_first[i] = (uint32_t)acc_map.size();
     for (uint32_t q = 0; q < p.P; ++q) acc_map.push_back((uint16_t)i);
   }
+  // the sort-word kernel serves the batch when it serves every sketch in the same form
+  bool sort_all = true;
+  for (uint32_t i = 0; i < count && sort_all; ++i) {
+    const csk_sketch* s = sketches[i];
+    sort_all = plan_sortbin(plans[i], d, mesh0, s->tables().tabs != nullptr, s0->upd_form, s0->upd_nt, s0->upd_rp,
+                            s0->upd_pf) &&
+               plans[i].nt == plans[0].nt && plans[i].rp == plans[0].rp && plans[i].pf == plans[0].pf;
+  }
+  BinPlan form{};
+  if (sort_all) {
+    form = plans[0];
+    for (uint32_t i = 0; i < count; ++i)
+      if (plans[i].lds_bytes > lds) lds = plans[i].lds_bytes;
+  } else {
+    lds = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+      BinPlan p;
+      (void)plan_bin_wg(max_n[i] ? max_n[i] : 1, d, sketches[i]->w, plans[i].nwg, p);
+      plans[i] = p;   // the general kernel's plan (same tiles, workgroups and regions)
+      if (p.lds_bytes > lds) lds = p.lds_bytes;
+    }
+  }
   if (wg_map.size() > 65535 || acc_map.size() > (1u << 30))
     return fail(CSK_E_INVALID, "batch_create: %zu workgroups exceed the launch limit", wg_map.size());
   csk_batch* b = new (std::nothrow) csk_batch();
@@ -834,6 +963,7 @@ csk_status batch_create_impl(csk_batch** out, csk_sketch* const* sketches, const
   b->nwg_total = (uint32_t)wg_map.size();
   b->nacc_total = (uint32_t)acc_map.size();
   b->lds_bytes = (uint32_t)lds;
+  b->form = form;
   hipError_t e = bmalloc(&b->bin, count);
   if (e == hipSuccess) e = bmalloc(&b->acc, count);
   if (e == hipSuccess) e = bmalloc(&b->wg_sketch, wg_map.size());
@@ -905,9 +1035,14 @@ csk_status csk_batch_update(csk_batch* b, const float* const* pos, const uint64_
     call.n[i] = n[i];
   }
   hipStream_t st = (hipStream_t)stream;
-  CSK_HIP(launch_bin_batch(b->bin, b->wg_sketch, b->wg_first, b->nwg_total, b->lds_bytes, b->d, b->mode, b->hm, call,
-                           st),
-          "batch_update (bin)");
+  if (b->form.sort)
+    CSK_HIP(launch_sortbin_batch(b->bin, b->wg_sketch, b->wg_first, b->nwg_total, b->lds_bytes, b->d, b->mode, b->form,
+                                 call, st),
+            "batch_update (bin)");
+  else
+    CSK_HIP(launch_bin_batch(b->bin, b->wg_sketch, b->wg_first, b->nwg_total, b->lds_bytes, b->d, b->mode, b->hm,
+                             call, st),
+            "batch_update (bin)");
   CSK_HIP(launch_accumulate_batch(b->acc, b->acc_sketch, b->acc_first, b->nacc_total, st), "batch_update (accumulate)");
   return CSK_OK;
 }

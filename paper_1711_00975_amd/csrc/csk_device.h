@@ -104,13 +104,17 @@ __device__ __forceinline__ bool cell_index_m(float p, const Mesh& m, int32_t& ou
   return ok;
 }
 
-template <uint32_t MODE>
+// GROUPED = false: the caller has checked that the mesh's group is 1, so the division
+// of group_key() is left out of the code altogether (a uniform branch on the group was
+// compiled into a computed-and-discarded division per particle).
+template <uint32_t MODE, bool GROUPED = true>
 __device__ __forceinline__ bool cell_key_m(float x, float y, float z, const Mesh& m, uint64_t& key) {
   int32_t ix, iy, iz;
   const bool ok = (int)cell_index_m<MODE>(x, m, ix) & (int)cell_index_m<MODE>(y, m, iy) &
                   (int)cell_index_m<MODE>(z, m, iz);
   const uint32_t xy = (uint32_t)ix * (uint32_t)m.G + (uint32_t)iy;  // < G^2 <= 2^32
-  key = group_key((uint64_t)xy * (uint64_t)(uint32_t)m.G + (uint64_t)(uint32_t)iz, m);
+  const uint64_t k = (uint64_t)xy * (uint64_t)(uint32_t)m.G + (uint64_t)(uint32_t)iz;
+  key = GROUPED ? group_key(k, m) : k;
   return ok;
 }
 
@@ -133,13 +137,15 @@ __device__ __forceinline__ bool cell_key(float x, float y, float z, const Mesh& 
 // Cell key of a packed particle: i = floor(q * G / 2^21) = umulhi(q * 2^11, G) exactly
 // (q < 2^21, G < 2^16); false for the outside marker (the key is then still a key of
 // the mesh, so table lookups stay in range).
+template <bool GROUPED = true>
 __device__ __forceinline__ bool packed_key(uint64_t w, const Mesh& m, uint64_t& key) {
   constexpr uint32_t mask = (1u << kPackBits) - 1u;
   const uint32_t G = (uint32_t)m.G;
   const uint32_t ix = __umulhi(((uint32_t)w & mask) << (32 - kPackBits), G);
   const uint32_t iy = __umulhi(((uint32_t)(w >> kPackBits) & mask) << (32 - kPackBits), G);
   const uint32_t iz = __umulhi(((uint32_t)(w >> (2 * kPackBits)) & mask) << (32 - kPackBits), G);
-  key = group_key((uint64_t)(ix * G + iy) * G + iz, m);
+  const uint64_t k = (uint64_t)(ix * G + iy) * G + iz;
+  key = GROUPED ? group_key(k, m) : k;
   return (w >> 63) == 0;
 }
 
@@ -360,6 +366,42 @@ __device__ __forceinline__ uint32_t hot_slot(uint32_t item) {
   x *= 0x846CA68Bu;
   x ^= x >> 16;
   return x & (kHotSlots - 1);
+}
+
+// Field-probe filter (d <= 5, w = 2^lw, lw <= 24).  Each row r has a fixed GF(2)-linear
+// map L_r of 25 bits plus a salt c_r; the probe field of item (r, b, neg) is
+// f = L_r((neg << lw) | b) ^ c_r: word = f mod 2^15 of a 2^15-word filter, two bit
+// positions from bits 15-19 and 20-24.  The bucket and the sign are bit selections of
+// the row's tabulated word, so f is itself a tabulation: the collect kernel reads it
+// from probe tables (four words per key-byte entry, row r's field at bit 25 r) with one
+// 16-byte LDS load per key byte and no per-row hashing.  The filter build computes f
+// from the columns of L_r (kFieldCols words per row: 25 columns, then the salt).
+constexpr int kFieldBits = 25;
+constexpr int kFieldCols = kFieldBits + 1;
+constexpr uint32_t kFieldFilterWords = 1u << 15;     // 128 KiB of LDS
+constexpr uint32_t kFieldFilterMaxItems = kFieldFilterWords * 32 / 4;
+constexpr uint32_t kFilterAllocWords = kFieldFilterWords > (uint32_t)kFilterWords ? kFieldFilterWords
+                                                                                   : (uint32_t)kFilterWords;
+
+__device__ __forceinline__ FilterProbe field_probe(uint32_t f) {
+  FilterProbe p;
+  p.word = f & (kFieldFilterWords - 1u);
+  p.mask = (1u << ((f >> 15) & 31u)) | (1u << ((f >> 20) & 31u));
+  return p;
+}
+
+// f = L_r(x) ^ c_r from the row's columns (build side; x < 2^25).
+__device__ __forceinline__ uint32_t item_field(const uint32_t* __restrict__ cols_r, uint32_t x) {
+  uint32_t f = cols_r[kFieldBits];
+  for (int i = 0; i < kFieldBits; ++i) f ^= ((x >> i) & 1u) ? cols_r[i] : 0u;
+  return f;
+}
+
+// Bits of field r (F bits at bit r * F) of a four-word XOR, not masked above F.
+template <int F>
+__device__ __forceinline__ uint32_t field_bits(const uint32_t (&q)[4], int r) {
+  const int o = r * F, wi = o >> 5, sh = o & 31;
+  return (sh + F <= 32) ? (q[wi] >> sh) : __builtin_amdgcn_alignbit(q[wi + 1], q[wi], (uint32_t)sh);
 }
 
 // Probe of the filter for the item (row r, bucket b, sign bit neg).  Buckets are already

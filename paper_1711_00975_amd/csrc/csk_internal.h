@@ -26,6 +26,10 @@ struct Tables {
   const uint32_t* tab;  // [d][6][256] uint32, device
   const uint32_t* tabi; // row-interleaved [6][256][dp] uint32 (d <= 8), device
   const uint32_t* tabp; // packed top-F-bit fields [6][256][4] uint32 (d = 5..8), device, or NULL
+  const uint32_t* tabs; // the packed fields permuted into sort words (see csk_sortbin.hip), or NULL
+  const uint32_t* tabq; // probe tables of the field-probe filter (d <= 5, w = 2^lw <= 2^24), or NULL
+  const uint32_t* fcols; // the columns and salts of its row maps (d x kFieldCols), or NULL
+  uint32_t lw;          // log2(w) when w is a power of two, else 0
   uint32_t dp;          // 4 (d <= 4), 6 (d <= 6) or 8 (d <= 8); 0 when d > 8
   uint32_t d;
   uint32_t w;
@@ -51,6 +55,10 @@ struct BinPlan {
   uint32_t tab_rows_lds;
   uint32_t lds_bytes;
   uint32_t fast;        // 1: row-interleaved kernel (d <= 8)
+  uint32_t sort;        // 1: the sort-word bin kernel (csk_sortbin.hip)
+  uint32_t rp;          // its rows per LDS pass (2 or 3)
+  uint32_t pf;          // 1: it loads the next tile's positions while sorting the current one
+  uint32_t nt;          // its threads per workgroup (512 or 1024)
 };
 
 constexpr int kBin2Threads = 1024;                 // row-interleaved bin kernel
@@ -72,6 +80,17 @@ bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& plan);
 // The same with at most max_wg workgroups (>= 1) for the bin kernel.
 bool plan_bin_wg(uint64_t n, uint32_t d, uint32_t w, uint64_t max_wg, BinPlan& plan);
 uint32_t bin_wg_cap(uint32_t d, uint32_t requested);
+// Bin kernel forms (csk_set_update_tiling): automatic, the general row-interleaved
+// kernel, or the sort-word kernel.
+constexpr uint32_t kFormAuto = 0;
+constexpr uint32_t kFormGeneral = 1;
+constexpr uint32_t kFormSortWord = 2;
+// Turn a fast bin plan into a sort-word plan when the form asks for it (or leaves it
+// to us) and the sketch, the mesh (ungrouped, not packed) and LDS allow: want_nt 0 (auto),
+// 512 or 1024 threads; want_rp 0 (auto), 2 or 3 rows per pass; want_pf 0 (auto), 1 (off)
+// or 2 (on; 512 threads only).  Returns true if the plan now uses the sort-word kernel.
+bool plan_sortbin(BinPlan& p, uint32_t d, const Mesh& mesh, bool have_tabs, uint32_t form, uint32_t want_nt,
+                  uint32_t want_rp, uint32_t want_pf);
 
 // Everything the bin kernel needs for one sketch and one stream.
 struct BinArgs {
@@ -81,6 +100,7 @@ struct BinArgs {
   const uint32_t* __restrict__ tab;
   const uint32_t* __restrict__ tabi;
   const uint32_t* __restrict__ tabp;
+  const uint32_t* __restrict__ tabs;
   uint32_t d, w, wshift, cm;
   BinPlan plan;
   uint16_t* __restrict__ tok;
@@ -105,6 +125,11 @@ struct BatchCall {
   uint64_t n[kMaxBatch];
 };
 
+uint32_t sortbin_lds_bytes(uint32_t d, uint32_t rp, uint32_t P);
+hipError_t launch_sortbin(const BinArgs& a, uint32_t mesh_mode, hipStream_t s);
+hipError_t launch_sortbin_batch(const BinArgs* descs, const uint16_t* wg_sketch, const uint32_t* wg_first,
+                                uint32_t nwg_total, uint32_t lds_bytes, uint32_t d, uint32_t mode, const BinPlan& form,
+                                const BatchCall& call, hipStream_t s);
 BinArgs make_bin_args(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
                       uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err);
 // One bin launch for many sketches of the same d, mesh mode and hash mode (fast path,
@@ -132,11 +157,13 @@ hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const
 // hot_table (kHotSlots words, may be NULL) receives every item when the count is at most
 // kHotMaxItems, and stays empty otherwise.
 hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta, uint32_t* filter, uint32_t* hot,
-                               uint32_t* hot_table, hipStream_t s);
+                               uint32_t* hot_table, bool field, hipStream_t s);
+// field: the filter is a field-probe filter (built with field = true; used only when the
+// sketch has probe tables, d = 5 and the packed hash).
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,
                           int32_t theta, const uint32_t* filter, const uint32_t* hot, const uint32_t* hot_table,
                           uint64_t* set, uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
-                          hipStream_t s);
+                          bool field, hipStream_t s);
 // Candidate pass over every key in [0, nkeys) (the whole G^3 dictionary); arguments as
 // launch_collect without the positions.
 hipError_t launch_collect_dictionary(uint64_t nkeys, const Mesh& mesh, const Tables& t, const int32_t* M,

@@ -155,13 +155,16 @@ __global__ __launch_bounds__(256) void collect_kernel(const float* __restrict__ 
   }
 }
 
-// Row-interleaved collect for d <= 8.  When a Bloom filter of the hot (row, bucket,
+// Row-interleaved collect for d <= 8 on an ungrouped mesh.  When a Bloom filter of the hot (row, bucket,
 // sign) items is supplied, a particle whose rows pass the filter fewer than `need`
 // times cannot have est >= theta (the filter has no false negatives) and is dropped
 // without touching the counters; the rest take the exact test.  Each thread loads
 // kCollectPPT particles before working on any of them, so that enough position loads
 // are in flight to cover HBM latency at one workgroup per CU.
-template <int D, uint32_t MODE, int HM>
+// FP: the field-probe filter (d = 5, packed hash).  Its probe tables take the place of the
+// hash tables in LDS and its filter is 2^15 words; the exact test of the particles that
+// pass reads the packed hash tables from device memory (all six key bytes).
+template <int D, uint32_t MODE, int HM, bool FP>
 __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* __restrict__ pos, uint64_t n, Mesh mesh,
                                                                    Tables t, const int32_t* __restrict__ M,
                                                                    int32_t theta, const uint32_t* __restrict__ filter,
@@ -170,20 +173,25 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
                                                                    uint64_t* set, uint32_t slot_mask,
                                                                    uint32_t* set_count, uint32_t max_cand,
                                                                    uint32_t* err) {
-  constexpr int DP = HashWords<D, HM>::value;
+  constexpr int DP = FP ? 4 : HashWords<D, HM>::value;
   constexpr int PPT = kCollectPPT;
+  constexpr uint32_t FW = FP ? kFieldFilterWords : (uint32_t)kFilterWords;
+  static_assert(!FP || (D <= 5 && HM == kHashPacked), "field probes: d <= 5 rows of 25 bits, packed hash");
   extern __shared__ __align__(16) uint32_t lds3[];
   uint32_t* ti = lds3;
   uint64_t* cache = (uint64_t*)(ti + kTableWords * DP);   // kCollectCache keys
   uint32_t* filt = (uint32_t*)(cache + kCollectCache);
   const uint32_t nhot = use_filter ? *hot : 0xFFFFFFFFu;
-  const bool uf = use_filter && nhot <= kFilterMaxItems;
+  const bool uf = use_filter && nhot <= (FP ? kFieldFilterMaxItems : kFilterMaxItems);
+  // the tables the exact test hashes with: staged in LDS, or (FP) read from device memory
+  const uint32_t* tx = FP ? t.tabp : ti;
+  const uint32_t nchx = FP ? (uint32_t)kChars : mesh.nch;
   // the exact hot-item set replaces the counter reads when it holds every hot item
   const bool uh = use_filter && hot_table != nullptr && nhot <= kHotMaxItems;
   if (uf)
-    for (uint32_t i = threadIdx.x; i < (uint32_t)kFilterWords; i += blockDim.x) filt[i] = filter[i];
+    for (uint32_t i = threadIdx.x; i < FW; i += blockDim.x) filt[i] = filter[i];
   for (uint32_t i = threadIdx.x; i < (uint32_t)kCollectCache; i += blockDim.x) cache[i] = kEmptyKey;
-  stage_tables<DP>(ti, HM == kHashPacked ? t.tabp : t.tabi, mesh.nch);
+  stage_tables<DP>(ti, FP ? t.tabq : (HM == kHashPacked ? t.tabp : t.tabi), mesh.nch);
   constexpr uint32_t kNeedCS = D - ((D - 1) >> 1);
   const uint32_t need = t.cm ? (uint32_t)D : kNeedCS;
   constexpr uint32_t NT = kCollectThreads;
@@ -215,19 +223,29 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
     for (int j = 0; j < PPT; ++j) {
       const bool in = full || (first + (uint64_t)j * NT + threadIdx.x) < n;
       bool ok;
-      if constexpr (MODE == kMeshPacked) ok = packed_key(pw[j], mesh, keys[j]);
-      else ok = cell_key_m<MODE>(px[j], py[j], pz[j], mesh, keys[j]);
+      if constexpr (MODE == kMeshPacked) ok = packed_key<false>(pw[j], mesh, keys[j]);
+      else ok = cell_key_m<MODE, false>(px[j], py[j], pz[j], mesh, keys[j]);
       bad |= in && !ok;
       bool go = in && ok;
       if (uf) {
-        uint32_t bk[D], sg[D];
-        rows_bucket_sign<D, HM>(ti, keys[j], mesh.nch, t.w, t.wshift, bk, sg);
         uint32_t fp = 0;
+        if constexpr (FP) {
+          uint32_t q[4];
+          row_hashes<4>(ti, keys[j], mesh.nch, q);
 #pragma unroll
-        for (int r = 0; r < D; ++r) {
-          const uint32_t ng = sg[r] & (t.cm ^ 1u);
-          const FilterProbe pr = filter_probe((uint32_t)r, bk[r], ng, t.bnorm);
-          fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
+          for (int r = 0; r < D; ++r) {
+            const FilterProbe pr = field_probe(field_bits<kFieldBits>(q, r));
+            fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
+          }
+        } else {
+          uint32_t bk[D], sg[D];
+          rows_bucket_sign<D, HM>(ti, keys[j], mesh.nch, t.w, t.wshift, bk, sg);
+#pragma unroll
+          for (int r = 0; r < D; ++r) {
+            const uint32_t ng = sg[r] & (t.cm ^ 1u);
+            const FilterProbe pr = filter_probe((uint32_t)r, bk[r], ng, t.bnorm);
+            fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
+          }
         }
         go = go && fp >= need;
       }
@@ -286,7 +304,7 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
             continue;
           }
           uint32_t bk[D], ng[D];
-          rows_bucket_sign<D, HM>(ti, keys[j0 + q], mesh.nch, t.w, t.wshift, bk, ng);
+          rows_bucket_sign<D, HM>(tx, keys[j0 + q], nchx, t.w, t.wshift, bk, ng);
 #pragma unroll
           for (int r = 0; r < D; ++r) {
             item[q][r] = hot_item((uint32_t)r, bk[r], ng[r] & (t.cm ^ 1u));
@@ -327,7 +345,7 @@ __global__ __launch_bounds__(kCollectThreads) void collect2_kernel(const float* 
       for (int j = 0; j < PPT; ++j) {
         if (!((todo >> j) & 1u) || recheck(keys[j])) continue;
         uint32_t bk[D], ng[D];
-        rows_bucket_sign<D, HM>(ti, keys[j], mesh.nch, t.w, t.wshift, bk, ng);
+        rows_bucket_sign<D, HM>(tx, keys[j], nchx, t.w, t.wshift, bk, ng);
         uint32_t pass = 0;
 #pragma unroll
         for (int r = 0; r < D; ++r) {
@@ -548,8 +566,11 @@ __device__ __forceinline__ void load_counters(const int32_t* __restrict__ Mr, ui
 
 // Pass 1: sets the Bloom filter bits of every hot item and counts the items into *hot
 // (per-workgroup count in LDS, one global add per workgroup).
+// fcols != NULL: the field-probe filter (item fields from the row maps' columns, w = 2^lw);
+// else the hashed probe of filter_probe().
 __global__ __launch_bounds__(256) void filter_build_kernel(const int32_t* __restrict__ M, uint32_t d, uint32_t w,
                                                            uint32_t cm, uint32_t bnorm, int32_t theta,
+                                                           const uint32_t* __restrict__ fcols, uint32_t lw,
                                                            uint32_t* __restrict__ filter, uint32_t* __restrict__ hot) {
   __shared__ uint32_t count;
   if (threadIdx.x == 0) count = 0;
@@ -569,11 +590,13 @@ __global__ __launch_bounds__(256) void filter_build_kernel(const int32_t* __rest
           bool hp, hn;
           hot_pair(c[v][e], cm, theta, b + e < w, hp, hn);
           if (hp) {
-            const FilterProbe pr = filter_probe(r, (uint32_t)(b + e), 0u, bnorm);
+            const FilterProbe pr = fcols ? field_probe(item_field(fcols + r * kFieldCols, (uint32_t)(b + e)))
+                                         : filter_probe(r, (uint32_t)(b + e), 0u, bnorm);
             atomicOr(&filter[pr.word], pr.mask);
           }
           if (hn) {
-            const FilterProbe pr = filter_probe(r, (uint32_t)(b + e), 1u, bnorm);
+            const FilterProbe pr = fcols ? field_probe(item_field(fcols + r * kFieldCols, (1u << lw) | (uint32_t)(b + e)))
+                                         : filter_probe(r, (uint32_t)(b + e), 1u, bnorm);
             atomicOr(&filter[pr.word], pr.mask);
           }
           mine += (uint32_t)hp + (uint32_t)hn;
@@ -623,10 +646,11 @@ __global__ __launch_bounds__(256) void hot_build_kernel(const int32_t* __restric
 }
 
 hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta, uint32_t* filter, uint32_t* hot,
-                               uint32_t* hot_table, hipStream_t s) {
+                               uint32_t* hot_table, bool field, hipStream_t s) {
+  field = field && t.fcols != nullptr;
   FillSpans f{};   // the three clears in one launch
   f.p[0] = filter;
-  f.n[0] = kFilterWords;
+  f.n[0] = field ? kFieldFilterWords : kFilterWords;
   f.p[1] = hot;
   f.n[1] = 1;
   f.p[2] = hot_table;
@@ -635,7 +659,8 @@ hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta,
   hipError_t e = launch_fill_spans(f, s);
   if (e != hipSuccess) return e;
   const dim3 grid(grid_for((t.w + 4 * kFilterVec - 1) / (4 * kFilterVec), 256, 8192));
-  hipLaunchKernelGGL(filter_build_kernel, grid, dim3(256), 0, s, M, t.d, t.w, t.cm, t.bnorm, theta, filter, hot);
+  hipLaunchKernelGGL(filter_build_kernel, grid, dim3(256), 0, s, M, t.d, t.w, t.cm, t.bnorm, theta,
+                     field ? t.fcols : nullptr, t.lw, filter, hot);
   if (hot_table != nullptr)
     hipLaunchKernelGGL(hot_build_kernel, grid, dim3(256), 0, s, M, t.d, t.w, t.cm, theta, hot, hot_table);
   return hipGetLastError();
@@ -657,16 +682,23 @@ struct CollectArgs {
   uint32_t* set_count;
   uint32_t max_cand;
   uint32_t* err;
+  bool field;   // the filter is a field-probe filter (collect2_kernel<..., FP = true>)
 };
 
-template <int D, uint32_t MM, int HM>
+template <int D, uint32_t MM, int HM, bool FP = false>
 static void launch_collect2_one(dim3 grid, dim3 block, size_t lds, hipStream_t s, const CollectArgs& c) {
-  hipLaunchKernelGGL((collect2_kernel<D, MM, HM>), grid, block, lds, s, c.pos, c.n, c.mesh, c.t, c.M, c.theta,
+  hipLaunchKernelGGL((collect2_kernel<D, MM, HM, FP>), grid, block, lds, s, c.pos, c.n, c.mesh, c.t, c.M, c.theta,
                      c.filter, c.hot, c.use_filter, c.hot_table, c.set, c.slot_mask, c.set_count, c.max_cand, c.err);
 }
 
 template <int D, uint32_t MM>
 static void launch_collect2_m(int hm, dim3 grid, dim3 block, size_t lds, hipStream_t s, const CollectArgs& c) {
+  if constexpr (D == 5) {
+    if (hm == kHashPacked && c.field) {
+      launch_collect2_one<D, MM, kHashPacked, true>(grid, block, lds, s, c);
+      return;
+    }
+  }
   if constexpr (D >= 5) {
     if (hm == kHashPacked) {
       launch_collect2_one<D, MM, kHashPacked>(grid, block, lds, s, c);
@@ -762,14 +794,16 @@ hipError_t launch_collect_dictionary(uint64_t nkeys, const Mesh& mesh, const Tab
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,
                           int32_t theta, const uint32_t* filter, const uint32_t* hot, const uint32_t* hot_table,
                           uint64_t* set, uint32_t slot_mask, uint32_t* set_count, uint32_t max_cand, uint32_t* err,
-                          hipStream_t s) {
-  if (t.d <= (uint32_t)kTabLdsRows) {
+                          bool field, hipStream_t s) {
+  if (t.d <= (uint32_t)kTabLdsRows && mesh.group == 1u) {   // collect2_kernel takes ungrouped keys
     const uint32_t use_filter = (filter != nullptr && hot != nullptr) ? 1u : 0u;
-    const size_t lds = ((size_t)kTableWords * t.dp + 2 * kCollectCache + (use_filter ? kFilterWords : 0)) *
-                       sizeof(uint32_t);
+    field = field && use_filter && t.d == 5 && t.hash_mode() == kHashPacked && t.tabq != nullptr;
+    const size_t lds = field ? ((size_t)kTableWords * 4 + 2 * kCollectCache + kFieldFilterWords) * sizeof(uint32_t)
+                             : ((size_t)kTableWords * t.dp + 2 * kCollectCache + (use_filter ? kFilterWords : 0)) *
+                                   sizeof(uint32_t);
     const dim3 grid(grid_for((n + kCollectPPT - 1) / kCollectPPT, kCollectThreads, 256)), block(kCollectThreads);
     const CollectArgs ca{pos, n, mesh, t, M, theta, filter, hot, use_filter, hot_table, set, slot_mask, set_count,
-                         max_cand, err};
+                         max_cand, err, field};
     launch_collect2_d(t.d, mesh.mode, t.hash_mode(), grid, block, lds, s, ca);
   } else {
     hipLaunchKernelGGL(collect_kernel<false>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, pos, n, mesh, t, M, theta,

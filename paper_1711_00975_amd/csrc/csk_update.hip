@@ -330,6 +330,37 @@ bool plan_bin_wg(uint64_t n, uint32_t d, uint32_t w, uint64_t max_wg, BinPlan& p
   cap = (cap + 7) & ~7ull;
   if ((uint64_t)p.P * cap + kDstBias >= 0x7FFFFFFFull) return false;   // 32-bit region offsets
   p.cap = (uint32_t)cap;
+  p.sort = 0;
+  p.rp = kBin2Rows;
+  p.pf = 0;
+  p.nt = kBin2Threads;
+  return true;
+}
+
+bool plan_sortbin(BinPlan& p, uint32_t d, const Mesh& mesh, bool have_tabs, uint32_t form, uint32_t want_nt,
+                  uint32_t want_rp, uint32_t want_pf) {
+  p.sort = 0;
+  if (form == kFormGeneral || !have_tabs || !p.fast || d < 5 || d > 8 || p.Pr > 512 || mesh.mode == kMeshPacked ||
+      mesh.group != 1u)
+    return false;
+  if (want_nt != 0 && want_nt != 512 && want_nt != 1024) return false;
+  if (want_rp != 0 && want_rp != 2 && want_rp != 3) return false;
+  if (want_pf > 2 || (want_pf == 2 && want_nt == 1024)) return false;
+  // automatic: the sort-word kernel from 32 slices per row (w >= 2^20) on.  Narrower rows
+  // have few bins per pass, and its two LDS atomics per token (count, then scatter) then
+  // contend on the same few words: at w = 2^16 it measured 59 us per 2^20 particles
+  // against 46 us for the general kernel, at w = 2^22 3.24 against 3.64 ms per 2^28.
+  if (form == kFormAuto && p.Pr < 32) return false;
+  uint32_t rp = want_rp ? want_rp : 3u;
+  if (want_rp == 0 && sortbin_lds_bytes(d, rp, p.P) > kMaxLds) rp = 2u;
+  const uint32_t lds = sortbin_lds_bytes(d, rp, p.P);
+  if (lds > kMaxLds) return false;
+  const uint32_t nt = want_nt ? want_nt : (want_pf == 2 ? 512u : 1024u);
+  p.sort = 1;
+  p.nt = nt;
+  p.rp = rp;
+  p.pf = (nt == 512 && want_pf != 1) ? 1u : 0u;
+  p.lds_bytes = lds;
   return true;
 }
 
@@ -379,6 +410,7 @@ BinArgs make_bin_args(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
   a.tab = t.tab;
   a.tabi = t.tabi;
   a.tabp = t.tabp;
+  a.tabs = t.tabs;
   a.d = t.d;
   a.w = t.w;
   a.wshift = t.wshift;
@@ -440,6 +472,7 @@ hipError_t launch_bin_batch(const BinArgs* descs, const uint16_t* wg_sketch, con
 hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
                       uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, hipStream_t s) {
   const BinArgs a = make_bin_args(pos, n, mesh, t, plan, tok, cnt, M, err);
+  if (plan.sort) return launch_sortbin(a, mesh.mode, s);
   if (plan.fast) {
     const dim3 grid(plan.nwg), block(kBin2Threads);
     launch_bin3_d(t.d, mesh.mode, t.hash_mode(), grid, block, plan.lds_bytes, s, a);
