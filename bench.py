@@ -296,7 +296,7 @@ def batched_subvolumes(csk, torch, reps=5):
     Plummer halos in L = 100 at delta = 0.1): the batched update (one bin and one
     accumulate launch, workgroup budget from the autotuner) against the same sketches
     updated one after another, and the whole update -> collect -> top-k pipeline of all
-    64 (collects on 8 streams, one batched top-k) eager against one HIP graph replay."""
+    64 (batched reset, update, candidate pass and top-k) eager against one HIP graph replay."""
     from concurrent.futures import ThreadPoolExecutor
     import workloads
     from paper_1711_00975_amd import autotune
@@ -378,21 +378,10 @@ def batched_subvolumes(csk, torch, reps=5):
     est = [torch.empty(k, dtype=torch.int32, device="cuda") for k in ks]
     outs = [torch.zeros(2, dtype=torch.int32, device="cuda") for _ in ks]
 
-    side = [torch.cuda.Stream() for _ in range(8)]   # default priority
-
-    def pipeline():   # one step of the batch: fresh counters, update, collects, one batched top-k
-        cur = torch.cuda.current_stream()
-        for s in sk:
-            s.reset()
-        b.update(pos)
-        for st in side:
-            st.wait_stream(cur)
-        for j, s in enumerate(sk):   # the 64 candidate passes run side by side
-            st = side[j % len(side)]
-            with torch.cuda.stream(st):
-                s.collect(pos[j], 0.1, 100.0, thetas[j])
-        for st in side:
-            cur.wait_stream(st)
+    def pipeline():   # one step of the batch: fresh counters, update, candidate passes, top-k
+        b.reset()                     # the 64 resets in one launch
+        b.update(pos)                 # one bin and one accumulate launch
+        b.collect(pos, thetas)        # the 64 candidate passes in one set of launches
         b.topk(ks, keys, est, outs)   # the 64 selections in one set of launches
 
     pipeline()

@@ -272,6 +272,19 @@ csk_status csk_batch_topk(csk_batch *b, const uint32_t *k, uint64_t *const *keys
                           uint32_t *const *out, void *stream);
 
 /* Free the batch (the handles stay). */
+/* Every sketch of the batch back to zero counters and an empty candidate set, as
+ * csk_reset on each, in one launch.  Asynchronous on `stream`. */
+csk_status csk_batch_reset(csk_batch *b, void *stream);
+
+/* The candidate pass of every sketch of the batch (csk_collect on each: pos[i] (device),
+ * n[i] particles, theta[i], on the mesh the sketch was batched with) as one set of
+ * launches: the filter and hot-set clears and builds of every sketch whose theta is > 0,
+ * then one collect launch whose workgroups are shared among the sketches in proportion
+ * to their max_n.  Sec. 3.1 item 4 per sketch; results as csk_collect one by one.
+ * Asynchronous; nothing is allocated, so it can be captured in a HIP graph. */
+csk_status csk_batch_collect(csk_batch *b, const float *const *pos, const uint64_t *n, const int32_t *theta,
+                             void *stream);
+
 csk_status csk_batch_destroy(csk_batch *b);
 
 /* ---- Learned router --------------------------------------------------------------

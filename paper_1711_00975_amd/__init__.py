@@ -39,6 +39,7 @@ EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "cs
            "csk_sketch_query", "csk_cell_keys", "csk_collect",
            "csk_pack_positions", "csk_sketch_update_packed", "csk_collect_packed", "csk_cell_keys_packed", "csk_collect_dictionary", "csk_collect_children", "csk_candidates_clear",
            "csk_topk", "csk_topk_async", "csk_batch_create", "csk_batch_create_meshes", "csk_batch_update", "csk_batch_topk", "csk_batch_destroy",
+           "csk_batch_reset", "csk_batch_collect",
            "csk_sample_counts", "csk_cell_features", "csk_mlp_create", "csk_mlp_destroy", "csk_mlp_params",
            "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_gemm_bf16", "csk_route_split", "csk_route_split_workspace", "csk_topk_with_table",
            "csk_exact_counts", "csk_table_topk", "csk_cell_list", "csk_cells_clear", "csk_cell_labels",
@@ -93,6 +94,8 @@ def load_library(path: str = LIB_PATH):
         "csk_batch_topk": [P, P, P, P, P, P],
         "csk_batch_update": [P, P, P, P],
         "csk_batch_destroy": [P],
+        "csk_batch_reset": [P, P],
+        "csk_batch_collect": [P, P, P, P, P],
         "csk_sample_counts": [P, u64, u64, f64, f64, u64, u32, P, P, P],
         "csk_cell_features": [P, f64, f64, P, u64, P, P],
         "csk_mlp_create": [PP, u64, u32],
@@ -348,6 +351,21 @@ class Batch:
         ptrs = (C.c_void_p * self.count)(*[_dev(t, torch.float32, 3) if t.shape[0] else None for t in positions])
         ns = (C.c_uint64 * self.count)(*[int(t.shape[0]) for t in positions])
         _check(load_library().csk_batch_update(self.h, ptrs, ns, _stream(stream)))
+
+    def reset(self, stream=None):
+        """Every sketch back to zero counters and an empty candidate set, in one launch."""
+        _check(load_library().csk_batch_reset(self.h, _stream(stream)))
+
+    def collect(self, positions, thetas, stream=None):
+        """The candidate pass of every sketch (positions: one float32 [n_i][3] device tensor
+        per sketch, thetas: one int per sketch) as one set of launches."""
+        import torch
+        if len(positions) != self.count or len(thetas) != self.count:
+            raise ValueError("one position tensor and one threshold per sketch")
+        ptrs = (C.c_void_p * self.count)(*[_dev(t, torch.float32, 3) if t.shape[0] else None for t in positions])
+        ns = (C.c_uint64 * self.count)(*[int(t.shape[0]) for t in positions])
+        th = (C.c_int32 * self.count)(*[int(x) for x in thetas])
+        _check(load_library().csk_batch_collect(self.h, ptrs, ns, th, _stream(stream)))
 
     def topk(self, ks, keys, est, outs, stream=None):
         """Top-k of every sketch in one set of launches: ks (ints), keys / est (device int64 /

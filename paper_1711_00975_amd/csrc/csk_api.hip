@@ -831,6 +831,7 @@ struct csk_batch {
   uint32_t count = 0, d = 0, mode = 0, nwg_total = 0, nacc_total = 0, lds_bytes = 0;
   int hm = 0;
   BinPlan form{};                // the sort-word kernel's form when form.sort (the same for all)
+  uint32_t kb = 6;               // key bytes its hashing looks up (the most any mesh needs)
   std::vector<csk_sketch*> sk;
   std::vector<uint64_t> max_n;
   BinArgs* bin = nullptr;        // per-sketch bin arguments (device)
@@ -843,12 +844,26 @@ struct csk_batch {
   uint32_t* cnt = nullptr;
   TopkDesc* topk = nullptr;      // per-sketch top-k descriptors (device), built on first use
   std::vector<TopkDesc> topk_host;
+  std::vector<double> delta, L;  // each sketch's mesh (latched again by a collect after a reset)
+  // batched candidate pass
+  CollectDesc* cdesc = nullptr;  // per-sketch collect descriptors (device)
+  std::vector<CollectDesc> cdesc_host;
+  uint16_t* cwg_sketch = nullptr; // collect workgroup -> sketch (device)
+  uint32_t* cwg_first = nullptr;  // sketch -> its first collect workgroup
+  uint32_t* cwg_count = nullptr;  // sketch -> its collect workgroups
+  uint32_t ncwg_total = 0;
+  bool cfield = false;            // every sketch uses the field-probe filter
+  bool cgrouped = false;          // some sketch has grouped items: collects go one by one
+  uint32_t w_max = 0;
+  ResetSpans* rspans = nullptr;   // the clears of every sketch's reset (device)
+  uint64_t rmax = 0;              // the longest span
 };
 
 namespace {
 
 void batch_free(csk_batch* b) {
-  void* ptrs[] = {b->bin, b->acc, b->wg_sketch, b->wg_first, b->acc_sketch, b->acc_first, b->tok, b->cnt, b->topk};
+  void* ptrs[] = {b->bin,       b->acc,       b->wg_sketch, b->wg_first,  b->acc_sketch, b->acc_first, b->tok,
+                  b->cnt,       b->topk,      b->cdesc,     b->cwg_sketch, b->cwg_first,  b->cwg_count,  b->rspans};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -964,6 +979,12 @@ csk_status batch_create_impl(csk_batch** out, csk_sketch* const* sketches, const
   b->nacc_total = (uint32_t)acc_map.size();
   b->lds_bytes = (uint32_t)lds;
   b->form = form;
+  b->kb = 5;
+  for (uint32_t i = 0; i < count; ++i) {
+    Mesh m;
+    (void)check_mesh(sketches[i], delta[i], L[i], &m);
+    if (key_bytes_kb(m.nch) > b->kb) b->kb = key_bytes_kb(m.nch);
+  }
   hipError_t e = bmalloc(&b->bin, count);
   if (e == hipSuccess) e = bmalloc(&b->acc, count);
   if (e == hipSuccess) e = bmalloc(&b->wg_sketch, wg_map.size());
@@ -992,6 +1013,67 @@ csk_status batch_create_impl(csk_batch** out, csk_sketch* const* sketches, const
   if (e == hipSuccess) e = hipMemcpy(b->wg_first, wg_first.data(), count * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->acc_sketch, acc_map.data(), acc_map.size() * 2, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->acc_first, acc_first.data(), count * 4, hipMemcpyHostToDevice);
+  // the batched candidate pass: one descriptor per sketch and a static share of the collect
+  // workgroups in proportion to each stream's tiles (at least one each)
+  b->delta.assign(delta, delta + count);
+  b->L.assign(L, L + count);
+  if (e == hipSuccess) {
+    const uint64_t ctile = (uint64_t)kCollectThreads * kCollectPPT;
+    const uint64_t cbudget = 1024;
+    uint64_t ct_total = 0;
+    std::vector<uint64_t> ct(count);
+    for (uint32_t i = 0; i < count; ++i) {
+      ct[i] = (max_n[i] + ctile - 1) / ctile;
+      ct_total += ct[i];
+    }
+    std::vector<uint16_t> cmap;
+    std::vector<uint32_t> cfirst(count), ccount(count);
+    b->cfield = true;
+    b->cdesc_host.resize(count);
+    ResetSpans rs{};
+    for (uint32_t i = 0; i < count; ++i) {
+      csk_sketch* s = sketches[i];
+      Mesh m;
+      (void)check_mesh(s, delta[i], L[i], &m);
+      const Tables t = s->tables();
+      b->cfield = b->cfield && collect_field_form(t);
+      b->cgrouped = b->cgrouped || s->group != 1u;
+      b->w_max = s->w > b->w_max ? s->w : b->w_max;
+      b->cdesc_host[i] = CollectDesc{m,           t,           s->M,          s->filter,
+                                     s->filter ? s->filter + kFilterAllocWords : nullptr,
+                                     s->hot_table, s->set,     s->slots - 1,  s->set_count(),
+                                     s->max_cand, s->err()};
+      uint64_t want = ct_total ? (cbudget * ct[i] + ct_total / 2) / ct_total : 1;
+      if (want > ct[i]) want = ct[i];
+      if (want < 1) want = 1;
+      cfirst[i] = (uint32_t)cmap.size();
+      ccount[i] = (uint32_t)want;
+      for (uint64_t g = 0; g < want; ++g) cmap.push_back((uint16_t)i);
+      rs.p[i][0] = (uint32_t*)s->M;
+      rs.n[i][0] = (uint64_t)s->d * s->w;
+      rs.p[i][1] = s->err();
+      rs.n[i][1] = 1;
+      rs.p[i][2] = (uint32_t*)s->set;
+      rs.n[i][2] = 2ull * s->slots;
+      rs.v[i][2] = 0xFFFFFFFFu;
+      rs.p[i][3] = s->set_count();
+      rs.n[i][3] = 1;
+      for (int r = 0; r < kFillSpans; ++r) b->rmax = rs.n[i][r] > b->rmax ? rs.n[i][r] : b->rmax;
+    }
+    b->ncwg_total = (uint32_t)cmap.size();
+    if (cmap.size() > 65535) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = bmalloc(&b->cdesc, count);
+    if (e == hipSuccess) e = bmalloc(&b->cwg_sketch, cmap.size());
+    if (e == hipSuccess) e = bmalloc(&b->cwg_first, count);
+    if (e == hipSuccess) e = bmalloc(&b->cwg_count, count);
+    if (e == hipSuccess) e = bmalloc(&b->rspans, 1);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->cdesc, b->cdesc_host.data(), count * sizeof(CollectDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->cwg_sketch, cmap.data(), cmap.size() * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->cwg_first, cfirst.data(), count * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->cwg_count, ccount.data(), count * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->rspans, &rs, sizeof(ResetSpans), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     batch_free(b);
@@ -1036,7 +1118,7 @@ csk_status csk_batch_update(csk_batch* b, const float* const* pos, const uint64_
   }
   hipStream_t st = (hipStream_t)stream;
   if (b->form.sort)
-    CSK_HIP(launch_sortbin_batch(b->bin, b->wg_sketch, b->wg_first, b->nwg_total, b->lds_bytes, b->d, b->mode, b->form,
+    CSK_HIP(launch_sortbin_batch(b->bin, b->wg_sketch, b->wg_first, b->nwg_total, b->lds_bytes, b->d, b->mode, b->form, b->kb,
                                  call, st),
             "batch_update (bin)");
   else
@@ -1104,6 +1186,53 @@ csk_status csk_batch_topk(csk_batch* b, const uint32_t* k, uint64_t* const* keys
     call.partial[i] = b->sk[i]->partial_set ? 1u : 0u;
   }
   CSK_HIP(launch_topk_batch(b->topk, b->count, b->d, slots_max, mc_max, k_max, call, st), "batch_topk");
+  return CSK_OK;
+}
+
+csk_status csk_batch_reset(csk_batch* b, void* stream) {
+  if (b == nullptr) return fail(CSK_E_INVALID, "batch_reset: NULL batch");
+  CSK_HIP(launch_fill_spans_batch(b->rspans, b->count, b->rmax, (hipStream_t)stream), "batch_reset");
+  for (csk_sketch* s : b->sk) {
+    s->mesh_set = false;
+    s->partial_set = false;
+  }
+  return CSK_OK;
+}
+
+csk_status csk_batch_collect(csk_batch* b, const float* const* pos, const uint64_t* n, const int32_t* theta,
+                             void* stream) {
+  if (b == nullptr || pos == nullptr || n == nullptr || theta == nullptr)
+    return fail(CSK_E_INVALID, "batch_collect: NULL argument");
+  for (uint32_t i = 0; i < b->count; ++i) {
+    if (n[i] > (1ull << 40)) return fail(CSK_E_INVALID, "batch_collect: n[%u] above 2^40", i);
+    if (n[i] > 0 && pos[i] == nullptr) return fail(CSK_E_INVALID, "batch_collect: pos[%u] is NULL", i);
+    Mesh m;
+    csk_status rc = check_mesh(b->sk[i], b->delta[i], b->L[i], &m);
+    if (rc != CSK_OK) return rc;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (b->cgrouped) {   // grouped items: the general collect, sketch by sketch
+    for (uint32_t i = 0; i < b->count; ++i) {
+      csk_status rc = csk_collect(b->sk[i], pos[i], n[i], b->delta[i], b->L[i], theta[i], stream);
+      if (rc != CSK_OK) return rc;
+    }
+    return CSK_OK;
+  }
+  CollectCall call{};
+  for (uint32_t i = 0; i < b->count; ++i) {
+    csk_sketch* s = b->sk[i];
+    Mesh m;
+    (void)check_mesh(s, b->delta[i], b->L[i], &m);
+    latch_mesh(s, b->delta[i], b->L[i], m);
+    if (theta[i] != INT32_MIN) s->partial_set = true;
+    call.pos[i] = n[i] ? pos[i] : nullptr;
+    call.n[i] = n[i];
+    call.theta[i] = theta[i];
+    call.use_filter[i] = (s->filter != nullptr && theta[i] > 0) ? 1u : 0u;
+  }
+  CSK_HIP(launch_collect_batch(b->cdesc, b->cdesc_host.data(), b->count, b->cwg_sketch, b->cwg_first, b->cwg_count,
+                               b->ncwg_total, b->d, b->mode, b->hm, b->cfield, b->w_max, call, st),
+          "batch_collect");
   return CSK_OK;
 }
 

@@ -206,6 +206,61 @@ __device__ __forceinline__ void row_hashes(const uint32_t* __restrict__ ti, uint
   }
 }
 
+// The same over exactly KB key bytes, with no branch on the mesh: every LDS load of a key is
+// issued before any is waited for.  The tables must have been staged with fold point KB
+// (stage_tables(..., KB)), and KB must be at least the mesh's nch: bytes nch..KB-1 of every
+// key are 0 and look up the value-0 entries, which is what the full hash does.
+template <int DP, int KB>
+__device__ __forceinline__ void row_hashes_kb(const uint32_t* __restrict__ ti, uint64_t key, uint32_t (&h)[DP]) {
+  static_assert(KB >= 1 && KB <= kChars, "key bytes");
+  const uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
+  const uint32_t byte[kChars] = {lo & 255u, (lo >> 8) & 255u, (lo >> 16) & 255u, lo >> 24, hi & 255u, (hi >> 8) & 255u};
+  if constexpr (DP % 4 == 0) {
+    uint4 v[KB][DP / 4];
+#pragma unroll
+    for (int c = 0; c < KB; ++c)
+#pragma unroll
+      for (int q = 0; q < DP / 4; ++q) v[c][q] = ((const uint4*)(ti + (c * 256 + byte[c]) * DP))[q];
+#pragma unroll
+    for (int q = 0; q < DP / 4; ++q) {
+      uint4 x = v[0][q];
+#pragma unroll
+      for (int c = 1; c < KB; ++c) {
+        x.x ^= v[c][q].x;
+        x.y ^= v[c][q].y;
+        x.z ^= v[c][q].z;
+        x.w ^= v[c][q].w;
+      }
+      h[4 * q + 0] = x.x;
+      h[4 * q + 1] = x.y;
+      h[4 * q + 2] = x.z;
+      h[4 * q + 3] = x.w;
+    }
+  } else {
+    static_assert(DP % 2 == 0, "8-byte entries");
+    uint2 v[KB][DP / 2];
+#pragma unroll
+    for (int c = 0; c < KB; ++c)
+#pragma unroll
+      for (int q = 0; q < DP / 2; ++q) v[c][q] = ((const uint2*)(ti + (c * 256 + byte[c]) * DP))[q];
+#pragma unroll
+    for (int q = 0; q < DP / 2; ++q) {
+      uint2 x = v[0][q];
+#pragma unroll
+      for (int c = 1; c < KB; ++c) {
+        x.x ^= v[c][q].x;
+        x.y ^= v[c][q].y;
+      }
+      h[2 * q + 0] = x.x;
+      h[2 * q + 1] = x.y;
+    }
+  }
+}
+
+// Key bytes the branch-free hashing looks up for a mesh with nch possible key bytes: 5 for
+// keys below 2^40 (G <= 10321), else 6.
+__host__ __device__ __forceinline__ uint32_t key_bytes_kb(uint32_t nch) { return nch <= 5u ? 5u : 6u; }
+
 // Number of key bytes that can be non-zero for a mesh of G cells per side.
 __host__ __device__ __forceinline__ uint32_t key_chars(int32_t G) {
   const uint64_t top = (uint64_t)G * (uint64_t)G * (uint64_t)G;  // keys are < G^3
@@ -294,6 +349,32 @@ __device__ __forceinline__ void rows_bucket_sign(const uint32_t* __restrict__ ti
       const uint32_t f = packed_field<F>(q, r);
       neg[r] = f >> (F - 1);
       b[r] = (f << (33 - F)) >> wshift;   // (h << 1) >> wshift with bits below the field cleared
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      b[r] = bucket_of_t<HM == kHashShift>(h[r], w, wshift);
+      neg[r] = h[r] >> 31;
+    }
+  }
+}
+
+// rows_bucket_sign over exactly KB key bytes (row_hashes_kb): tables staged with fold
+// point KB, or unstaged tables with KB = 6.
+template <int D, int HM, int KB>
+__device__ __forceinline__ void rows_bucket_sign_kb(const uint32_t* __restrict__ ti, uint64_t key, uint32_t w,
+                                                    uint32_t wshift, uint32_t (&b)[D], uint32_t (&neg)[D]) {
+  constexpr int DP = HashWords<D, HM>::value;
+  uint32_t h[DP];
+  row_hashes_kb<DP, KB>(ti, key, h);
+  if constexpr (HM == kHashPacked) {
+    constexpr int F = packed_bits(D);
+    const uint32_t q[4] = {h[0], h[1], h[2], h[3]};
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      const uint32_t f = packed_field<F>(q, r);
+      neg[r] = f >> (F - 1);
+      b[r] = (f << (33 - F)) >> wshift;
     }
   } else {
 #pragma unroll

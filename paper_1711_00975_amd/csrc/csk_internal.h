@@ -129,7 +129,7 @@ uint32_t sortbin_lds_bytes(uint32_t d, uint32_t rp, uint32_t P);
 hipError_t launch_sortbin(const BinArgs& a, uint32_t mesh_mode, hipStream_t s);
 hipError_t launch_sortbin_batch(const BinArgs* descs, const uint16_t* wg_sketch, const uint32_t* wg_first,
                                 uint32_t nwg_total, uint32_t lds_bytes, uint32_t d, uint32_t mode, const BinPlan& form,
-                                const BatchCall& call, hipStream_t s);
+                                uint32_t kb, const BatchCall& call, hipStream_t s);
 BinArgs make_bin_args(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
                       uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err);
 // One bin launch for many sketches of the same d, mesh mode and hash mode (fast path,
@@ -158,6 +158,40 @@ hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const
 // kHotMaxItems, and stays empty otherwise.
 hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta, uint32_t* filter, uint32_t* hot,
                                uint32_t* hot_table, bool field, hipStream_t s);
+// A sketch's candidate-pass arguments (kernel argument, or one entry of a batch's
+// descriptor array).
+struct CollectDesc {
+  Mesh mesh;
+  Tables t;
+  const int32_t* M;
+  uint32_t* filter;           // Bloom filter (device) or NULL
+  uint32_t* hot;              // its hot-item count
+  uint32_t* hot_table;        // exact hot-item set or NULL
+  uint64_t* set;
+  uint32_t slot_mask;
+  uint32_t* set_count;
+  uint32_t max_cand;
+  uint32_t* err;
+};
+// Per-call arguments of a batched candidate pass (kernel argument).
+struct CollectCall {
+  const float* pos[kMaxBatch];
+  uint64_t n[kMaxBatch];
+  int32_t theta[kMaxBatch];
+  uint32_t use_filter[kMaxBatch];   // theta > 0 and the sketch has a filter
+};
+size_t collect2_lds_bytes(const Tables& t, bool use_filter, bool field);
+// The field-probe filter serves this sketch (d = 5, packed hash, probe tables).
+bool collect_field_form(const Tables& t);
+// Batched candidate pass: the clears, the filter and hot-set builds of every sketch whose
+// theta is > 0, then one collect launch of nwg_total workgroups (workgroup g serves sketch
+// wg_sketch[g] as its workgroup g - wg_first[sketch] of wg_count[sketch]).  All sketches
+// share d, the mesh mode and the hash mode; field: every one uses the field-probe filter.
+hipError_t launch_collect_batch(const CollectDesc* descs, const CollectDesc* host_descs, uint32_t count,
+                                const uint16_t* wg_sketch, const uint32_t* wg_first, const uint32_t* wg_count,
+                                uint32_t nwg_total, uint32_t d, uint32_t mesh_mode, int hm, bool field,
+                                uint32_t w_max, const CollectCall& call, hipStream_t s);
+
 // field: the filter is a field-probe filter (built with field = true; used only when the
 // sketch has probe tables, d = 5 and the packed hash).
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,
@@ -191,6 +225,14 @@ struct FillSpans {
   uint32_t v[kFillSpans];
 };
 hipError_t launch_fill_spans(const FillSpans& f, hipStream_t s);
+// The clears of up to kMaxBatch handles in one launch: spans (device) holds, for sketch y,
+// kFillSpans spans of 32-bit words, span r set to v[y][r]; blockIdx.y = sketch.
+struct ResetSpans {
+  uint32_t* p[kMaxBatch][kFillSpans];
+  uint64_t n[kMaxBatch][kFillSpans];
+  uint32_t v[kMaxBatch][kFillSpans];
+};
+hipError_t launch_fill_spans_batch(const ResetSpans* spans, uint32_t count, uint64_t max_words, hipStream_t s);
 // ov_keys / ov_counts / ov_mask: an exact table whose counts replace the estimates of the
 // candidates found in it (NULL: none).
 hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, const int32_t* M,

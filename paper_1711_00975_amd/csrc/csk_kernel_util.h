@@ -100,6 +100,52 @@ __device__ __forceinline__ void load_tables(uint32_t* dst, const uint32_t* __res
   for (uint32_t i = threadIdx.x; i < rows * kTableWords; i += blockDim.x) dst[i] = src[i];
 }
 
+// ------------------------------------------------------------------ candidate set
+
+// Longest probe sequence of the candidate set.  Inserts stop at max_candidates, so the
+// table (2^ceil(log2(2 max_candidates)) slots) stays at most about half full and real
+// probe runs are far shorter; the cap only bounds the work when the set is over capacity.
+constexpr uint32_t kMaxProbe = 4096;
+
+// Is key already in the candidate set?  (A stale read can only miss a key.)
+__device__ __forceinline__ bool set_contains(const uint64_t* set, uint32_t mask, uint64_t key) {
+  uint32_t i = (uint32_t)slot_mix(key) & mask;
+  for (uint32_t probe = 0; probe <= mask && probe < kMaxProbe; ++probe) {
+    const uint64_t cur = set[i];
+    if (cur == key) return true;
+    if (cur == kEmptyKey) return false;
+    i = (i + 1) & mask;
+  }
+  return false;
+}
+
+__device__ __forceinline__ void set_insert(uint64_t* set, uint32_t mask, uint64_t key, uint32_t* count,
+                                           uint32_t max_cand, uint32_t* err) {
+  uint32_t i = (uint32_t)slot_mix(key) & mask;
+  for (uint32_t probe = 0; probe <= mask && probe < kMaxProbe; ++probe) {
+    // A slot only ever changes from empty to a key, so a stale read can only show
+    // "empty"; the compare-and-swap then tells the truth.
+    const uint64_t cur = set[i];
+    if (cur == key) return;
+    if (cur == kEmptyKey) {
+      // a new key: once the set holds max_candidates keys no more go in (capacity error)
+      if (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= max_cand) {
+        atomicOr(err, kErrCapacity);
+        return;
+      }
+      const uint64_t old = atomicCAS((unsigned long long*)&set[i], (unsigned long long)kEmptyKey,
+                                     (unsigned long long)key);
+      if (old == kEmptyKey) {
+        if (atomicAdd(count, 1u) >= max_cand) atomicOr(err, kErrCapacity);
+        return;
+      }
+      if (old == key) return;
+    }
+    i = (i + 1) & mask;
+  }
+  atomicOr(err, kErrCapacity);
+}
+
 static inline uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t max_blocks) {
   uint64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;

@@ -118,7 +118,7 @@ constexpr uint32_t kDstDrop = 0xFFFFFFFFu;      // dummy bin: never written
 constexpr uint32_t kDstOverflow = 0xFFFFFFFEu;  // run added with atomics
 constexpr uint32_t kDstBias = 1u << 16;         // keeps offset + cursor - base positive
 
-template <int D, uint32_t MODE, int NT, int RP, int HM>
+template <int D, uint32_t MODE, int NT, int RP, int HM, int KB>
 __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const float* __restrict__ pos, uint64_t n,
                                           uint32_t g) {
   const BinArgs& a = *ap;   // read in place (argument segment or descriptor), not copied
@@ -140,7 +140,7 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
 
   for (uint32_t i = tid; i < pl.P; i += NT) cursor[i] = 0;
   for (uint32_t i = tid; i < nbins; i += NT) hist[i] = 0;
-  stage_tables<DP>(ti, HM == kHashPacked ? a.tabp : a.tabi, a.mesh.nch);
+  stage_tables<DP>(ti, HM == kHashPacked ? a.tabp : a.tabi, (uint32_t)KB);   // fold point KB >= nch
 
   const uint32_t per = (nbins + NT - 1) / NT;           // scan: bins per thread
   const uint32_t blo = min(nbins, tid * per), bhi = min(nbins, blo + per);
@@ -198,13 +198,14 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
       inside |= (uint32_t)in << j;
       valid |= (uint32_t)ok << j;
       uint32_t bk[D], sg[D];
-      rows_bucket_sign<D, HM>(ti, key, a.mesh.nch, a.w, a.wshift, bk, sg);
+      rows_bucket_sign_kb<D, HM, KB>(ti, key, a.w, a.wshift, bk, sg);
 #pragma unroll
       for (int r = 0; r < D; ++r) {
         const uint32_t b = bk[r];
         const uint32_t neg = sg[r] & (a.cm ^ 1u);
         const uint32_t bin = (uint32_t)(r % RP) * pl.Pr + (b >> kSliceBits);
         sv[r][j] = ok ? ((bin << 16) | (b & (kSlice - 1)) | (neg << 15)) : (dummy << 16);
+        asm volatile("" : "+v"(sv[r][j]));   // materialised here (see the sort-word kernel)
       }
     }
     // particles of the stream that are outside the domain latch the error
@@ -280,20 +281,20 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
   for (uint32_t s = tid; s < pl.P; s += NT) a.cnt[(uint64_t)s * pl.nwg + g] = cursor[s];
 }
 
-template <int D, uint32_t MODE, int NT, int RP, int HM>
+template <int D, uint32_t MODE, int NT, int RP, int HM, int KB>
 __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
-  bin3_body<D, MODE, NT, RP, HM>(&a, a.pos, a.n, blockIdx.x);
+  bin3_body<D, MODE, NT, RP, HM, KB>(&a, a.pos, a.n, blockIdx.x);
 }
 
 // Many sketches in one launch: workgroup blockIdx.x serves sketch wg_sketch[blockIdx.x] as
 // its workgroup blockIdx.x - wg_first[sketch]; the per-call stream of each sketch comes in
 // `call`, the rest of its arguments from descs.
-template <int D, uint32_t MODE, int NT, int RP, int HM>
+template <int D, uint32_t MODE, int NT, int RP, int HM, int KB>
 __global__ __launch_bounds__(NT) void bin3_batch_kernel(const BinArgs* __restrict__ descs,
                                                         const uint16_t* __restrict__ wg_sketch,
                                                         const uint32_t* __restrict__ wg_first, BatchCall call) {
   const uint32_t i = wg_sketch[blockIdx.x];
-  bin3_body<D, MODE, NT, RP, HM>(descs + i, call.pos[i], call.n[i], blockIdx.x - wg_first[i]);
+  bin3_body<D, MODE, NT, RP, HM, KB>(descs + i, call.pos[i], call.n[i], blockIdx.x - wg_first[i]);
 }
 
 bool plan_bin(uint64_t n, uint32_t d, uint32_t w, BinPlan& p) {
@@ -346,6 +347,8 @@ bool plan_sortbin(BinPlan& p, uint32_t d, const Mesh& mesh, bool have_tabs, uint
   if (want_nt != 0 && want_nt != 512 && want_nt != 1024) return false;
   if (want_rp != 0 && want_rp != 2 && want_rp != 3) return false;
   if (want_pf > 2 || (want_pf == 2 && want_nt == 1024)) return false;
+  if (want_nt == 512 && d != 5) return false;   // the 512-thread forms are compiled for d = 5
+  if (want_nt == 512 && want_rp == 2 && want_pf == 1) return false;   // not compiled
   // automatic: the sort-word kernel from 32 slices per row (w >= 2^20) on.  Narrower rows
   // have few bins per pass, and its two LDS atomics per token (count, then scatter) then
   // contend on the same few words: at w = 2^16 it measured 59 us per 2^20 particles
@@ -364,18 +367,23 @@ bool plan_sortbin(BinPlan& p, uint32_t d, const Mesh& mesh, bool have_tabs, uint
   return true;
 }
 
+// Key bytes hashed: d = 5 with packed fields looks up exactly those its mesh needs (5 below
+// 2^40, else 6); every other form looks up all six.
 template <int D, uint32_t MM>
 static void launch_bin3_m(int hm, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, const BinArgs& a) {
   if constexpr (D >= 5) {
     if (hm == kHashPacked) {
-      hipLaunchKernelGGL((bin3_kernel<D, MM, kBin2Threads, kBin2Rows, kHashPacked>), grid, block, lds, s, a);
+      if (D == 5 && key_bytes_kb(a.mesh.nch) == 5)
+        hipLaunchKernelGGL((bin3_kernel<D, MM, kBin2Threads, kBin2Rows, kHashPacked, 5>), grid, block, lds, s, a);
+      else
+        hipLaunchKernelGGL((bin3_kernel<D, MM, kBin2Threads, kBin2Rows, kHashPacked, kChars>), grid, block, lds, s, a);
       return;
     }
   }
   if (hm == kHashMulHi)
-    hipLaunchKernelGGL((bin3_kernel<D, MM, kBin2Threads, kBin2Rows, kHashMulHi>), grid, block, lds, s, a);
+    hipLaunchKernelGGL((bin3_kernel<D, MM, kBin2Threads, kBin2Rows, kHashMulHi, kChars>), grid, block, lds, s, a);
   else
-    hipLaunchKernelGGL((bin3_kernel<D, MM, kBin2Threads, kBin2Rows, kHashShift>), grid, block, lds, s, a);
+    hipLaunchKernelGGL((bin3_kernel<D, MM, kBin2Threads, kBin2Rows, kHashShift, kChars>), grid, block, lds, s, a);
 }
 
 template <int D>
@@ -426,8 +434,9 @@ BinArgs make_bin_args(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
 template <int D, uint32_t MM, int HM>
 static void launch_bin3_batch_one(dim3 grid, uint32_t lds, hipStream_t s, const BinArgs* descs,
                                   const uint16_t* wg_sketch, const uint32_t* wg_first, const BatchCall& call) {
-  hipLaunchKernelGGL((bin3_batch_kernel<D, MM, kBin2Threads, kBin2Rows, HM>), grid, dim3(kBin2Threads), lds, s, descs,
-                     wg_sketch, wg_first, call);
+  // a batch hashes all six key bytes (its meshes may need different counts)
+  hipLaunchKernelGGL((bin3_batch_kernel<D, MM, kBin2Threads, kBin2Rows, HM, kChars>), grid, dim3(kBin2Threads), lds,
+                     s, descs, wg_sketch, wg_first, call);
 }
 
 template <int D, uint32_t MM>
