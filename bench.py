@@ -418,7 +418,7 @@ def learned_router(csk, torch, workloads, n=1 << 28, k=10_000, w_plain=1 << 22, 
     evaluation snapshot is routed (sample pre-pass -> features -> MLP -> admission ->
     split -> rest sketch -> merged top-k) and compared with a plain d x w_plain sketch
     on recall of the exact top-k."""
-    from paper_1711_00975_amd.router import Router, rest_width, TABLE_BYTES_PER_SLOT
+    from paper_1711_00975_amd.router import Router, RoutedStep, rest_width, TABLE_BYTES_PER_SLOT
     base = workloads.SCALE.with_(n=n, w=w_plain, k=k, name=f"plummer-2^{n.bit_length() - 1}-L1000-d0.25")
     r = Router(base.delta, base.L)
     snaps = []
@@ -488,13 +488,11 @@ def learned_router(csk, torch, workloads, n=1 << 28, k=10_000, w_plain=1 << 22, 
     plain_ms, (plain_keys, _, _) = timed(lambda: plain_run(theta_p))
     log(f"  plain: theta {theta_p}, {plain_ms:.2f} ms")
 
-    # routed: admission, split, rest sketch, merged top-k
+    # routed: the sync-free step (admission, the rest update with the split fused in, the
+    # candidate pass over the whole stream, the merged top-k), eager and as a HIP graph
     w_rest = rest_width(w_plain, wl.d, r.table_slots)
     rs = csk.Sketch(wl.d, w_rest, wl.seed, max_candidates=1 << 22)
-    ttk, ttc = csk.new_table(r.table_slots)
-    rest = torch.empty_like(pos)
-    rcount = torch.zeros(1, dtype=torch.int64, device="cuda")
-    rerr = torch.zeros(1, dtype=torch.int32, device="cuda")
+    step = RoutedStep(r, rs, k)
     stage = {}
 
     def routed_run(theta, times=None):
@@ -504,35 +502,45 @@ def learned_router(csk, torch, workloads, n=1 << 28, k=10_000, w_plain=1 << 22, 
             if times is not None:
                 torch.cuda.synchronize()
                 marks.append(time.perf_counter())
-        admitted = r.admit(pos)
+        step.admit(pos)
         mark()
-        ttk.fill_(-1)
-        ttc.zero_()
-        rcount.zero_()
-        r.split(pos, admitted, ttk, ttc, rest, rcount, rerr)
-        nrest = int(rcount.item())
+        step.update(pos)
         mark()
-        rs.reset()
-        rs.update(rest[:nrest], wl.delta, wl.L)
-        mark()
-        rs.collect(rest[:nrest], wl.delta, wl.L, theta)
-        keys, est, rc = csk.topk_with_table(rs, ttk, ttc, k)
-        mark()
+        step.select(pos, theta)
+        torch.cuda.synchronize()
+        marks.append(time.perf_counter())
         if times is not None:
-            names = ["admit_ms", "split_ms", "rest_update_ms", "collect_topk_ms"]
-            for nm, a, b in zip(names, marks[:-1], marks[1:]):
+            for nm, a, b in zip(["admit_ms", "update_routed_ms", "collect_topk_ms"], marks[:-1], marks[1:]):
                 times[nm] = min(times.get(nm, 1e30), (b - a) * 1e3)
-            times["admitted_cells"] = int(admitted.numel())
-            times["table_particles"] = n - nrest
-        return keys, est, rc
+        keys, est, partial = step.result()
+        return keys, est, (csk.CSK_W_INCOMPLETE if partial else csk.CSK_OK)
     theta_r = search_theta(routed_run)
     routed_ms, (routed_keys, _, _) = timed(lambda: routed_run(theta_r))
     for _ in range(2):
         routed_run(theta_r, stage)
-    assert rerr.item() == 0
-    log(f"  routed: theta {theta_r}, {routed_ms:.2f} ms, {stage}")
-    # the same trained router at smaller memory: the split is done once, then each width
-    # gets its own plain and rest sketch and threshold search (recall only, untimed)
+    na = int(step.na.item())
+    stage["admitted_cells"] = na
+    stage["scored_cells"] = int(step.m.item())
+    stage["table_particles"] = int(step.table_counts.sum().item())
+    assert step.err.item() == 0 and stage["scored_cells"] <= step.cells.numel()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step.run(pos, theta_r)
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(step.result()[0], routed_keys)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    graph_ms = None
+    for _ in range(3):
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        graph_ms = t if graph_ms is None else min(graph_ms, t)
+    del g
+    log(f"  routed: theta {theta_r}, {routed_ms:.2f} ms eager, {graph_ms:.2f} ms as a graph, {stage}")
+    # the same trained router at smaller memory (recall only, untimed)
     sweep = []
     for wp in sweep_widths:
         ps = csk.Sketch(wl.d, wp, wl.seed, max_candidates=1 << 22)
@@ -546,13 +554,13 @@ def learned_router(csk, torch, workloads, n=1 << 28, k=10_000, w_plain=1 << 22, 
         pk = small_plain(tp)[0]
         wr = rest_width(wp, wl.d, r.table_slots)
         rs2 = csk.Sketch(wl.d, wr, wl.seed, max_candidates=1 << 22)
-        nrest = n - stage["table_particles"]
+        step2 = RoutedStep(r, rs2, k)
 
         def small_routed(theta):
-            rs2.reset()
-            rs2.update(rest[:nrest], wl.delta, wl.L)
-            rs2.collect(rest[:nrest], wl.delta, wl.L, theta)
-            return csk.topk_with_table(rs2, ttk, ttc, k)
+            step2.run(pos, theta)
+            torch.cuda.synchronize()
+            keys, est, partial = step2.result()
+            return keys, est, (csk.CSK_W_INCOMPLETE if partial else csk.CSK_OK)
         tr2 = search_theta(small_routed)
         rk = small_routed(tr2)[0]
         sweep.append({"w_plain": wp, "w_rest": wr, "plain_theta": tp, "routed_theta": tr2,
@@ -566,10 +574,12 @@ def learned_router(csk, torch, workloads, n=1 << 28, k=10_000, w_plain=1 << 22, 
                      "particles_per_s": n / (plain_ms / 1e3), "recall": score(plain_keys)},
            "routed": {"d": wl.d, "w_rest": w_rest, "table_slots": r.table_slots,
                       "bytes": wl.d * w_rest * 4 + r.table_slots * TABLE_BYTES_PER_SLOT, "max_admitted": r.max_admit,
-                      "theta": theta_r, "ms": routed_ms, "particles_per_s": n / (routed_ms / 1e3),
+                      "theta": theta_r, "ms": routed_ms, "graph_ms": graph_ms,
+                      "particles_per_s": n / (routed_ms / 1e3), "vs_plain": routed_ms / plain_ms,
                       "stages": stage, "recall": score(routed_keys)},
            "smaller_memory": sweep,
-           "note": "times include the host synchronizations of the admission calls; recall against the exact "
+           "note": "eager times: one host synchronization at the end of each step (plain: the top-k's "
+                   "readback); graph_ms: the routed step captured once and replayed; recall against the exact "
                    "top-k from csk_exact_counts + csk_table_topk"}
     plain.close()
     rs.close()
@@ -839,7 +849,8 @@ def ceilings(pos, torch, reps=5):
     lib.probe_stream_read.argtypes = [P, u64, P, u32, P]
     lib.probe_lds_atomics.argtypes = [u64, u32, P, P]
     lib.probe_global_atomics.argtypes = [P, u32, u64, u32, P]
-    for f in (lib.probe_stream_read, lib.probe_lds_atomics, lib.probe_global_atomics):
+    lib.probe_xcd_atomics.argtypes = [P, u32, u64, u32, P]
+    for f in (lib.probe_stream_read, lib.probe_lds_atomics, lib.probe_global_atomics, lib.probe_xcd_atomics):
         f.restype = C.c_int
     st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -868,11 +879,19 @@ def ceilings(pos, torch, reps=5):
         ms = timed(lambda: lib.probe_global_atomics(table.data_ptr(), lw, g_iters, g_blocks, st))
         glob[label] = g_iters * g_blocks * 256 / (ms / 1e3)
         del table
+    xcd = {}
+    for lw, label in ((14, "64KiB"), (18, "1MiB"), (22, "16MiB")):
+        table = torch.zeros(8 << lw, dtype=torch.int32, device="cuda")
+        ms = timed(lambda: lib.probe_xcd_atomics(table.data_ptr(), lw, g_iters, g_blocks, st))
+        xcd[label] = g_iters * g_blocks * 256 / (ms / 1e3)
+        del table
     return {"stream_read_GBs": 12 * n / (read_ms / 1e3) / 1e9,
+            "xcd_private_atomics_per_s": xcd,
             "lds_atomics_per_s": lds_iters * lds_blocks * 1024 / (lds_ms / 1e3),
             "global_atomics_per_s": glob,
             "note": "libcsk_probe.so: 12-byte records read with eight dwordx3 loads in flight per thread; random "
-                    "ds_add on 2^15 LDS words; random device-scope atomicAdd into 2^14, 2^24 and 2^28 words"}
+                    "ds_add on 2^15 LDS words; random device-scope atomicAdd into 2^14, 2^24 and 2^28 words; random workgroup-scope atomicAdd, each "
+                    "into the issuing XCD's own copy of a 2^14, 2^18 or 2^22-word table (performed in that XCD's L2)"}
 
 
 def small_workload(csk, torch, workloads, reps=1000, cold_reps=20):

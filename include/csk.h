@@ -295,8 +295,9 @@ csk_status csk_batch_destroy(csk_batch *b);
 
 /* Add, for each particle index0 + i (i < n) in the sample, 1 to counts[coarse key]
  * (device, G_c^3 uint32, G_c = round(L / delta_c)).  Particle g is in the sample when
- * the first word of Philox4x32-10 at counter (g mod 2^32, g / 2^32, 4, 0) under key
- * (seed mod 2^32, seed / 2^32) is below `threshold` (1 %: 42949672).  Out-of-domain
+ * word g of the Philox4x32-10 stream 4 under key (seed mod 2^32, seed / 2^32) -- word
+ * g mod 4 at counter (g / 4 mod 2^32, g / 4 / 2^32, 4, 0) -- is below `threshold`
+ * (1 %: 42949672).  Out-of-domain
  * particles are skipped.  pos (device).  bitmap (device, ceil(G_c^3 / 32) words, or NULL):
  * a cell's bit (word key / 32, bit key mod 32) is set when its count leaves 0, so that
  * csk_cell_list and csk_cells_clear touch only the sampled cells. */
@@ -400,6 +401,58 @@ csk_status csk_route_admit(const uint64_t *cells, const float *logits, uint64_t 
 csk_status csk_topk_with_table(csk_sketch *s, const uint64_t *table_keys, const uint32_t *table_counts,
                                uint32_t table_slots, uint32_t k, uint64_t *keys, int32_t *est, uint32_t *k_out,
                                void *stream);
+
+/* ---- The routed step without host synchronization (Sec. 2.2 Add and Estimate on the rest;
+ * the learned router around them).  Every call below only enqueues work on `stream`:
+ * counts stay on the device, nothing is allocated, so that the whole step -- sample,
+ * listing, scoring, admission, routed update, candidate pass, merged top-k -- can be
+ * captured in a HIP graph once each handle has run it eagerly.  Workspaces are device
+ * scratch of the stated size, not shared between calls in flight. */
+
+/* As csk_cell_list with *total (device uint64) instead of a host count.  workspace: at
+ * least csk_cell_list_workspace(ncells) bytes. */
+csk_status csk_cell_list_workspace(uint64_t ncells, uint64_t *bytes);
+csk_status csk_cell_list_async(const uint32_t *counts, uint64_t ncells, uint32_t min_count, const uint32_t *bitmap,
+                               uint64_t *cells, uint64_t cap, uint64_t *total, void *workspace,
+                               uint64_t workspace_bytes, void *stream);
+
+/* Logits (device float) of the coarse cells cells[0 .. min(*m, cap)) (m: device uint64):
+ * the features of csk_cell_features fed through the model's fp32 master parameters with
+ * every product and sum in fp32 (no bf16 rounding), all in one kernel. */
+csk_status csk_route_score(csk_mlp *m, const uint32_t *counts, double delta_c, double L, const uint64_t *cells,
+                           const uint64_t *m_dev, uint64_t cap, float *logits, void *stream);
+
+/* As csk_route_admit over the first min(*m, cap) cells (m: device uint64; cap < 2^31,
+ * 1 <= A <= 2^16): the admitted keys in ascending order into admitted (device, room for
+ * A) and their number into *na (device uint32). */
+csk_status csk_route_admit_workspace(uint64_t cap, uint32_t A, uint64_t *bytes);
+csk_status csk_route_admit_async(const uint64_t *cells, const float *logits, const uint64_t *m, uint64_t cap,
+                                 uint32_t A, uint64_t *admitted, uint32_t *na, void *workspace,
+                                 uint64_t workspace_bytes, void *stream);
+
+/* csk_route_split fused into the rest sketch's update: every in-domain particle whose
+ * coarse parent (fine index / factor per axis) is one of admitted[0 .. *na) (device;
+ * *na device uint32) adds 1 to its fine key's count in the exact table (cleared by the
+ * caller: keys all-ones, counts 0), and every other one is added to s (Sec. 2.2 Add) --
+ * the counters and the table of csk_route_split followed by csk_sketch_update of the
+ * rest, with no rest stream written.  The sketch must count single cells (group 1);
+ * factor divides G.  At most na_max = min(512, 2^15 / factor^3, table_slots / 2 /
+ * factor^3) admitted cells are used: a larger *na sets bit 2 of *err (device), a full
+ * table bit 1.  Domain errors latch on s as for csk_sketch_update.  workspace: at least
+ * csk_route_update_workspace(factor, table_slots) bytes.  The candidate pass of the rest
+ * sketch may then run over the whole stream: an admitted key reaches the top-k with its
+ * exact count whatever its estimate (csk_topk_with_table). */
+csk_status csk_route_update_workspace(uint32_t factor, uint32_t table_slots, uint64_t *bytes);
+csk_status csk_sketch_update_routed(csk_sketch *s, const float *pos, uint64_t n, double delta, double L,
+                                    uint32_t factor, const uint64_t *admitted, const uint32_t *na,
+                                    uint64_t *table_keys, uint32_t *table_counts, uint32_t table_slots, uint32_t *err,
+                                    void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* As csk_topk_with_table with out (device, 2 uint32) in place of k_out, as csk_topk_async
+ * (the first call with a larger k allocates and synchronizes). */
+csk_status csk_topk_with_table_async(csk_sketch *s, const uint64_t *table_keys, const uint32_t *table_counts,
+                                     uint32_t table_slots, uint32_t k, uint64_t *keys, int32_t *est, uint32_t *out,
+                                     void *stream);
 
 #ifdef __cplusplus
 }

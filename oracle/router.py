@@ -46,7 +46,8 @@ def bf16(x):
 # ---------------------------------------------------------------- sample and features
 
 def sample_mask(n, seed, index0=0, threshold=SAMPLE_THRESHOLD):
-    """Particle index0 + i is sampled when its first Philox word (stream 4) is below threshold."""
+    """Particle g = index0 + i is sampled when word g of the Philox stream 4 (word g mod 4 of
+    counter g / 4) is below threshold."""
     return workloads.philox_words(index0, n, SAMPLE_STREAM, seed) < np.uint32(threshold)
 
 
@@ -85,6 +86,16 @@ def forward(p, x):
     return z, h1, h2
 
 
+def forward_fp32(p, x):
+    """Logits in plain float32 with no bf16 rounding anywhere: the CPU FP32 reference the
+    bf16-operand MLP is held to (within 2e-2 absolute)."""
+    w = unpack(p)
+    x = np.asarray(x, dtype=np.float32)
+    h1 = np.maximum(x @ w["W1"].T + w["b1"], np.float32(0)).astype(np.float32)
+    h2 = np.maximum(h1 @ w["W2"].T + w["b2"], np.float32(0)).astype(np.float32)
+    return (h2 @ w["w3"] + w["b3"][0]).astype(np.float32)
+
+
 def gradients(p, x, y):
     """Gradients of the mean binary cross-entropy, with the GPU's roundings: dz, dw3, db3,
     db2, db1 in float32; dW2, the back-propagated dA1 and dW1 from bf16-rounded operands."""
@@ -101,6 +112,19 @@ def gradients(p, x, y):
     g["W1"] = bf16(dA1).T @ bf16(x)
     g["b1"] = dA1.sum(axis=0)
     return pack(g)
+
+
+def forward_loops_exact(p, x):
+    """forward_fp32 as explicit float64 loops over neurons, no rounding of any operand (an
+    independent check of `forward_fp32` on small inputs)."""
+    w = unpack(p)
+    W1, W2, w3 = (w[k].astype(np.float64) for k in ("W1", "W2", "w3"))
+    out = []
+    for row in np.asarray(x, dtype=np.float32).astype(np.float64):
+        h1 = [max(0.0, sum(W1[j, k] * row[k] for k in range(FEAT)) + float(w["b1"][j])) for j in range(HIDDEN)]
+        h2 = [max(0.0, sum(W2[j, k] * h1[k] for k in range(HIDDEN)) + float(w["b2"][j])) for j in range(HIDDEN)]
+        out.append(sum(w3[j] * h2[j] for j in range(HIDDEN)) + float(w["b3"][0]))
+    return np.array(out)
 
 
 def forward_loops(p, x):

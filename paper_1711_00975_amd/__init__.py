@@ -43,7 +43,9 @@ EXPORTS = ["csk_sketch_init", "csk_sketch_init_ex", "csk_sketch_init_group", "cs
            "csk_sample_counts", "csk_cell_features", "csk_mlp_create", "csk_mlp_destroy", "csk_mlp_params",
            "csk_mlp_grads", "csk_mlp_forward", "csk_mlp_train_step", "csk_gemm_bf16", "csk_route_split", "csk_route_split_workspace", "csk_topk_with_table",
            "csk_exact_counts", "csk_table_topk", "csk_cell_list", "csk_cells_clear", "csk_cell_labels",
-           "csk_route_admit",
+           "csk_route_admit", "csk_cell_list_workspace", "csk_cell_list_async", "csk_route_score",
+           "csk_route_admit_workspace", "csk_route_admit_async", "csk_route_update_workspace",
+           "csk_sketch_update_routed", "csk_topk_with_table_async",
            "csk_get_counters", "csk_set_counters", "csk_reset", "csk_check", "csk_device_bytes",
            "csk_last_error"]
 
@@ -114,6 +116,14 @@ def load_library(path: str = LIB_PATH):
         "csk_cells_clear": [P, P, u64, P],
         "csk_cell_labels": [P, u64, P, u32, f64, f64, u32, P, P],
         "csk_route_admit": [P, P, u64, u32, P, C.POINTER(C.c_uint32), P],
+        "csk_cell_list_workspace": [u64, C.POINTER(C.c_uint64)],
+        "csk_cell_list_async": [P, u64, u32, P, P, u64, P, P, u64, P],
+        "csk_route_score": [P, P, f64, f64, P, P, u64, P, P],
+        "csk_route_admit_workspace": [u64, u32, C.POINTER(C.c_uint64)],
+        "csk_route_admit_async": [P, P, P, u64, u32, P, P, P, u64, P],
+        "csk_route_update_workspace": [u32, u32, C.POINTER(C.c_uint64)],
+        "csk_sketch_update_routed": [P, P, u64, f64, f64, u32, P, P, P, P, u32, P, P, u64, P],
+        "csk_topk_with_table_async": [P, P, P, u32, u32, P, P, P, P],
         "csk_get_counters": [P, P, P],
         "csk_set_counters": [P, P, P],
         "csk_reset": [P, P],
@@ -700,6 +710,91 @@ def cell_labels(cells, fine_keys, delta, L, factor, stream=None):
                                               fine_keys.shape[0], delta, L, factor, _dev(labels, torch.float32),
                                               _stream(stream)))
     return labels
+
+
+# ---- the routed step without host synchronization: device counts, caller-held buffers
+
+def _workspace(nbytes, device):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def cell_list_workspace_bytes(ncells):
+    need = C.c_uint64(0)
+    _check(load_library().csk_cell_list_workspace(ncells, C.byref(need)))
+    return need.value
+
+
+def cell_list_async(counts, out, total, min_count=1, bitmap=None, workspace=None, stream=None):
+    """The cells with counts >= min_count into out (device int64; the first out.numel() of
+    them, ascending) and their number into total (device int64 [1]), with no host
+    synchronization.  workspace: device uint8 of cell_list_workspace_bytes(counts.numel())."""
+    import torch
+    if workspace is None:
+        workspace = _workspace(cell_list_workspace_bytes(counts.numel()), counts.device)
+    _check(load_library().csk_cell_list_async(_dev(counts, torch.int32), counts.numel(), min_count,
+                                              _dev(bitmap, torch.int32) if bitmap is not None else None,
+                                              _dev(out, torch.int64), out.numel(), _dev(total, torch.int64),
+                                              workspace.data_ptr(), workspace.numel(), _stream(stream)))
+
+
+def route_score(mlp, counts, delta_c, L, cells, m, logits, stream=None):
+    """fp32 logits of cells[0 .. min(m, cells.numel())) (m: device int64 [1]) from their
+    features, in one kernel."""
+    import torch
+    _check(load_library().csk_route_score(mlp.h, _dev(counts, torch.int32), delta_c, L, _dev(cells, torch.int64),
+                                          _dev(m, torch.int64), cells.numel(), _dev(logits, torch.float32),
+                                          _stream(stream)))
+
+
+def route_admit_workspace_bytes(cap, A):
+    need = C.c_uint64(0)
+    _check(load_library().csk_route_admit_workspace(cap, A, C.byref(need)))
+    return need.value
+
+
+def route_admit_async(cells, logits, m, A, admitted, na, workspace=None, stream=None):
+    """The min(A, m) best cells (m: device int64 [1]) into admitted (device int64 [A],
+    ascending) and their number into na (device int32 [1])."""
+    import torch
+    cap = cells.numel()
+    if workspace is None:
+        workspace = _workspace(route_admit_workspace_bytes(cap, A), cells.device)
+    _check(load_library().csk_route_admit_async(_dev(cells, torch.int64), _dev(logits, torch.float32),
+                                                _dev(m, torch.int64), cap, A, _dev(admitted, torch.int64),
+                                                _dev(na, torch.int32), workspace.data_ptr(), workspace.numel(),
+                                                _stream(stream)))
+
+
+def route_update_workspace_bytes(factor, table_slots):
+    need = C.c_uint64(0)
+    _check(load_library().csk_route_update_workspace(factor, table_slots, C.byref(need)))
+    return need.value
+
+
+def update_routed(sketch, pos, delta, L, factor, admitted, na, table_keys, table_counts, err, workspace=None,
+                  stream=None):
+    """Add pos to sketch except the particles of the admitted coarse cells (admitted[0 .. na),
+    na device int32 [1]), which go to the exact table (cleared by the caller)."""
+    import torch
+    if workspace is None:
+        workspace = _workspace(route_update_workspace_bytes(factor, table_keys.shape[0]), pos.device)
+    n = pos.shape[0]
+    _check(load_library().csk_sketch_update_routed(sketch.h, _dev(pos, torch.float32, 3) if n else None, n, delta, L,
+                                                   factor, _dev(admitted, torch.int64), _dev(na, torch.int32),
+                                                   _dev(table_keys, torch.int64), _dev(table_counts, torch.int32),
+                                                   table_keys.shape[0], _dev(err, torch.int32), workspace.data_ptr(),
+                                                   workspace.numel(), _stream(stream)))
+
+
+def topk_with_table_async(sketch, table_keys, table_counts, k, keys, est, out, stream=None):
+    """As topk_with_table into keys / est (device, >= k), out (device int32 [2]) = (number
+    written, 1 if incomplete), with no host synchronization."""
+    import torch
+    _check(load_library().csk_topk_with_table_async(sketch.h, _dev(table_keys, torch.int64),
+                                                    _dev(table_counts, torch.int32), table_keys.shape[0], k,
+                                                    _dev(keys, torch.int64), _dev(est, torch.int32),
+                                                    _dev(out, torch.int32), _stream(stream)))
 
 
 def route_admit(cells, logits, A, stream=None):

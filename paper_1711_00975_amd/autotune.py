@@ -1,11 +1,20 @@
 """Autotuner for the update kernels.
 
 Every update plan gives the same counters (the binned update and the global-atomic
-update add the same +-1s, Sec. 2.2 Add), so tuning only chooses speed:
+update add the same +-1s, Sec. 2.2 Add), so tuning only chooses speed.  The axes:
 
-* per (w, n) class of one sketch: the LDS-binned update with a cap of 32..256 bin
-  workgroups, or one global atomic per row and particle (fastest for short streams);
-* per batch shape: the number of bin workgroups shared out among the sketches.
+* where the increments are privatised: LDS tiles of 2^15 counters fed by a token
+  partition (the binned update), or nowhere (one device-scope atomic per row and
+  particle: fastest for short streams into narrow rows);
+* for the binned update, the bin kernel's form and tiling: the general row-interleaved
+  kernel with a cap of 64..256 workgroups, or the sort-word kernel with 1024 threads and
+  2 or 3 rows per LDS pass, or 512 threads with the next tile's positions prefetched;
+* per batch shape: the bin kernel form and the number of bin workgroups shared out
+  among the sketches.
+
+A per-XCD L2 copy of the counters is not an axis: its atomics (performed in the issuing
+XCD's L2) are measured by bench.py's ceilings and are orders of magnitude slower than LDS
+adds at these stream sizes.
 
 Results are cached as JSON, keyed by the device (name, architecture, compute units),
 in ``$CSK_AUTOTUNE_CACHE`` or ``~/.cache/csk_autotune.json``.
@@ -16,11 +25,35 @@ import json
 import math
 import os
 
-from . import CSK_UPDATE_BINNED, CSK_UPDATE_DIRECT, Batch, Sketch
+from . import (CSK_BIN_AUTO, CSK_BIN_GENERAL, CSK_BIN_SORT_WORD, CSK_UPDATE_BINNED, CSK_UPDATE_DIRECT, Batch,
+               CskError, Sketch)
 
-UPDATE_CANDIDATES = [(CSK_UPDATE_BINNED, 32), (CSK_UPDATE_BINNED, 64), (CSK_UPDATE_BINNED, 128),
-                     (CSK_UPDATE_BINNED, 256), (CSK_UPDATE_DIRECT, 0)]
+
+def _plan(mode, max_wg=0, form=CSK_BIN_AUTO, threads=0, rows=0, prefetch=0):
+    return {"mode": mode, "max_wg": max_wg, "form": form, "threads": threads, "rows": rows, "prefetch": prefetch}
+
+
+UPDATE_CANDIDATES = [
+    _plan(CSK_UPDATE_DIRECT),
+    _plan(CSK_UPDATE_BINNED, 64, CSK_BIN_GENERAL),
+    _plan(CSK_UPDATE_BINNED, 128, CSK_BIN_GENERAL),
+    _plan(CSK_UPDATE_BINNED, 256, CSK_BIN_GENERAL),
+    _plan(CSK_UPDATE_BINNED, 256, CSK_BIN_SORT_WORD, 1024, 2, 1),
+    _plan(CSK_UPDATE_BINNED, 256, CSK_BIN_SORT_WORD, 1024, 3, 1),
+    _plan(CSK_UPDATE_BINNED, 256, CSK_BIN_SORT_WORD, 512, 3, 2),
+]
 BATCH_BUDGETS = [256, 512, 1024, 2048]
+BATCH_FORMS = [_plan(CSK_UPDATE_BINNED, 0, CSK_BIN_GENERAL), _plan(CSK_UPDATE_BINNED, 0, CSK_BIN_SORT_WORD, 1024, 3, 1)]
+
+
+def plan_key(p: dict) -> str:
+    return "{mode}:{max_wg}:{form}:{threads}:{rows}:{prefetch}".format(**p)
+
+
+def set_plan(sketch: Sketch, p: dict) -> None:
+    """Apply a plan; plans cached before the tiling axes existed take the automatic tiling."""
+    sketch.set_update_plan(p["mode"], p["max_wg"])
+    sketch.set_update_tiling(p.get("form", CSK_BIN_AUTO), p.get("threads", 0), p.get("rows", 0), p.get("prefetch", 0))
 
 
 def default_cache_path() -> str:
@@ -44,8 +77,9 @@ def batch_class(d: int, widths, counts) -> str:
 
 
 class Tuner:
-    """The cache: {device key: {class: plan}} with plans {"mode", "max_wg", "ms"} for one
-    sketch and {"wg_budget", "ms"} for a batch."""
+    """The cache: {device key: {class: plan}} with plans {"mode", "max_wg", "form",
+    "threads", "rows", "prefetch", "ms"} for one sketch and {"wg_budget", "form", ..., "ms"}
+    for a batch."""
 
     def __init__(self, path: str | None = None, device: str | None = None):
         self.path = path or default_cache_path()
@@ -81,9 +115,12 @@ class Tuner:
         gen = torch.Generator(device="cuda").manual_seed(seed)
         pos = torch.rand((max(n, 1), 3), generator=gen, device="cuda", dtype=torch.float32) * L
         s = Sketch(d, w, seed)
-        times = {}
-        for mode, wg in UPDATE_CANDIDATES:
-            s.set_update_plan(mode, wg)
+        times, plans = {}, {}
+        for p in UPDATE_CANDIDATES:
+            try:
+                set_plan(s, p)
+            except CskError:                              # a form this sketch cannot take
+                continue
             s.update(pos, delta, L)                       # warm-up (sizes the scratch)
             best = float("inf")
             for _ in range(reps):
@@ -93,11 +130,11 @@ class Tuner:
                 e1.record()
                 torch.cuda.synchronize()
                 best = min(best, e0.elapsed_time(e1))
-            times[f"{mode}:{wg}"] = best
+            times[plan_key(p)] = best
+            plans[plan_key(p)] = p
         s.close()
         key = min(times, key=times.get)
-        mode, wg = (int(x) for x in key.split(":"))
-        plan = {"mode": mode, "max_wg": wg, "ms": times[key], "all_ms": times}
+        plan = dict(plans[key], ms=times[key], all_ms=times)
         self.record(size_class(w, n), plan)
         return plan
 
@@ -106,33 +143,52 @@ class Tuner:
         plan = self.lookup(size_class(sketch.w, n))
         if plan is None:
             return False
-        sketch.set_update_plan(plan["mode"], plan["max_wg"])
+        set_plan(sketch, plan)
         return True
 
     # ---- a batch
     def tune_batch(self, sketches, positions, delta: float, L: float, reps: int = 3) -> dict:
-        """Time the batched update with each workgroup budget; record the fastest."""
-        import torch
+        """Time the batched update with each bin kernel form and workgroup budget; record the
+        fastest and leave its form set on the first sketch (a batch takes that sketch's)."""
         counts = [int(p.shape[0]) for p in positions]
-        times = {}
-        for budget in BATCH_BUDGETS:
-            b = Batch(sketches, counts, delta, L, wg_budget=budget)
-            b.update(positions)
-            best = float("inf")
-            for _ in range(reps):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                b.update(positions)
-                e1.record()
-                torch.cuda.synchronize()
-                best = min(best, e0.elapsed_time(e1))
-            b.close()
-            times[str(budget)] = best
-        budget = int(min(times, key=times.get))
-        plan = {"wg_budget": budget, "ms": times[str(budget)], "all_ms": times}
+        times, forms = {}, {}
+        for f in BATCH_FORMS:
+            try:
+                set_plan(sketches[0], f)
+            except CskError:                              # a form this batch cannot take
+                continue
+            for budget in BATCH_BUDGETS:
+                key = f"{budget}:{f['form']}"
+                times[key] = self._time_batch(sketches, positions, counts, delta, L, budget, reps)
+                forms[key] = f
+        key = min(times, key=times.get)
+        set_plan(sketches[0], forms[key])
+        plan = dict(forms[key], wg_budget=int(key.split(":")[0]), ms=times[key], all_ms=times)
         self.record(batch_class(sketches[0].d, [s.w for s in sketches], counts), plan)
         return plan
 
+    @staticmethod
+    def _time_batch(sketches, positions, counts, delta, L, budget, reps):
+        import torch
+        b = Batch(sketches, counts, delta, L, wg_budget=budget)
+        b.update(positions)
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.update(positions)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        b.close()
+        return best
+
     def batch_budget(self, sketches, counts) -> int:
+        """The tuned budget of this batch shape (0: none), its bin kernel form set on the first
+        sketch."""
         plan = self.lookup(batch_class(sketches[0].d, [s.w for s in sketches], counts))
-        return plan["wg_budget"] if plan else 0
+        if not plan:
+            return 0
+        if "form" in plan:
+            set_plan(sketches[0], plan)
+        return plan["wg_budget"]

@@ -467,6 +467,35 @@ namespace {
 // The update of a float (x, y, z) stream, or of a packed stream (src = 64-bit words).
 // noalloc: tokens go to the device's static scratch, never to memory allocated here;
 // a stream whose bin plan does not fit it is refused before anything runs.
+// The handle's token and count scratch grown to what the plan needs (a growth synchronizes
+// the stream first: earlier work may still read the old buffers).
+hipError_t ensure_update_scratch(csk_sketch* s, const BinPlan& plan, hipStream_t st) {
+  const uint64_t tok_need = (uint64_t)plan.P * plan.nwg * plan.cap * sizeof(uint16_t);
+  const uint64_t cnt_need = (uint64_t)plan.P * plan.nwg * sizeof(uint32_t);
+  if (tok_need <= s->tok_bytes && cnt_need <= s->cnt_bytes) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  if (tok_need > s->tok_bytes) {
+    if (s->tok) (void)hipFree(s->tok);
+    s->bytes -= s->tok_bytes;
+    s->tok = nullptr;
+    s->tok_bytes = 0;
+    e = dmalloc(s, &s->tok, tok_need / sizeof(uint16_t));
+    if (e != hipSuccess) return e;
+    s->tok_bytes = tok_need;
+  }
+  if (cnt_need > s->cnt_bytes) {
+    if (s->cnt) (void)hipFree(s->cnt);
+    s->bytes -= s->cnt_bytes;
+    s->cnt = nullptr;
+    s->cnt_bytes = 0;
+    e = dmalloc(s, &s->cnt, cnt_need / sizeof(uint32_t));
+    if (e != hipSuccess) return e;
+    s->cnt_bytes = cnt_need;
+  }
+  return hipSuccess;
+}
+
 csk_status update_impl(csk_sketch* s, const void* src, bool packed, uint64_t n, double delta, double L,
                        void* stream, bool noalloc = false) {
   if (s == nullptr) return fail(CSK_E_INVALID, "update: NULL handle");
@@ -528,27 +557,7 @@ csk_status update_impl(csk_sketch* s, const void* src, bool packed, uint64_t n, 
       continue;
     }
     (void)plan_sortbin(plan, s->d, mesh, t.tabs != nullptr, s->upd_form, s->upd_nt, s->upd_rp, s->upd_pf);
-    const uint64_t tok_need = (uint64_t)plan.P * plan.nwg * plan.cap * sizeof(uint16_t);
-    const uint64_t cnt_need = (uint64_t)plan.P * plan.nwg * sizeof(uint32_t);
-    if (tok_need > s->tok_bytes || cnt_need > s->cnt_bytes) {
-      CSK_HIP(hipStreamSynchronize(st), "update: grow scratch");
-      if (tok_need > s->tok_bytes) {
-        if (s->tok) (void)hipFree(s->tok);
-        s->bytes -= s->tok_bytes;
-        s->tok = nullptr;
-        s->tok_bytes = 0;
-        CSK_HIP(dmalloc(s, &s->tok, tok_need / sizeof(uint16_t)), "update: token scratch");
-        s->tok_bytes = tok_need;
-      }
-      if (cnt_need > s->cnt_bytes) {
-        if (s->cnt) (void)hipFree(s->cnt);
-        s->bytes -= s->cnt_bytes;
-        s->cnt = nullptr;
-        s->cnt_bytes = 0;
-        CSK_HIP(dmalloc(s, &s->cnt, cnt_need / sizeof(uint32_t)), "update: count scratch");
-        s->cnt_bytes = cnt_need;
-      }
-    }
+    CSK_HIP(ensure_update_scratch(s, plan, st), "update: token scratch");
     CSK_HIP(launch_bin(p, m, mesh, t, plan, s->tok, s->cnt, s->M, s->err(), st), "update (bin)");
     CSK_HIP(launch_accumulate(s->tok, s->cnt, plan, s->w, s->M, st), "update (accumulate)");
   }
@@ -1274,15 +1283,21 @@ void mlp_free(csk_mlp* m) {
 }
 
 // forward of rows [0, b) of x into H1, H2 and z (logits)
+// The forward pass over b rows.  The training pass (y != NULL) rounds every matrix operand to
+// bf16; the scoring pass carries each as a hi + lo bf16 pair (three products per MFMA tile)
+// and does not round the output layer, so its logits stay within fp32 roundings of the fp32
+// forward pass of the same weights.
 hipError_t mlp_forward_rows(csk_mlp* m, const float* x, uint32_t b, float* z, const float* y, hipStream_t st) {
   const float* P = m->p;
+  const bool split = (y == nullptr);
   hipError_t e = launch_gemm_bf16(b, kHidden, kFeatPad, x, kFeatPad, 1, P + kOffW1, 1, kFeatPad, m->H1, kHidden, 1,
-                                  0.0f, st);
+                                  0.0f, st, nullptr, 0, split);
   if (e == hipSuccess) e = launch_bias_act(m->H1, b, kHidden, P + kOffB1, true, st);
   if (e == hipSuccess)
-    e = launch_gemm_bf16(b, kHidden, kHidden, m->H1, kHidden, 1, P + kOffW2, 1, kHidden, m->H2, kHidden, 1, 0.0f, st);
+    e = launch_gemm_bf16(b, kHidden, kHidden, m->H1, kHidden, 1, P + kOffW2, 1, kHidden, m->H2, kHidden, 1, 0.0f, st,
+                         nullptr, 0, split);
   if (e == hipSuccess) e = launch_bias_act(m->H2, b, kHidden, P + kOffB2, true, st);
-  if (e == hipSuccess) e = launch_head(m->H2, b, P + kOffW3, P + kOffB3, z, y, m->dz, m->loss, st);
+  if (e == hipSuccess) e = launch_head(m->H2, b, P + kOffW3, P + kOffB3, z, y, m->dz, m->loss, !split, st);
   return e;
 }
 
@@ -1678,4 +1693,217 @@ csk_status csk_topk_with_table(csk_sketch* s, const uint64_t* table_keys, const 
   if (got < k && s->partial_set)
     return fail(CSK_W_INCOMPLETE, "topk_with_table: only %u of %u candidates", got, k);
   return CSK_OK;
+}
+
+// ---------------------------------------------------------------- the sync-free routed step
+
+namespace {
+
+uint64_t align256(uint64_t b) { return (b + 255) & ~255ull; }
+
+// Admission scratch: SelState | ord (cap int32) | sk, ok (A uint64) | se, oe, rank (A words) | err.
+uint64_t admit_workspace_bytes(uint64_t cap, uint32_t A) {
+  return align256(sizeof(SelState)) + align256(cap * 4) + 2 * align256((uint64_t)A * 8) +
+         3 * align256((uint64_t)A * 4) + 256;
+}
+
+// The most admitted cells an exclusion of this factor and table serves.
+uint32_t routed_na_max(uint32_t factor, uint32_t table_slots) {
+  const uint64_t f3 = (uint64_t)factor * factor * factor;
+  uint64_t na = kMaxAdmitted;
+  if (na * f3 > kSplitMaxChildren) na = kSplitMaxChildren / f3;
+  if (na * f3 > table_slots / 2) na = (table_slots / 2) / f3;
+  return (uint32_t)na;
+}
+
+csk_status topk_with_table_impl(csk_sketch* s, const uint64_t* table_keys, const uint32_t* table_counts,
+                                uint32_t table_slots, uint32_t k, uint64_t* keys, int32_t* est, uint32_t* out,
+                                hipStream_t st, const char* who) {
+  if (s == nullptr || out == nullptr || table_keys == nullptr || table_counts == nullptr)
+    return fail(CSK_E_INVALID, "%s: NULL argument", who);
+  if (table_slots < 2 || (table_slots & (table_slots - 1)) != 0)
+    return fail(CSK_E_INVALID, "%s: table_slots=%u is not a power of two", who, table_slots);
+  if (k > 0 && (keys == nullptr || est == nullptr)) return fail(CSK_E_INVALID, "%s: NULL output", who);
+  if (k > s->max_cand) return fail(CSK_E_INVALID, "%s: k=%u above max_candidates", who, k);
+  CSK_HIP(launch_table_to_set(table_keys, table_slots, s->set, s->slots - 1, s->set_count(), s->max_cand, s->err(), st),
+          who);
+  if (k > s->sel_cap) {   // first call with a larger k: grow the scratch (synchronizes)
+    CSK_HIP(hipStreamSynchronize(st), who);
+    if (s->sel_key) (void)hipFree(s->sel_key);
+    if (s->sel_est) (void)hipFree(s->sel_est);
+    s->bytes -= (uint64_t)s->sel_cap * (sizeof(uint64_t) + sizeof(int32_t));
+    s->sel_key = nullptr;
+    s->sel_est = nullptr;
+    s->sel_cap = 0;
+    CSK_HIP(dmalloc(s, &s->sel_key, k), who);
+    CSK_HIP(dmalloc(s, &s->sel_est, k), who);
+    s->sel_cap = k;
+  }
+  if (k > 0) {
+    CSK_HIP(launch_topk(s->set, s->slots, s->tables(), s->M, s->max_cand, k, s->sel, s->cand_key, s->cand_est,
+                        s->sel_key, s->sel_est, keys, est, s->err(), st, table_keys, table_counts, table_slots - 1),
+            who);
+  } else {
+    CSK_HIP(launch_fill_u32((uint32_t*)s->sel, sizeof(SelState) / 4, 0u, st), who);
+  }
+  CSK_HIP(launch_topk_out(s->sel, k, s->partial_set ? 1u : 0u, out, st), who);
+  return CSK_OK;
+}
+
+}  // namespace
+
+csk_status csk_cell_list_workspace(uint64_t ncells, uint64_t* bytes) {
+  if (bytes == nullptr) return fail(CSK_E_INVALID, "cell_list_workspace: bytes is NULL");
+  uint64_t chunk = 0;
+  *bytes = (uint64_t)cell_list_blocks(ncells, &chunk) * sizeof(uint64_t);
+  return CSK_OK;
+}
+
+csk_status csk_cell_list_async(const uint32_t* counts, uint64_t ncells, uint32_t min_count, const uint32_t* bitmap,
+                               uint64_t* cells, uint64_t cap, uint64_t* total, void* workspace,
+                               uint64_t workspace_bytes, void* stream) {
+  if (total == nullptr || counts == nullptr || (cap > 0 && cells == nullptr) || workspace == nullptr)
+    return fail(CSK_E_INVALID, "cell_list_async: NULL pointer");
+  uint64_t chunk = 0;
+  const uint64_t need = (uint64_t)cell_list_blocks(ncells, &chunk) * sizeof(uint64_t);
+  if (workspace_bytes < need)
+    return fail(CSK_E_INVALID, "cell_list_async: workspace of %llu bytes below the %llu needed",
+                (unsigned long long)workspace_bytes, (unsigned long long)need);
+  hipStream_t st = (hipStream_t)stream;
+  if (ncells == 0) {
+    CSK_HIP(launch_fill_u32((uint32_t*)total, 2, 0u, st), "cell_list_async");
+    return CSK_OK;
+  }
+  CSK_HIP(launch_cell_list(counts, ncells, min_count, bitmap, (uint64_t*)workspace, cells, cap,
+                           (unsigned long long*)total, st),
+          "cell_list_async");
+  return CSK_OK;
+}
+
+csk_status csk_route_score(csk_mlp* m, const uint32_t* counts, double delta_c, double L, const uint64_t* cells,
+                           const uint64_t* m_dev, uint64_t cap, float* logits, void* stream) {
+  if (m == nullptr) return fail(CSK_E_INVALID, "route_score: NULL model");
+  Mesh coarse;
+  csk_status rc = check_mesh(nullptr, delta_c, L, &coarse);
+  if (rc != CSK_OK) return rc;
+  if (cap > 0 && (counts == nullptr || cells == nullptr || m_dev == nullptr || logits == nullptr))
+    return fail(CSK_E_INVALID, "route_score: NULL pointer");
+  CSK_HIP(launch_route_score(counts, (uint32_t)coarse.G, cells, m_dev, cap, m->p, logits, (hipStream_t)stream),
+          "route_score");
+  return CSK_OK;
+}
+
+csk_status csk_route_admit_workspace(uint64_t cap, uint32_t A, uint64_t* bytes) {
+  if (bytes == nullptr) return fail(CSK_E_INVALID, "route_admit_workspace: bytes is NULL");
+  *bytes = admit_workspace_bytes(cap, A);
+  return CSK_OK;
+}
+
+csk_status csk_route_admit_async(const uint64_t* cells, const float* logits, const uint64_t* m, uint64_t cap,
+                                 uint32_t A, uint64_t* admitted, uint32_t* na, void* workspace,
+                                 uint64_t workspace_bytes, void* stream) {
+  if (cap >= (1ull << 31)) return fail(CSK_E_INVALID, "route_admit_async: cap=%llu reaches 2^31", (unsigned long long)cap);
+  if (A < 1 || A > (1u << 16)) return fail(CSK_E_INVALID, "route_admit_async: A=%u outside 1..2^16", A);
+  if (m == nullptr || na == nullptr || admitted == nullptr || workspace == nullptr ||
+      (cap > 0 && (cells == nullptr || logits == nullptr)))
+    return fail(CSK_E_INVALID, "route_admit_async: NULL pointer");
+  if (workspace_bytes < admit_workspace_bytes(cap, A))
+    return fail(CSK_E_INVALID, "route_admit_async: workspace of %llu bytes below the %llu needed",
+                (unsigned long long)workspace_bytes, (unsigned long long)admit_workspace_bytes(cap, A));
+  uint8_t* w = (uint8_t*)workspace;
+  SelState* sel = (SelState*)w;
+  w += align256(sizeof(SelState));
+  int32_t* ord = (int32_t*)w;
+  w += align256(cap * 4);
+  uint64_t* sk = (uint64_t*)w;
+  w += align256((uint64_t)A * 8);
+  uint64_t* ok = (uint64_t*)w;
+  w += align256((uint64_t)A * 8);
+  int32_t* se = (int32_t*)w;
+  w += align256((uint64_t)A * 4);
+  int32_t* oe = (int32_t*)w;
+  w += align256((uint64_t)A * 4);
+  uint32_t* rank = (uint32_t*)w;
+  w += align256((uint64_t)A * 4);
+  uint32_t* err = (uint32_t*)w;
+  hipStream_t st = (hipStream_t)stream;
+  CSK_HIP(launch_fill_u32(err, 1, 0u, st), "route_admit_async");
+  CSK_HIP(launch_admit_dev(cells, logits, m, cap, A, ord, sel, sk, se, rank, ok, oe, err, admitted, na, st),
+          "route_admit_async");
+  return CSK_OK;
+}
+
+csk_status csk_route_update_workspace(uint32_t factor, uint32_t table_slots, uint64_t* bytes) {
+  if (bytes == nullptr) return fail(CSK_E_INVALID, "route_update_workspace: bytes is NULL");
+  if (factor < 1 || factor > 32) return fail(CSK_E_INVALID, "route_update_workspace: factor %u outside 1..32", factor);
+  *bytes = (uint64_t)routed_na_max(factor, table_slots) * factor * factor * factor * sizeof(uint32_t);
+  return CSK_OK;
+}
+
+csk_status csk_sketch_update_routed(csk_sketch* s, const float* pos, uint64_t n, double delta, double L,
+                                    uint32_t factor, const uint64_t* admitted, const uint32_t* na,
+                                    uint64_t* table_keys, uint32_t* table_counts, uint32_t table_slots, uint32_t* err,
+                                    void* workspace, uint64_t workspace_bytes, void* stream) {
+  if (s == nullptr) return fail(CSK_E_INVALID, "update_routed: NULL handle");
+  Mesh mesh;
+  csk_status rc = check_mesh(s, delta, L, &mesh);
+  if (rc != CSK_OK) return rc;
+  if (mesh.group != 1u) return fail(CSK_E_INVALID, "update_routed: the sketch counts groups of cells");
+  if (factor < 1 || factor > 32 || (uint32_t)mesh.G % factor != 0)
+    return fail(CSK_E_INVALID, "update_routed: factor %u does not divide G=%d", factor, mesh.G);
+  if (table_slots < 2 || (table_slots & (table_slots - 1)) != 0)
+    return fail(CSK_E_INVALID, "update_routed: table_slots=%u is not a power of two", table_slots);
+  const uint32_t f3 = factor * factor * factor;
+  const uint32_t na_max = routed_na_max(factor, table_slots);
+  if (na_max < 1) return fail(CSK_E_INVALID, "update_routed: a table of %u slots takes no %u^3 cell", table_slots, factor);
+  if (workspace_bytes < (uint64_t)na_max * f3 * sizeof(uint32_t))
+    return fail(CSK_E_INVALID, "update_routed: workspace of %llu bytes below the %llu needed",
+                (unsigned long long)workspace_bytes, (unsigned long long)na_max * f3 * sizeof(uint32_t));
+  if (n > (1ull << 40)) return fail(CSK_E_INVALID, "update_routed: n above 2^40");
+  if ((n > 0 && pos == nullptr) || admitted == nullptr || na == nullptr || table_keys == nullptr ||
+      table_counts == nullptr || err == nullptr || workspace == nullptr)
+    return fail(CSK_E_INVALID, "update_routed: NULL pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const Tables t = s->tables();
+  RouteExclude ex;
+  ex.admitted = admitted;
+  ex.na = na;
+  ex.na_max = na_max;
+  ex.factor = factor;
+  ex.fmagic = (uint32_t)(((1ull << 32) + factor - 1) / factor);
+  ex.f3 = f3;
+  ex.gc = (uint32_t)mesh.G / factor;
+  ex.child = (uint32_t*)workspace;
+  ex.err = err;
+  latch_mesh(s, delta, L, mesh);
+  CSK_HIP(launch_fill_u32(ex.child, (uint64_t)na_max * f3, 0u, st), "update_routed");
+  const uint64_t piece_max = 1ull << 30;
+  for (uint64_t off = 0; off < n; off += piece_max) {
+    const uint64_t m = (n - off < piece_max) ? n - off : piece_max;
+    const float* p = pos + 3 * off;
+    BinPlan plan;
+    bool binned = s->upd_mode != CSK_UPDATE_DIRECT && s->d == 5 &&
+                  plan_bin_wg(m, s->d, s->w, bin_wg_cap(s->d, s->upd_max_wg), plan) && plan.fast;
+    if (binned) {
+      plan.lds_bytes += kAdmLdsWords * sizeof(uint32_t);
+      binned = plan.lds_bytes <= kMaxLds;
+    }
+    if (!binned) {
+      CSK_HIP(launch_update_direct_routed(p, m, mesh, t, s->M, s->err(), ex, st), "update_routed (direct)");
+      continue;
+    }
+    CSK_HIP(ensure_update_scratch(s, plan, st), "update_routed: token scratch");
+    CSK_HIP(launch_bin_routed(p, m, mesh, t, plan, s->tok, s->cnt, s->M, s->err(), ex, st), "update_routed (bin)");
+    CSK_HIP(launch_accumulate(s->tok, s->cnt, plan, s->w, s->M, st), "update_routed (accumulate)");
+  }
+  CSK_HIP(launch_route_table(ex, (uint32_t)mesh.G, table_keys, table_counts, table_slots - 1, err, st),
+          "update_routed (table)");
+  return CSK_OK;
+}
+
+csk_status csk_topk_with_table_async(csk_sketch* s, const uint64_t* table_keys, const uint32_t* table_counts,
+                                     uint32_t table_slots, uint32_t k, uint64_t* keys, int32_t* est, uint32_t* out,
+                                     void* stream) {
+  return topk_with_table_impl(s, table_keys, table_counts, table_slots, k, keys, est, out, (hipStream_t)stream,
+                              "topk_with_table_async");
 }

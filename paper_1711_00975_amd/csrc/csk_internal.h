@@ -92,6 +92,26 @@ constexpr uint32_t kFormSortWord = 2;
 bool plan_sortbin(BinPlan& p, uint32_t d, const Mesh& mesh, bool have_tabs, uint32_t form, uint32_t want_nt,
                   uint32_t want_rp, uint32_t want_pf);
 
+// The learned router's exclusion (csk_sketch_update_routed): a particle whose coarse parent
+// (its fine index divided by `factor` on each axis, on the mesh of G / factor cells a side)
+// is one of the admitted coarse cells is counted exactly, in child[position of the parent
+// in the admitted list * factor^3 + position of the fine cell inside it], and is not added
+// to the sketch.  admitted == NULL: no exclusion.
+struct RouteExclude {
+  const uint64_t* admitted;   // admitted coarse keys (device)
+  const uint32_t* na;         // how many (device); at most na_max are used
+  uint32_t na_max;            // min(kMaxAdmitted, floor(2^15 / factor^3))
+  uint32_t factor;
+  uint32_t fmagic;            // ceil(2^32 / factor): i / factor = umulhi(i, fmagic) for i < 2^16
+  uint32_t f3;                // factor^3
+  uint32_t gc;                // G / factor
+  uint32_t* child;            // na_max * f3 counters (device)
+  uint32_t* err;              // bit 2: *na was above na_max (device)
+};
+// LDS of the admitted-key hash: 2 kMaxAdmitted 64-bit keys, then as many 16-bit positions.
+constexpr uint32_t kAdmHashSlots = 1024;
+constexpr uint32_t kAdmLdsWords = kAdmHashSlots * 2 + kAdmHashSlots / 2;
+
 // Everything the bin kernel needs for one sketch and one stream.
 struct BinArgs {
   const float* __restrict__ pos;
@@ -107,6 +127,7 @@ struct BinArgs {
   uint32_t* __restrict__ cnt;
   int32_t* __restrict__ M;
   uint32_t* __restrict__ err;
+  RouteExclude ex;
 };
 
 // Everything the accumulate kernel needs for one sketch.
@@ -148,6 +169,14 @@ hipError_t launch_accumulate(const uint16_t* tok, const uint32_t* cnt, const Bin
                              int32_t* M, hipStream_t s);
 hipError_t launch_update_direct(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, int32_t* M,
                                 uint32_t* err, hipStream_t s);
+// The update with the learned router's exclusion: the general bin kernel (d = 5, a fast
+// general plan whose lds_bytes include kAdmLdsWords words) or the direct update (any d);
+// both need float positions on an ungrouped mesh.
+hipError_t launch_bin_routed(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
+                             uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, const RouteExclude& ex,
+                             hipStream_t s);
+hipError_t launch_update_direct_routed(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, int32_t* M,
+                                       uint32_t* err, const RouteExclude& ex, hipStream_t s);
 hipError_t launch_keys(const float* pos, uint64_t n, const Mesh& mesh, uint64_t* keys, hipStream_t s);
 hipError_t launch_pack(const float* pos, uint64_t n, const Mesh& pm, uint64_t* out, uint32_t* err, hipStream_t s);
 hipError_t launch_query(const uint64_t* keys, uint64_t m, const Tables& t, const int32_t* M, int32_t* est,
@@ -272,6 +301,10 @@ hipError_t launch_topk_batch(const TopkDesc* D, uint32_t count, uint32_t d, uint
 hipError_t launch_select_pairs(const uint64_t* ck, const int32_t* ce, uint32_t m, uint32_t k, SelState* st,
                                uint64_t* sk, int32_t* se, uint32_t* rank, uint64_t* ok, int32_t* oe,
                                const uint32_t* err, hipStream_t s);
+// The same over the first min(*m_dev, cap) pairs of a device count.
+hipError_t launch_select_pairs_dev(const uint64_t* ck, const int32_t* ce, const uint64_t* m_dev, uint32_t cap,
+                                   uint32_t k, SelState* st, uint64_t* sk, int32_t* se, uint32_t* rank, uint64_t* ok,
+                                   int32_t* oe, const uint32_t* err, hipStream_t s);
 // Insert every non-empty key of an exact table (tslots slots) into a candidate set.
 hipError_t launch_table_to_set(const uint64_t* tk, uint32_t tslots, uint64_t* set, uint32_t slot_mask,
                                uint32_t* set_count, uint32_t max_cand, uint32_t* err, hipStream_t s);

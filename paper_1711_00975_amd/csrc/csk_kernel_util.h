@@ -146,6 +146,67 @@ __device__ __forceinline__ void set_insert(uint64_t* set, uint32_t mask, uint64_
   atomicOr(err, kErrCapacity);
 }
 
+// ---- the admitted coarse cells of the learned router: an LDS hash of their keys (load at
+// most 1/2) that maps a key to its position in the admitted list.
+constexpr uint64_t kAdmEmpty = ~0ull;
+
+__device__ __forceinline__ uint32_t adm_hash(uint64_t key) {
+  return ((uint32_t)(key ^ (key >> 32)) * 0x9E3779B9u) >> 22;   // top 10 bits: kAdmHashSlots
+}
+
+// Fill the hash with admitted[0 .. na) (na <= kAdmHashSlots / 2, distinct keys); every thread
+// of the block calls it; ends with a barrier.
+__device__ __forceinline__ void adm_hash_fill(const uint64_t* __restrict__ admitted, uint32_t na, uint64_t* hkey,
+                                              uint16_t* hidx) {
+  for (uint32_t i = threadIdx.x; i < kAdmHashSlots; i += blockDim.x) hkey[i] = kAdmEmpty;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < na; i += blockDim.x) {
+    const uint64_t key = admitted[i];
+    uint32_t sl = adm_hash(key);
+    for (uint32_t probe = 0; probe < kAdmHashSlots; ++probe) {
+      if (atomicCAS((unsigned long long*)&hkey[sl], kAdmEmpty, (unsigned long long)key) == kAdmEmpty) {
+        hidx[sl] = (uint16_t)i;
+        break;
+      }
+      sl = (sl + 1) & (kAdmHashSlots - 1);
+    }
+  }
+  __syncthreads();
+}
+
+// Position of coarse key ck in the admitted list, or -1.
+__device__ __forceinline__ int32_t adm_find(uint64_t ck, const uint64_t* hkey, const uint16_t* hidx) {
+  uint32_t sl = adm_hash(ck);
+  for (uint32_t probe = 0; probe < kAdmHashSlots; ++probe) {
+    const uint64_t k = hkey[sl];
+    if (k == ck) return (int32_t)hidx[sl];
+    if (k == kAdmEmpty) return -1;
+    sl = (sl + 1) & (kAdmHashSlots - 1);
+  }
+  return -1;
+}
+
+// Coarse key of the fine cell (ix, iy, iz) (each index < G <= 2^16) and the fine cell's
+// position inside its coarse cell, (x * f + y) * f + z.
+__device__ __forceinline__ uint64_t adm_coarse(int32_t ix, int32_t iy, int32_t iz, const RouteExclude& ex,
+                                               uint32_t& child) {
+  const uint32_t f = ex.factor;
+  const uint32_t cx = __umulhi((uint32_t)ix, ex.fmagic), cy = __umulhi((uint32_t)iy, ex.fmagic),
+                 cz = __umulhi((uint32_t)iz, ex.fmagic);
+  child = (((uint32_t)ix - cx * f) * f + ((uint32_t)iy - cy * f)) * f + ((uint32_t)iz - cz * f);
+  return ((uint64_t)cx * ex.gc + cy) * ex.gc + cz;
+}
+
+// The admitted count an exclusion uses: *na clamped to na_max (bit 2 of *err when above).
+__device__ __forceinline__ uint32_t adm_count(const RouteExclude& ex) {
+  const uint32_t na = *ex.na;
+  if (na > ex.na_max) {
+    if (threadIdx.x == 0) atomicOr(ex.err, 4u);
+    return ex.na_max;
+  }
+  return na;
+}
+
 static inline uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t max_blocks) {
   uint64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;

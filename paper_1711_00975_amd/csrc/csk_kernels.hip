@@ -626,6 +626,10 @@ __global__ void sel_set_m_kernel(SelState* st, uint32_t m) {
   if (threadIdx.x == 0) st->m = m;
 }
 
+__global__ void sel_set_m_dev_kernel(SelState* st, const uint64_t* m_dev, uint32_t cap) {
+  if (threadIdx.x == 0) st->m = (uint32_t)(*m_dev < cap ? *m_dev : cap);
+}
+
 // Radix select of the top k of the st->m pairs (ck, ce) in (ce desc, ck asc) order (ck
 // below 2^48), then the winners placed at their ranks in ok / oe.  rank: k words.
 static hipError_t select_stages(const uint64_t* ck, const int32_t* ce, uint32_t m_max, uint32_t k, SelState* st,
@@ -754,6 +758,14 @@ hipError_t launch_topk(const uint64_t* set, uint32_t slots, const Tables& t, con
   hipLaunchKernelGGL(clamp_m_kernel, dim3(1), dim3(64), 0, s, st, max_cand);
   // the candidate estimates are no longer needed once gathered: their first k words hold the ranks
   return select_stages(ck, ce, max_cand, k, st, sk, se, (uint32_t*)ce, ok, oe, err, s);
+}
+
+hipError_t launch_select_pairs_dev(const uint64_t* ck, const int32_t* ce, const uint64_t* m_dev, uint32_t cap,
+                                   uint32_t k, SelState* st, uint64_t* sk, int32_t* se, uint32_t* rank, uint64_t* ok,
+                                   int32_t* oe, const uint32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, s, st);
+  hipLaunchKernelGGL(sel_set_m_dev_kernel, dim3(1), dim3(64), 0, s, st, m_dev, cap);
+  return select_stages(ck, ce, cap, k, st, sk, se, rank, ok, oe, err, s);
 }
 
 hipError_t launch_select_pairs(const uint64_t* ck, const int32_t* ce, uint32_t m, uint32_t k, SelState* st,

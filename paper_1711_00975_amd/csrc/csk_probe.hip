@@ -1,8 +1,9 @@
 // csk_probe.hip — measurement probes for the ceilings the update is priced against: the
 // achievable read bandwidth of 12-byte particle records (the update's own load pattern),
-// the LDS atomic rate on a 128 KiB array, and the global atomic rate into tables of a given
-// size (resident in L2, in the MALL, or in HBM).  Built as libcsk_probe.so and used only
-// by the benchmark; not part of the C ABI of the sketch.
+// the LDS atomic rate on a 128 KiB array, the device-scope global atomic rate into tables of
+// a given size (resident in L2, in the MALL, or in HBM), and the rate of workgroup-scope
+// atomics into a per-XCD copy of a table (performed in that XCD's L2).  Built as
+// libcsk_probe.so and used only by the benchmark; not part of the C ABI of the sketch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -61,7 +62,34 @@ __global__ __launch_bounds__(256) void global_atomic_kernel(int32_t* __restrict_
   }
 }
 
+// The XCD (accelerator complex die) this wave runs on: hardware register XCC_ID, bits 3:0.
+__device__ __forceinline__ uint32_t xcc_id() {
+  return (uint32_t)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u;
+}
+
+// iters random workgroup-scope atomicAdd per thread into this XCD's private copy of a table
+// of 2^log2_words words (table holds 8 copies).  Such an atomic is performed in the L2 of the
+// XCD that issues it; the rate is what a per-XCD privatised update could reach.
+__global__ __launch_bounds__(256) void xcd_atomic_kernel(int32_t* __restrict__ table, uint32_t log2_words,
+                                                         uint64_t iters) {
+  int32_t* __restrict__ mine = table + ((uint64_t)xcc_id() << log2_words);
+  uint32_t x = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + 11u;
+  const uint32_t shift = 32u - log2_words;
+  for (uint64_t it = 0; it < iters; ++it) {
+    x = lcg(x);
+    __hip_atomic_fetch_add(&mine[x >> shift], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
 }  // namespace
+
+// blocks * 256 * iters workgroup-scope atomics, each into the issuing XCD's copy of a
+// 2^log2_words-word table: table (device) holds 8 << log2_words int32.  0 or a HIP error.
+extern "C" int probe_xcd_atomics(int32_t* table, uint32_t log2_words, uint64_t iters, uint32_t blocks, void* stream) {
+  if (blocks == 0 || log2_words < 1 || log2_words > 28) return -1;
+  hipLaunchKernelGGL(xcd_atomic_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, table, log2_words, iters);
+  return (int)hipGetLastError();
+}
 
 // n records at pos (device); sink (device) holds blocks * 1024 words.  0 or a HIP error.
 extern "C" int probe_stream_read(const float* pos, uint64_t n, uint32_t* sink, uint32_t blocks, void* stream) {

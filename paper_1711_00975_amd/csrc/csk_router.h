@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "csk_device.h"
+#include "csk_internal.h"
 
 namespace csk {
 
@@ -28,10 +29,11 @@ hipError_t launch_features(const uint32_t* counts, uint32_t Gc, const uint64_t* 
 constexpr uint32_t kSplitK = 256;
 hipError_t launch_gemm_bf16(uint32_t M, uint32_t N, uint32_t K, const float* A, uint64_t sai, uint64_t sak,
                             const float* B, uint64_t sbk, uint64_t sbj, float* C, uint64_t sci, uint64_t scj,
-                            float beta, hipStream_t s, float* partial = nullptr, uint64_t partial_floats = 0);
+                            float beta, hipStream_t s, float* partial = nullptr, uint64_t partial_floats = 0,
+                            bool split = false);
 hipError_t launch_bias_act(float* Y, uint32_t M, uint32_t N, const float* bias, bool relu, hipStream_t s);
 hipError_t launch_head(const float* H2, uint32_t M, const float* w3, const float* b3, float* z, const float* y,
-                       float* dz, float* loss, hipStream_t s);
+                       float* dz, float* loss, bool round, hipStream_t s);
 hipError_t launch_head_back(const float* dz, const float* H2, const float* w3, uint32_t M, float* dA, hipStream_t s);
 hipError_t launch_relu_back(float* dA, const float* H, uint64_t total, hipStream_t s);
 hipError_t launch_colsum(const float* X, uint32_t M, uint32_t N, uint32_t ld, const float* w, float* out, hipStream_t s);
@@ -67,5 +69,19 @@ hipError_t launch_rank_sort(const uint64_t* in, uint32_t n, uint64_t* out, hipSt
 hipError_t launch_labels(const uint64_t* cells, uint64_t m, const uint64_t* par, uint32_t np, float* labels,
                          hipStream_t s);
 hipError_t launch_logit_order(const float* z, uint64_t m, int32_t* out, hipStream_t s);
+
+// ---- the sync-free routed step
+// Features and fp32 logits of cells[0 .. min(*m_dev, cap)) (params: the MLP's 6337 fp32
+// parameters, device).
+hipError_t launch_route_score(const uint32_t* counts, uint32_t Gc, const uint64_t* cells, const uint64_t* m_dev,
+                              uint64_t cap, const float* params, float* z, hipStream_t s);
+// Admission over a device count: ord (cap words), st, sk / se / rank / ok / oe (A each) and
+// err are scratch; admitted (A keys, ascending) and *na (device) are the result.
+hipError_t launch_admit_dev(const uint64_t* cells, const float* logits, const uint64_t* m_dev, uint64_t cap, uint32_t A,
+                            int32_t* ord, SelState* st, uint64_t* sk, int32_t* se, uint32_t* rank, uint64_t* ok,
+                            int32_t* oe, uint32_t* err, uint64_t* admitted, uint32_t* na, hipStream_t s);
+// The exclusion's child counters added to the exact table (table_slot probing).
+hipError_t launch_route_table(const RouteExclude& ex, uint32_t G, uint64_t* tkeys, uint32_t* tcounts, uint32_t tmask,
+                              uint32_t* err, hipStream_t s);
 
 }  // namespace csk

@@ -29,23 +29,30 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
   }
 }
 
-// Particle index0 + i is in the sample when the first Philox word of counter
-// (index lo, index hi, kSampleStream, 0) under the seed is below `threshold`.  With a
-// bitmap, a cell's bit is set when its count leaves 0.
+// Particle g = index0 + i is in the sample when word g of the Philox stream kSampleStream
+// under the seed (word g mod 4 of counter (g / 4 lo, g / 4 hi, kSampleStream, 0)) is below
+// `threshold`.  Each thread draws one counter and so decides four consecutive particles, and
+// loads the positions of the sampled ones only.  With a bitmap, a cell's bit is set when its
+// count leaves 0.
 __global__ __launch_bounds__(256) void sample_counts_kernel(const float* __restrict__ pos, uint64_t n, uint64_t index0,
                                                             uint64_t seed, uint32_t threshold, Mesh coarse,
                                                             uint32_t* __restrict__ counts,
                                                             uint32_t* __restrict__ bitmap) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint64_t g = index0 + i;
-    uint32_t c[4] = {(uint32_t)g, (uint32_t)(g >> 32), kSampleStream, 0u};
-    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    if (c[0] >= threshold) continue;
-    uint64_t key;
-    if (cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], coarse, key)) {
-      const uint32_t old = atomicAdd(&counts[key], 1u);
-      if (bitmap != nullptr && old == 0) atomicOr(&bitmap[key >> 5], 1u << (key & 31u));   // first touch
+  const uint64_t c_lo = index0 >> 2, c_hi = (index0 + n + 3) >> 2;   // counters that cover the range
+  for (uint64_t c = c_lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < c_hi; c += stride) {
+    uint32_t r[4] = {(uint32_t)c, (uint32_t)(c >> 32), kSampleStream, 0u};
+    philox4x32_10(r, (uint32_t)seed, (uint32_t)(seed >> 32));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t g = 4 * c + (uint64_t)q;
+      if (g < index0 || g - index0 >= n || r[q] >= threshold) continue;
+      const uint64_t i = g - index0;
+      uint64_t key;
+      if (cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], coarse, key)) {
+        const uint32_t old = atomicAdd(&counts[key], 1u);
+        if (bitmap != nullptr && old == 0) atomicOr(&bitmap[key >> 5], 1u << (key & 31u));   // first touch
+      }
     }
   }
 }
@@ -74,6 +81,53 @@ __global__ __launch_bounds__(256) void features_kernel(const uint32_t* __restric
   }
 }
 
+// Features and the float32 forward pass of the router's model for cells j < min(*m, cap):
+// x = log1p of the 27 neighbour counts (in the order of features_kernel), h1 = relu(W1 x +
+// b1), h2 = relu(W2 h1 + b2), z = w3 . h2 + b3; every sum is fmaf in index order, then the
+// bias, all in fp32.  The 6337 parameters sit in LDS (read as broadcasts); one cell per
+// thread, h1 in registers.
+__global__ __launch_bounds__(256) void route_score_kernel(const uint32_t* __restrict__ counts, uint32_t Gc,
+                                                          const uint64_t* __restrict__ cells,
+                                                          const uint64_t* __restrict__ m_dev, uint64_t cap,
+                                                          const float* __restrict__ P, float* __restrict__ z) {
+  __shared__ float w[kParams];
+  for (uint32_t i = threadIdx.x; i < kParams; i += blockDim.x) w[i] = P[i];
+  __syncthreads();
+  const uint64_t m = *m_dev < cap ? *m_dev : cap;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    const uint64_t key = cells[j];
+    const uint64_t G = Gc;
+    const int64_t cx = (int64_t)(key / (G * G)), cy = (int64_t)((key / G) % G), cz = (int64_t)(key % G);
+    float x[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+      const int dx = q / 9 - 1, dy = (q / 3) % 3 - 1, dz = q % 3 - 1;
+      const uint64_t nx = (uint64_t)((cx + dx + (int64_t)G) % (int64_t)G);
+      const uint64_t ny = (uint64_t)((cy + dy + (int64_t)G) % (int64_t)G);
+      const uint64_t nz = (uint64_t)((cz + dz + (int64_t)G) % (int64_t)G);
+      x[q] = log1pf((float)counts[(nx * G + ny) * G + nz]);
+    }
+    float h1[kHidden];
+#pragma unroll
+    for (int o = 0; o < kHidden; ++o) {
+      float t = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 27; ++q) t = fmaf(w[kOffW1 + o * kFeatPad + q], x[q], t);
+      h1[o] = fmaxf(t + w[kOffB1 + o], 0.0f);
+    }
+    float out = 0.0f;
+#pragma unroll 4
+    for (int o = 0; o < kHidden; ++o) {
+      float t = 0.0f;
+#pragma unroll
+      for (int q = 0; q < kHidden; ++q) t = fmaf(w[kOffW2 + o * kHidden + q], h1[q], t);
+      out = fmaf(w[kOffW3 + o], fmaxf(t + w[kOffB2 + o], 0.0f), out);
+    }
+    z[j] = out + w[kOffB3];
+  }
+}
+
 // ------------------------------------------------------------------ MLP
 
 // fp32 -> bf16, round to nearest even (finite inputs)
@@ -83,36 +137,59 @@ __device__ __forceinline__ short to_bf16(float x) {
   return (short)(u >> 16);
 }
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+__device__ __forceinline__ float bf16_value(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
+
 // Partial product of one 16x16 tile of C over k in [k_lo, k_hi): A(i, k) = A[i * sai + k * sak],
-// B(k, j) = B[k * sbk + j * sbj] read as fp32 and rounded to bf16, products accumulated in
-// fp32 by v_mfma_f32_16x16x16_bf16; elements outside the matrices read as 0.
-// Lane l of the MFMA holds A rows l % 16, k = 4 (l / 16) .. +3; B columns l % 16 at the
-// same k; the result rows 4 (l / 16) .. +3 of column l % 16.
+// B(k, j) = B[k * sbk + j * sbj] read as fp32, products accumulated in fp32 by gfx950's
+// v_mfma_f32_16x16x32_bf16; elements outside the matrices read as 0.  Lane l holds A row
+// l % 16 at k = 8 (l / 16) .. +7 and B column l % 16 at the same k; the result is rows
+// 4 (l / 16) .. +3 of column l % 16.
+// SPLIT = false: every operand is rounded to bf16 (one product per k block).
+// SPLIT = true: every operand x is carried as hi = bf16(x) plus lo = bf16(x - hi), and the
+// tile sums hi.hi + hi.lo + lo.hi (three products): the operands keep 16 significant bits
+// and the result is within a few fp32 roundings of the fp32 product (lo.lo, below 2^-16
+// relative, is left out).
+template <bool SPLIT>
 __device__ __forceinline__ f32x4 gemm_tile(uint32_t M, uint32_t N, uint32_t k_lo, uint32_t k_hi,
                                            const float* __restrict__ A, uint64_t sai, uint64_t sak,
                                            const float* __restrict__ B, uint64_t sbk, uint64_t sbj, uint32_t i0,
                                            uint32_t j0, uint32_t lane) {
-  const uint32_t r = lane & 15u, kq = (lane >> 4) * 4;
+  const uint32_t r = lane & 15u, kq = (lane >> 4) * 8;
   const uint32_t ia = i0 + r, jb = j0 + r;
   f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (uint32_t k0 = k_lo; k0 < k_hi; k0 += 16) {
-    bf16x4 a, b;
+  for (uint32_t k0 = k_lo; k0 < k_hi; k0 += 32) {
+    s16x8 ah, bh, al, bl;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < 8; ++e) {
       const uint32_t k = k0 + kq + (uint32_t)e;
-      a[e] = to_bf16((ia < M && k < k_hi) ? A[ia * sai + k * sak] : 0.0f);
-      b[e] = to_bf16((jb < N && k < k_hi) ? B[k * sbk + jb * sbj] : 0.0f);
+      const float av = (ia < M && k < k_hi) ? A[ia * sai + k * sak] : 0.0f;
+      const float bv = (jb < N && k < k_hi) ? B[k * sbk + jb * sbj] : 0.0f;
+      ah[e] = to_bf16(av);
+      bh[e] = to_bf16(bv);
+      if (SPLIT) {
+        al[e] = to_bf16(av - bf16_value(ah[e]));
+        bl[e] = to_bf16(bv - bf16_value(bh[e]));
+      }
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh), acc,
+                                                  0, 0, 0);
+    if (SPLIT) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl),
+                                                    acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh),
+                                                    acc, 0, 0, 0);
+    }
   }
   return acc;
 }
 
 // C[i][j] = beta * C[i][j] + sum_k A(i, k) * B(k, j) for i < M, j < N.  One wave per 16x16
 // tile of C; elements outside C are not written.
+template <bool SPLIT>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(uint32_t M, uint32_t N, uint32_t K, const float* __restrict__ A,
                                                         uint64_t sai, uint64_t sak, const float* __restrict__ B,
                                                         uint64_t sbk, uint64_t sbj, float* __restrict__ C,
@@ -123,7 +200,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(uint32_t M, uint32_t N, 
   const uint64_t tiles = (uint64_t)((M + 15) / 16) * tiles_n;
   if (tile >= tiles) return;   // whole waves only: every lane of a wave shares its tile
   const uint32_t i0 = (uint32_t)(tile / tiles_n) * 16, j0 = (uint32_t)(tile % tiles_n) * 16;
-  const f32x4 acc = gemm_tile(M, N, 0, K, A, sai, sak, B, sbk, sbj, i0, j0, lane);
+  const f32x4 acc = gemm_tile<SPLIT>(M, N, 0, K, A, sai, sak, B, sbk, sbj, i0, j0, lane);
   const uint32_t r = lane & 15u, kq = (lane >> 4) * 4;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -149,7 +226,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_splitk_kernel(uint32_t M, uint3
   if (tile >= tiles) return;
   const uint32_t i0 = (uint32_t)(tile / tiles_n) * 16, j0 = (uint32_t)(tile % tiles_n) * 16;
   const uint32_t k_lo = blockIdx.y * kc, k_hi = (k_lo + kc < K) ? k_lo + kc : K;
-  const f32x4 acc = gemm_tile(M, N, k_lo, k_hi, A, sai, sak, B, sbk, sbj, i0, j0, lane);
+  const f32x4 acc = gemm_tile<false>(M, N, k_lo, k_hi, A, sai, sak, B, sbk, sbj, i0, j0, lane);
   float* out = P + (uint64_t)blockIdx.y * M * N;
   const uint32_t r = lane & 15u, kq = (lane >> 4) * 4;
 #pragma unroll
@@ -183,17 +260,21 @@ __global__ __launch_bounds__(256) void bias_act_kernel(float* __restrict__ Y, ui
   }
 }
 
-// Output layer and loss: z[i] = H2[i] . w3 + b3 (w3 rounded to bf16, fp32 sums); with
-// labels y, dz[i] = (sigmoid(z) - y) / M and loss[0] += mean binary cross-entropy.
+// Output layer and loss: z[i] = H2[i] . w3 + b3 in fp32 sums, with H2 and w3 rounded to
+// bf16 (round = 1, the training pass) or not (the scoring pass); with labels y,
+// dz[i] = (sigmoid(z) - y) / M and loss[0] += mean binary cross-entropy.
 __global__ __launch_bounds__(256) void head_kernel(const float* __restrict__ H2, uint32_t M, const float* __restrict__ w3,
                                                    const float* __restrict__ b3, float* __restrict__ z,
                                                    const float* __restrict__ y, float* __restrict__ dz,
-                                                   float* __restrict__ loss) {
+                                                   float* __restrict__ loss, uint32_t round) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < M; i += gridDim.x * blockDim.x) {
     float s = 0.0f;
     for (int j = 0; j < kHidden; ++j) {
-      const float wj = __uint_as_float((uint32_t)(uint16_t)to_bf16(w3[j]) << 16);
-      const float hj = __uint_as_float((uint32_t)(uint16_t)to_bf16(H2[(uint64_t)i * kHidden + j]) << 16);
+      float wj = w3[j], hj = H2[(uint64_t)i * kHidden + j];
+      if (round) {
+        wj = bf16_value(to_bf16(wj));
+        hj = bf16_value(to_bf16(hj));
+      }
       s = fmaf(hj, wj, s);
     }
     s += b3[0];
@@ -276,29 +357,12 @@ struct SplitArgs {
   uint64_t wchunk;      // particles per wave (a multiple of kSplitWaveTile)
 };
 
-constexpr uint32_t kAdmHashSlots = 2 * kMaxAdmitted;   // load <= 1/2
-constexpr uint64_t kEmptySlot = ~0ull;
-
-__device__ __forceinline__ uint32_t adm_hash(uint64_t key) {
-  return ((uint32_t)(key ^ (key >> 32)) * 0x9E3779B9u) >> 22;   // top 10 bits
-}
+static_assert(kAdmHashSlots == 2 * kMaxAdmitted, "the admitted-key hash is loaded at most 1/2");
+constexpr uint64_t kEmptySlot = kAdmEmpty;
 
 // Fill the LDS hash (key -> position in the admitted list); ends with a barrier.
 __device__ __forceinline__ void adm_hash_build(const SplitArgs& a, uint64_t* hkey, uint16_t* hidx) {
-  for (uint32_t i = threadIdx.x; i < kAdmHashSlots; i += blockDim.x) hkey[i] = kEmptySlot;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < a.na; i += blockDim.x) {
-    const uint64_t key = a.admitted[i];
-    uint32_t sl = adm_hash(key);
-    for (uint32_t probe = 0; probe < kAdmHashSlots; ++probe) {
-      if (atomicCAS((unsigned long long*)&hkey[sl], kEmptySlot, (unsigned long long)key) == kEmptySlot) {
-        hidx[sl] = (uint16_t)i;
-        break;
-      }
-      sl = (sl + 1) & (kAdmHashSlots - 1);
-    }
-  }
-  __syncthreads();
+  adm_hash_fill(a.admitted, a.na, hkey, hidx);
 }
 
 // Classes of a wave tile's PPT particles: cls[j] = position of the admitted coarse
@@ -791,6 +855,75 @@ __global__ __launch_bounds__(256) void logit_order_kernel(const float* __restric
   }
 }
 
+// The same for the cells j < min(*m, cap) of a device count.
+__global__ __launch_bounds__(256) void logit_order_dev_kernel(const float* __restrict__ z,
+                                                              const uint64_t* __restrict__ m_dev, uint64_t cap,
+                                                              int32_t* __restrict__ out) {
+  const uint64_t m = *m_dev < cap ? *m_dev : cap;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    uint32_t u = __float_as_uint(z[j]);
+    if (u == 0x80000000u) u = 0u;
+    const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    out[j] = (int32_t)(ord ^ 0x80000000u);
+  }
+}
+
+// The n = min(winners, A) admitted keys in ascending order (the ranks of rank_sort_kernel
+// over a device count); *na = n.
+__global__ __launch_bounds__(256) void admit_sort_kernel(const uint64_t* __restrict__ in, const SelState* st, uint32_t A,
+                                                         uint64_t* __restrict__ out, uint32_t* __restrict__ na) {
+  __shared__ uint64_t tile[256];
+  const uint32_t n = st->n_sel < A ? st->n_sel : A;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t v = i < n ? in[i] : 0;
+  uint32_t r = 0;
+  for (uint32_t j0 = 0; j0 < n; j0 += 256) {
+    __syncthreads();
+    if (j0 + threadIdx.x < n) tile[threadIdx.x] = in[j0 + threadIdx.x];
+    __syncthreads();
+    const uint32_t lim = n - j0 < 256 ? n - j0 : 256;
+    for (uint32_t t = 0; t < lim; ++t) r += (tile[t] < v) || (tile[t] == v && j0 + t < i);
+  }
+  if (i < n) out[r] = v;
+  if (i == 0) *na = n;
+}
+
+// The exclusion's child counters into the exact table: child e = position * f3 + c of the
+// admitted cell admitted[position] with a nonzero count is added under its fine key
+// (linear probing from table_slot; bit 1 of *err if the table is full).
+__global__ __launch_bounds__(256) void route_table_kernel(RouteExclude ex, uint32_t G, uint64_t* __restrict__ tkeys,
+                                                          uint32_t* __restrict__ tcounts, uint32_t tmask,
+                                                          uint32_t* __restrict__ err) {
+  const uint32_t na = *ex.na < ex.na_max ? *ex.na : ex.na_max;
+  const uint32_t nd = na * ex.f3;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nd; e += gridDim.x * blockDim.x) {
+    const uint32_t cnt = ex.child[e];
+    if (cnt == 0) continue;
+    const uint32_t f = ex.factor, c = e % ex.f3;
+    const uint64_t Gc = ex.gc, P = ex.admitted[e / ex.f3];
+    const uint64_t px = P / (Gc * Gc), py = (P / Gc) % Gc, pz = P % Gc;
+    const uint64_t ix = px * f + c / (f * f), iy = py * f + (c / f) % f, iz = pz * f + c % f;
+    const uint64_t key = (ix * G + iy) * G + iz;
+    uint32_t sl = table_slot(key, tmask);
+    bool placed = false;
+    for (uint32_t probe = 0; probe <= tmask; ++probe) {
+      uint64_t cur = __hip_atomic_load(&tkeys[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (cur == ~0ull) {
+        cur = atomicCAS((unsigned long long*)&tkeys[sl], ~0ull, (unsigned long long)key);
+        if (cur == ~0ull) cur = key;
+      }
+      if (cur == key) {
+        atomicAdd(&tcounts[sl], cnt);
+        placed = true;
+        break;
+      }
+      sl = (sl + 1) & tmask;
+    }
+    if (!placed) atomicOr(err, 2u);
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 
 static uint32_t grid_of(uint64_t n, uint32_t threads, uint32_t max_blocks) {
@@ -802,7 +935,7 @@ static uint32_t grid_of(uint64_t n, uint32_t threads, uint32_t max_blocks) {
 
 hipError_t launch_sample_counts(const float* pos, uint64_t n, uint64_t index0, uint64_t seed, uint32_t threshold,
                                 const Mesh& coarse, uint32_t* counts, uint32_t* bitmap, hipStream_t s) {
-  hipLaunchKernelGGL(sample_counts_kernel, dim3(grid_of(n, 256, 8192)), dim3(256), 0, s, pos, n, index0, seed,
+  hipLaunchKernelGGL(sample_counts_kernel, dim3(grid_of(n / 4 + 2, 256, 8192)), dim3(256), 0, s, pos, n, index0, seed,
                      threshold, coarse, counts, bitmap);
   return hipGetLastError();
 }
@@ -815,17 +948,22 @@ hipError_t launch_features(const uint32_t* counts, uint32_t Gc, const uint64_t* 
 
 hipError_t launch_gemm_bf16(uint32_t M, uint32_t N, uint32_t K, const float* A, uint64_t sai, uint64_t sak,
                             const float* B, uint64_t sbk, uint64_t sbj, float* C, uint64_t sci, uint64_t scj,
-                            float beta, hipStream_t s, float* partial, uint64_t partial_floats) {
+                            float beta, hipStream_t s, float* partial, uint64_t partial_floats, bool split) {
   const uint64_t tiles = (uint64_t)((M + 15) / 16) * ((N + 15) / 16);
   uint64_t nsplit = (K + kSplitK - 1) / kSplitK;
   if (partial != nullptr && (uint64_t)M * N > 0 && nsplit * (uint64_t)M * N > partial_floats)
     nsplit = partial_floats / ((uint64_t)M * N);
-  if (partial == nullptr || K < 2 * kSplitK || tiles >= 256 || nsplit < 2) {
-    hipLaunchKernelGGL(gemm_bf16_kernel, dim3((uint32_t)((tiles + 3) / 4)), dim3(256), 0, s, M, N, K, A, sai, sak, B,
-                       sbk, sbj, C, sci, scj, beta);
+  if (split) {   // the scoring pass: no split over k
+    hipLaunchKernelGGL(gemm_bf16_kernel<true>, dim3((uint32_t)((tiles + 3) / 4)), dim3(256), 0, s, M, N, K, A, sai,
+                       sak, B, sbk, sbj, C, sci, scj, beta);
     return hipGetLastError();
   }
-  const uint32_t kc = (uint32_t)(((K + nsplit - 1) / nsplit + 15) / 16 * 16);
+  if (partial == nullptr || K < 2 * kSplitK || tiles >= 256 || nsplit < 2) {
+    hipLaunchKernelGGL(gemm_bf16_kernel<false>, dim3((uint32_t)((tiles + 3) / 4)), dim3(256), 0, s, M, N, K, A, sai,
+                       sak, B, sbk, sbj, C, sci, scj, beta);
+    return hipGetLastError();
+  }
+  const uint32_t kc = (uint32_t)(((K + nsplit - 1) / nsplit + 31) / 32 * 32);
   nsplit = (K + kc - 1) / kc;
   hipLaunchKernelGGL(gemm_bf16_splitk_kernel, dim3((uint32_t)((tiles + 3) / 4), (uint32_t)nsplit), dim3(256), 0, s, M,
                      N, K, kc, A, sai, sak, B, sbk, sbj, partial);
@@ -841,8 +979,9 @@ hipError_t launch_bias_act(float* Y, uint32_t M, uint32_t N, const float* bias, 
 }
 
 hipError_t launch_head(const float* H2, uint32_t M, const float* w3, const float* b3, float* z, const float* y,
-                       float* dz, float* loss, hipStream_t s) {
-  hipLaunchKernelGGL(head_kernel, dim3(grid_of(M, 256, 4096)), dim3(256), 0, s, H2, M, w3, b3, z, y, dz, loss);
+                       float* dz, float* loss, bool round, hipStream_t s) {
+  hipLaunchKernelGGL(head_kernel, dim3(grid_of(M, 256, 4096)), dim3(256), 0, s, H2, M, w3, b3, z, y, dz, loss,
+                     round ? 1u : 0u);
   return hipGetLastError();
 }
 
@@ -989,6 +1128,33 @@ hipError_t launch_labels(const uint64_t* cells, uint64_t m, const uint64_t* par,
 
 hipError_t launch_logit_order(const float* z, uint64_t m, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(logit_order_kernel, dim3(grid_of(m, 256, 8192)), dim3(256), 0, s, z, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_route_score(const uint32_t* counts, uint32_t Gc, const uint64_t* cells, const uint64_t* m_dev,
+                              uint64_t cap, const float* params, float* z, hipStream_t s) {
+  if (cap == 0) return hipSuccess;
+  hipLaunchKernelGGL(route_score_kernel, dim3(grid_of(cap, 256, 2048)), dim3(256), 0, s, counts, Gc, cells, m_dev, cap,
+                     params, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_admit_dev(const uint64_t* cells, const float* logits, const uint64_t* m_dev, uint64_t cap, uint32_t A,
+                            int32_t* ord, SelState* st, uint64_t* sk, int32_t* se, uint32_t* rank, uint64_t* ok,
+                            int32_t* oe, uint32_t* err, uint64_t* admitted, uint32_t* na, hipStream_t s) {
+  hipLaunchKernelGGL(logit_order_dev_kernel, dim3(grid_of(cap, 256, 8192)), dim3(256), 0, s, logits, m_dev, cap, ord);
+  hipError_t e = launch_select_pairs_dev(cells, ord, m_dev, (uint32_t)cap, A, st, sk, se, rank, ok, oe, err, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(admit_sort_kernel, dim3((A + 255) / 256), dim3(256), 0, s, ok, st, A, admitted, na);
+  return hipGetLastError();
+}
+
+hipError_t launch_route_table(const RouteExclude& ex, uint32_t G, uint64_t* tkeys, uint32_t* tcounts, uint32_t tmask,
+                              uint32_t* err, hipStream_t s) {
+  const uint32_t nd = ex.na_max * ex.f3;
+  if (nd == 0) return hipSuccess;
+  hipLaunchKernelGGL(route_table_kernel, dim3(grid_of(nd, 256, 1024)), dim3(256), 0, s, ex, G, tkeys, tcounts, tmask,
+                     err);
   return hipGetLastError();
 }
 

@@ -112,13 +112,15 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
 // the stream or the domain go to a dummy bin that is never written.  A run that would
 // overflow its region goes to the counters through atomics instead (same sum).
 // Token scratch is workgroup-major: region (g, s) starts at (g * P + s) * cap.
-// LDS layout (words): Ti [1536 * DP] | dst [RP*Pr + 1] | cursor [P] | hist [RP*Pr + 1] |
-// base [RP*Pr + 1] | stage [RP * tile] | wsum [NW].
+// LDS layout (words): [EX: admitted hash, kAdmLdsWords] | Ti [1536 * DP] | dst [RP*Pr + 1] |
+// cursor [P] | hist [RP*Pr + 1] | base [RP*Pr + 1] | stage [RP * tile] | wsum [NW].
+// EX (the learned router's rest sketch): a particle in an admitted coarse cell is counted in
+// the exclusion's child counters and goes to the dummy bin instead of the sketch.
 constexpr uint32_t kDstDrop = 0xFFFFFFFFu;      // dummy bin: never written
 constexpr uint32_t kDstOverflow = 0xFFFFFFFEu;  // run added with atomics
 constexpr uint32_t kDstBias = 1u << 16;         // keeps offset + cursor - base positive
 
-template <int D, uint32_t MODE, int NT, int RP, int HM, int KB>
+template <int D, uint32_t MODE, int NT, int RP, int HM, int KB, bool EX = false>
 __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const float* __restrict__ pos, uint64_t n,
                                           uint32_t g) {
   const BinArgs& a = *ap;   // read in place (argument segment or descriptor), not copied
@@ -128,7 +130,9 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
   const BinPlan& pl = a.plan;
   const uint32_t nbins = RP * pl.Pr + 1;                 // + the dummy bin
   const uint32_t dummy = nbins - 1;
-  uint32_t* ti = lds2;
+  uint64_t* hkey = (uint64_t*)lds2;                                 // EX only
+  uint16_t* hidx = (uint16_t*)(lds2 + 2 * kAdmHashSlots);           // EX only
+  uint32_t* ti = lds2 + (EX ? kAdmLdsWords : 0);
   uint32_t* dst = ti + kTableWords * DP;
   uint32_t* cursor = dst + nbins;
   uint32_t* hist = cursor + pl.P;
@@ -141,6 +145,7 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
   for (uint32_t i = tid; i < pl.P; i += NT) cursor[i] = 0;
   for (uint32_t i = tid; i < nbins; i += NT) hist[i] = 0;
   stage_tables<DP>(ti, HM == kHashPacked ? a.tabp : a.tabi, (uint32_t)KB);   // fold point KB >= nch
+  if constexpr (EX) adm_hash_fill(a.ex.admitted, adm_count(a.ex), hkey, hidx);   // ends with a barrier
 
   const uint32_t per = (nbins + NT - 1) / NT;           // scan: bins per thread
   const uint32_t blo = min(nbins, tid * per), bhi = min(nbins, blo + per);
@@ -193,10 +198,28 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
       const bool in = full || (first + (uint64_t)j * NT + tid) < n;
       uint64_t key;   // always a key of the mesh, so the table lookups stay in range
       bool ok;
-      if constexpr (MODE == kMeshPacked) ok = packed_key(pw[j], a.mesh, key) && in;
-      else ok = cell_key_m<MODE>(px[j], py[j], pz[j], a.mesh, key) && in;
+      if constexpr (EX) {
+        static_assert(MODE != kMeshPacked, "the exclusion reads float positions");
+        int32_t ix, iy, iz;
+        ok = ((int)cell_index_m<MODE>(px[j], a.mesh, ix) & (int)cell_index_m<MODE>(py[j], a.mesh, iy) &
+              (int)cell_index_m<MODE>(pz[j], a.mesh, iz)) && in;
+        key = ((uint64_t)((uint32_t)ix * (uint32_t)a.mesh.G + (uint32_t)iy)) * (uint64_t)(uint32_t)a.mesh.G +
+              (uint64_t)(uint32_t)iz;   // ungrouped: the caller checks
+        valid |= (uint32_t)ok << j;
+        if (ok) {
+          uint32_t child;
+          const int32_t c = adm_find(adm_coarse(ix, iy, iz, a.ex, child), hkey, hidx);
+          if (c >= 0) {
+            atomicAdd(&a.ex.child[(uint32_t)c * a.ex.f3 + child], 1u);
+            ok = false;   // counted exactly; its tokens go to the dummy bin
+          }
+        }
+      } else {
+        if constexpr (MODE == kMeshPacked) ok = packed_key(pw[j], a.mesh, key) && in;
+        else ok = cell_key_m<MODE>(px[j], py[j], pz[j], a.mesh, key) && in;
+        valid |= (uint32_t)ok << j;
+      }
       inside |= (uint32_t)in << j;
-      valid |= (uint32_t)ok << j;
       uint32_t bk[D], sg[D];
       rows_bucket_sign_kb<D, HM, KB>(ti, key, a.w, a.wshift, bk, sg);
 #pragma unroll
@@ -205,7 +228,6 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
         const uint32_t neg = sg[r] & (a.cm ^ 1u);
         const uint32_t bin = (uint32_t)(r % RP) * pl.Pr + (b >> kSliceBits);
         sv[r][j] = ok ? ((bin << 16) | (b & (kSlice - 1)) | (neg << 15)) : (dummy << 16);
-        asm volatile("" : "+v"(sv[r][j]));   // materialised here (see the sort-word kernel)
       }
     }
     // particles of the stream that are outside the domain latch the error
@@ -284,6 +306,11 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
 template <int D, uint32_t MODE, int NT, int RP, int HM, int KB>
 __global__ __launch_bounds__(NT) void bin3_kernel(BinArgs a) {
   bin3_body<D, MODE, NT, RP, HM, KB>(&a, a.pos, a.n, blockIdx.x);
+}
+
+template <int D, uint32_t MODE, int NT, int RP, int HM>
+__global__ __launch_bounds__(NT) void bin3_ex_kernel(BinArgs a) {
+  bin3_body<D, MODE, NT, RP, HM, kChars, true>(&a, a.pos, a.n, blockIdx.x);
 }
 
 // Many sketches in one launch: workgroup blockIdx.x serves sketch wg_sketch[blockIdx.x] as
@@ -428,6 +455,7 @@ BinArgs make_bin_args(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
   a.cnt = cnt;
   a.M = M;
   a.err = err;
+  a.ex = RouteExclude{};
   return a;
 }
 
@@ -488,6 +516,32 @@ hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
   } else {
     hipLaunchKernelGGL(bin_kernel<false>, dim3(plan.nwg), dim3(kBinThreads), plan.lds_bytes, s, a);
   }
+  return hipGetLastError();
+}
+
+// The general bin kernel with the router's exclusion (d = 5, float positions, ungrouped
+// mesh; the plan's LDS includes kAdmLdsWords).
+template <uint32_t MM>
+static void launch_bin3_ex_m(int hm, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, const BinArgs& a) {
+  if (hm == kHashPacked)
+    hipLaunchKernelGGL((bin3_ex_kernel<5, MM, kBin2Threads, kBin2Rows, kHashPacked>), grid, block, lds, s, a);
+  else if (hm == kHashMulHi)
+    hipLaunchKernelGGL((bin3_ex_kernel<5, MM, kBin2Threads, kBin2Rows, kHashMulHi>), grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL((bin3_ex_kernel<5, MM, kBin2Threads, kBin2Rows, kHashShift>), grid, block, lds, s, a);
+}
+
+hipError_t launch_bin_routed(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
+                             uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, const RouteExclude& ex,
+                             hipStream_t s) {
+  if (t.d != 5 || !plan.fast || plan.sort || mesh.mode == kMeshPacked || mesh.group != 1u) return hipErrorInvalidValue;
+  BinArgs a = make_bin_args(pos, n, mesh, t, plan, tok, cnt, M, err);
+  a.ex = ex;
+  const dim3 grid(plan.nwg), block(kBin2Threads);
+  if (mesh.mode == kMeshPow2Ratio) launch_bin3_ex_m<kMeshPow2Ratio>(t.hash_mode(), grid, block, plan.lds_bytes, s, a);
+  else if (mesh.mode == kMeshExactRatio)
+    launch_bin3_ex_m<kMeshExactRatio>(t.hash_mode(), grid, block, plan.lds_bytes, s, a);
+  else launch_bin3_ex_m<kMeshGeneral>(t.hash_mode(), grid, block, plan.lds_bytes, s, a);
   return hipGetLastError();
 }
 
@@ -596,6 +650,48 @@ hipError_t launch_update_direct(const float* pos, uint64_t n, const Mesh& mesh, 
                                 uint32_t* err, hipStream_t s) {
   hipLaunchKernelGGL(update_direct_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, pos, n, mesh, t.tab,
                      t.d, t.w, t.cm, M, err);
+  return hipGetLastError();
+}
+
+// The direct update with the router's exclusion (any d, float positions, ungrouped mesh):
+// a particle in an admitted coarse cell adds 1 to its child counter instead of d counters.
+__global__ __launch_bounds__(256) void update_direct_ex_kernel(const float* __restrict__ pos, uint64_t n, Mesh mesh,
+                                                               const uint32_t* __restrict__ tab, uint32_t d,
+                                                               uint32_t w, uint32_t cm, int32_t* __restrict__ M,
+                                                               uint32_t* __restrict__ err, RouteExclude ex) {
+  __shared__ uint64_t hkey[kAdmHashSlots];
+  __shared__ uint16_t hidx[kAdmHashSlots];
+  adm_hash_fill(ex.admitted, adm_count(ex), hkey, hidx);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    int32_t ix, iy, iz;
+    const bool ok = (int)cell_index(pos[3 * i], mesh, ix) & (int)cell_index(pos[3 * i + 1], mesh, iy) &
+                    (int)cell_index(pos[3 * i + 2], mesh, iz);
+    if (!ok) {
+      atomicOr(err, kErrDomain);
+      continue;
+    }
+    uint32_t child;
+    const int32_t c = adm_find(adm_coarse(ix, iy, iz, ex, child), hkey, hidx);
+    if (c >= 0) {
+      atomicAdd(&ex.child[(uint32_t)c * ex.f3 + child], 1u);
+      continue;
+    }
+    const uint64_t key =
+        ((uint64_t)((uint32_t)ix * (uint32_t)mesh.G + (uint32_t)iy)) * (uint64_t)(uint32_t)mesh.G + (uint32_t)iz;
+    for (uint32_t r = 0; r < d; ++r) {
+      const uint32_t h = row_hash(tab + r * kTableWords, key);
+      const uint32_t neg = (h >> 31) & (cm ^ 1u);
+      atomicAdd(&M[(uint64_t)r * w + bucket_of(h, w)], neg ? -1 : 1);
+    }
+  }
+}
+
+hipError_t launch_update_direct_routed(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, int32_t* M,
+                                       uint32_t* err, const RouteExclude& ex, hipStream_t s) {
+  if (mesh.mode == kMeshPacked || mesh.group != 1u) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(update_direct_ex_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, pos, n, mesh, t.tab,
+                     t.d, t.w, t.cm, M, err, ex);
   return hipGetLastError();
 }
 

@@ -19,8 +19,10 @@ from __future__ import annotations
 
 import math
 
-from . import (FEAT, MLP, Sketch, cell_features, cell_labels, cell_list, cells_clear, exact_counts, new_table,
-               route_admit, route_split, sample_counts, table_topk, topk_with_table)
+from . import (FEAT, MLP, Sketch, cell_features, cell_labels, cell_list, cell_list_async, cell_list_workspace_bytes,
+               cells_clear, exact_counts, new_table, route_admit, route_admit_async, route_admit_workspace_bytes,
+               route_score, route_split, route_update_workspace_bytes, sample_counts, table_topk, topk_with_table,
+               topk_with_table_async, update_routed)
 
 TABLE_BYTES_PER_SLOT = 12     # 8-byte key + 4-byte count
 
@@ -109,8 +111,73 @@ class Router:
         self.mlp.close()
 
 
+class RoutedStep:
+    """One routed step with no host synchronization, on buffers held here:
+
+    sample -> coarse-cell listing (device count) -> features and fp32 logits (one kernel)
+    -> admission of the best max_admit cells (device count) -> update of the rest sketch
+    with the admitted cells' particles counted in the exact table instead (no rest stream
+    is written) -> candidate pass of the rest sketch over the whole stream -> merged top-k.
+
+    Every call only enqueues kernels, so that after one eager run (which sizes the
+    libraries' scratch) the step can be captured in a HIP graph and replayed."""
+
+    def __init__(self, router: Router, rest: Sketch, k: int, max_cells: int = 1 << 20):
+        import torch
+        dev = "cuda"
+        self.r, self.rest, self.k = router, rest, k
+        self.cells = torch.empty(max_cells, dtype=torch.int64, device=dev)
+        self.m = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.logits = torch.empty(max_cells, dtype=torch.float32, device=dev)
+        self.admitted = torch.empty(router.max_admit, dtype=torch.int64, device=dev)
+        self.na = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.table_keys, self.table_counts = new_table(router.table_slots)
+        self.err = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.keys = torch.empty(max(k, 1), dtype=torch.int64, device=dev)
+        self.est = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
+        self.out = torch.zeros(2, dtype=torch.int32, device=dev)
+        u8 = torch.uint8
+        self.list_ws = torch.empty(cell_list_workspace_bytes(router.counts.numel()), dtype=u8, device=dev)
+        self.admit_ws = torch.empty(route_admit_workspace_bytes(max_cells, router.max_admit), dtype=u8, device=dev)
+        self.update_ws = torch.empty(route_update_workspace_bytes(router.factor, router.table_slots), dtype=u8,
+                                     device=dev)
+
+    def admit(self, pos):
+        r = self.r
+        sample_counts(pos, r.delta_c, r.L, r.sample_seed, r.counts, bitmap=r.bitmap)
+        cell_list_async(r.counts, self.cells, self.m, r.min_count, bitmap=r.bitmap, workspace=self.list_ws)
+        route_score(r.mlp, r.counts, r.delta_c, r.L, self.cells, self.m, self.logits)
+        cells_clear(r.counts, r.bitmap)
+        route_admit_async(self.cells, self.logits, self.m, r.max_admit, self.admitted, self.na,
+                          workspace=self.admit_ws)
+
+    def update(self, pos):
+        r = self.r
+        self.table_keys.fill_(-1)
+        self.table_counts.zero_()
+        self.rest.reset()
+        update_routed(self.rest, pos, r.delta, r.L, r.factor, self.admitted, self.na, self.table_keys,
+                      self.table_counts, self.err, workspace=self.update_ws)
+
+    def select(self, pos, theta):
+        r = self.r
+        self.rest.collect(pos, r.delta, r.L, theta)
+        topk_with_table_async(self.rest, self.table_keys, self.table_counts, self.k, self.keys, self.est, self.out)
+
+    def run(self, pos, theta):
+        self.admit(pos)
+        self.update(pos)
+        self.select(pos, theta)
+
+    def result(self):
+        """(keys, estimates, status) after the stream has synchronized: status 0, or 1 when
+        fewer than k keys came from a partial candidate set."""
+        n, partial = (int(v) for v in self.out.cpu())
+        return self.keys[:n], self.est[:n], partial
+
+
 def routed_topk(sketch: Sketch, table_keys, table_counts, k: int):
     return topk_with_table(sketch, table_keys, table_counts, k)
 
 
-__all__ = ["Router", "rest_width", "routed_topk", "TABLE_BYTES_PER_SLOT", "FEAT"]
+__all__ = ["Router", "RoutedStep", "rest_width", "routed_topk", "TABLE_BYTES_PER_SLOT", "FEAT"]

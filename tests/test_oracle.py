@@ -598,11 +598,13 @@ def test_router_features_and_sample_by_brute_force():
                     assert f[r, q] == np.float32(np.log1p(np.float32(counts[nb])))
                     q += 1
         assert not f[r, 27:].any()
-    # the sample: about 1 % of the stream, and the coin is the published Philox word
+    # the sample: about 1 % of the stream, and particle g's coin is word g mod 4 of the
+    # published Philox block at counter g / 4
     m = router.sample_mask(200_000, 9)
     assert 0.009 < m.mean() < 0.011
-    w = workloads.philox4x32_10([12345, 0, 4, 0], [9, 0])[0]
-    assert m[12345] == (w < router.SAMPLE_THRESHOLD)
+    for g in (12344, 12345, 12346, 12347):
+        w = workloads.philox4x32_10([g // 4, 0, 4, 0], [9, 0])[g % 4]
+        assert m[g] == (w < router.SAMPLE_THRESHOLD)
 
 
 def test_router_forward_and_gradients_by_loops_and_differences():
@@ -795,19 +797,21 @@ def test_philox_matches_an_independent_engine(torch_philox):
               for _ in range(500)]
     for ctr, key in cases:
         assert np.array_equal(workloads.philox4x32_10(ctr, key), torch_philox(ctr, key)), (ctr, key)
-    # the batch form: word 0 at counter (index mod 2^32, index / 2^32, stream, 0), key = seed
-    for index0, stream, seed in [(0, 1, 1), (2 ** 32 - 3, 4, 2 ** 40 + 5), (10 ** 12, 2, 9)]:
-        got = workloads.philox_words(index0, 6, stream, seed)
-        for i in range(6):
+    # the stream form: word g is word g mod 4 at counter (g / 4 mod 2^32, g / 4 / 2^32,
+    # stream, 0), key = seed; ranges that start and end inside a block and cross 2^34
+    for index0, stream, seed in [(0, 1, 1), (2 ** 34 - 3, 4, 2 ** 40 + 5), (10 ** 12 + 1, 2, 9)]:
+        got = workloads.philox_words(index0, 7, stream, seed)
+        for i in range(7):
             g = index0 + i
-            want = torch_philox([g & 0xFFFFFFFF, g >> 32, stream, 0], [seed & 0xFFFFFFFF, seed >> 32])[0]
+            c = g // 4
+            want = torch_philox([c & 0xFFFFFFFF, c >> 32, stream, 0], [seed & 0xFFFFFFFF, seed >> 32])[g % 4]
             assert got[i] == want, (index0, stream, seed, i)
 
 
 def test_router_sample_counts_by_particle_loop(torch_philox):
-    # One particle at a time: the coin is word 0 of the independent engine at counter
-    # (index, stream 4), the cell is the exact floor by rationals, and a particle outside the
-    # domain is never counted.
+    # One particle at a time: the coin of particle g is word g mod 4 of the independent
+    # engine at counter (g / 4, stream 4), the cell is the exact floor by rationals, and a
+    # particle outside the domain is never counted.
     from oracle import router
     rng = np.random.default_rng(31)
     L, dc, seed = 10.0, 2.5, 2 ** 33 + 17
@@ -816,12 +820,13 @@ def test_router_sample_counts_by_particle_loop(torch_philox):
     pos[5] = [np.nan, 1.0, 1.0]
     pos[6] = [1.0, 2 * L, 1.0]
     pos[7] = [-1.0, 0.0, np.float32(L)]        # wraps into the box
-    for index0, threshold in [(0, 2 ** 31), (2 ** 32 - 1000, 2 ** 30), (123, router.SAMPLE_THRESHOLD)]:
+    for index0, threshold in [(0, 2 ** 31), (2 ** 34 - 1001, 2 ** 30), (123, router.SAMPLE_THRESHOLD)]:
         want = np.zeros(Gc ** 3, dtype=np.int64)
         for i, p in enumerate(pos):
             g = index0 + i
-            coin = torch_philox([g & 0xFFFFFFFF, g >> 32, router.SAMPLE_STREAM, 0],
-                                [seed & 0xFFFFFFFF, seed >> 32])[0]
+            c = g // 4
+            coin = torch_philox([c & 0xFFFFFFFF, c >> 32, router.SAMPLE_STREAM, 0],
+                                [seed & 0xFFFFFFFF, seed >> 32])[g % 4]
             if coin >= threshold:
                 continue
             if not all(math.isfinite(float(c)) and abs(float(c)) < 2 * L for c in p):
@@ -861,3 +866,22 @@ def test_router_topk_routed_by_dict_merge():
         gk, gv = router.topk_routed(tkeys, tcounts, M, T, rest, delta, L, theta, k)
         assert list(gk) == [kk for kk, _ in want] and list(gv) == [v for _, v in want], (theta, k)
         assert len(gk) == min(k, len(cand))
+
+
+def test_router_fp32_forward_matches_exact_loops():
+    # the unrounded float32 reference against float64 loops over neurons: only float32
+    # summation and storage rounding separate them (a pin of forward_fp32, which the GPU
+    # logits are held to within 2e-2)
+    from oracle import router as ref
+    rng = np.random.default_rng(17)
+    w = ref.unpack(rng.normal(0, 0.3, ref.N_PARAMS).astype(np.float32))
+    w["W1"][:, 27:] = 0
+    p = ref.pack(w)
+    x = np.zeros((24, 32), np.float32)
+    x[:, :27] = np.log1p(rng.poisson(4.0, (24, 27))).astype(np.float32)
+    z = ref.forward_fp32(p, x).astype(np.float64)
+    ze = ref.forward_loops_exact(p, x)
+    assert np.max(np.abs(z - ze)) < 1e-4 * max(1.0, np.max(np.abs(ze)))
+    # a wrong layer (the bf16 one) is visibly different from the exact reference
+    zb = ref.forward(p, x)[0].astype(np.float64)
+    assert np.max(np.abs(zb - ze)) > 10 * np.max(np.abs(z - ze))

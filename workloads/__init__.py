@@ -60,7 +60,8 @@ def philox4x32_10(ctr, key) -> np.ndarray:
 
 
 def philox_words(index0: int, n: int, stream: int, seed: int) -> np.ndarray:
-    """First Philox4x32-10 word at counter (index, stream, 0) for indices index0 .. index0 + n - 1."""
+    """Words index0 .. index0 + n - 1 of the Philox4x32-10 output stream: word g is word g mod 4
+    of the counter (g / 4, stream, 0)."""
     out = np.empty(max(n, 1), dtype=np.uint32)
     _load().wl_philox_words(index0, n, stream, seed, _p(out))
     return out[:n]

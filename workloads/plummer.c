@@ -320,17 +320,18 @@ int64_t wl_alias_records(uint64_t seed, uint32_t n_halo, double L, double m_lo, 
     return 0;
 }
 
-/* out[i] = first word of Philox4x32-10 at counter ((index0 + i) mod 2^32, (index0 + i) / 2^32,
- * stream, 0) under key (seed mod 2^32, seed / 2^32), for i < n. */
+/* out[i] = word g mod 4 of Philox4x32-10 at counter ((g / 4) mod 2^32, (g / 4) / 2^32, stream, 0)
+ * under key (seed mod 2^32, seed / 2^32), g = index0 + i, for i < n: the g-th 32-bit word of the
+ * generator's output stream, four words per counter. */
 void wl_philox_words(uint64_t index0, uint64_t n, uint32_t stream, uint64_t seed, uint32_t *out)
 {
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     #pragma omp parallel for schedule(static)
     for (int64_t ii = 0; ii < (int64_t)n; ++ii) {
-        const uint64_t g = index0 + (uint64_t)ii;
-        const uint32_t ctr[4] = {(uint32_t)g, (uint32_t)(g >> 32), stream, 0u};
+        const uint64_t g = index0 + (uint64_t)ii, c = g >> 2;
+        const uint32_t ctr[4] = {(uint32_t)c, (uint32_t)(c >> 32), stream, 0u};
         uint32_t r[4];
         wl_philox4x32_10(ctr, key, r);
-        out[ii] = r[0];
+        out[ii] = r[g & 3u];
     }
 }
