@@ -138,7 +138,17 @@ def host_info():
         aff = len(os.sched_getaffinity(0))
     except AttributeError:
         aff = None
-    return {"nproc": os.cpu_count(), "usable": aff, "cpu_model": model}
+    info = {"nproc": os.cpu_count(), "usable": aff, "cpu_model": model}
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            key, _, val = line.partition(":")
+            if key.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info["lscpu_" + key.strip().lower().replace("(s)", "s").replace(" ", "_")] = val.strip()
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return info
 
 
 def cpu_baseline(pos_dev, wl, sample, threads):
@@ -159,24 +169,70 @@ def cpu_baseline(pos_dev, wl, sample, threads):
                       f"({t2 - t1:.1f} s, one thread)"}
 
 
-def oracle_full(pos_dev, wl, threads):
-    """The oracle on the whole stream: keys + Add on `threads` host threads (one sketch per
-    thread, summed), then the estimates of every distinct cell and the top-k on one thread,
-    and the exact histogram by sort (the recall reference)."""
+def oracle_full(pos_dev, wl, threads, chunk=1 << 26, key_block=1 << 24, s=None, theta=None):
+    """The oracle on the whole stream, in pieces that each report when done:
+    - Add (oracle.sketch) on `threads` host threads per chunk of `chunk` particles; the
+      counters of the chunks are summed, which is the sketch of the stream (Add is additive);
+    - the distinct cell keys (oracle.keys per chunk, then one np.unique over the chunks');
+    - the top-k of Sec. 2.2 over every distinct cell with theta = INT32_MIN: oracle.topk_keys
+      on disjoint blocks of `key_block` distinct keys, then the same order (estimate desc,
+      key asc) over the blocks' winners.
+    With a sketch handle s (and its calibrated theta), the GPU's counters and top-k of the
+    same stream are compared with the oracle's."""
     import numpy as np
     import oracle
+    n = pos_dev.shape[0]
+    T = oracle.hash_tables(wl.seed, wl.d)
     t0 = time.perf_counter()
-    pos = pos_dev.cpu().numpy()
+    M = np.zeros((wl.d, wl.w), dtype=np.int64)
+    skipped = 0
+    uniq_parts = []
+    t_add = t_keys = 0.0
+    for a in range(0, n, chunk):
+        pos = pos_dev[a:a + chunk].cpu().numpy()
+        ta = time.perf_counter()
+        Mc, sk = oracle.sketch(pos, wl.d, wl.w, wl.seed, wl.delta, wl.L, threads=threads)
+        tb = time.perf_counter()
+        M += Mc
+        skipped += int(sk)
+        uniq_parts.append(np.unique(oracle.keys(pos, wl.delta, wl.L)))
+        tc = time.perf_counter()
+        t_add += tb - ta
+        t_keys += tc - tb
+        log(f"  oracle: particles {a + pos.shape[0]}/{n}: Add {tb - ta:.1f} s, keys {tc - tb:.1f} s")
+    M = M.astype(np.int32)     # exact: every counter of the whole stream fits int32 (n < 2^31)
     t1 = time.perf_counter()
-    M, skipped = oracle.sketch(pos, wl.d, wl.w, wl.seed, wl.delta, wl.L, threads=threads)
+    uniq = np.unique(np.concatenate(uniq_parts))
+    del uniq_parts
     t2 = time.perf_counter()
-    ko, eo, st = oracle.topk_sketch(M, oracle.hash_tables(wl.seed, wl.d), pos, wl.delta, wl.L, oracle.INT32_MIN, wl.k)
+    log(f"  oracle: {uniq.size} distinct cells ({t2 - t1:.1f} s)")
+    wk, we = [], []
+    for b in range(0, uniq.size, key_block):
+        kk, ee = oracle.topk_keys(M, T, uniq[b:b + key_block], oracle.INT32_MIN, wl.k)
+        wk.append(kk)
+        we.append(ee)
+        log(f"  oracle: estimates and top-k of distinct cells {min(b + key_block, uniq.size)}/{uniq.size}")
+    kk, ee = np.concatenate(wk), np.concatenate(we)
+    order = np.lexsort((kk, -ee.astype(np.int64)))[:wl.k]
+    ko, eo = kk[order], ee[order]
     t3 = time.perf_counter()
-    n = pos.shape[0]
-    return {"oracle_full": {"particles": n, "threads_add": threads, "host": host_info(),
-                            "copy_to_host_s": t1 - t0, "keys_add_s": t2 - t1, "estimates_topk_s": t3 - t2,
-                            "add_particles_per_s": n / (t2 - t1), "whole_particles_per_s": n / (t3 - t1),
-                            "skipped": int(skipped), "kth_estimate": int(eo[-1]) if len(eo) else None}}
+    out = {"particles": n, "threads_add": threads, "host": host_info(), "chunk": chunk,
+           "keys_add_s": t_add, "distinct_keys_s": t_keys + (t2 - t1), "estimates_topk_s": t3 - t2,
+           "whole_s": t3 - t0, "add_particles_per_s": n / t_add, "whole_particles_per_s": n / (t3 - t0),
+           "distinct_cells": int(uniq.size), "skipped": skipped, "kth_estimate": int(eo[-1]) if len(eo) else None}
+    if s is not None:
+        s.reset()
+        s.update(pos_dev, wl.delta, wl.L)
+        s.collect(pos_dev, wl.delta, wl.L, theta)
+        gk, ge, _ = s.topk(wl.k)
+        gk = gk.cpu().numpy().view(np.uint64)
+        ge = ge.cpu().numpy()
+        out["gpu_counters_equal"] = bool(np.array_equal(s.counters().cpu().numpy(), M))
+        # the GPU's candidate pass keeps every cell whose estimate is >= theta: its top-k is
+        # the oracle's whenever the oracle's k-th estimate is >= theta
+        out["gpu_theta"] = theta
+        out["gpu_topk_equal"] = bool(np.array_equal(gk, ko) and np.array_equal(ge, eo))
+    return {"oracle_full": out}
 
 
 def update_protocols(pos, wl, csk, torch, reps=10):
@@ -1032,17 +1088,17 @@ def main():
         keys, est, rc = s.topk(wl.k)
         return rc, keys, est
 
-    if args.oracle_full:
-        log(f"oracle on all {n} particles, {host_threads()} threads for Add ...")
-        print(json.dumps(oracle_full(pos, wl, host_threads())), flush=True)
-        return
-
     # warm-up: first update allocates scratch; then find theta
     s.update(pos, wl.delta, wl.L)
     torch.cuda.synchronize()
     t_theta = time.perf_counter()
     theta, kth = calibrate_theta(s, pos, wl, csk)
     theta_ms = (time.perf_counter() - t_theta) * 1e3
+
+    if args.oracle_full:
+        log(f"oracle on all {n} particles, {host_threads()} threads for Add ...")
+        print(json.dumps(oracle_full(pos, wl, host_threads(), s=s, theta=theta)), flush=True)
+        return
     log(f"theta = {theta} (k-th estimate {kth}; search {theta_ms:.1f} ms)")
     for _ in range(args.warmup):
         step(theta)

@@ -1884,8 +1884,13 @@ csk_status csk_sketch_update_routed(csk_sketch* s, const float* pos, uint64_t n,
     BinPlan plan;
     bool binned = s->upd_mode != CSK_UPDATE_DIRECT && s->d == 5 &&
                   plan_bin_wg(m, s->d, s->w, bin_wg_cap(s->d, s->upd_max_wg), plan) && plan.fast;
-    if (binned) {
-      plan.lds_bytes += kAdmLdsWords * sizeof(uint32_t);
+    if (binned) {   // two rows per LDS pass, or three when the handle's tiling asks and they
+                    // fit beside the exclusion's table (at 2^22 - 39 322 counters per row two
+                    // measured 5.31 ms per 2^28 particles against 5.68: three spill registers)
+      const uint32_t lds3 = bin3_lds_bytes(plan, s->d, 3, true);
+      const bool three = s->upd_rp == 3 && lds3 <= kMaxLds;
+      plan.rp = three ? 3u : 2u;
+      plan.lds_bytes = three ? lds3 : bin3_lds_bytes(plan, s->d, 2, true);
       binned = plan.lds_bytes <= kMaxLds;
     }
     if (!binned) {

@@ -108,9 +108,13 @@ struct RouteExclude {
   uint32_t* child;            // na_max * f3 counters (device)
   uint32_t* err;              // bit 2: *na was above na_max (device)
 };
-// LDS of the admitted-key hash: 2 kMaxAdmitted 64-bit keys, then as many 16-bit positions.
+// The routing split's LDS hash of the admitted keys: 1024 slots (load <= 1/2).
 constexpr uint32_t kAdmHashSlots = 1024;
-constexpr uint32_t kAdmLdsWords = kAdmHashSlots * 2 + kAdmHashSlots / 2;
+// The exclusion's LDS table inside the update kernels: 2048 64-bit key slots (load <= 1/4),
+// their 16-bit positions, and a 2^16-bit prefilter that most particles stop at.
+constexpr uint32_t kExSlots = 2048;
+constexpr uint32_t kExBitWords = 2048;
+constexpr uint32_t kExLdsWords = kExSlots * 2 + kExSlots / 2 + kExBitWords;
 
 // Everything the bin kernel needs for one sketch and one stream.
 struct BinArgs {
@@ -170,11 +174,14 @@ hipError_t launch_accumulate(const uint16_t* tok, const uint32_t* cnt, const Bin
 hipError_t launch_update_direct(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, int32_t* M,
                                 uint32_t* err, hipStream_t s);
 // The update with the learned router's exclusion: the general bin kernel (d = 5, a fast
-// general plan whose lds_bytes include kAdmLdsWords words) or the direct update (any d);
-// both need float positions on an ungrouped mesh.
+// general plan with plan.rp 2 or 3 rows per pass and lds_bytes = bin3_lds_bytes(.., true))
+// or the direct update (any d); both need float positions on an ungrouped mesh.
 hipError_t launch_bin_routed(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
                              uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, const RouteExclude& ex,
                              hipStream_t s);
+// LDS bytes of the general bin kernel for a plan with rp rows per pass (with the exclusion's
+// hash when ex).
+uint32_t bin3_lds_bytes(const BinPlan& p, uint32_t d, uint32_t rp, bool ex);
 hipError_t launch_update_direct_routed(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, int32_t* M,
                                        uint32_t* err, const RouteExclude& ex, hipStream_t s);
 hipError_t launch_keys(const float* pos, uint64_t n, const Mesh& mesh, uint64_t* keys, hipStream_t s);

@@ -174,14 +174,60 @@ __device__ __forceinline__ void adm_hash_fill(const uint64_t* __restrict__ admit
   __syncthreads();
 }
 
+// ---- the exclusion's table (update kernels): keys at kExSlots slots, their positions, and
+// a 2^16-bit prefilter (one bit per admitted key, under a second hash).  A particle whose
+// bit is clear -- nearly every one outside the admitted cells -- stops after one LDS read.
+struct ExLds {
+  uint64_t* key;   // kExSlots
+  uint16_t* idx;   // kExSlots
+  uint32_t* bits;  // kExBitWords
+};
+
+// The table at the start of an LDS array of at least kExLdsWords words (8-byte aligned).
+__device__ __forceinline__ ExLds ex_lds(uint32_t* base) {
+  ExLds t;
+  t.key = (uint64_t*)base;
+  t.idx = (uint16_t*)(base + 2 * kExSlots);
+  t.bits = base + 2 * kExSlots + kExSlots / 2;
+  return t;
+}
+
+__device__ __forceinline__ uint32_t ex_fold(uint64_t key) { return (uint32_t)key ^ (uint32_t)(key >> 32); }
+__device__ __forceinline__ uint32_t ex_slot(uint32_t x) { return (x * 0x9E3779B9u) >> 21; }   // 11 bits
+__device__ __forceinline__ uint32_t ex_bit(uint32_t x) { return (x * 0x85EBCA77u) >> 16; }    // 16 bits
+
+// Fill the table with admitted[0 .. na) (na <= kExSlots / 4, distinct keys); every thread
+// of the block calls it; ends with a barrier.
+__device__ __forceinline__ void ex_fill(const uint64_t* __restrict__ admitted, uint32_t na, const ExLds& t) {
+  for (uint32_t i = threadIdx.x; i < kExSlots; i += blockDim.x) t.key[i] = kAdmEmpty;
+  for (uint32_t i = threadIdx.x; i < kExBitWords; i += blockDim.x) t.bits[i] = 0u;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < na; i += blockDim.x) {
+    const uint64_t key = admitted[i];
+    const uint32_t x = ex_fold(key), b = ex_bit(x);
+    atomicOr(&t.bits[b >> 5], 1u << (b & 31u));
+    uint32_t sl = ex_slot(x);
+    for (uint32_t probe = 0; probe < kExSlots; ++probe) {
+      if (atomicCAS((unsigned long long*)&t.key[sl], kAdmEmpty, (unsigned long long)key) == kAdmEmpty) {
+        t.idx[sl] = (uint16_t)i;
+        break;
+      }
+      sl = (sl + 1) & (kExSlots - 1);
+    }
+  }
+  __syncthreads();
+}
+
 // Position of coarse key ck in the admitted list, or -1.
-__device__ __forceinline__ int32_t adm_find(uint64_t ck, const uint64_t* hkey, const uint16_t* hidx) {
-  uint32_t sl = adm_hash(ck);
-  for (uint32_t probe = 0; probe < kAdmHashSlots; ++probe) {
-    const uint64_t k = hkey[sl];
-    if (k == ck) return (int32_t)hidx[sl];
+__device__ __forceinline__ int32_t ex_find(uint64_t ck, const ExLds& t) {
+  const uint32_t x = ex_fold(ck), b = ex_bit(x);
+  if (((t.bits[b >> 5] >> (b & 31u)) & 1u) == 0u) return -1;
+  uint32_t sl = ex_slot(x);
+  for (uint32_t probe = 0; probe < kExSlots; ++probe) {
+    const uint64_t k = t.key[sl];
+    if (k == ck) return (int32_t)t.idx[sl];
     if (k == kAdmEmpty) return -1;
-    sl = (sl + 1) & (kAdmHashSlots - 1);
+    sl = (sl + 1) & (kExSlots - 1);
   }
   return -1;
 }

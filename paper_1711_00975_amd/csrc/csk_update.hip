@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(BinArgs a) {
 // the stream or the domain go to a dummy bin that is never written.  A run that would
 // overflow its region goes to the counters through atomics instead (same sum).
 // Token scratch is workgroup-major: region (g, s) starts at (g * P + s) * cap.
-// LDS layout (words): [EX: admitted hash, kAdmLdsWords] | Ti [1536 * DP] | dst [RP*Pr + 1] |
+// LDS layout (words): [EX: the exclusion's table, kExLdsWords] | Ti [1536 * DP] | dst [RP*Pr + 1] |
 // cursor [P] | hist [RP*Pr + 1] | base [RP*Pr + 1] | stage [RP * tile] | wsum [NW].
 // EX (the learned router's rest sketch): a particle in an admitted coarse cell is counted in
 // the exclusion's child counters and goes to the dummy bin instead of the sketch.
@@ -130,9 +130,8 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
   const BinPlan& pl = a.plan;
   const uint32_t nbins = RP * pl.Pr + 1;                 // + the dummy bin
   const uint32_t dummy = nbins - 1;
-  uint64_t* hkey = (uint64_t*)lds2;                                 // EX only
-  uint16_t* hidx = (uint16_t*)(lds2 + 2 * kAdmHashSlots);           // EX only
-  uint32_t* ti = lds2 + (EX ? kAdmLdsWords : 0);
+  const ExLds ext = ex_lds(lds2);                                   // EX only
+  uint32_t* ti = lds2 + (EX ? kExLdsWords : 0);
   uint32_t* dst = ti + kTableWords * DP;
   uint32_t* cursor = dst + nbins;
   uint32_t* hist = cursor + pl.P;
@@ -145,7 +144,7 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
   for (uint32_t i = tid; i < pl.P; i += NT) cursor[i] = 0;
   for (uint32_t i = tid; i < nbins; i += NT) hist[i] = 0;
   stage_tables<DP>(ti, HM == kHashPacked ? a.tabp : a.tabi, (uint32_t)KB);   // fold point KB >= nch
-  if constexpr (EX) adm_hash_fill(a.ex.admitted, adm_count(a.ex), hkey, hidx);   // ends with a barrier
+  if constexpr (EX) ex_fill(a.ex.admitted, adm_count(a.ex), ext);   // ends with a barrier
 
   const uint32_t per = (nbins + NT - 1) / NT;           // scan: bins per thread
   const uint32_t blo = min(nbins, tid * per), bhi = min(nbins, blo + per);
@@ -208,7 +207,7 @@ __device__ __forceinline__ void bin3_body(const BinArgs* __restrict__ ap, const 
         valid |= (uint32_t)ok << j;
         if (ok) {
           uint32_t child;
-          const int32_t c = adm_find(adm_coarse(ix, iy, iz, a.ex, child), hkey, hidx);
+          const int32_t c = ex_find(adm_coarse(ix, iy, iz, a.ex, child), ext);
           if (c >= 0) {
             atomicAdd(&a.ex.child[(uint32_t)c * a.ex.f3 + child], 1u);
             ok = false;   // counted exactly; its tokens go to the dummy bin
@@ -520,21 +519,37 @@ hipError_t launch_bin(const float* pos, uint64_t n, const Mesh& mesh, const Tabl
 }
 
 // The general bin kernel with the router's exclusion (d = 5, float positions, ungrouped
-// mesh; the plan's LDS includes kAdmLdsWords).
+// mesh; the plan's LDS includes kExLdsWords).
+template <uint32_t MM, int RP>
+static void launch_bin3_ex_mr(int hm, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, const BinArgs& a) {
+  if (hm == kHashPacked)
+    hipLaunchKernelGGL((bin3_ex_kernel<5, MM, kBin2Threads, RP, kHashPacked>), grid, block, lds, s, a);
+  else if (hm == kHashMulHi)
+    hipLaunchKernelGGL((bin3_ex_kernel<5, MM, kBin2Threads, RP, kHashMulHi>), grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL((bin3_ex_kernel<5, MM, kBin2Threads, RP, kHashShift>), grid, block, lds, s, a);
+}
+
 template <uint32_t MM>
 static void launch_bin3_ex_m(int hm, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, const BinArgs& a) {
-  if (hm == kHashPacked)
-    hipLaunchKernelGGL((bin3_ex_kernel<5, MM, kBin2Threads, kBin2Rows, kHashPacked>), grid, block, lds, s, a);
-  else if (hm == kHashMulHi)
-    hipLaunchKernelGGL((bin3_ex_kernel<5, MM, kBin2Threads, kBin2Rows, kHashMulHi>), grid, block, lds, s, a);
-  else
-    hipLaunchKernelGGL((bin3_ex_kernel<5, MM, kBin2Threads, kBin2Rows, kHashShift>), grid, block, lds, s, a);
+  if (a.plan.rp == 3) launch_bin3_ex_mr<MM, 3>(hm, grid, block, lds, s, a);
+  else launch_bin3_ex_mr<MM, kBin2Rows>(hm, grid, block, lds, s, a);
+}
+
+uint32_t bin3_lds_bytes(const BinPlan& p, uint32_t d, uint32_t rp, bool ex) {
+  const uint64_t dp = (d <= 4) ? 4u : (d <= 6 ? 6u : 8u);
+  const uint64_t nb = (uint64_t)rp * p.Pr + 1;
+  const uint64_t words = (uint64_t)kTableWords * dp + nb + p.P + 2 * nb + (uint64_t)rp * p.tile + kBin2Threads / 64 +
+                         (ex ? kExLdsWords : 0u);
+  return words * 4 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)(words * 4);
 }
 
 hipError_t launch_bin_routed(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const BinPlan& plan,
                              uint16_t* tok, uint32_t* cnt, int32_t* M, uint32_t* err, const RouteExclude& ex,
                              hipStream_t s) {
-  if (t.d != 5 || !plan.fast || plan.sort || mesh.mode == kMeshPacked || mesh.group != 1u) return hipErrorInvalidValue;
+  if (t.d != 5 || !plan.fast || plan.sort || (plan.rp != 2 && plan.rp != 3) || mesh.mode == kMeshPacked ||
+      mesh.group != 1u)
+    return hipErrorInvalidValue;
   BinArgs a = make_bin_args(pos, n, mesh, t, plan, tok, cnt, M, err);
   a.ex = ex;
   const dim3 grid(plan.nwg), block(kBin2Threads);
@@ -659,9 +674,9 @@ __global__ __launch_bounds__(256) void update_direct_ex_kernel(const float* __re
                                                                const uint32_t* __restrict__ tab, uint32_t d,
                                                                uint32_t w, uint32_t cm, int32_t* __restrict__ M,
                                                                uint32_t* __restrict__ err, RouteExclude ex) {
-  __shared__ uint64_t hkey[kAdmHashSlots];
-  __shared__ uint16_t hidx[kAdmHashSlots];
-  adm_hash_fill(ex.admitted, adm_count(ex), hkey, hidx);
+  __shared__ __align__(16) uint32_t ex_words[kExLdsWords];
+  const ExLds ext = ex_lds(ex_words);
+  ex_fill(ex.admitted, adm_count(ex), ext);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     int32_t ix, iy, iz;
@@ -672,7 +687,7 @@ __global__ __launch_bounds__(256) void update_direct_ex_kernel(const float* __re
       continue;
     }
     uint32_t child;
-    const int32_t c = adm_find(adm_coarse(ix, iy, iz, ex, child), hkey, hidx);
+    const int32_t c = ex_find(adm_coarse(ix, iy, iz, ex, child), ext);
     if (c >= 0) {
       atomicAdd(&ex.child[(uint32_t)c * ex.f3 + child], 1u);
       continue;
