@@ -17,8 +17,10 @@ namespace csk {
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
-    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    // each 32 x 32 -> 64-bit product in one v_mad_u64_u32
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
     c[0] = n0;
     c[1] = lo1;
@@ -84,47 +86,79 @@ __global__ __launch_bounds__(256) void features_kernel(const uint32_t* __restric
 // Features and the float32 forward pass of the router's model for cells j < min(*m, cap):
 // x = log1p of the 27 neighbour counts (in the order of features_kernel), h1 = relu(W1 x +
 // b1), h2 = relu(W2 h1 + b2), z = w3 . h2 + b3; every sum is fmaf in index order, then the
-// bias, all in fp32.  The 6337 parameters sit in LDS (read as broadcasts); one cell per
-// thread, h1 in registers.
-__global__ __launch_bounds__(256) void route_score_kernel(const uint32_t* __restrict__ counts, uint32_t Gc,
-                                                          const uint64_t* __restrict__ cells,
-                                                          const uint64_t* __restrict__ m_dev, uint64_t cap,
-                                                          const float* __restrict__ P, float* __restrict__ z) {
-  __shared__ float w[kParams];
-  for (uint32_t i = threadIdx.x; i < kParams; i += blockDim.x) w[i] = P[i];
+// bias, all in fp32.  The parameters sit in LDS (W1 transposed, so that a feature's 64
+// weights are consecutive) and are read as broadcast operands; each thread scores one cell,
+// its features in LDS, h1 in registers.  The loops over a feature and over a layer-2 output
+// stay rolled, so that the weights are not hoisted into registers (the unrolled form took
+// 425 VGPRs: one wave per SIMD).
+constexpr int kScoreThreads = 256;
+__global__ __launch_bounds__(kScoreThreads) void route_score_kernel(const uint32_t* __restrict__ counts, uint32_t Gc,
+                                                                    const uint64_t* __restrict__ cells,
+                                                                    const uint64_t* __restrict__ m_dev, uint64_t cap,
+                                                                    const float* __restrict__ P,
+                                                                    float* __restrict__ z) {
+  __shared__ __align__(16) float w1t[27 * kHidden];              // w1t[q][o] = W1[o][q]
+  __shared__ __align__(16) float w[kParams - kOffB1];            // b1, W2, b2, w3, b3
+  __shared__ float xs[27 * kScoreThreads];                       // xs[q][thread]
+  for (uint32_t i = threadIdx.x; i < 27u * kHidden; i += blockDim.x) {
+    const uint32_t q = i / kHidden, o = i % kHidden;
+    w1t[i] = P[kOffW1 + o * kFeatPad + q];
+  }
+  for (uint32_t i = threadIdx.x; i < kParams - kOffB1; i += blockDim.x) w[i] = P[kOffB1 + i];
   __syncthreads();
+  const float* b1 = w;
+  const float* W2 = w + (kOffW2 - kOffB1);
+  const float* b2 = w + (kOffB2 - kOffB1);
+  const float* w3 = w + (kOffW3 - kOffB1);
+  const float b3 = w[kOffB3 - kOffB1];
   const uint64_t m = *m_dev < cap ? *m_dev : cap;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
     const uint64_t key = cells[j];
     const uint64_t G = Gc;
     const int64_t cx = (int64_t)(key / (G * G)), cy = (int64_t)((key / G) % G), cz = (int64_t)(key % G);
-    float x[27];
 #pragma unroll
     for (int q = 0; q < 27; ++q) {
       const int dx = q / 9 - 1, dy = (q / 3) % 3 - 1, dz = q % 3 - 1;
       const uint64_t nx = (uint64_t)((cx + dx + (int64_t)G) % (int64_t)G);
       const uint64_t ny = (uint64_t)((cy + dy + (int64_t)G) % (int64_t)G);
       const uint64_t nz = (uint64_t)((cz + dz + (int64_t)G) % (int64_t)G);
-      x[q] = log1pf((float)counts[(nx * G + ny) * G + nz]);
+      xs[q * kScoreThreads + threadIdx.x] = log1pf((float)counts[(nx * G + ny) * G + nz]);
     }
     float h1[kHidden];
 #pragma unroll
-    for (int o = 0; o < kHidden; ++o) {
-      float t = 0.0f;
+    for (int o = 0; o < kHidden; ++o) h1[o] = 0.0f;
+#pragma unroll 1
+    for (int q = 0; q < 27; ++q) {
+      const float xq = xs[q * kScoreThreads + threadIdx.x];
+      const float4* wq = (const float4*)(w1t + q * kHidden);
 #pragma unroll
-      for (int q = 0; q < 27; ++q) t = fmaf(w[kOffW1 + o * kFeatPad + q], x[q], t);
-      h1[o] = fmaxf(t + w[kOffB1 + o], 0.0f);
+      for (int o4 = 0; o4 < kHidden / 4; ++o4) {
+        const float4 c = wq[o4];
+        h1[4 * o4] = fmaf(c.x, xq, h1[4 * o4]);
+        h1[4 * o4 + 1] = fmaf(c.y, xq, h1[4 * o4 + 1]);
+        h1[4 * o4 + 2] = fmaf(c.z, xq, h1[4 * o4 + 2]);
+        h1[4 * o4 + 3] = fmaf(c.w, xq, h1[4 * o4 + 3]);
+      }
     }
+#pragma unroll
+    for (int o = 0; o < kHidden; ++o) h1[o] = fmaxf(h1[o] + b1[o], 0.0f);
     float out = 0.0f;
-#pragma unroll 4
+#pragma unroll 1
     for (int o = 0; o < kHidden; ++o) {
+      const float4* wo = (const float4*)(W2 + o * kHidden);
       float t = 0.0f;
 #pragma unroll
-      for (int q = 0; q < kHidden; ++q) t = fmaf(w[kOffW2 + o * kHidden + q], h1[q], t);
-      out = fmaf(w[kOffW3 + o], fmaxf(t + w[kOffB2 + o], 0.0f), out);
+      for (int q4 = 0; q4 < kHidden / 4; ++q4) {
+        const float4 c = wo[q4];
+        t = fmaf(c.x, h1[4 * q4], t);
+        t = fmaf(c.y, h1[4 * q4 + 1], t);
+        t = fmaf(c.z, h1[4 * q4 + 2], t);
+        t = fmaf(c.w, h1[4 * q4 + 3], t);
+      }
+      out = fmaf(w3[o], fmaxf(t + b2[o], 0.0f), out);
     }
-    z[j] = out + w[kOffB3];
+    z[j] = out + b3;
   }
 }
 
@@ -1134,8 +1168,8 @@ hipError_t launch_logit_order(const float* z, uint64_t m, int32_t* out, hipStrea
 hipError_t launch_route_score(const uint32_t* counts, uint32_t Gc, const uint64_t* cells, const uint64_t* m_dev,
                               uint64_t cap, const float* params, float* z, hipStream_t s) {
   if (cap == 0) return hipSuccess;
-  hipLaunchKernelGGL(route_score_kernel, dim3(grid_of(cap, 256, 2048)), dim3(256), 0, s, counts, Gc, cells, m_dev, cap,
-                     params, z);
+  hipLaunchKernelGGL(route_score_kernel, dim3(grid_of(cap, kScoreThreads, 2048)), dim3(kScoreThreads), 0, s, counts, Gc,
+                     cells, m_dev, cap, params, z);
   return hipGetLastError();
 }
 
