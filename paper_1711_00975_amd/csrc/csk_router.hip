@@ -33,27 +33,58 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 
 // Particle g = index0 + i is in the sample when word g of the Philox stream kSampleStream
 // under the seed (word g mod 4 of counter (g / 4 lo, g / 4 hi, kSampleStream, 0)) is below
-// `threshold`.  Each thread draws one counter and so decides four consecutive particles, and
-// loads the positions of the sampled ones only.  With a bitmap, a cell's bit is set when its
-// count leaves 0.
+// `threshold`.  Each thread draws kSampleU consecutive counters per round (4 kSampleU
+// particles), then loads the positions of the sampled ones, up to four at a time with every
+// load issued before any is used: about one particle in a hundred is sampled, so a round
+// waits on one memory round trip instead of one per counter.  With a bitmap, a cell's bit
+// is set when its count leaves 0.
+constexpr int kSampleU = 4;
 __global__ __launch_bounds__(256) void sample_counts_kernel(const float* __restrict__ pos, uint64_t n, uint64_t index0,
                                                             uint64_t seed, uint32_t threshold, Mesh coarse,
                                                             uint32_t* __restrict__ counts,
                                                             uint32_t* __restrict__ bitmap) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t c_lo = index0 >> 2, c_hi = (index0 + n + 3) >> 2;   // counters that cover the range
-  for (uint64_t c = c_lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < c_hi; c += stride) {
-    uint32_t r[4] = {(uint32_t)c, (uint32_t)(c >> 32), kSampleStream, 0u};
-    philox4x32_10(r, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * kSampleU;
+  for (uint64_t c0 = c_lo + ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kSampleU; c0 < c_hi; c0 += stride) {
+    uint32_t hits = 0;   // bit 4 u + q: particle 4 (c0 + u) + q is sampled
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint64_t g = 4 * c + (uint64_t)q;
-      if (g < index0 || g - index0 >= n || r[q] >= threshold) continue;
-      const uint64_t i = g - index0;
-      uint64_t key;
-      if (cell_key(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], coarse, key)) {
-        const uint32_t old = atomicAdd(&counts[key], 1u);
-        if (bitmap != nullptr && old == 0) atomicOr(&bitmap[key >> 5], 1u << (key & 31u));   // first touch
+    for (int u = 0; u < kSampleU; ++u) {
+      const uint64_t c = c0 + (uint64_t)u;
+      uint32_t r[4] = {(uint32_t)c, (uint32_t)(c >> 32), kSampleStream, 0u};
+      philox4x32_10(r, (uint32_t)seed, (uint32_t)(seed >> 32));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t g = 4 * c + (uint64_t)q;
+        const bool take = c < c_hi && g >= index0 && g - index0 < n && r[q] < threshold;
+        hits |= (uint32_t)take << (4 * u + q);
+      }
+    }
+    while (hits) {
+      uint64_t ii[4];
+      bool have[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        have[k] = hits != 0;
+        const uint32_t b = have[k] ? (uint32_t)__ffs(hits) - 1u : 0u;
+        hits &= hits - 1u;
+        ii[k] = have[k] ? 4 * c0 + b - index0 : 0;
+      }
+      float px[4], py[4], pz[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (have[k]) {
+          px[k] = pos[3 * ii[k]];
+          py[k] = pos[3 * ii[k] + 1];
+          pz[k] = pos[3 * ii[k] + 2];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        uint64_t key;
+        if (have[k] && cell_key(px[k], py[k], pz[k], coarse, key)) {
+          const uint32_t old = atomicAdd(&counts[key], 1u);
+          if (bitmap != nullptr && old == 0) atomicOr(&bitmap[key >> 5], 1u << (key & 31u));   // first touch
+        }
       }
     }
   }
@@ -969,7 +1000,8 @@ static uint32_t grid_of(uint64_t n, uint32_t threads, uint32_t max_blocks) {
 
 hipError_t launch_sample_counts(const float* pos, uint64_t n, uint64_t index0, uint64_t seed, uint32_t threshold,
                                 const Mesh& coarse, uint32_t* counts, uint32_t* bitmap, hipStream_t s) {
-  hipLaunchKernelGGL(sample_counts_kernel, dim3(grid_of(n / 4 + 2, 256, 8192)), dim3(256), 0, s, pos, n, index0, seed,
+  hipLaunchKernelGGL(sample_counts_kernel, dim3(grid_of(n / (4 * kSampleU) + 2, 256, 8192)), dim3(256), 0, s, pos, n,
+                     index0, seed,
                      threshold, coarse, counts, bitmap);
   return hipGetLastError();
 }
