@@ -27,8 +27,8 @@ BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
 # rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) scaled by a 1 GiB device copy
 # (profiles/update_kernels_plummer_2e30.md).  Reported only while the kernel sources hash
 # to what was profiled; any change to them makes `traffic` null until measured again.
-TRAFFIC = {"bytes": 45_250_130_321, "particles": 1 << 30,
-           "sources_sha256": "a8fe89323b803db13ecad33bc87e3af2d603b12166fe8b5cb171127511b36287"}
+TRAFFIC = {"bytes": 45_251_084_913, "particles": 1 << 30,
+           "sources_sha256": "e2206bda02fdc8f6d2b5712d53533e1ef519b433dc43c29ebc6da7644ace119f"}
 TRAFFIC_SOURCES = ["csk_update.hip", "csk_sortbin.hip", "csk_kernel_util.h", "csk_device.h", "csk_internal.h"]
 
 

@@ -119,19 +119,22 @@ std::vector<uint32_t> probe_columns(uint64_t seed, uint32_t d) {
   return C;
 }
 
-// Probe tables of the field-probe filter for w = 2^lw: entry (c, v) holds, for every row r
-// at bit 25 r, L_r applied to the (sign, bucket) bits of T[r][c][v] (a bit selection, so
-// the XOR over a key's bytes gives L_r of the key's own (sign, bucket)), with the salt
-// added to the entries of byte 0 only, so that every key's XOR holds it exactly once.
-std::vector<uint32_t> probe_tables(const std::vector<uint32_t>& T, uint32_t d, uint32_t lw, bool count_min,
+// Probe tables of the field-probe filter with P prefix bits (w <= 2^P < 2w): entry (c, v)
+// holds, for every row r at bit 25 r, L_r applied to x = (sign << P) | (top P bits of the
+// bucket input h << 1) of T[r][c][v] -- a bit selection, so the XOR over a key's bytes gives
+// L_r of the key's own x -- with the salt added to the entries of byte 0 only, so that
+// every key's XOR holds it exactly once.  For w = 2^P the prefix is the bucket itself; for
+// any other w the bucket, umulhi(h << 1, w), is fixed by one of at most fspan prefixes,
+// all of which the filter build inserts.
+std::vector<uint32_t> probe_tables(const std::vector<uint32_t>& T, uint32_t d, uint32_t P, bool count_min,
                                    const std::vector<uint32_t>& C) {
   std::vector<uint32_t> Q((size_t)kTableWords * 4, 0u);
   for (uint32_t e = 0; e < (uint32_t)kTableWords; ++e) {
     for (uint32_t r = 0; r < d; ++r) {
       const uint32_t H = T[(size_t)r * kTableWords + e];
-      const uint32_t b = (H << 1) >> (32u - lw);
+      const uint32_t b = (H << 1) >> (32u - P);
       const uint32_t sign = count_min ? 0u : (H >> 31);
-      const uint32_t x = (sign << lw) | b;
+      const uint32_t x = (sign << P) | b;
       const uint32_t* col = &C[(size_t)r * kFieldCols];
       uint32_t f = (e < 256u) ? col[kFieldBits] : 0u;
       for (uint32_t i = 0; i < (uint32_t)kFieldBits; ++i)
@@ -189,7 +192,8 @@ struct csk_sketch {
   uint32_t* tabi = nullptr;  // row-interleaved tables (d <= 8)
   uint32_t* tabp = nullptr;  // packed top-bit tables (d = 5..8)
   uint32_t* tabs = nullptr;  // the packed fields as sort words (d = 5..8, w = 2^lw <= 2^24)
-  uint32_t* tabq = nullptr;  // probe tables of the field-probe filter (d = 5, w = 2^lw <= 2^24)
+  uint32_t* tabq = nullptr;  // probe tables of the field-probe filter (d = 5, w <= 2^24)
+  uint32_t fp = 0, fspan = 0; // its prefix bits and prefixes per bucket
   uint32_t* fcols = nullptr; // the columns and salts of its row maps
   uint32_t dp = 0;
   uint32_t* filter = nullptr; // Bloom filter of hot items + [kFilterAllocWords] item count
@@ -226,6 +230,8 @@ struct csk_sketch {
     t.tabs = tabs;
     t.tabq = tabq;
     t.fcols = fcols;
+    t.fp = tabq ? fp : 0u;
+    t.fspan = tabq ? fspan : 0u;
     t.lw = (w >= 2 && (w & (w - 1)) == 0) ? (uint32_t)__builtin_ctz(w) : 0u;
     t.dp = dp;
     t.d = d;
@@ -376,9 +382,13 @@ csk_status csk_sketch_init_group(csk_sketch** out, uint32_t d, uint32_t w, uint6
       Ts = sort_tables(T, d, lw, variant == CSK_VARIANT_COUNT_MIN);
   }
   std::vector<uint32_t> Fc, Tq;
-  if (d == 5 && !Tp.empty() && w >= 2 && (w & (w - 1)) == 0 && __builtin_ctz(w) <= 24) {
+  if (d == 5 && !Tp.empty() && w >= 2 && w <= (1u << 24)) {   // the field-probe filter: P + 1 <= 25 bits
+    uint32_t P = 1;
+    while ((1u << P) < w) ++P;
+    s->fp = P;
+    s->fspan = ((1u << P) == w) ? 1u : (uint32_t)(((1ull << P) + w - 1) / w) + 1u;
     Fc = probe_columns(seed, d);
-    Tq = probe_tables(T, d, (uint32_t)__builtin_ctz(w), variant == CSK_VARIANT_COUNT_MIN, Fc);
+    Tq = probe_tables(T, d, P, variant == CSK_VARIANT_COUNT_MIN, Fc);
   }
   if (e == hipSuccess) e = dmalloc(s, &s->M, (uint64_t)d * w);
   if (e == hipSuccess) e = dmalloc(s, &s->tab, T.size());

@@ -47,9 +47,10 @@ __global__ __launch_bounds__(256) void collect_kernel(const float* __restrict__ 
 // without touching the counters; the rest take the exact test.  Each thread loads
 // kCollectPPT particles before working on any of them, so that enough position loads
 // are in flight to cover HBM latency at one workgroup per CU.
-// FP: the field-probe filter (d = 5, packed hash).  Its probe tables take the place of the
-// hash tables in LDS and its filter is 2^15 words; the exact test of the particles that
-// pass reads the packed hash tables from device memory (all six key bytes).
+// FP: the field-probe filter (d = 5, w <= 2^24; packed or multiply-high buckets).  Its probe
+// tables take the place of the hash tables in LDS and its filter is 2^15 words; the exact
+// test of the particles that pass reads the packed or row-interleaved hash tables from
+// device memory (all six key bytes).
 // Workgroup g of nwg runs the chunks g, g + nwg, ... of the stream.  The sketch's
 // arguments are read in place through cp (argument segment or descriptor array).
 template <int D, uint32_t MODE, int HM, bool FP, int KB>
@@ -71,13 +72,15 @@ __device__ __forceinline__ void collect2_body(const CollectDesc* __restrict__ cp
   constexpr int DP = FP ? 4 : HashWords<D, HM>::value;
   constexpr int PPT = kCollectPPT;
   constexpr uint32_t FW = FP ? kFieldFilterWords : (uint32_t)kFilterWords;
-  static_assert(!FP || (D <= 5 && HM == kHashPacked), "field probes: d <= 5 rows of 25 bits, packed hash");
+  static_assert(!FP || (D <= 5 && (HM == kHashPacked || HM == kHashMulHi)),
+                "field probes: d <= 5 rows of 25 bits, packed or multiply-high buckets");
   extern __shared__ __align__(16) uint32_t lds3[];
   uint32_t* ti = lds3;
   uint64_t* cache = (uint64_t*)(ti + kTableWords * DP);   // kCollectCache keys
   uint32_t* filt = (uint32_t*)(cache + kCollectCache);
   const uint32_t nhot = use_filter ? *hot : 0xFFFFFFFFu;
-  const bool uf = use_filter && nhot <= (FP ? kFieldFilterMaxItems : kFilterMaxItems);
+  // a hot item takes up to fspan entries of the field-probe filter (1 for w = 2^P)
+  const bool uf = use_filter && (FP ? (uint64_t)nhot * t.fspan <= kFieldFilterMaxItems : nhot <= kFilterMaxItems);
   // the exact hot-item set replaces the counter reads when it holds every hot item
   const bool uh = use_filter && hot_table != nullptr && nhot <= kHotMaxItems;
   if (uf)
@@ -85,9 +88,9 @@ __device__ __forceinline__ void collect2_body(const CollectDesc* __restrict__ cp
   for (uint32_t i = threadIdx.x; i < (uint32_t)kCollectCache; i += blockDim.x) cache[i] = kEmptyKey;
   stage_tables<DP>(ti, FP ? t.tabq : (HM == kHashPacked ? t.tabp : t.tabi), (uint32_t)KB);
   // (bucket, sign) of every row for the exact test: from the staged tables, or (FP) from
-  // the packed tables in device memory over all six key bytes
+  // the packed or row-interleaved tables in device memory over all six key bytes
   auto exact_rows = [&](uint64_t key, uint32_t (&bk)[D], uint32_t (&ng)[D]) {
-    if constexpr (FP) rows_bucket_sign_kb<D, HM, kChars>(t.tabp, key, t.w, t.wshift, bk, ng);
+    if constexpr (FP) rows_bucket_sign_kb<D, HM, kChars>(HM == kHashPacked ? t.tabp : t.tabi, key, t.w, t.wshift, bk, ng);
     else rows_bucket_sign_kb<D, HM, KB>(ti, key, t.w, t.wshift, bk, ng);
   };
   constexpr uint32_t kNeedCS = D - ((D - 1) >> 1);
@@ -97,22 +100,23 @@ __device__ __forceinline__ void collect2_body(const CollectDesc* __restrict__ cp
   bool bad = false;
   for (uint64_t first = (uint64_t)g * chunk; first < n; first += (uint64_t)nwg * chunk) {
     const bool full = first + chunk <= n;
-    // all PPT position loads are issued before any is used (a clamped index keeps the
-    // loads unconditional; particles beyond the stream are masked below)
+    // all PPT position loads are issued before any is used; float records come through a
+    // buffer resource over the rest of the stream (loads past it return 0), packed words
+    // with a clamped index; particles beyond the stream are masked below
     float px[PPT], py[PPT], pz[PPT];
     uint64_t pw[PPT];
-    const uint64_t last = n - 1;
+    if constexpr (MODE == kMeshPacked) {
+      const uint64_t last = n - 1;
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-      uint64_t i = first + (uint64_t)j * NT + threadIdx.x;
-      i = i < last ? i : last;
-      if constexpr (MODE == kMeshPacked) {
+      for (int j = 0; j < PPT; ++j) {
+        uint64_t i = first + (uint64_t)j * NT + threadIdx.x;
+        i = i < last ? i : last;
         pw[j] = __builtin_nontemporal_load((const uint64_t*)pos + i);
-      } else {
-        px[j] = __builtin_nontemporal_load(pos + 3 * i);
-        py[j] = __builtin_nontemporal_load(pos + 3 * i + 1);
-        pz[j] = __builtin_nontemporal_load(pos + 3 * i + 2);
       }
+    } else {
+      const __amdgpu_buffer_rsrc_t span = byte_span(pos + 3 * first, (n - first) * 12);
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) load_xyz(span, 12u * threadIdx.x, 12u * (uint32_t)j * NT, px[j], py[j], pz[j]);
     }
     // keys and the filter verdict of all PPT particles, without branches
     uint64_t keys[PPT];
@@ -314,12 +318,31 @@ __device__ __forceinline__ void load_counters(const int32_t* __restrict__ Mr, ui
 
 // Pass 1: sets the Bloom filter bits of every hot item and counts the items into *hot
 // (per-workgroup count in LDS, one global add per workgroup).
-// fcols != NULL: the field-probe filter (item fields from the row maps' columns, w = 2^lw);
-// else the hashed probe of filter_probe().
+// fcols != NULL: the field-probe filter (item fields from the row maps' columns, P prefix
+// bits); else the hashed probe of filter_probe().
 // Block bx of nbx scans its share of every row.
+
+// The field-probe filter entries of item (row r, bucket b, sign sg): x = (sg << P) | p for
+// every P-bit prefix p of a bucket input h' = h << 1 with umulhi(h', w) = b, i.e.
+// h' in [ceil(b 2^32 / w), ceil((b + 1) 2^32 / w) - 1].  For w = 2^P that prefix is b.
+__device__ __forceinline__ void field_insert(const uint32_t* __restrict__ cols_r, uint32_t w, uint32_t P, uint32_t b,
+                                             uint32_t sg, uint32_t* __restrict__ filter) {
+  uint32_t p_lo = b, p_hi = b;
+  if ((1u << P) != w) {
+    const uint64_t lo = (((uint64_t)b << 32) + w - 1) / w;
+    const uint64_t hi = ((((uint64_t)b + 1) << 32) + w - 1) / w - 1;
+    p_lo = (uint32_t)(lo >> (32 - P));
+    p_hi = (uint32_t)(hi >> (32 - P));
+  }
+  for (uint32_t p = p_lo; p <= p_hi; ++p) {
+    const FilterProbe pr = field_probe(item_field(cols_r, (sg << P) | p));
+    atomicOr(&filter[pr.word], pr.mask);
+  }
+}
+
 __device__ __forceinline__ void filter_build_body(const int32_t* __restrict__ M, uint32_t d, uint32_t w, uint32_t cm,
                                                   uint32_t bnorm, int32_t theta, const uint32_t* __restrict__ fcols,
-                                                  uint32_t lw, uint32_t* __restrict__ filter,
+                                                  uint32_t P, uint32_t* __restrict__ filter,
                                                   uint32_t* __restrict__ hot, uint32_t bx, uint32_t nbx) {
   __shared__ uint32_t count;
   if (threadIdx.x == 0) count = 0;
@@ -339,14 +362,20 @@ __device__ __forceinline__ void filter_build_body(const int32_t* __restrict__ M,
           bool hp, hn;
           hot_pair(c[v][e], cm, theta, b + e < w, hp, hn);
           if (hp) {
-            const FilterProbe pr = fcols ? field_probe(item_field(fcols + r * kFieldCols, (uint32_t)(b + e)))
-                                         : filter_probe(r, (uint32_t)(b + e), 0u, bnorm);
-            atomicOr(&filter[pr.word], pr.mask);
+            if (fcols) {
+              field_insert(fcols + r * kFieldCols, w, P, (uint32_t)(b + e), 0u, filter);
+            } else {
+              const FilterProbe pr = filter_probe(r, (uint32_t)(b + e), 0u, bnorm);
+              atomicOr(&filter[pr.word], pr.mask);
+            }
           }
           if (hn) {
-            const FilterProbe pr = fcols ? field_probe(item_field(fcols + r * kFieldCols, (1u << lw) | (uint32_t)(b + e)))
-                                         : filter_probe(r, (uint32_t)(b + e), 1u, bnorm);
-            atomicOr(&filter[pr.word], pr.mask);
+            if (fcols) {
+              field_insert(fcols + r * kFieldCols, w, P, (uint32_t)(b + e), 1u, filter);
+            } else {
+              const FilterProbe pr = filter_probe(r, (uint32_t)(b + e), 1u, bnorm);
+              atomicOr(&filter[pr.word], pr.mask);
+            }
           }
           mine += (uint32_t)hp + (uint32_t)hn;
         }
@@ -360,9 +389,9 @@ __device__ __forceinline__ void filter_build_body(const int32_t* __restrict__ M,
 
 __global__ __launch_bounds__(256) void filter_build_kernel(const int32_t* __restrict__ M, uint32_t d, uint32_t w,
                                                            uint32_t cm, uint32_t bnorm, int32_t theta,
-                                                           const uint32_t* __restrict__ fcols, uint32_t lw,
+                                                           const uint32_t* __restrict__ fcols, uint32_t P,
                                                            uint32_t* __restrict__ filter, uint32_t* __restrict__ hot) {
-  filter_build_body(M, d, w, cm, bnorm, theta, fcols, lw, filter, hot, blockIdx.x, gridDim.x);
+  filter_build_body(M, d, w, cm, bnorm, theta, fcols, P, filter, hot, blockIdx.x, gridDim.x);
 }
 
 __device__ __forceinline__ void hot_insert(uint32_t* table, uint32_t item) {
@@ -428,7 +457,7 @@ __global__ __launch_bounds__(256) void filter_build_batch_kernel(const CollectDe
   const uint32_t i = blockIdx.y;
   if (!call.use_filter[i]) return;
   const CollectDesc& c = descs[i];
-  filter_build_body(c.M, c.t.d, c.t.w, c.t.cm, c.t.bnorm, call.theta[i], field ? c.t.fcols : nullptr, c.t.lw,
+  filter_build_body(c.M, c.t.d, c.t.w, c.t.cm, c.t.bnorm, call.theta[i], field ? c.t.fcols : nullptr, c.t.fp,
                     c.filter, c.hot, blockIdx.x, gridDim.x);
 }
 
@@ -455,7 +484,7 @@ hipError_t launch_filter_build(const Tables& t, const int32_t* M, int32_t theta,
   if (e != hipSuccess) return e;
   const dim3 grid(grid_for((t.w + 4 * kFilterVec - 1) / (4 * kFilterVec), 256, 8192));
   hipLaunchKernelGGL(filter_build_kernel, grid, dim3(256), 0, s, M, t.d, t.w, t.cm, t.bnorm, theta,
-                     field ? t.fcols : nullptr, t.lw, filter, hot);
+                     field ? t.fcols : nullptr, t.fp, filter, hot);
   if (hot_table != nullptr)
     hipLaunchKernelGGL(hot_build_kernel, grid, dim3(256), 0, s, M, t.d, t.w, t.cm, theta, hot, hot_table);
   return hipGetLastError();
@@ -507,6 +536,12 @@ static void launch_collect2_m(int hm, dim3 grid, dim3 block, size_t lds, hipStre
       launch_collect2_one<D, MM, kHashPacked, true>(grid, block, lds, s, c);
       return;
     }
+    if constexpr (MM != kMeshPacked) {
+      if (hm == kHashMulHi && c.field) {
+        launch_collect2_one<D, MM, kHashMulHi, true>(grid, block, lds, s, c);
+        return;
+      }
+    }
   }
   if constexpr (D >= 5) {
     if (hm == kHashPacked) {
@@ -547,7 +582,7 @@ size_t collect2_lds_bytes(const Tables& t, bool use_filter, bool field) {
 }
 
 bool collect_field_form(const Tables& t) {
-  return t.d == 5 && t.hash_mode() == kHashPacked && t.tabq != nullptr;
+  return t.d == 5 && t.tabq != nullptr && (t.hash_mode() == kHashPacked || t.hash_mode() == kHashMulHi);
 }
 
 hipError_t launch_collect(const float* pos, uint64_t n, const Mesh& mesh, const Tables& t, const int32_t* M,

@@ -30,6 +30,8 @@ struct Tables {
   const uint32_t* tabq; // probe tables of the field-probe filter (d <= 5, w = 2^lw <= 2^24), or NULL
   const uint32_t* fcols; // the columns and salts of its row maps (d x kFieldCols), or NULL
   uint32_t lw;          // log2(w) when w is a power of two, else 0
+  uint32_t fp;          // the field-probe filter's prefix bits P (w <= 2^P < 2w), 0 without tabq
+  uint32_t fspan;       // at most this many P-bit prefixes per bucket (1 when w = 2^P)
   uint32_t dp;          // 4 (d <= 4), 6 (d <= 6) or 8 (d <= 8); 0 when d > 8
   uint32_t d;
   uint32_t w;

@@ -253,6 +253,25 @@ __device__ __forceinline__ uint32_t adm_count(const RouteExclude& ex) {
   return na;
 }
 
+// A buffer resource over the bytes [base, base + bytes), bytes clamped to 2^32 - 16: a load at
+// an offset past them returns 0.  Its last word (0x00020000) selects the raw 32-bit data
+// format of gfx9 buffers.  With one resource per tile, a lane's byte offsets are the same
+// for every tile, so the loads need no per-particle address arithmetic and no clamping.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t byte_span(const void* base, uint64_t bytes) {
+  const uint32_t nrec = bytes > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nrec, 0x00020000);
+}
+
+// The 12-byte record (x, y, z) at byte offset voff + soff of the span (voff per lane, soff
+// the same for the whole wave), one nontemporal load.
+__device__ __forceinline__ void load_xyz(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float& x, float& y,
+                                         float& z) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, (int)soff, 2);
+  x = __uint_as_float(v[0]);
+  y = __uint_as_float(v[1]);
+  z = __uint_as_float(v[2]);
+}
+
 static inline uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t max_blocks) {
   uint64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
