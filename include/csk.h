@@ -118,11 +118,16 @@ csk_status csk_sketch_update_noalloc(csk_sketch *s, const float *pos, uint64_t n
  * for the binned path behaves as CSK_UPDATE_AUTO. */
 csk_status csk_set_update_plan(csk_sketch *s, int32_t mode, uint32_t max_wg);
 
-#define CSK_BIN_AUTO      0 /* the sort-word kernel where it applies, else the general one */
+#define CSK_BIN_AUTO      0 /* the sort-word kernel where it applies and is the faster, else
+                               the general one */
 #define CSK_BIN_GENERAL   1 /* row-interleaved hashing, bucket and sign taken apart per row */
-#define CSK_BIN_SORT_WORD 2 /* packed tables whose fields already are the LDS sort words:
-                               d = 5..8, w = 2^lw <= 2^24 with lw + 1 <= floor(128 / d),
-                               a mesh that is neither grouped nor packed (else: general) */
+#define CSK_BIN_SORT_WORD 2 /* tokens counting-sorted by their LDS sort words; d = 5..8,
+                               w <= 2^24, a mesh that is neither grouped nor packed (else:
+                               general).  The words come from packed tables when
+                               w = 2^lw with lw + 1 <= floor(128 / d), else from the
+                               row-interleaved tables (1024 threads, no prefetch).  For
+                               csk_sketch_update_routed it selects the sort-word kernel with
+                               the exclusion (row tables, two rows per pass). */
 
 /* The tiling of the binned update (an autotuner's axes); the counters come out the same
  * for every choice.  form: CSK_BIN_*.  threads: workgroup size of the sort-word kernel,
@@ -441,7 +446,9 @@ csk_status csk_route_admit_async(const uint64_t *cells, const float *logits, con
  * table bit 1.  Domain errors latch on s as for csk_sketch_update.  workspace: at least
  * csk_route_update_workspace(factor, table_slots) bytes.  The candidate pass of the rest
  * sketch may then run over the whole stream: an admitted key reaches the top-k with its
- * exact count whatever its estimate (csk_topk_with_table). */
+ * exact count whatever its estimate (csk_topk_with_table).  The bin kernel follows the
+ * handle's csk_set_update_tiling form (d = 5): the general kernel unless CSK_BIN_SORT_WORD
+ * asks for the sort-word one; the counters are the same. */
 csk_status csk_route_update_workspace(uint32_t factor, uint32_t table_slots, uint64_t *bytes);
 csk_status csk_sketch_update_routed(csk_sketch *s, const float *pos, uint64_t n, double delta, double L,
                                     uint32_t factor, const uint64_t *admitted, const uint32_t *na,

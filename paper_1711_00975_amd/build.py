@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcsk.so")
 PROBE_LIB = os.path.join(HERE, "libcsk_probe.so")   # measurement probes for the benchmark
 OBJ_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["csk_api.hip", "csk_update.hip", "csk_sortbin.hip", "csk_collect.hip", "csk_kernels.hip", "csk_router.hip"]
+SOURCES = ["csk_api.hip", "csk_update.hip", "csk_sortbin.hip", "csk_sortbin_rows.hip", "csk_collect.hip", "csk_kernels.hip", "csk_router.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 GPU_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

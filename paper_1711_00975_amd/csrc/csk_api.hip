@@ -542,7 +542,7 @@ csk_status update_impl(csk_sketch* s, const void* src, bool packed, uint64_t n, 
     latch_mesh(s, delta, L, mesh);
     if (n == 0) return CSK_OK;
     if (packed) mesh.mode = kMeshPacked;
-    if (binned) (void)plan_sortbin(plan, s->d, mesh, t.tabs != nullptr, s->upd_form, s->upd_nt, s->upd_rp, s->upd_pf);
+    if (binned) (void)plan_sortbin(plan, s->d, mesh, t, s->upd_form, s->upd_nt, s->upd_rp, s->upd_pf, true);
     if (!binned) {
       CSK_HIP(launch_update_direct((const float*)src, n, mesh, t, s->M, s->err(), st), "update_noalloc (direct)");
       return CSK_OK;
@@ -566,7 +566,7 @@ csk_status update_impl(csk_sketch* s, const void* src, bool packed, uint64_t n, 
       CSK_HIP(launch_update_direct(p, m, mesh, t, s->M, s->err(), st), "update (direct)");
       continue;
     }
-    (void)plan_sortbin(plan, s->d, mesh, t.tabs != nullptr, s->upd_form, s->upd_nt, s->upd_rp, s->upd_pf);
+    (void)plan_sortbin(plan, s->d, mesh, t, s->upd_form, s->upd_nt, s->upd_rp, s->upd_pf, true);
     CSK_HIP(ensure_update_scratch(s, plan, st), "update: token scratch");
     CSK_HIP(launch_bin(p, m, mesh, t, plan, s->tok, s->cnt, s->M, s->err(), st), "update (bin)");
     CSK_HIP(launch_accumulate(s->tok, s->cnt, plan, s->w, s->M, st), "update (accumulate)");
@@ -965,8 +965,8 @@ csk_status batch_create_impl(csk_batch** out, csk_sketch* const* sketches, const
   bool sort_all = true;
   for (uint32_t i = 0; i < count && sort_all; ++i) {
     const csk_sketch* s = sketches[i];
-    sort_all = plan_sortbin(plans[i], d, mesh0, s->tables().tabs != nullptr, s0->upd_form, s0->upd_nt, s0->upd_rp,
-                            s0->upd_pf) &&
+    sort_all = plan_sortbin(plans[i], d, mesh0, s->tables(), s0->upd_form, s0->upd_nt, s0->upd_rp, s0->upd_pf,
+                            false) &&
                plans[i].nt == plans[0].nt && plans[i].rp == plans[0].rp && plans[i].pf == plans[0].pf;
   }
   BinPlan form{};
@@ -1894,21 +1894,41 @@ csk_status csk_sketch_update_routed(csk_sketch* s, const float* pos, uint64_t n,
     BinPlan plan;
     bool binned = s->upd_mode != CSK_UPDATE_DIRECT && s->d == 5 &&
                   plan_bin_wg(m, s->d, s->w, bin_wg_cap(s->d, s->upd_max_wg), plan) && plan.fast;
-    if (binned) {   // two rows per LDS pass, or three when the handle's tiling asks and they
-                    // fit beside the exclusion's table (at 2^22 - 39 322 counters per row two
-                    // measured 5.31 ms per 2^28 particles against 5.68: three spill registers)
-      const uint32_t lds3 = bin3_lds_bytes(plan, s->d, 3, true);
-      const bool three = s->upd_rp == 3 && lds3 <= kMaxLds;
-      plan.rp = three ? 3u : 2u;
-      plan.lds_bytes = three ? lds3 : bin3_lds_bytes(plan, s->d, 2, true);
-      binned = plan.lds_bytes <= kMaxLds;
+    bool sorted = false;
+    if (binned) {
+      // the sort-word kernel on the row tables (two rows per pass beside the exclusion's
+      // table) when the handle's tiling asks for it: at 2^22 - 39 322 counters per row it
+      // took 3.96 ms per 2^28 particles against 3.81 for the general kernel, which is the
+      // default: two rows per LDS pass, or three when the handle's tiling asks and they fit
+      // (two measured 5.31 ms against 5.68 there: three spill registers)
+      const uint32_t lds_s = sortbin_lds_bytes(5, 2, plan.Pr, plan.P, true, mesh.nch, true);
+      sorted = s->upd_form == kFormSortWord && plan.Pr <= 512 && t.tabi != nullptr && lds_s <= kMaxLds;
+      if (sorted) {
+        plan.sort = kSortRows;
+        plan.rp = 2u;
+        plan.nt = kBin2Threads;
+        plan.pf = 0u;
+        plan.lds_bytes = lds_s;
+      } else {
+        const uint32_t lds3 = bin3_lds_bytes(plan, s->d, 3, true);
+        const bool three = s->upd_rp == 3 && lds3 <= kMaxLds;
+        plan.rp = three ? 3u : 2u;
+        plan.lds_bytes = three ? lds3 : bin3_lds_bytes(plan, s->d, 2, true);
+        binned = plan.lds_bytes <= kMaxLds;
+      }
     }
     if (!binned) {
       CSK_HIP(launch_update_direct_routed(p, m, mesh, t, s->M, s->err(), ex, st), "update_routed (direct)");
       continue;
     }
     CSK_HIP(ensure_update_scratch(s, plan, st), "update_routed: token scratch");
-    CSK_HIP(launch_bin_routed(p, m, mesh, t, plan, s->tok, s->cnt, s->M, s->err(), ex, st), "update_routed (bin)");
+    if (sorted) {
+      BinArgs a = make_bin_args(p, m, mesh, t, plan, s->tok, s->cnt, s->M, s->err());
+      a.ex = ex;
+      CSK_HIP(launch_sortbin_routed(a, mesh.mode, st), "update_routed (bin)");
+    } else {
+      CSK_HIP(launch_bin_routed(p, m, mesh, t, plan, s->tok, s->cnt, s->M, s->err(), ex, st), "update_routed (bin)");
+    }
     CSK_HIP(launch_accumulate(s->tok, s->cnt, plan, s->w, s->M, st), "update_routed (accumulate)");
   }
   CSK_HIP(launch_route_table(ex, (uint32_t)mesh.G, table_keys, table_counts, table_slots - 1, err, st),

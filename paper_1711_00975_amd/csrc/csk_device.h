@@ -269,11 +269,12 @@ __host__ __device__ __forceinline__ uint32_t key_chars(int32_t G) {
   return n;
 }
 
-// Copy the interleaved tables into LDS; entries of byte nch - 1 absorb the XOR of the
-// value-0 entries of bytes nch..5.  Ends with a barrier.
+// Copy the interleaved tables of key bytes 0..bytes-1 (bytes >= nch) into LDS; entries of
+// byte nch - 1 absorb the XOR of the value-0 entries of bytes nch..5.  Ends with a barrier.
 template <int DP>
-__device__ __forceinline__ void stage_tables(uint32_t* ti, const uint32_t* __restrict__ src, uint32_t nch) {
-  for (uint32_t i = threadIdx.x; i < (uint32_t)(kTableWords * DP); i += blockDim.x) {
+__device__ __forceinline__ void stage_tables(uint32_t* ti, const uint32_t* __restrict__ src, uint32_t nch,
+                                             uint32_t bytes = kChars) {
+  for (uint32_t i = threadIdx.x; i < (uint32_t)(256 * DP) * bytes; i += blockDim.x) {
     uint32_t v = src[i];
     const uint32_t c = i / (256 * DP);
     if (c == nch - 1) {

@@ -57,7 +57,7 @@ struct BinPlan {
   uint32_t tab_rows_lds;
   uint32_t lds_bytes;
   uint32_t fast;        // 1: row-interleaved kernel (d <= 8)
-  uint32_t sort;        // 1: the sort-word bin kernel (csk_sortbin.hip)
+  uint32_t sort;        // the sort-word bin kernel: kSortPacked or kSortRows, 0: not
   uint32_t rp;          // its rows per LDS pass (2 or 3)
   uint32_t pf;          // 1: it loads the next tile's positions while sorting the current one
   uint32_t nt;          // its threads per workgroup (512 or 1024)
@@ -87,12 +87,18 @@ uint32_t bin_wg_cap(uint32_t d, uint32_t requested);
 constexpr uint32_t kFormAuto = 0;
 constexpr uint32_t kFormGeneral = 1;
 constexpr uint32_t kFormSortWord = 2;
+// Sort-word bin kernel forms: on the packed sort-word table (w = 2^lw within the packed
+// fields), or on the row-interleaved tables with multiply-high buckets (any w <= 2^24).
+constexpr uint32_t kSortPacked = 1;
+constexpr uint32_t kSortRows = 2;
 // Turn a fast bin plan into a sort-word plan when the form asks for it (or leaves it
 // to us) and the sketch, the mesh (ungrouped, not packed) and LDS allow: want_nt 0 (auto),
 // 512 or 1024 threads; want_rp 0 (auto), 2 or 3 rows per pass; want_pf 0 (auto), 1 (off)
-// or 2 (on; 512 threads only).  Returns true if the plan now uses the sort-word kernel.
-bool plan_sortbin(BinPlan& p, uint32_t d, const Mesh& mesh, bool have_tabs, uint32_t form, uint32_t want_nt,
-                  uint32_t want_rp, uint32_t want_pf);
+// or 2 (on; 512 threads only).  The packed table is used when the sketch has it; else,
+// with rows_ok, the row tables (1024 threads, no prefetch).  Returns true if the plan now
+// uses the sort-word kernel.
+bool plan_sortbin(BinPlan& p, uint32_t d, const Mesh& mesh, const Tables& t, uint32_t form, uint32_t want_nt,
+                  uint32_t want_rp, uint32_t want_pf, bool rows_ok);
 
 // The learned router's exclusion (csk_sketch_update_routed): a particle whose coarse parent
 // (its fine index divided by `factor` on each axis, on the mesh of G / factor cells a side)
@@ -152,8 +158,14 @@ struct BatchCall {
   uint64_t n[kMaxBatch];
 };
 
-uint32_t sortbin_lds_bytes(uint32_t d, uint32_t rp, uint32_t P);
+// LDS of the sort-word bin kernel: rows false for the packed sort-word table, true for the
+// row-interleaved tables over the mesh's nch key bytes; ex: with the router's exclusion table.
+uint32_t sortbin_lds_bytes(uint32_t d, uint32_t rp, uint32_t Pr, uint32_t P, bool rows, uint32_t nch, bool ex);
 hipError_t launch_sortbin(const BinArgs& a, uint32_t mesh_mode, hipStream_t s);
+// The row-table form (plan.sort == kSortRows), and its d = 5 form with the exclusion in a.ex
+// (two rows per pass; plan.lds_bytes from sortbin_lds_bytes(5, 2, ..., true, nch, true)).
+hipError_t launch_sortbin_rows(const BinArgs& a, uint32_t mesh_mode, hipStream_t s);
+hipError_t launch_sortbin_routed(const BinArgs& a, uint32_t mesh_mode, hipStream_t s);
 hipError_t launch_sortbin_batch(const BinArgs* descs, const uint16_t* wg_sketch, const uint32_t* wg_first,
                                 uint32_t nwg_total, uint32_t lds_bytes, uint32_t d, uint32_t mode, const BinPlan& form,
                                 uint32_t kb, const BatchCall& call, hipStream_t s);

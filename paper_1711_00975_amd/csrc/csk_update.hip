@@ -364,28 +364,35 @@ bool plan_bin_wg(uint64_t n, uint32_t d, uint32_t w, uint64_t max_wg, BinPlan& p
   return true;
 }
 
-bool plan_sortbin(BinPlan& p, uint32_t d, const Mesh& mesh, bool have_tabs, uint32_t form, uint32_t want_nt,
-                  uint32_t want_rp, uint32_t want_pf) {
+bool plan_sortbin(BinPlan& p, uint32_t d, const Mesh& mesh, const Tables& t, uint32_t form, uint32_t want_nt,
+                  uint32_t want_rp, uint32_t want_pf, bool rows_ok) {
   p.sort = 0;
-  if (form == kFormGeneral || !have_tabs || !p.fast || d < 5 || d > 8 || p.Pr > 512 || mesh.mode == kMeshPacked ||
-      mesh.group != 1u)
+  const bool packed = t.tabs != nullptr;
+  const bool rows = !packed && rows_ok && t.tabi != nullptr;
+  if (form == kFormGeneral || (!packed && !rows) || !p.fast || d < 5 || d > 8 || p.Pr > 512 ||
+      mesh.mode == kMeshPacked || mesh.group != 1u)
     return false;
   if (want_nt != 0 && want_nt != 512 && want_nt != 1024) return false;
   if (want_rp != 0 && want_rp != 2 && want_rp != 3) return false;
   if (want_pf > 2 || (want_pf == 2 && want_nt == 1024)) return false;
   if (want_nt == 512 && d != 5) return false;   // the 512-thread forms are compiled for d = 5
   if (want_nt == 512 && want_rp == 2 && want_pf == 1) return false;   // not compiled
+  if (rows && (want_nt == 512 || want_pf == 2)) return false;         // 1024 threads only
   // automatic: the sort-word kernel from 32 slices per row (w >= 2^20) on.  Narrower rows
   // have few bins per pass, and its two LDS atomics per token (count, then scatter) then
   // contend on the same few words: at w = 2^16 it measured 59 us per 2^20 particles
   // against 46 us for the general kernel, at w = 2^22 3.24 against 3.64 ms per 2^28.
   if (form == kFormAuto && p.Pr < 32) return false;
+  // automatic, row tables: from d = 6 on.  Per 2^28 particles of the 2^30-particle stream's
+  // recipe, d = 5 at w = 2^22 - 39 322 took 3.75 ms against 3.71 for the general kernel,
+  // d = 6 at w = 2^21 4.34 against 4.42, d = 8 at w = 2^22 - 3 5.53 against 9.62.
+  if (form == kFormAuto && rows && d == 5) return false;
   uint32_t rp = want_rp ? want_rp : 3u;
-  if (want_rp == 0 && sortbin_lds_bytes(d, rp, p.P) > kMaxLds) rp = 2u;
-  const uint32_t lds = sortbin_lds_bytes(d, rp, p.P);
+  if (want_rp == 0 && sortbin_lds_bytes(d, rp, p.Pr, p.P, rows, mesh.nch, false) > kMaxLds) rp = 2u;
+  const uint32_t lds = sortbin_lds_bytes(d, rp, p.Pr, p.P, rows, mesh.nch, false);
   if (lds > kMaxLds) return false;
   const uint32_t nt = want_nt ? want_nt : (want_pf == 2 ? 512u : 1024u);
-  p.sort = 1;
+  p.sort = rows ? kSortRows : kSortPacked;
   p.nt = nt;
   p.rp = rp;
   p.pf = (nt == 512 && want_pf != 1) ? 1u : 0u;

@@ -124,11 +124,21 @@ def test_route_admit_async_matches_reference(A, m):
     assert np.array_equal(admitted.cpu().numpy()[:len(want)], want)
 
 
-# (d, w, L, delta, factor, na, n, plan): the bin kernel with each hash form (w not a power of
-# two; a power of two with packed fields) and each mesh form (power-of-two ratio G / L,
-# general, exact ratio 3), another factor, the direct update for d != 5 and when asked for,
-# no admitted cell, the most admitted cells, ragged and empty streams
+# (d, w, L, delta, factor, na, n, plan): the general bin kernel (the default, or asked for)
+# and the sort-word kernel on the row tables (asked for), each
+# with each hash form (w not a power of two; a power of two) and each mesh form
+# (power-of-two ratio G / L, general, exact ratio 3), another factor, the direct update for
+# d != 5 and when asked for, no admitted cell, the most admitted cells, ragged and empty
+# streams
 ROUTED = [
+    (5, (1 << 22) - 39322, 100.0, 0.25, 4, 512, 2_000_003, "sortword"),
+    (5, 1 << 22, 100.0, 0.25, 4, 100, 1_000_000, "sortword"),
+    (5, (1 << 22) - 39322, 100.0, 0.25, 4, 512, 2_000_003, "general"),
+    (5, 9973 * 7, 50.0, 0.25, 4, 40, 300_001, "sortword"),
+    (5, 1 << 16, 123.456, 0.123456, 4, 40, 200_000, "sortword"),
+    (5, 1 << 16, 100.0, 1.0 / 3.0, 3, 40, 200_000, "sortword"),
+    (5, 1 << 16, 50.0, 0.25, 4, 0, 100_000, "sortword"),
+    (5, 1 << 16, 50.0, 0.25, 4, 5, 0, "sortword"),
     (5, 9973 * 7, 50.0, 0.25, 4, 40, 300_001, "auto"),
     (5, 1 << 16, 50.0, 0.25, 4, 40, 250_000, "auto"),
     (5, 1 << 15, 64.0, 0.25, 2, 100, 200_000, "auto"),
@@ -154,6 +164,10 @@ def test_update_routed_matches_route_then_add(d, w, L, delta, factor, na, n, pla
     s = csk.Sketch(d, w, seed)
     if plan == "direct":
         s.set_update_plan(csk.CSK_UPDATE_DIRECT, 0)
+    elif plan == "general":
+        s.set_update_tiling(csk.CSK_BIN_GENERAL)
+    elif plan == "sortword":
+        s.set_update_tiling(csk.CSK_BIN_SORT_WORD)
     slots = 1 << 16
     tk, tc = csk.new_table(slots)
     err = torch.zeros(1, dtype=torch.int32, device="cuda")

@@ -1,8 +1,9 @@
 """Every tiling of the binned update gives the oracle's counters (Sec. 2.2 Add; Alg. 4
-Update): the bin kernel forms (general row-interleaved, sort-word), workgroup sizes, rows
-per LDS pass and prefetch differ only in speed, so each is checked bit for bit on streams
-with several tiles per workgroup and a ragged tail, on the region-overflow path, for the
-Count-Min variant, for every d the sort-word tables serve, and in a batch."""
+Update): the bin kernel forms (general row-interleaved, sort-word on the packed table or on
+the row tables), workgroup sizes, rows per LDS pass and prefetch differ only in speed, so
+each is checked bit for bit on streams with several tiles per workgroup and a ragged tail,
+on the region-overflow path, for the Count-Min variant, for every d the sort-word kernel
+serves, and in a batch."""
 import numpy as np
 import pytest
 
@@ -121,3 +122,40 @@ def test_forms_in_a_batch(form):
     finally:
         for s in sk:
             s.close()
+
+
+# The sort-word kernel on the row tables (multiply-high buckets): widths that are not powers
+# of two, and powers of two too wide for the packed fields (d = 6: 2^21 > 2^(21 - 1)).
+ROW_FORMS = [
+    (csk.CSK_BIN_GENERAL, 0, 0, 0),
+    (csk.CSK_BIN_SORT_WORD, 1024, 2, 1),
+    (csk.CSK_BIN_SORT_WORD, 1024, 3, 1),
+    (csk.CSK_BIN_AUTO, 0, 0, 0),
+]
+
+
+@pytest.mark.parametrize("form", ROW_FORMS)
+@pytest.mark.parametrize("d,w,L,delta,variant", [(5, 3 * (1 << 20) + 5, 1000.0, 0.25, 0),
+                                                 (5, (1 << 24) - 1, 1000.0, 0.25, 1),
+                                                 (6, 1 << 21, 123.456, 0.123456, 0),
+                                                 (7, 999_999, 100.0, 1.0 / 3.0, 1),
+                                                 (8, (1 << 24) - 3, 3000.0, 1.0, 0),
+                                                 (5, 9973 * 7, 50.0, 0.25, 0)])
+def test_row_table_forms(form, d, w, L, delta, variant):
+    print("row form", form, d, w, L, delta, variant, flush=True)
+    pos = _clustered(1_200_007, L, 61 + d, nclump=200, sigma=0.3)
+    M = _counters(pos, d, w, 13, delta, L, form, variant=variant, max_wg=8)
+    Mo, skipped = oracle.sketch(pos, d, w, 13, delta, L, variant=variant, threads=8)
+    assert skipped == 0
+    assert np.array_equal(M, Mo)
+
+
+@pytest.mark.parametrize("form", ROW_FORMS[1:3])
+def test_row_table_forms_one_cell_overflows_regions(form):
+    print("row form overflow", form, flush=True)
+    n, w = 300_000, (1 << 21) + 77
+    pos = np.full((n, 3), 12.34, dtype=np.float32)
+    M = _counters(pos, 5, w, 3, 0.1, 100.0, form)
+    Mo, _ = oracle.sketch(pos, 5, w, 3, 0.1, 100.0)
+    assert np.array_equal(M, Mo)
+    assert sorted(np.abs(M).max(axis=1).tolist()) == [n] * 5
