@@ -781,18 +781,45 @@ __device__ __forceinline__ uint32_t bits_taken(uint32_t bits, uint64_t w, const 
   return q;
 }
 
+// The bitmap listing reads kBitmapWPT consecutive words per thread (four 16-byte loads in
+// flight when the bitmap is 16-byte aligned; chunks are whole multiples of it): at 10^9
+// cells the bitmap is 125 MB and almost every word is zero, so the pass is a streaming read.
+constexpr uint32_t kBitmapWPT = 16;
+
+__device__ __forceinline__ void load_words(const uint32_t* __restrict__ bitmap, uint64_t w0, uint64_t hi,
+                                           bool vec, uint32_t (&wd)[kBitmapWPT]) {
+  if (vec && w0 + kBitmapWPT <= hi) {
+#pragma unroll
+    for (uint32_t k = 0; k < kBitmapWPT / 4; ++k) {
+      const uint4 v = ((const uint4*)(bitmap + w0))[k];
+      wd[4 * k] = v.x;
+      wd[4 * k + 1] = v.y;
+      wd[4 * k + 2] = v.z;
+      wd[4 * k + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (uint32_t k = 0; k < kBitmapWPT; ++k) wd[k] = (w0 + k < hi) ? bitmap[w0 + k] : 0u;
+  }
+}
+
 __global__ __launch_bounds__(256) void bitmap_list_count_kernel(const uint32_t* __restrict__ bitmap, uint64_t nwords,
                                                                 uint64_t ncells, uint64_t chunk,
                                                                 const uint32_t* __restrict__ counts,
                                                                 uint32_t min_count,
-                                                                uint64_t* __restrict__ block_count) {
+                                                                uint64_t* __restrict__ block_count, uint32_t vec) {
   __shared__ uint64_t part[256];
   const uint64_t lo = (uint64_t)blockIdx.x * chunk;
   const uint64_t hi = lo + chunk < nwords ? lo + chunk : nwords;
   uint64_t c = 0;
-  for (uint64_t w = lo + threadIdx.x; w < hi; w += blockDim.x) {
-    const uint32_t bits = valid_bits(bitmap[w], w, ncells);
-    if (bits) c += bits_taken(bits, w, counts, min_count);
+  for (uint64_t w0 = lo + (uint64_t)threadIdx.x * kBitmapWPT; w0 < hi; w0 += (uint64_t)blockDim.x * kBitmapWPT) {
+    uint32_t wd[kBitmapWPT];
+    load_words(bitmap, w0, hi, vec != 0u, wd);
+#pragma unroll
+    for (uint32_t k = 0; k < kBitmapWPT; ++k) {
+      const uint32_t bits = valid_bits(wd[k], w0 + k, ncells);
+      if (bits) c += bits_taken(bits, w0 + k, counts, min_count);
+    }
   }
   part[threadIdx.x] = c;
   __syncthreads();
@@ -808,16 +835,23 @@ __global__ __launch_bounds__(256) void bitmap_list_write_kernel(const uint32_t* 
                                                                 const uint32_t* __restrict__ counts,
                                                                 uint32_t min_count,
                                                                 const uint64_t* __restrict__ block_off,
-                                                                uint64_t* __restrict__ cells, uint64_t cap) {
+                                                                uint64_t* __restrict__ cells, uint64_t cap,
+                                                                uint32_t vec) {
   __shared__ uint32_t wsum[4];
   const uint64_t lo = (uint64_t)blockIdx.x * chunk;
   const uint64_t hi = lo + chunk < nwords ? lo + chunk : nwords;
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   uint64_t base = block_off[blockIdx.x];
-  for (uint64_t t0 = lo; t0 < hi; t0 += blockDim.x) {   // uniform over the block
-    const uint64_t w = t0 + threadIdx.x;
-    const uint32_t bits = w < hi ? valid_bits(bitmap[w], w, ncells) : 0u;
-    const uint32_t q = bits ? bits_taken(bits, w, counts, min_count) : 0u;
+  for (uint64_t t0 = lo; t0 < hi; t0 += (uint64_t)blockDim.x * kBitmapWPT) {   // uniform over the block
+    const uint64_t w0 = t0 + (uint64_t)threadIdx.x * kBitmapWPT;   // this thread's words, in order
+    uint32_t wd[kBitmapWPT];
+    load_words(bitmap, w0, hi, vec != 0u, wd);
+    uint32_t q = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kBitmapWPT; ++k) {
+      wd[k] = valid_bits(wd[k], w0 + k, ncells);
+      if (wd[k]) q += bits_taken(wd[k], w0 + k, counts, min_count);
+    }
     const uint32_t incl = wave_incl_scan(q);
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
@@ -827,14 +861,18 @@ __global__ __launch_bounds__(256) void bitmap_list_write_kernel(const uint32_t* 
       if (v < wave) off += wsum[v];
       tile += wsum[v];
     }
-    uint32_t rem = bits;
-    while (rem) {
-      const uint32_t b = (uint32_t)__ffs(rem) - 1u;
-      rem &= rem - 1u;
-      const uint64_t cell = w * 32 + b;
-      if (min_count <= 1 || counts[cell] >= min_count) {
-        if (off < cap) cells[off] = cell;
-        ++off;
+    if (q) {
+      for (uint32_t k = 0; k < kBitmapWPT; ++k) {
+        uint32_t rem = wd[k];
+        while (rem) {
+          const uint32_t b = (uint32_t)__ffs(rem) - 1u;
+          rem &= rem - 1u;
+          const uint64_t cell = (w0 + k) * 32 + b;
+          if (min_count <= 1 || counts[cell] >= min_count) {
+            if (off < cap) cells[off] = cell;
+            ++off;
+          }
+        }
       }
     }
     base += tile;
@@ -844,18 +882,33 @@ __global__ __launch_bounds__(256) void bitmap_list_write_kernel(const uint32_t* 
 
 // Zero the counts of every touched cell and the bitmap itself.
 __global__ __launch_bounds__(256) void bitmap_clear_kernel(uint32_t* __restrict__ bitmap, uint64_t nwords,
-                                                           uint64_t ncells, uint32_t* __restrict__ counts) {
+                                                           uint64_t ncells, uint32_t* __restrict__ counts,
+                                                           uint32_t vec) {
+  // four words per thread: one 16-byte load (a 16-byte aligned bitmap), and a store only
+  // where a word is set
+  const uint64_t ng = (nwords + 3) / 4;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
-    const uint32_t raw = bitmap[w];
-    if (!raw) continue;
-    uint32_t bits = valid_bits(raw, w, ncells);
-    while (bits) {
-      const uint32_t b = (uint32_t)__ffs(bits) - 1u;
-      bits &= bits - 1u;
-      counts[w * 32 + b] = 0u;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += stride) {
+    uint32_t wd[4];
+    if (vec && 4 * i + 4 <= nwords) {
+      const uint4 v = ((const uint4*)bitmap)[i];
+      wd[0] = v.x, wd[1] = v.y, wd[2] = v.z, wd[3] = v.w;
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) wd[k] = (4 * i + k < nwords) ? bitmap[4 * i + k] : 0u;
     }
-    bitmap[w] = 0u;
+    if ((wd[0] | wd[1] | wd[2] | wd[3]) == 0u) continue;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+      const uint64_t w = 4 * i + k;
+      uint32_t bits = valid_bits(wd[k], w, ncells);
+      while (bits) {
+        const uint32_t b = (uint32_t)__ffs(bits) - 1u;
+        bits &= bits - 1u;
+        counts[w * 32 + b] = 0u;
+      }
+      if (wd[k]) bitmap[w] = 0u;
+    }
   }
 }
 
@@ -1149,11 +1202,13 @@ hipError_t launch_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t mi
   if (bitmap != nullptr) {
     const uint64_t nwords = (ncells + 31) / 32;
     const uint32_t nb = cell_list_blocks(nwords, &chunk);
+    chunk = (chunk + kBitmapWPT - 1) / kBitmapWPT * kBitmapWPT;   // aligned loads; trailing blocks may be empty
+    const uint32_t vec = ((uintptr_t)bitmap & 15u) == 0 ? 1u : 0u;
     hipLaunchKernelGGL(bitmap_list_count_kernel, dim3(nb), dim3(256), 0, s, bitmap, nwords, ncells, chunk, counts,
-                       min_count, block_scratch);
+                       min_count, block_scratch, vec);
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, block_scratch, nb, total);
     hipLaunchKernelGGL(bitmap_list_write_kernel, dim3(nb), dim3(256), 0, s, bitmap, nwords, ncells, chunk, counts,
-                       min_count, block_scratch, cells, cap);
+                       min_count, block_scratch, cells, cap, vec);
     return hipGetLastError();
   }
   const uint32_t nb = cell_list_blocks(ncells, &chunk);
@@ -1167,8 +1222,9 @@ hipError_t launch_cell_list(const uint32_t* counts, uint64_t ncells, uint32_t mi
 
 hipError_t launch_bitmap_clear(uint32_t* bitmap, uint64_t ncells, uint32_t* counts, hipStream_t s) {
   const uint64_t nwords = (ncells + 31) / 32;
-  hipLaunchKernelGGL(bitmap_clear_kernel, dim3(grid_of(nwords, 256, 8192)), dim3(256), 0, s, bitmap, nwords, ncells,
-                     counts);
+  const uint32_t vec = ((uintptr_t)bitmap & 15u) == 0 ? 1u : 0u;
+  hipLaunchKernelGGL(bitmap_clear_kernel, dim3(grid_of((nwords + 3) / 4, 256, 8192)), dim3(256), 0, s, bitmap, nwords,
+                     ncells, counts, vec);
   return hipGetLastError();
 }
 

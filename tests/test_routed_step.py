@@ -51,7 +51,10 @@ def test_cell_list_async_matches_reference():
     cd = dev(counts.view(np.int32))
     words = np.packbits(counts > 0, bitorder="little").view(np.uint32)
     total = torch.zeros(1, dtype=torch.int64, device="cuda")
-    for bm in (None, dev(words.view(np.int32))):
+    wd = dev(words.view(np.int32))
+    padded = torch.zeros(wd.numel() + 1, dtype=torch.int32, device="cuda")
+    padded[1:] = wd                                      # a bitmap one word past a 16-byte boundary
+    for bm in (None, wd, padded[1:]):
         for mc, cap in ((1, 30_000), (3, 50), (9, 1 << 16)):
             out = torch.full((cap,), -7, dtype=torch.int64, device="cuda")
             csk.cell_list_async(cd, out, total, mc, bitmap=bm)

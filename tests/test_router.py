@@ -300,22 +300,26 @@ def test_bitmap_bits_beyond_the_cells_are_ignored():
     # 1000 cells (the last bitmap word has 24 bits past the end, all set here): listing and
     # clearing touch only real cells; the counters sit at the front of a larger buffer whose
     # tail must stay untouched
+    # (a bitmap at a 16-byte boundary takes the vector loads, one a word past it the scalar ones)
     import torch
-    buf = torch.full((1024,), 7, dtype=torch.int32, device="cuda")
-    counts = buf[:1000]
-    counts.zero_()
-    counts[[3, 500, 999]] = torch.tensor([2, 5, 1], dtype=torch.int32, device="cuda")
-    words = np.zeros(32, dtype=np.uint32)
-    for c in (3, 500, 999):
-        words[c // 32] |= np.uint32(1 << (c % 32))
-    words[31] |= np.uint32(0xFFFFFF00)                  # bits of cells 1000 .. 1023
-    bm = dev(words.view(np.int32))
-    assert csk.cell_list(counts, 1, bitmap=bm).cpu().numpy().tolist() == [3, 500, 999]
-    assert csk.cell_list(counts, 2, bitmap=bm).cpu().numpy().tolist() == [3, 500]
-    csk.cells_clear(counts, bm)
-    torch.cuda.synchronize()
-    assert not counts.any().item() and not bm.any().item()
-    assert (buf[1000:] == 7).all().item()
+    for off in (0, 1):
+        buf = torch.full((1024,), 7, dtype=torch.int32, device="cuda")
+        counts = buf[:1000]
+        counts.zero_()
+        counts[[3, 500, 999]] = torch.tensor([2, 5, 1], dtype=torch.int32, device="cuda")
+        words = np.zeros(32, dtype=np.uint32)
+        for c in (3, 500, 999):
+            words[c // 32] |= np.uint32(1 << (c % 32))
+        words[31] |= np.uint32(0xFFFFFF00)              # bits of cells 1000 .. 1023
+        store = torch.zeros(32 + off, dtype=torch.int32, device="cuda")
+        store[off:] = dev(words.view(np.int32))
+        bm = store[off:]
+        assert csk.cell_list(counts, 1, bitmap=bm).cpu().numpy().tolist() == [3, 500, 999]
+        assert csk.cell_list(counts, 2, bitmap=bm).cpu().numpy().tolist() == [3, 500]
+        csk.cells_clear(counts, bm)
+        torch.cuda.synchronize()
+        assert not counts.any().item() and not bm.any().item()
+        assert (buf[1000:] == 7).all().item()
 
 
 def test_trained_router_logits_match_the_fp32_reference():
