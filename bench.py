@@ -27,8 +27,8 @@ BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
 # rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) scaled by a 1 GiB device copy
 # (profiles/update_kernels_plummer_2e30.md).  Reported only while the kernel sources hash
 # to what was profiled; any change to them makes `traffic` null until measured again.
-TRAFFIC = {"bytes": 45_253_031_936, "particles": 1 << 30,
-           "sources_sha256": "46ef90d3045e97ab4eef7500b82f346bed358182e326d86a56537fbc45a7ba2f"}
+TRAFFIC = {"bytes": 45_246_008_944, "particles": 1 << 30,
+           "sources_sha256": "4a22c0857edefa9985b5e8ca525f04f295581de93b7280e881cff311b58daaad"}
 TRAFFIC_SOURCES = ["csk_update.hip", "csk_sortbin.hip", "csk_sortbin_body.h", "csk_kernel_util.h", "csk_device.h",
                    "csk_internal.h"]
 

@@ -135,10 +135,7 @@ __device__ __forceinline__ void collect2_body(const CollectDesc* __restrict__ cp
           uint32_t q[4];
           row_hashes_kb<4, KB>(ti, keys[j], q);
 #pragma unroll
-          for (int r = 0; r < D; ++r) {
-            const FilterProbe pr = field_probe(field_bits<kFieldBits>(q, r));
-            fp += ((filt[pr.word] & pr.mask) == pr.mask) ? 1u : 0u;
-          }
+          for (int r = 0; r < D; ++r) fp += field_hit(filt, field_bits<kFieldBits>(q, r));
         } else {
           uint32_t bk[D], sg[D];
           rows_bucket_sign_kb<D, HM, KB>(ti, keys[j], t.w, t.wshift, bk, sg);

@@ -97,8 +97,8 @@ __device__ __forceinline__ bool cell_index_m(float p, const Mesh& m, int32_t& ou
     i += (r1 >= 0.0) ? 1 : 0;
     i -= (r0 < 0.0) ? 1 : 0;
   }
-  i += (i < 0) ? m.G : 0;
-  i += (i < 0) ? m.G : 0;
+  // i in [-2G, 2G): + 2G below 0 gives [0, 2G), then - G from G on gives [0, G)
+  i += (i < 0) ? 2 * m.G : 0;
   i -= (i >= m.G) ? m.G : 0;
   out = i;
   return ok;
@@ -470,6 +470,13 @@ __device__ __forceinline__ FilterProbe field_probe(uint32_t f) {
   p.word = f & (kFieldFilterWords - 1u);
   p.mask = (1u << ((f >> 15) & 31u)) | (1u << ((f >> 20) & 31u));
   return p;
+}
+
+// 1 when both bits of field_probe(f) are set in the filter words filt, else 0: the bits
+// shifted down and anded (no mask to build and compare).
+__device__ __forceinline__ uint32_t field_hit(const uint32_t* filt, uint32_t f) {
+  const uint32_t x = filt[f & (kFieldFilterWords - 1u)];
+  return (x >> ((f >> 15) & 31u)) & (x >> ((f >> 20) & 31u)) & 1u;
 }
 
 // f = L_r(x) ^ c_r from the row's columns (build side; x < 2^25).
