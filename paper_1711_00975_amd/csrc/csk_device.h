@@ -97,10 +97,13 @@ __device__ __forceinline__ bool cell_index_m(float p, const Mesh& m, int32_t& ou
     i += (r1 >= 0.0) ? 1 : 0;
     i -= (r0 < 0.0) ? 1 : 0;
   }
-  // i in [-2G, 2G): + 2G below 0 gives [0, 2G), then - G from G on gives [0, G)
-  i += (i < 0) ? 2 * m.G : 0;
-  i -= (i >= m.G) ? m.G : 0;
-  out = i;
+  // i in [-2G, 2G) into [0, G) with unsigned minima: u = i + 2G is in [0, 4G), and
+  // min(u, u - 2G) (u - 2G = i as unsigned, huge when i < 0) is in [0, 2G); then
+  // min(u, u - G) is in [0, G)
+  uint32_t u = (uint32_t)(i + 2 * m.G);
+  u = __builtin_elementwise_min(u, (uint32_t)i);
+  u = __builtin_elementwise_min(u, u - (uint32_t)m.G);
+  out = (int32_t)u;
   return ok;
 }
 
@@ -221,11 +224,20 @@ __device__ __forceinline__ void row_hashes_kb(const uint32_t* __restrict__ ti, u
     for (int c = 0; c < KB; ++c)
 #pragma unroll
       for (int q = 0; q < DP / 4; ++q) v[c][q] = ((const uint4*)(ti + (c * 256 + byte[c]) * DP))[q];
+    // three-input XORs (truth table 0x96), two entries folded in per instruction
+    auto xor3 = [](uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); };
 #pragma unroll
     for (int q = 0; q < DP / 4; ++q) {
       uint4 x = v[0][q];
+      int c = 1;
 #pragma unroll
-      for (int c = 1; c < KB; ++c) {
+      for (; c + 1 < KB; c += 2) {
+        x.x = xor3(x.x, v[c][q].x, v[c + 1][q].x);
+        x.y = xor3(x.y, v[c][q].y, v[c + 1][q].y);
+        x.z = xor3(x.z, v[c][q].z, v[c + 1][q].z);
+        x.w = xor3(x.w, v[c][q].w, v[c + 1][q].w);
+      }
+      if (c < KB) {
         x.x ^= v[c][q].x;
         x.y ^= v[c][q].y;
         x.z ^= v[c][q].z;
