@@ -27,8 +27,8 @@ BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
 # rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) scaled by a 1 GiB device copy
 # (profiles/update_kernels_plummer_2e30.md).  Reported only while the kernel sources hash
 # to what was profiled; any change to them makes `traffic` null until measured again.
-TRAFFIC = {"bytes": 45_244_817_488, "particles": 1 << 30,
-           "sources_sha256": "4b9d6fa747811d474d7a7a1214fbaa7c297ccd3ac30d0debdba6f7d93cf898da"}
+TRAFFIC = {"bytes": 45_242_652_432, "particles": 1 << 30,
+           "sources_sha256": "19f935bf0f5f367c4334ad095d79f670c8cc0f1bb2a92e948903307ecfc43a10"}
 TRAFFIC_SOURCES = ["csk_update.hip", "csk_sortbin.hip", "csk_sortbin_body.h", "csk_kernel_util.h", "csk_device.h",
                    "csk_internal.h"]
 

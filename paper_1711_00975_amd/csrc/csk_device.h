@@ -477,18 +477,21 @@ constexpr uint32_t kFieldFilterMaxItems = kFieldFilterWords * 32 / 4;
 constexpr uint32_t kFilterAllocWords = kFieldFilterWords > (uint32_t)kFilterWords ? kFieldFilterWords
                                                                                    : (uint32_t)kFilterWords;
 
+// Probe of the field-probe filter for a 25-bit field f (bits above 24 ignored): the word
+// from bits 10..24, the two bit positions from bits 0..4 and 5..9.
 __device__ __forceinline__ FilterProbe field_probe(uint32_t f) {
   FilterProbe p;
-  p.word = f & (kFieldFilterWords - 1u);
-  p.mask = (1u << ((f >> 15) & 31u)) | (1u << ((f >> 20) & 31u));
+  p.word = (f >> 10) & (kFieldFilterWords - 1u);
+  p.mask = (1u << (f & 31u)) | (1u << ((f >> 5) & 31u));
   return p;
 }
 
-// 1 when both bits of field_probe(f) are set in the filter words filt, else 0: the bits
-// shifted down and anded (no mask to build and compare).
+// 1 when both bits of field_probe(f) are set in the filter words filt, else 0: the word
+// shifted down by each bit position and anded (no mask to build and compare; a shift takes
+// the low five bits of its amount, so bits 0..4 need no extraction).
 __device__ __forceinline__ uint32_t field_hit(const uint32_t* filt, uint32_t f) {
-  const uint32_t x = filt[f & (kFieldFilterWords - 1u)];
-  return (x >> ((f >> 15) & 31u)) & (x >> ((f >> 20) & 31u)) & 1u;
+  const uint32_t x = filt[(f >> 10) & (kFieldFilterWords - 1u)];
+  return (x >> (f & 31u)) & (x >> ((f >> 5) & 31u)) & 1u;
 }
 
 // f = L_r(x) ^ c_r from the row's columns (build side; x < 2^25).
