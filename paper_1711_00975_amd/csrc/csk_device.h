@@ -81,7 +81,9 @@ __device__ __forceinline__ bool cell_index_m(float p, const Mesh& m, int32_t& ou
   bool ok;
   if (MODE == kMeshPow2Ratio) {
     ok = __builtin_fabsf(p) < m.twoLf;
-    i = ok ? (int32_t)__builtin_floorf(p * m.Rf) : 0;
+    // floor and conversion in one instruction, defined for every input (out-of-range
+    // values clamp, NaN gives 0), so no select is needed for the particles that fail ok
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(p * m.Rf));
   } else if (MODE == kMeshExactRatio) {
     const double x = (double)p;
     ok = __builtin_fabs(x) < m.twoL;
@@ -100,7 +102,7 @@ __device__ __forceinline__ bool cell_index_m(float p, const Mesh& m, int32_t& ou
   // i in [-2G, 2G) into [0, G) with unsigned minima: u = i + 2G is in [0, 4G), and
   // min(u, u - 2G) (u - 2G = i as unsigned, huge when i < 0) is in [0, 2G); then
   // min(u, u - G) is in [0, G)
-  uint32_t u = (uint32_t)(i + 2 * m.G);
+  uint32_t u = (uint32_t)i + 2u * (uint32_t)m.G;
   u = __builtin_elementwise_min(u, (uint32_t)i);
   u = __builtin_elementwise_min(u, u - (uint32_t)m.G);
   out = (int32_t)u;
