@@ -27,8 +27,8 @@ BYTES_PER_PARTICLE = 12         # algorithmic: each float32 position read once
 # rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) scaled by a 1 GiB device copy
 # (profiles/update_kernels_plummer_2e30.md).  Reported only while the kernel sources hash
 # to what was profiled; any change to them makes `traffic` null until measured again.
-TRAFFIC = {"bytes": 45_240_697_168, "particles": 1 << 30,
-           "sources_sha256": "dfa075a4d6d241a4e44b9dadf670fa800ef966d6dbaa2b8f7bc1db3683dfe81a"}
+TRAFFIC = {"bytes": 45_239_779_984, "particles": 1 << 30,
+           "sources_sha256": "e0e1f7bd342daf50b0b5635228e7ed48f7592ae02dc0c50787f91da9329cb834"}
 TRAFFIC_SOURCES = ["csk_update.hip", "csk_sortbin.hip", "csk_sortbin_body.h", "csk_kernel_util.h", "csk_device.h",
                    "csk_internal.h"]
 

@@ -1203,6 +1203,10 @@ csk_status csk_batch_topk(csk_batch* b, const uint32_t* k, uint64_t* const* keys
     call.out[i] = out[i];
     call.k[i] = k[i];
     call.partial[i] = b->sk[i]->partial_set ? 1u : 0u;
+    // the set holds keys of the latched mesh only (a different mesh needs a reset), all
+    // below G^3: the rank count compares (estimate, key) as one word when that is <= 2^32
+    const uint64_t G = b->sk[i]->mesh_set ? (uint64_t)b->sk[i]->mesh.G : 0u;
+    call.key32[i] = (b->sk[i]->mesh_set && G * G * G <= (1ull << 32)) ? 1u : 0u;
   }
   CSK_HIP(launch_topk_batch(b->topk, b->count, b->d, slots_max, mc_max, k_max, call, st), "batch_topk");
   return CSK_OK;

@@ -87,7 +87,8 @@ __device__ __forceinline__ bool cell_index_m(float p, const Mesh& m, int32_t& ou
   } else if (MODE == kMeshExactRatio) {
     const double x = (double)p;
     ok = __builtin_fabs(x) < m.twoL;
-    i = ok ? (int32_t)__builtin_floor(x * m.R) : 0;
+    // the conversion as one instruction, defined for every input (as above)
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(i) : "v"(__builtin_floor(x * m.R)));
   } else {
     const double x = (double)p;
     ok = __builtin_fabs(x) < m.twoL;

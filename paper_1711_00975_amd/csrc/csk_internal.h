@@ -315,6 +315,7 @@ struct TopkCall {
   uint32_t* out[kMaxBatch];
   uint32_t k[kMaxBatch];
   uint32_t partial[kMaxBatch];
+  uint32_t key32[kMaxBatch];   // 1: the sketch's keys are below 2^32 (G^3 <= 2^32)
 };
 hipError_t launch_topk_batch(const TopkDesc* D, uint32_t count, uint32_t d, uint32_t slots_max,
                              uint32_t max_cand_max, uint32_t k_max, const TopkCall& call, hipStream_t s);

@@ -552,9 +552,16 @@ __global__ __launch_bounds__(256) void sel_gather_kernel(const uint64_t* __restr
 // so the ranks are a permutation of [0, n).
 constexpr uint32_t kRankChunk = 1024;      // smallest chunk
 constexpr uint32_t kMaxGridY = 65535;
+// (est, key) as one 64-bit word for keys below 2^32: j comes before i in the output order
+// (higher estimate, then lower key) exactly when its word is the larger.
+__device__ __forceinline__ uint64_t rank_word(int32_t e, uint64_t k) {
+  return ((uint64_t)((uint32_t)e ^ 0x80000000u) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
+}
+
 __device__ __forceinline__ void rank_count_body(const uint64_t* __restrict__ sk, const int32_t* __restrict__ se,
                                                 const SelState* st, uint32_t k, uint32_t chunk,
-                                                uint32_t* __restrict__ rank, uint32_t cy = blockIdx.y) {
+                                                uint32_t* __restrict__ rank, uint32_t cy = blockIdx.y,
+                                                bool key32 = false) {
   __shared__ uint64_t tk[256];
   __shared__ int32_t te[256];
   const uint32_t n = min(st->n_sel, k);
@@ -568,15 +575,26 @@ __device__ __forceinline__ void rank_count_body(const uint64_t* __restrict__ sk,
   const uint64_t ki = act ? sk[i] : 0;
   const int32_t ei = act ? se[i] : 0;
   uint32_t cnt = 0;
-  for (uint32_t j0 = j_lo; j0 < j_hi; j0 += 256) {
-    __syncthreads();
-    if (j0 + threadIdx.x < j_hi) {
-      tk[threadIdx.x] = sk[j0 + threadIdx.x];
-      te[threadIdx.x] = se[j0 + threadIdx.x];
+  if (key32) {   // one 64-bit comparison per pair
+    const uint64_t wi = rank_word(ei, ki);
+    for (uint32_t j0 = j_lo; j0 < j_hi; j0 += 256) {
+      __syncthreads();
+      if (j0 + threadIdx.x < j_hi) tk[threadIdx.x] = rank_word(se[j0 + threadIdx.x], sk[j0 + threadIdx.x]);
+      __syncthreads();
+      const uint32_t lim = min(256u, j_hi - j0);
+      for (uint32_t t = 0; t < lim; ++t) cnt += tk[t] > wi;
     }
-    __syncthreads();
-    const uint32_t lim = min(256u, j_hi - j0);
-    for (uint32_t t = 0; t < lim; ++t) cnt += (te[t] > ei) || (te[t] == ei && tk[t] < ki);
+  } else {
+    for (uint32_t j0 = j_lo; j0 < j_hi; j0 += 256) {
+      __syncthreads();
+      if (j0 + threadIdx.x < j_hi) {
+        tk[threadIdx.x] = sk[j0 + threadIdx.x];
+        te[threadIdx.x] = se[j0 + threadIdx.x];
+      }
+      __syncthreads();
+      const uint32_t lim = min(256u, j_hi - j0);
+      for (uint32_t t = 0; t < lim; ++t) cnt += (te[t] > ei) || (te[t] == ei && tk[t] < ki);
+    }
   }
   if (act && cnt) atomicAdd(&rank[i], cnt);
 }
@@ -701,7 +719,7 @@ __global__ __launch_bounds__(256) void rank_clear_batch_kernel(const TopkDesc* _
 __global__ __launch_bounds__(256) void rank_count_batch_kernel(const TopkDesc* __restrict__ D, TopkCall call,
                                                                uint32_t chunk) {
   const TopkDesc& d = D[blockIdx.z];
-  rank_count_body(d.sk, d.se, d.st, call.k[blockIdx.z], chunk, (uint32_t*)d.ce, blockIdx.y);
+  rank_count_body(d.sk, d.se, d.st, call.k[blockIdx.z], chunk, (uint32_t*)d.ce, blockIdx.y, call.key32[blockIdx.z] != 0u);
 }
 
 __global__ __launch_bounds__(256) void rank_place_batch_kernel(const TopkDesc* __restrict__ D, TopkCall call) {
